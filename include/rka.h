@@ -1,0 +1,156 @@
+/*
+ * rka.h -- C ABI of librka.so: randomized Kaczmarz with averaging (RKA) and
+ * its block-averaging variant (RKAB) for dense overdetermined A x = b, on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Paper: Ferreira, Acebron, Monteiro, "Parallelization Strategies for the
+ * Randomized Kaczmarz Algorithm on Large-Scale Dense Systems", arXiv
+ * 2401.17474.  The problem is the one of Sec. 1 (Eqs. (1)-(2)): A in
+ * R^{m x n}, b in R^m, find x with A x = b, or the least-squares x when the
+ * system is inconsistent; m >= n is the intended use (m < n is accepted).
+ *
+ * General conventions (apply to every entry point):
+ *   - Every array argument is a DEVICE pointer into memory owned by the
+ *     caller (for instance a torch tensor's storage).  The library never
+ *     frees caller memory.  `info` arguments are HOST pointers.
+ *   - A is row-major, m rows of n elements, consecutive rows lda >= n
+ *     elements apart.  Element type is given by `dtype` (rka_dtype).  The
+ *     fast vector path is used when the base address and the row pitch
+ *     (lda * element size) are multiples of 16 bytes and n is a multiple of
+ *     16 / element size; other layouts take a scalar path with identical
+ *     results for the sampler and row norms.
+ *   - b, x0, x, x_ref are FP64 vectors (b: m entries, the others n).
+ *   - All work is ordered on `stream` (a hipStream_t; NULL = the null
+ *     stream).  Entry points that return an rka_info wait for the stream
+ *     once, at the end, to read it back; the others only enqueue work.
+ *   - Scratch memory is allocated and freed on `stream` (stream-ordered
+ *     allocation); no scratch outlives a call.
+ *   - Results depend only on the inputs and the method parameters for a
+ *     given device and library build; two identical calls give bitwise
+ *     identical outputs.
+ *   - Return value: an rka_status.  Arguments are validated before any
+ *     work is enqueued; a violation returns RKA_EINVAL and touches nothing.
+ *     No entry point throws, aborts or exits.  rka_status_string() names a
+ *     status; rka_last_error() gives a thread-local message for the last
+ *     failing call.
+ */
+#ifndef RKA_H
+#define RKA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rka_dtype { RKA_F64 = 0, RKA_F32 = 1, RKA_BF16 = 2 } rka_dtype;
+
+typedef enum rka_status {
+    RKA_OK = 0,             /* converged (or ran max_iter with tol == 0)          */
+    RKA_NOT_CONVERGED = 1,  /* max_iter reached with tol > 0; x is the last iterate */
+    RKA_EINVAL = -1,        /* invalid argument; nothing was enqueued              */
+    RKA_EZERONORM = -2,     /* ||A||_F^2 is zero or not finite                     */
+    RKA_EDIVERGED = -3,     /* the stopping measure became non-finite              */
+    RKA_ENOMEM = -4,        /* scratch allocation failed                           */
+    RKA_EDEVICE = -5        /* a HIP call failed (no device, launch error, ...)    */
+} rka_status;
+
+typedef struct rka_info {
+    int64_t iterations;   /* outer iterations performed                           */
+    int64_t projections;  /* row projections performed = iterations * q * bs      */
+    double rel_err;       /* last stopping measure computed (NaN if none)         */
+    int32_t status;       /* same as the return value                             */
+    int32_t reserved;
+} rka_info;
+
+/*
+ * rka_solve -- RKA with uniform weight alpha, Eq. (7) of Sec. 3.3.1 (Eq. (5)
+ * with w_i = alpha): per iteration k, q rows i are drawn independently, with
+ * replacement, with probability ||A^(i)||^2 / ||A||_F^2 (Eq. (4)), and
+ *     x^(k+1) = x^(k) + (alpha/q) sum_i (b_i - <A^(i), x^(k)>) / ||A^(i)||^2 A^(i)^T.
+ * The draw for worker w at iteration k uses Philox4x32-10 with counter
+ * (k + iter_offset, w, 0, 0) and key = seed, mapped to u in [0,1) with 53
+ * bits, and picks the smallest row l whose running sum of squared row norms
+ * (summed left to right) exceeds u * ||A||_F^2.
+ *
+ *   x0          start vector, or NULL for zero (the paper's usual start).
+ *   x           output, n doubles; may alias x0.  Valid when the return
+ *               value is >= 0 (RKA_NOT_CONVERGED returns the last iterate).
+ *   q           workers averaged per iteration, >= 1 (Sec. 2.3.1).
+ *   alpha       relaxation weight, finite and > 0.
+ *   max_iter    iteration cap, >= 0.
+ *   tol         relative tolerance >= 0.  tol == 0 runs exactly max_iter
+ *               iterations.  Otherwise the stopping measure -- ||x - x_ref||
+ *               / ||x_ref|| if x_ref is given (Sec. 3.1 stops on the error
+ *               to the solution), else ||b - A x|| / ||b|| -- is taken on x^(k)
+ *               for every k that is a multiple of check_every and for k =
+ *               max_iter; the solve stops at the first k where it is <= tol.
+ *   seed        Philox key.
+ *   x_ref       reference solution (NULL: use the residual measure).
+ *   iter_offset added to k in the random counter, so that a solve of K2
+ *               iterations started from the result of a K1-iteration solve
+ *               with iter_offset = K1 continues the same stream.
+ *   check_every stopping-test interval (values < 1 mean 1).
+ */
+int rka_solve(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const double* b,
+              const double* x0, double* x, int32_t q, double alpha, int64_t max_iter, double tol,
+              uint64_t seed, const double* x_ref, int64_t iter_offset, int64_t check_every,
+              void* stream, rka_info* info);
+
+/*
+ * rkab_solve -- RKAB, the block-averaging variant of Sec. 3.4.1
+ * (Algorithm 3): per outer iteration every worker w starts from
+ * v = x^(k) and applies block_size relaxed projections
+ *     v <- v + alpha (b_i - <A^(i), v>) / ||A^(i)||^2 A^(i)^T
+ * with rows drawn as above using counter (k + iter_offset, w, j, 0) for the
+ * j-th projection; then x^(k+1) = (1/q) sum_w v_w.  block_size = 1 is RKA.
+ * Arguments as rka_solve; block_size must be in [1, 2^24).  The stopping
+ * measure is taken on the averaged iterates only.
+ */
+int rkab_solve(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const double* b,
+               const double* x0, double* x, int32_t q, int32_t block_size, double alpha,
+               int64_t max_iter, double tol, uint64_t seed, const double* x_ref,
+               int64_t iter_offset, int64_t check_every, void* stream, rka_info* info);
+
+/*
+ * rka_row_norms -- w_l = sum_c A[l,c]^2 for every row (the numerators of
+ * Eq. (4)), each summed left to right in FP64 with a rounded square and a
+ * rounded add per term (narrow types widen exactly first).  w: m doubles.
+ * Enqueue only.
+ */
+int rka_row_norms(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, double* w,
+                  void* stream);
+
+/*
+ * rka_prefix -- running sum c_l = c_{l-1} + w_l, left to right, so that
+ * c[m-1] = ||A||_F^2 (Eq. (4) denominator); also stores in *last_pos (device
+ * int64, may be NULL) the largest l with w_l > 0.  Waits for the stream to
+ * read c[m-1] back and returns RKA_EZERONORM if it is zero or not finite.
+ */
+int rka_prefix(const double* w, int64_t m, double* c, int64_t* last_pos, void* stream);
+
+/*
+ * rka_sample_indices -- the row stream both solvers use: for k in [0, K),
+ * w in [0, q), j in [0, bs): idx[(k*q + w)*bs + j] = the row picked by the
+ * draw with counter (k + iter_offset, w, j, dom) and key seed (see
+ * rka_solve).  w, c as produced by rka_row_norms / rka_prefix; idx: K*q*bs
+ * int32 on the device.  dom in [0, 255] selects an independent stream (0 is
+ * the solvers' row stream).  Enqueue only.
+ */
+int rka_sample_indices(const double* w, const double* c, int64_t m, uint64_t seed,
+                       int64_t iter_offset, int64_t K, int32_t q, int32_t bs, int32_t dom,
+                       int32_t* idx, void* stream);
+
+/* Name of a status code (static string). */
+const char* rka_status_string(int status);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* rka_last_error(void);
+
+/* Library version, as major*10000 + minor*100 + patch. */
+int rka_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RKA_H */

@@ -1,0 +1,210 @@
+"""MI355X-native randomized Kaczmarz with averaging (RKA) and its block
+variant (RKAB) -- arXiv 2401.17474 -- Python binding over ``librka.so``.
+
+This module only marshals torch tensors into the C ABI declared in
+``include/rka.h``; every step of the solve runs in the HIP kernels of the
+library.  PyTorch supplies device memory and the current stream.  There is no
+CPU fallback: if the library is not built, or a tensor is not on the GPU, the
+call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "librka.so")
+
+OK, NOT_CONVERGED, EINVAL, EZERONORM, EDIVERGED, ENOMEM, EDEVICE = 0, 1, -1, -2, -3, -4, -5
+
+_lib = None
+
+
+class RKAError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{status_string(status)}: {msg}")
+        self.status = status
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("projections", ctypes.c_int64),
+                ("rel_err", ctypes.c_double), ("status", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+@dataclass
+class Info:
+    iterations: int
+    projections: int
+    rel_err: float
+    status: int
+
+
+def lib():
+    """Load librka.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I64, I32, D, U64 = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                               ctypes.c_double, ctypes.c_uint64)
+        L.rka_solve.argtypes = [P, ctypes.c_int, I64, I64, I64, P, P, P, I32, D, I64, D, U64, P,
+                                I64, I64, P, ctypes.POINTER(_Info)]
+        L.rkab_solve.argtypes = [P, ctypes.c_int, I64, I64, I64, P, P, P, I32, I32, D, I64, D,
+                                 U64, P, I64, I64, P, ctypes.POINTER(_Info)]
+        L.rka_row_norms.argtypes = [P, ctypes.c_int, I64, I64, I64, P, P]
+        L.rka_prefix.argtypes = [P, I64, P, P, P]
+        L.rka_sample_indices.argtypes = [P, P, I64, U64, I64, I64, I32, I32, I32, P, P]
+        L.rka_status_string.argtypes = [ctypes.c_int]
+        L.rka_status_string.restype = ctypes.c_char_p
+        L.rka_last_error.argtypes = []
+        L.rka_last_error.restype = ctypes.c_char_p
+        L.rka_version.restype = ctypes.c_int
+        for f in ("rka_solve", "rkab_solve", "rka_row_norms", "rka_prefix",
+                  "rka_sample_indices"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    names = {OK: "RKA_OK", NOT_CONVERGED: "RKA_NOT_CONVERGED", EINVAL: "RKA_EINVAL",
+             EZERONORM: "RKA_EZERONORM", EDIVERGED: "RKA_EDIVERGED", ENOMEM: "RKA_ENOMEM",
+             EDEVICE: "RKA_EDEVICE"}
+    return names.get(status, f"status {status}")
+
+
+def _raise_if(status):
+    if status < 0:
+        raise RKAError(status, lib().rka_last_error().decode())
+
+
+# -- tensor marshalling --------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t):
+    torch = _torch()
+    codes = {torch.float64: 0, torch.float32: 1, torch.bfloat16: 2}
+    if t.dtype not in codes:
+        raise TypeError(f"A must be float64, float32 or bfloat16, got {t.dtype}")
+    return codes[t.dtype]
+
+
+def _matrix(A):
+    if A.dim() != 2:
+        raise ValueError("A must be a 2-D tensor")
+    if not A.is_cuda:
+        raise ValueError("A must be a GPU tensor")
+    if A.stride(1) != 1 or (A.shape[0] > 1 and A.stride(0) < A.shape[1]):
+        raise ValueError("A must be row-major with unit column stride")
+    lda = A.stride(0) if A.shape[0] > 1 else A.shape[1]
+    return _dtype_code(A), A.shape[0], A.shape[1], lda
+
+
+def _vec(v, n, name, allow_none=True):
+    torch = _torch()
+    if v is None:
+        if allow_none:
+            return None
+        raise ValueError(f"{name} is required")
+    if not v.is_cuda or v.dtype != torch.float64 or v.dim() != 1 or v.shape[0] != n \
+            or not v.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 GPU vector of length {n}")
+    return v
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+# -- solvers -------------------------------------------------------------------
+
+def rka_solve(A, b, *, q, alpha=1.0, max_iter=1000, tol=0.0, seed=1, x0=None, x_ref=None,
+              iter_offset=0, check_every=1, out=None, stream=None, raise_on_error=True):
+    """RKA with uniform weight alpha (Eq. (7), Sec. 3.3.1).  Returns (x, Info)."""
+    torch = _torch()
+    code, m, n, lda = _matrix(A)
+    b = _vec(b, m, "b", False)
+    x = out if out is not None else torch.empty(n, dtype=torch.float64, device=A.device)
+    _vec(x, n, "out", False)
+    info = _Info()
+    st = lib().rka_solve(_ptr(A), code, m, n, lda, _ptr(b), _ptr(_vec(x0, n, "x0")), _ptr(x), q,
+                         alpha, max_iter, tol, seed, _ptr(_vec(x_ref, n, "x_ref")), iter_offset,
+                         check_every, _stream(stream), ctypes.byref(info))
+    if raise_on_error:
+        _raise_if(st)
+    return x, Info(info.iterations, info.projections, info.rel_err, st)
+
+
+def rkab_solve(A, b, *, q, block_size, alpha=1.0, max_iter=1000, tol=0.0, seed=1, x0=None,
+               x_ref=None, iter_offset=0, check_every=1, out=None, stream=None,
+               raise_on_error=True):
+    """RKAB (Sec. 3.4.1, Algorithm 3).  Returns (x, Info)."""
+    torch = _torch()
+    code, m, n, lda = _matrix(A)
+    b = _vec(b, m, "b", False)
+    x = out if out is not None else torch.empty(n, dtype=torch.float64, device=A.device)
+    _vec(x, n, "out", False)
+    info = _Info()
+    st = lib().rkab_solve(_ptr(A), code, m, n, lda, _ptr(b), _ptr(_vec(x0, n, "x0")), _ptr(x),
+                          q, block_size, alpha, max_iter, tol, seed,
+                          _ptr(_vec(x_ref, n, "x_ref")), iter_offset, check_every,
+                          _stream(stream), ctypes.byref(info))
+    if raise_on_error:
+        _raise_if(st)
+    return x, Info(info.iterations, info.projections, info.rel_err, st)
+
+
+def row_norms(A, stream=None):
+    """Squared row norms (Eq. (4) numerators) as a float64 GPU tensor."""
+    torch = _torch()
+    code, m, n, lda = _matrix(A)
+    w = torch.empty(m, dtype=torch.float64, device=A.device)
+    _raise_if(lib().rka_row_norms(_ptr(A), code, m, n, lda, _ptr(w), _stream(stream)))
+    return w
+
+
+def prefix(w, stream=None):
+    """Running sum of the weights and the last row with positive weight."""
+    torch = _torch()
+    m = w.shape[0]
+    _vec(w, m, "w", False)
+    c = torch.empty_like(w)
+    last = torch.empty(1, dtype=torch.int64, device=w.device)
+    _raise_if(lib().rka_prefix(_ptr(w), m, _ptr(c), _ptr(last), _stream(stream)))
+    return c, last
+
+
+def sample_indices(w, c, *, seed, iter_offset=0, K, q, bs=1, dom=0, stream=None):
+    """The row stream: int32 tensor of K*q*bs indices, layout (k, worker, j)."""
+    torch = _torch()
+    m = w.shape[0]
+    _vec(w, m, "w", False)
+    _vec(c, m, "c", False)
+    idx = torch.empty(K * q * bs, dtype=torch.int32, device=w.device)
+    _raise_if(lib().rka_sample_indices(_ptr(w), _ptr(c), m, seed, iter_offset, K, q, bs, dom,
+                                       _ptr(idx), _stream(stream)))
+    return idx
+
+
+# -- host helpers --------------------------------------------------------------
+
+def alpha_star(s_min: float, s_max: float, q: int) -> float:
+    """Optimal uniform weight for consistent systems, Eq. (6) (Sec. 2.3.1):
+    s = sigma^2(A) / ||A||_F^2 at the extreme singular values."""
+    if q == 1 or s_max - s_min <= 1.0 / (q - 1):  # q = 1: the first case always holds
+        return q / (1.0 + (q - 1) * s_min)
+    return 2.0 * q / (1.0 + (q - 1) * (s_min + s_max))

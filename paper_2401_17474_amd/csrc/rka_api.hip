@@ -1,0 +1,323 @@
+// rka_api.hip -- the C ABI declared in include/rka.h: argument validation,
+// stream-ordered scratch, and the sequence of launches of one solve:
+//
+//   status init -> b finite check -> row norms -> running sum (+ W check)
+//   -> [reference norm, measure at k = 0]
+//   -> for each chunk: row stream for the chunk -> persistent iteration
+//      kernel [-> residual measure at multiples of check_every]
+//   -> [final measure at k = max_iter] -> one read-back of the status.
+//
+// Later launches of a solve see the device status and return at once when
+// an earlier one decided to stop, so the host never waits mid-solve.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "rka.h"
+#include "rka_device.hpp"
+#include "rka_internal.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int esize(int dtype) { return dtype == RKA_F64 ? 8 : (dtype == RKA_F32 ? 4 : 2); }
+
+bool vector_path_ok(const void* A, int dtype, int64_t n, int64_t lda) {
+  const int es = esize(dtype);
+  const int V = 16 / es;
+  return ((uintptr_t)A % 16 == 0) && ((lda * es) % 16 == 0) && (n % V == 0);
+}
+
+int num_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  return cus;
+}
+
+// Stream-ordered scratch for one call; freed (on the stream) by release().
+struct Scratch {
+  hipStream_t s;
+  void* ptrs[16];
+  int n = 0;
+  explicit Scratch(hipStream_t st) : s(st) {}
+  template <typename U>
+  hipError_t get(U** out, size_t count) {
+    void* p = nullptr;
+    const size_t bytes = count * sizeof(U) > 0 ? count * sizeof(U) : 16;
+    hipError_t e = hipMallocAsync(&p, bytes, s);
+    if (e != hipSuccess) return e;
+    ptrs[n++] = p;
+    *out = (U*)p;
+    return hipSuccess;
+  }
+  void release() {
+    for (int i = n - 1; i >= 0; --i) (void)hipFreeAsync(ptrs[i], s);
+    n = 0;
+  }
+  ~Scratch() { release(); }
+};
+
+#define HIP_TRY(call)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) {                                                                 \
+      return fail(e_ == hipErrorOutOfMemory ? RKA_ENOMEM : RKA_EDEVICE, "%s: %s", #call,   \
+                  hipGetErrorString(e_));                                                   \
+    }                                                                                       \
+  } while (0)
+
+bool bad_dtype(int d) { return d != RKA_F64 && d != RKA_F32 && d != RKA_BF16; }
+
+int validate(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const double* b,
+             double* x, int32_t q, int32_t bs, double alpha, int64_t max_iter, double tol,
+             int64_t iter_offset) {
+  if (!A || !b || !x) return fail(RKA_EINVAL, "A, b and x must be non-null");
+  if (bad_dtype(dtype)) return fail(RKA_EINVAL, "dtype %d is not an rka_dtype", dtype);
+  if (m < 1 || n < 1) return fail(RKA_EINVAL, "m and n must be >= 1 (got %lld, %lld)",
+                                  (long long)m, (long long)n);
+  if (m > INT32_MAX) return fail(RKA_EINVAL, "m must be < 2^31");
+  if (lda < n) return fail(RKA_EINVAL, "lda (%lld) must be >= n (%lld)", (long long)lda,
+                           (long long)n);
+  if (q < 1) return fail(RKA_EINVAL, "q must be >= 1");
+  if (bs < 1 || bs >= (1 << 24)) return fail(RKA_EINVAL, "block_size must be in [1, 2^24)");
+  if (!(alpha > 0.0) || !isfinite(alpha)) return fail(RKA_EINVAL, "alpha must be finite and > 0");
+  if (max_iter < 0) return fail(RKA_EINVAL, "max_iter must be >= 0");
+  if (!(tol >= 0.0) || !isfinite(tol)) return fail(RKA_EINVAL, "tol must be finite and >= 0");
+  if (iter_offset < 0) return fail(RKA_EINVAL, "iter_offset must be >= 0");
+  return RKA_OK;
+}
+
+// Indices per chunk: at most 16 Mi entries (64 MiB).
+constexpr int64_t kIdxBudget = 16ll << 20;
+
+int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
+               const double* b, const double* x0, double* x, int32_t q, int32_t bs, double alpha,
+               int64_t max_iter, double tol, uint64_t seed, const double* x_ref,
+               int64_t iter_offset, int64_t check_every, void* stream, rka_info* info) {
+  g_last_error.clear();
+  if (info) {
+    info->iterations = 0;
+    info->projections = 0;
+    info->rel_err = NAN;
+    info->status = RKA_EINVAL;
+    info->reserved = 0;
+  }
+  int v = validate(A, dtype, m, n, lda, b, x, q, bs, alpha, max_iter, tol, iter_offset);
+  if (v != RKA_OK) return v;
+  if (check_every < 1) check_every = 1;
+  const int ncu = num_cus();
+  if (ncu <= 0) return fail(RKA_EDEVICE, "no HIP device available");
+  hipStream_t s = (hipStream_t)stream;
+
+  rka::SolveShape sh;
+  sh.A = A;
+  sh.dtype = dtype;
+  sh.m = m;
+  sh.n = n;
+  sh.lda = lda;
+  sh.vec_ok = vector_path_ok(A, dtype, n, lda);
+  sh.b = b;
+  sh.x = x;
+  sh.x_ref = (tol > 0.0) ? x_ref : nullptr;
+  sh.alpha = alpha;
+  sh.q = q;
+  sh.bs = block ? bs : 1;
+  sh.num_cu = ncu;
+
+  rka::RkaColGeom cgeo{};
+  rka::RkabGeom bgeo{};
+  bool use_col = !block && rka::rka_col_plan(sh, &cgeo);
+  if (!use_col) {
+    // RKA whose q rows do not fit the column kernel's tile runs as RKAB with
+    // one projection per worker, which is the same iteration (Sec. 3.4.2).
+    if (!rka::rkab_plan(sh, &bgeo))
+      return fail(RKA_EINVAL, "n = %lld is too large for this build's worker kernel",
+                  (long long)n);
+  }
+
+  Scratch sc(s);
+  rka::DevStatus* st;
+  double *w, *c, *part, *scal = nullptr, *vbuf = nullptr;
+  int64_t* last_pos;
+  int32_t* idx;
+  unsigned* bar;
+  const int64_t per_iter = (int64_t)q * sh.bs;
+  int64_t kc_max = kIdxBudget / per_iter;
+  if (kc_max < 1) kc_max = 1;
+  if (kc_max > max_iter) kc_max = max_iter > 0 ? max_iter : 1;
+  const int G = use_col ? cgeo.G : bgeo.G;
+  size_t part_len = use_col ? (size_t)G * (q + 1) : (size_t)G;
+  if (!sh.x_ref && tol > 0.0) {
+    const size_t rb = (size_t)rka::resid_blocks(m);
+    if (rb > part_len) part_len = rb;
+  }
+  HIP_TRY(sc.get(&st, 1));
+  HIP_TRY(sc.get(&w, (size_t)m));
+  HIP_TRY(sc.get(&c, (size_t)m));
+  HIP_TRY(sc.get(&last_pos, 1));
+  HIP_TRY(sc.get(&idx, (size_t)(kc_max * per_iter)));
+  HIP_TRY(sc.get(&part, part_len));
+  HIP_TRY(sc.get(&bar, 1));
+  if (use_col)
+    HIP_TRY(sc.get(&scal, (size_t)q + 1));
+  else
+    HIP_TRY(sc.get(&vbuf, (size_t)q * (size_t)n));
+  sh.wn = w;
+
+  HIP_TRY(rka::launch_status_init(st, tol, s));
+  HIP_TRY(rka::launch_check_finite(b, m, st, s));
+  HIP_TRY(rka::launch_row_norms(A, dtype, m, n, lda, sh.vec_ok, w, s));
+  HIP_TRY(rka::launch_prefix(w, m, c, last_pos, st, s));
+  if (x0) {
+    if (x0 != x) HIP_TRY(hipMemcpyAsync(x, x0, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  } else {
+    HIP_TRY(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), s));
+  }
+  const bool resid_mode = tol > 0.0 && !sh.x_ref;
+  if (tol > 0.0) {
+    HIP_TRY(rka::launch_ref_norm(sh.x_ref ? sh.x_ref : b, sh.x_ref ? n : m, tol, st, s));
+    HIP_TRY(rka::launch_measure(sh, 0, part, st, s));
+  }
+  const int64_t in_kernel_check = (tol > 0.0 && sh.x_ref) ? check_every : 0;
+  for (int64_t k = 0; k < max_iter;) {
+    int64_t kc = max_iter - k < kc_max ? max_iter - k : kc_max;
+    if (resid_mode) {
+      const int64_t to_check = check_every - (k % check_every);
+      if (to_check < kc) kc = to_check;
+    }
+    HIP_TRY(rka::launch_sample(c, m, last_pos, seed, k + iter_offset, kc, q, sh.bs, 0, idx, st, s));
+    if (use_col)
+      HIP_TRY(rka::launch_rka_chunk(sh, cgeo, idx, k, kc, in_kernel_check, part, scal, bar, st, s));
+    else
+      HIP_TRY(rka::launch_rkab_chunk(sh, bgeo, idx, k, kc, in_kernel_check, vbuf, part, bar, st, s));
+    k += kc;
+    if (resid_mode && k % check_every == 0 && k < max_iter)
+      HIP_TRY(rka::launch_measure(sh, k, part, st, s));
+  }
+  if (tol > 0.0 && max_iter > 0) HIP_TRY(rka::launch_measure(sh, max_iter, part, st, s));
+
+  rka::DevStatus hst;
+  HIP_TRY(hipMemcpyAsync(&hst, st, sizeof hst, hipMemcpyDeviceToHost, s));
+  sc.release();
+  HIP_TRY(hipStreamSynchronize(s));
+
+  int status = hst.status;
+  if (status == RKA_EZERONORM) fail(status, "||A||_F^2 is zero or not finite");
+  if (status == RKA_EINVAL) fail(status, "b has a non-finite entry");
+  if (status == RKA_EDIVERGED) fail(status, "the stopping measure became non-finite");
+  if (info) {
+    info->iterations = hst.iterations;
+    info->projections = hst.iterations * per_iter;
+    info->rel_err = isnan(hst.rel2) ? NAN : sqrt(hst.rel2);
+    info->status = status;
+  }
+  return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rka_solve(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const double* b,
+              const double* x0, double* x, int32_t q, double alpha, int64_t max_iter, double tol,
+              uint64_t seed, const double* x_ref, int64_t iter_offset, int64_t check_every,
+              void* stream, rka_info* info) {
+  return solve_impl(false, A, dtype, m, n, lda, b, x0, x, q, 1, alpha, max_iter, tol, seed, x_ref,
+                    iter_offset, check_every, stream, info);
+}
+
+int rkab_solve(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const double* b,
+               const double* x0, double* x, int32_t q, int32_t block_size, double alpha,
+               int64_t max_iter, double tol, uint64_t seed, const double* x_ref,
+               int64_t iter_offset, int64_t check_every, void* stream, rka_info* info) {
+  return solve_impl(true, A, dtype, m, n, lda, b, x0, x, q, block_size, alpha, max_iter, tol, seed,
+                    x_ref, iter_offset, check_every, stream, info);
+}
+
+int rka_row_norms(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, double* w,
+                  void* stream) {
+  g_last_error.clear();
+  if (!A || !w) return fail(RKA_EINVAL, "A and w must be non-null");
+  if (bad_dtype(dtype)) return fail(RKA_EINVAL, "dtype %d is not an rka_dtype", dtype);
+  if (m < 1 || n < 1 || lda < n) return fail(RKA_EINVAL, "need m, n >= 1 and lda >= n");
+  if (num_cus() <= 0) return fail(RKA_EDEVICE, "no HIP device available");
+  HIP_TRY(rka::launch_row_norms(A, dtype, m, n, lda, vector_path_ok(A, dtype, n, lda), w,
+                                (hipStream_t)stream));
+  return RKA_OK;
+}
+
+int rka_prefix(const double* w, int64_t m, double* c, int64_t* last_pos, void* stream) {
+  g_last_error.clear();
+  if (!w || !c) return fail(RKA_EINVAL, "w and c must be non-null");
+  if (m < 1 || m > INT32_MAX) return fail(RKA_EINVAL, "m must be in [1, 2^31)");
+  if (num_cus() <= 0) return fail(RKA_EDEVICE, "no HIP device available");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(rka::launch_prefix(w, m, c, last_pos, nullptr, s));
+  double W = 0.0;
+  HIP_TRY(hipMemcpyAsync(&W, c + (m - 1), sizeof W, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (!(W > 0.0) || !isfinite(W)) return fail(RKA_EZERONORM, "||A||_F^2 is zero or not finite");
+  return RKA_OK;
+}
+
+int rka_sample_indices(const double* w, const double* c, int64_t m, uint64_t seed,
+                       int64_t iter_offset, int64_t K, int32_t q, int32_t bs, int32_t dom,
+                       int32_t* idx, void* stream) {
+  g_last_error.clear();
+  if (!w || !c || !idx) return fail(RKA_EINVAL, "w, c and idx must be non-null");
+  if (m < 1 || m > INT32_MAX) return fail(RKA_EINVAL, "m must be in [1, 2^31)");
+  if (K < 0 || q < 1 || bs < 1 || bs >= (1 << 24) || iter_offset < 0 || dom < 0 || dom > 255)
+    return fail(RKA_EINVAL, "need K >= 0, q >= 1, 1 <= bs < 2^24, iter_offset >= 0, 0 <= dom < 256");
+  if (num_cus() <= 0) return fail(RKA_EDEVICE, "no HIP device available");
+  hipStream_t s = (hipStream_t)stream;
+  // The fallback row (largest l with w_l > 0) comes from a pass over w.
+  int64_t* last_pos = nullptr;
+  double* cscratch = nullptr;
+  HIP_TRY(hipMallocAsync((void**)&last_pos, sizeof(int64_t), s));
+  hipError_t e = hipMallocAsync((void**)&cscratch, (size_t)m * sizeof(double), s);
+  if (e == hipSuccess) e = rka::launch_prefix(w, m, cscratch, last_pos, nullptr, s);
+  if (e == hipSuccess)
+    e = rka::launch_sample(c, m, last_pos, seed, iter_offset, K, q, bs, dom, idx, nullptr, s);
+  if (cscratch) (void)hipFreeAsync(cscratch, s);
+  (void)hipFreeAsync(last_pos, s);
+  if (e != hipSuccess)
+    return fail(e == hipErrorOutOfMemory ? RKA_ENOMEM : RKA_EDEVICE, "sampling: %s",
+                hipGetErrorString(e));
+  return RKA_OK;
+}
+
+const char* rka_status_string(int status) {
+  switch (status) {
+    case RKA_OK: return "RKA_OK";
+    case RKA_NOT_CONVERGED: return "RKA_NOT_CONVERGED";
+    case RKA_EINVAL: return "RKA_EINVAL";
+    case RKA_EZERONORM: return "RKA_EZERONORM";
+    case RKA_EDIVERGED: return "RKA_EDIVERGED";
+    case RKA_ENOMEM: return "RKA_ENOMEM";
+    case RKA_EDEVICE: return "RKA_EDEVICE";
+    default: return "RKA_UNKNOWN";
+  }
+}
+
+const char* rka_last_error(void) { return g_last_error.c_str(); }
+
+int rka_version(void) { return 100; }
+
+}  // extern "C"

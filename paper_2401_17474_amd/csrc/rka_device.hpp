@@ -1,0 +1,166 @@
+// rka_device.hpp -- device-side building blocks shared by the RKA/RKAB
+// kernels for gfx950 (CDNA4): 16-byte row loads for every storage type,
+// Philox4x32-10, deterministic wave/workgroup reductions, and a grid barrier
+// for persistent (cooperatively launched) kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace rka {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Storage types.  Narrow types are widened exactly to double before use.
+// bf16 is carried as its raw 16-bit pattern (upper half of a binary32).
+// ---------------------------------------------------------------------------
+struct bf16_t {
+  uint16_t bits;
+};
+
+__device__ __forceinline__ double widen(double v) { return v; }
+__device__ __forceinline__ double widen(float v) { return (double)v; }
+__device__ __forceinline__ double widen(bf16_t v) {
+  return (double)__uint_as_float((uint32_t)v.bits << 16);
+}
+
+// A "vec" is the unit one lane loads from a row: V elements of T, which is
+// 16 bytes on the vector path and one element on the scalar path.
+template <typename T, int V>
+struct Vec {
+  static constexpr int kBytes = (int)sizeof(T) * V;
+  static_assert(kBytes == 16 || V == 1, "vector path loads 16 bytes");
+  using raw_t = typename std::conditional<
+      kBytes == 16, uint4,
+      typename std::conditional<kBytes == 8, uint2,
+                                typename std::conditional<kBytes == 4, uint32_t, uint16_t>::type>::
+          type>::type;
+};
+
+template <typename T, int V>
+__device__ __forceinline__ typename Vec<T, V>::raw_t load_raw(const T* p) {
+  return *reinterpret_cast<const typename Vec<T, V>::raw_t*>(p);
+}
+
+// Element e (0 <= e < V) of a raw vec, widened to double.
+template <typename T, int V>
+__device__ __forceinline__ double raw_elem(const typename Vec<T, V>::raw_t& r, int e) {
+  union {
+    typename Vec<T, V>::raw_t raw;
+    T el[V];
+  } u;
+  u.raw = r;
+  return widen(u.el[e]);
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Counter for the row
+// stream: (k_lo, k_hi, worker, j | dom << 24); key: (seed_lo, seed_hi).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint4 ctr, uint2 key) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * ctr.x;
+    const uint32_t hi0 = __umulhi(0xD2511F53u, ctr.x);
+    const uint32_t lo1 = 0xCD9E8D57u * ctr.z;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, ctr.z);
+    ctr = make_uint4(hi1 ^ ctr.y ^ key.x, lo1, hi0 ^ ctr.w ^ key.y, lo0);
+    key.x += 0x9E3779B9u;
+    key.y += 0xBB67AE85u;
+  }
+  return ctr;
+}
+
+// 53-bit uniform in [0, 1) from the first two output words.
+__device__ __forceinline__ double draw_uniform(uint64_t seed, uint64_t k, uint32_t w, uint32_t j,
+                                               uint32_t dom) {
+  const uint4 ctr = make_uint4((uint32_t)k, (uint32_t)(k >> 32), w, j | (dom << 24));
+  const uint2 key = make_uint2((uint32_t)seed, (uint32_t)(seed >> 32));
+  const uint4 r = philox4x32_10(ctr, key);
+  const uint64_t bits = (((uint64_t)r.x << 32) | (uint64_t)r.y) >> 11;
+  return (double)bits * 0x1.0p-53;
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic reductions.  The xor butterfly combines the same pairs in
+// the same tree on every lane, so every lane ends with the bitwise-same sum.
+// Blocks must be a whole number of waves.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Sum over the block; every thread receives the same value.  `scratch` holds
+// at least blockDim.x / 64 doubles of LDS and is free for reuse on return.
+__device__ __forceinline__ double block_sum(double v, double* scratch) {
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  v = wave_sum(v);
+  if (lane == 0) scratch[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < nw; ++i) s += scratch[i];
+  __syncthreads();
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Coherent (agent-scope) loads and stores for data exchanged between
+// workgroups that may sit on different XCDs (each XCD has its own L2).
+// ---------------------------------------------------------------------------
+template <typename U>
+__device__ __forceinline__ U load_agent(const U* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename U>
+__device__ __forceinline__ void store_agent(U* p, U v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid barrier for a cooperatively launched grid of `nblocks` workgroups.
+// `ctr` is zeroed before the launch; `target` counts arrivals so far and is
+// advanced identically by every workgroup.  Each thread first publishes its
+// own global writes at agent scope; after the wait every thread acquires.
+__device__ __forceinline__ void grid_barrier(unsigned* ctr, unsigned& target, unsigned nblocks) {
+  target += nblocks;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target)
+      __builtin_amdgcn_s_sleep(1);
+  }
+  __syncthreads();
+  __threadfence();
+}
+
+// All workgroups of the grid (one workgroup: just a fenced block barrier).
+__device__ __forceinline__ void sync_grid(unsigned* ctr, unsigned& target, unsigned nblocks) {
+  if (nblocks > 1) {
+    grid_barrier(ctr, target, nblocks);
+  } else {
+    __threadfence();
+    __syncthreads();
+    __threadfence();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Solve status kept on the device across the kernels of one solve.
+// ---------------------------------------------------------------------------
+struct DevStatus {
+  int64_t iterations;  // outer iterations completed
+  int32_t done;        // nonzero: stop (converged, diverged or failed)
+  int32_t status;      // rka_status value
+  double rel2;         // last squared relative measure
+  double ref2;         // squared norm of the measure's denominator
+  double thresh2;      // tol^2 * ref2
+  int64_t last_pos;    // largest row with a positive weight
+};
+
+}  // namespace rka

@@ -1,0 +1,79 @@
+// rka_internal.hpp -- host-side launchers shared between the translation
+// units of librka.so (not part of the public C ABI in include/rka.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rka {
+
+struct DevStatus;
+
+// --- sampler side (rka_setup.hip) ------------------------------------------
+hipError_t launch_row_norms(const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
+                            bool vec_ok, double* w, hipStream_t s);
+hipError_t launch_prefix(const double* w, int64_t m, double* c, int64_t* last_pos, DevStatus* st,
+                         hipStream_t s);
+hipError_t launch_sample(const double* c, int64_t m, const int64_t* last_pos, uint64_t seed,
+                         int64_t k_base, int64_t K, int32_t q, int32_t bs, int32_t dom,
+                         int32_t* idx, const DevStatus* st, hipStream_t s);
+hipError_t launch_check_finite(const double* v, int64_t len, DevStatus* st, hipStream_t s);
+
+// --- iterations (rka_iter.hip) ---------------------------------------------
+// Geometry of the column-split RKA kernel for one problem.
+struct RkaColGeom {
+  int G;       // workgroups (column slices)
+  int nsv;     // vecs per slice
+  int rg;      // row groups per workgroup
+  int nt;      // threads per workgroup (multiple of 64)
+  int rpt;     // rows per thread (template bucket)
+  size_t lds;  // dynamic LDS bytes
+};
+
+struct SolveShape {
+  const void* A;
+  int dtype;
+  int64_t m, n, lda;
+  bool vec_ok;
+  const double* b;
+  const double* wn;
+  double* x;
+  const double* x_ref;
+  double alpha;
+  int32_t q, bs;
+  int num_cu;
+};
+
+// Returns false when q rows of a slice do not fit the kernel's register tile.
+bool rka_col_plan(const SolveShape& sh, RkaColGeom* geo);
+
+// One chunk of iterations [k0, k0 + K) with indices idx[K*q*bs].
+// check_every = 0 disables the in-kernel stopping test (x_ref mode only).
+hipError_t launch_rka_chunk(const SolveShape& sh, const RkaColGeom& geo, const int32_t* idx,
+                            int64_t k0, int64_t K, int64_t check_every, double* part,
+                            double* scal, unsigned* bar, DevStatus* st, hipStream_t s);
+
+struct RkabGeom {
+  int G;     // workgroups (each runs workers g, g + G, ...)
+  int nt;    // threads per workgroup
+  int vpt;   // vecs per thread (template bucket)
+  int ns;    // vecs per workgroup in the averaging phase
+};
+bool rkab_plan(const SolveShape& sh, RkabGeom* geo);
+hipError_t launch_rkab_chunk(const SolveShape& sh, const RkabGeom& geo, const int32_t* idx,
+                             int64_t k0, int64_t K, int64_t check_every, double* vbuf,
+                             double* part, unsigned* bar, DevStatus* st, hipStream_t s);
+
+// --- stopping measures (rka_iter.hip) ---------------------------------------
+hipError_t launch_status_init(DevStatus* st, double tol, hipStream_t s);
+// ||ref||^2 into st->ref2 and tol^2 * ||ref||^2 into st->thresh2
+hipError_t launch_ref_norm(const double* ref, int64_t len, double tol, DevStatus* st,
+                           hipStream_t s);
+// Measure x at iteration k and stop the solve if within tolerance (or
+// non-finite).  x_ref != NULL: error measure; else residual (needs part of
+// at least resid_blocks() doubles).
+hipError_t launch_measure(const SolveShape& sh, int64_t k, double* part, DevStatus* st,
+                          hipStream_t s);
+int resid_blocks(int64_t m);
+
+}  // namespace rka

@@ -1,0 +1,709 @@
+// rka_iter.hip -- the iteration side of the hot path on gfx950.
+//
+// RKA (Eq. (7), arXiv 2401.17474 Sec. 3.3.1) and RKAB (Sec. 3.4.1) are
+// HBM-bound random row gathers: a projection reads one row once and does two
+// flops per element with it (dot product, then update).  Both kernels are
+// persistent and cooperatively launched, so one launch runs a whole chunk of
+// iterations with grid barriers in place of kernel boundaries.
+//
+// * RKA, column-split.  Workgroup g owns a fixed slice of the columns of x
+//   and keeps that slice of x on chip for the whole chunk.  Per iteration it
+//   gathers the slice of each of the q sampled rows into registers, forms q
+//   partial dot products, and exchanges only those partials (q doubles per
+//   workgroup) through a two-barrier all-reduce; the scales then update the
+//   slice of x from the row data still in registers.  Each element of A is
+//   read from HBM exactly once per iteration and x never leaves the chip.
+//   This replaces the serial critical section of Algorithm 1 and the q x n
+//   iterate matrix of the averaging alternatives with a fixed-order,
+//   atomic-free reduction.
+// * RKAB, worker-split.  A worker's bs projections depend on each other, so
+//   a worker lives in one workgroup with its private iterate v in registers;
+//   the only grid-wide step per outer iteration is the average of the q
+//   iterates, done column-sliced in fixed worker order (the layout of the
+//   per-thread iterate matrix of Sec. 3.3.1, one row per worker).
+//
+// Sums are always taken in a fixed order, so a given launch geometry gives
+// bitwise-reproducible results.
+#include <math.h>
+
+#include "rka_device.hpp"
+#include "rka_internal.hpp"
+
+namespace rka {
+
+// ===========================================================================
+// RKA, column-split persistent kernel.
+// ===========================================================================
+struct RkaColArgs {
+  const void* A;
+  int64_t lda, nvec;
+  const double* b;
+  const double* wn;
+  const int32_t* idx;
+  double* x;
+  const double* x_ref;
+  double alpha, inv_q;
+  int32_t q, nsv, rg, G;
+  int64_t k0, K, check_every;
+  double* part;  // G x (q+1)
+  double* scal;  // q+1
+  unsigned* bar;
+  DevStatus* st;
+};
+
+constexpr int kMaxColThreads = 512;
+
+template <typename T, int V, int RPT>
+__global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
+  using raw_t = typename Vec<T, V>::raw_t;
+  if (p.st->done) return;
+  const T* __restrict__ A = (const T*)p.A;
+  const int t = threadIdx.x, g = blockIdx.x, NT = blockDim.x;
+  const int q = p.q, nsv = p.nsv, rg = p.rg;
+  const bool active = t < nsv * rg;
+  const int j = active ? t % nsv : 0;
+  const int rgi = active ? t / nsv : rg;
+  const int64_t cv = (int64_t)g * nsv + j;
+  const bool colv = active && cv < p.nvec;
+
+  extern __shared__ double lds[];
+  double* P = lds;                    // q * nsv      row partials per vec
+  double* U = P + (size_t)q * nsv;    // NT * V       update partials per thread
+  double* XS = U + (size_t)NT * V;    // nsv * V      new slice of x
+  double* E = XS + (size_t)nsv * V;   // nsv          error partials
+  double* RED = E + nsv;              // 16           block_sum scratch
+  double* SC = RED + 16;              // q + 1        dot totals, then scales
+
+  double xv[V], xr[V];
+#pragma unroll
+  for (int e = 0; e < V; ++e) {
+    xv[e] = colv ? p.x[cv * V + e] : 0.0;
+    xr[e] = (colv && p.x_ref) ? p.x_ref[cv * V + e] : 0.0;
+  }
+
+  raw_t a[RPT], an[RPT];
+  int rows[RPT], rows_n[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = rgi + rg * i;
+    rows[i] = (active && r < q) ? p.idx[r] : 0;
+    if (colv && r < q) a[i] = load_raw<T, V>(A + (int64_t)rows[i] * p.lda + cv * V);
+  }
+
+  unsigned target = 0;
+  int64_t kl = 0;
+  bool stopped = false;
+  for (; kl < p.K; ++kl) {
+    const int64_t k = p.k0 + kl;
+    const bool check = p.check_every > 0 && k > 0 && (k % p.check_every) == 0;
+    const bool more = kl + 1 < p.K;
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int r = rgi + rg * i;
+        rows_n[i] = (active && r < q) ? p.idx[(kl + 1) * q + r] : 0;
+      }
+    }
+    // partial dot products of this slice, one per (row, vec)
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = rgi + rg * i;
+      if (active && r < q) {
+        double s = 0.0;
+        if (colv) {
+#pragma unroll
+          for (int e = 0; e < V; ++e) s = fma(raw_elem<T, V>(a[i], e), xv[e], s);
+        }
+        P[r * nsv + j] = s;
+      }
+    }
+    if (check && active && rgi == 0) {
+      double s = 0.0;
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        const double d = xv[e] - xr[e];
+        s = fma(d, d, s);
+      }
+      E[j] = s;
+    }
+    __syncthreads();
+    for (int r = t; r < q; r += NT) {
+      double d = 0.0;
+      for (int jj = 0; jj < nsv; ++jj) d += P[r * nsv + jj];
+      if (p.G > 1)
+        store_agent(&p.part[(size_t)g * (q + 1) + r], d);
+      else
+        SC[r] = d;
+    }
+    if (check && t == 0) {
+      double s = 0.0;
+      for (int jj = 0; jj < nsv; ++jj) s += E[jj];
+      if (p.G > 1)
+        store_agent(&p.part[(size_t)g * (q + 1) + q], s);
+      else
+        SC[q] = s;
+    }
+    // next iteration's rows are independent of x: start fetching them now,
+    // so that they stream in while the all-reduce below waits
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int r = rgi + rg * i;
+        if (colv && r < q) an[i] = load_raw<T, V>(A + (int64_t)rows_n[i] * p.lda + cv * V);
+      }
+    }
+    const int nr = q + (check ? 1 : 0);
+    if (p.G > 1) {
+      grid_barrier(p.bar, target, (unsigned)p.G);
+      for (int r = g; r < nr; r += p.G) {
+        double v = 0.0;
+        for (int gg = t; gg < p.G; gg += NT) v += load_agent(&p.part[(size_t)gg * (q + 1) + r]);
+        const double D = block_sum(v, RED);
+        if (t == 0) {
+          double s = D;
+          if (r < q) {
+            const int64_t ir = p.idx[kl * q + r];
+            s = p.alpha * (p.b[ir] - D) / p.wn[ir];
+          }
+          store_agent(&p.scal[r], s);
+        }
+      }
+      grid_barrier(p.bar, target, (unsigned)p.G);
+      for (int r = t; r < nr; r += NT) SC[r] = load_agent(&p.scal[r]);
+    } else {
+      __syncthreads();
+      for (int r = t; r < q; r += NT) {
+        const int64_t ir = p.idx[kl * q + r];
+        SC[r] = p.alpha * (p.b[ir] - SC[r]) / p.wn[ir];
+      }
+    }
+    __syncthreads();
+    if (check) {
+      const double e2 = SC[q];
+      const bool conv = e2 <= p.st->thresh2;
+      const bool div = !isfinite(e2);
+      if (conv || div) {
+        if (g == 0 && t == 0) {
+          p.st->iterations = k;
+          p.st->rel2 = e2 / p.st->ref2;
+          p.st->status = conv ? 0 : -3;
+          p.st->done = 1;
+        }
+        stopped = true;
+        break;
+      }
+    }
+    // x_slice += (1/q) sum_r s_r * A[i_r, slice]   (fixed row order)
+    double u[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) u[e] = 0.0;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = rgi + rg * i;
+      if (colv && r < q) {
+        const double s = SC[r];
+#pragma unroll
+        for (int e = 0; e < V; ++e) u[e] = fma(s, raw_elem<T, V>(a[i], e), u[e]);
+      }
+    }
+    if (active) {
+#pragma unroll
+      for (int e = 0; e < V; ++e) U[t * V + e] = u[e];
+    }
+    __syncthreads();
+    if (colv && rgi == 0) {
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        double acc = 0.0;
+        for (int gg = 0; gg < rg; ++gg) acc += U[(gg * nsv + j) * V + e];
+        xv[e] = fma(acc, p.inv_q, xv[e]);
+        XS[j * V + e] = xv[e];
+      }
+    }
+    __syncthreads();
+    if (colv) {
+#pragma unroll
+      for (int e = 0; e < V; ++e) xv[e] = XS[j * V + e];
+    }
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        a[i] = an[i];
+        rows[i] = rows_n[i];
+      }
+    }
+  }
+  if (colv && rgi == 0) {
+#pragma unroll
+    for (int e = 0; e < V; ++e) p.x[cv * V + e] = xv[e];
+  }
+  if (!stopped && g == 0 && t == 0) p.st->iterations = p.k0 + p.K;
+}
+
+static int rpt_bucket(int need) {
+  if (need <= 1) return 1;
+  if (need <= 2) return 2;
+  if (need <= 4) return 4;
+  if (need <= 8) return 8;
+  if (need <= 16) return 16;
+  return 0;
+}
+
+bool rka_col_plan(const SolveShape& sh, RkaColGeom* geo) {
+  const int esz = sh.dtype == 0 ? 8 : (sh.dtype == 1 ? 4 : 2);
+  const int V = sh.vec_ok ? 16 / esz : 1;
+  const int64_t nvec = sh.n / V;
+  const int64_t bytes_per_iter = (int64_t)sh.q * sh.n * esz;
+  int G, nsv;
+  if (bytes_per_iter <= (64 << 10) && nvec <= kMaxColThreads) {
+    G = 1;
+    nsv = (int)nvec;
+  } else {
+    const int64_t g0 = nvec < sh.num_cu ? nvec : sh.num_cu;
+    nsv = (int)((nvec + g0 - 1) / g0);
+    G = (int)((nvec + nsv - 1) / nsv);
+    if (nsv > kMaxColThreads) return false;
+  }
+  int rg = kMaxColThreads / nsv;
+  if (rg > sh.q) rg = sh.q;
+  if (rg < 1) rg = 1;
+  const int rpt = rpt_bucket((sh.q + rg - 1) / rg);
+  if (rpt == 0) return false;
+  if (rpt == 16 && sh.vec_ok && sh.dtype == 2) return false;  // would spill
+  const int nt = ((nsv * rg + kWave - 1) / kWave) * kWave;
+  const size_t lds =
+      sizeof(double) * ((size_t)sh.q * nsv + (size_t)nt * V + (size_t)nsv * V + nsv + 16 + sh.q + 1);
+  if (lds > 64 * 1024) return false;
+  geo->G = G;
+  geo->nsv = nsv;
+  geo->rg = rg;
+  geo->nt = nt;
+  geo->rpt = rpt;
+  geo->lds = lds;
+  return true;
+}
+
+template <typename T, int V>
+static hipError_t launch_col_t(const RkaColGeom& geo, RkaColArgs& a, hipStream_t s) {
+  void* args[] = {&a};
+  const void* fn = nullptr;
+  switch (geo.rpt) {
+    case 1: fn = (const void*)rka_col_kernel<T, V, 1>; break;
+    case 2: fn = (const void*)rka_col_kernel<T, V, 2>; break;
+    case 4: fn = (const void*)rka_col_kernel<T, V, 4>; break;
+    case 8: fn = (const void*)rka_col_kernel<T, V, 8>; break;
+    default: fn = (const void*)rka_col_kernel<T, V, 16>; break;
+  }
+  return hipLaunchCooperativeKernel(fn, dim3(geo.G), dim3(geo.nt), args, (unsigned)geo.lds, s);
+}
+
+hipError_t launch_rka_chunk(const SolveShape& sh, const RkaColGeom& geo, const int32_t* idx,
+                            int64_t k0, int64_t K, int64_t check_every, double* part,
+                            double* scal, unsigned* bar, DevStatus* st, hipStream_t s) {
+  const int esz = sh.dtype == 0 ? 8 : (sh.dtype == 1 ? 4 : 2);
+  const int V = sh.vec_ok ? 16 / esz : 1;
+  RkaColArgs a;
+  a.A = sh.A;
+  a.lda = sh.lda;
+  a.nvec = sh.n / V;
+  a.b = sh.b;
+  a.wn = sh.wn;
+  a.idx = idx;
+  a.x = sh.x;
+  a.x_ref = sh.x_ref;
+  a.alpha = sh.alpha;
+  a.inv_q = 1.0 / (double)sh.q;
+  a.q = sh.q;
+  a.nsv = geo.nsv;
+  a.rg = geo.rg;
+  a.G = geo.G;
+  a.k0 = k0;
+  a.K = K;
+  a.check_every = check_every;
+  a.part = part;
+  a.scal = scal;
+  a.bar = bar;
+  a.st = st;
+  if (geo.G > 1) {
+    hipError_t e = hipMemsetAsync(bar, 0, sizeof(unsigned), s);
+    if (e != hipSuccess) return e;
+  }
+  switch (sh.dtype) {
+    case 0: return sh.vec_ok ? launch_col_t<double, 2>(geo, a, s) : launch_col_t<double, 1>(geo, a, s);
+    case 1: return sh.vec_ok ? launch_col_t<float, 4>(geo, a, s) : launch_col_t<float, 1>(geo, a, s);
+    default:
+      return sh.vec_ok ? launch_col_t<bf16_t, 8>(geo, a, s) : launch_col_t<bf16_t, 1>(geo, a, s);
+  }
+}
+
+// ===========================================================================
+// RKAB, worker-split persistent kernel.
+// ===========================================================================
+struct RkabArgs {
+  const void* A;
+  int64_t lda, nvec;
+  const double* b;
+  const double* wn;
+  const int32_t* idx;
+  double* x;
+  const double* x_ref;
+  double alpha;
+  int32_t q, bs, G, ns;
+  int64_t k0, K, check_every;
+  double* vbuf;  // q x (nvec * V): the workers' iterates
+  double* part;  // G
+  unsigned* bar;
+  DevStatus* st;
+};
+
+constexpr int kRkabThreads = 512;
+
+template <typename T, int V, int VPT>
+__global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
+  using raw_t = typename Vec<T, V>::raw_t;
+  if (p.st->done) return;
+  const T* __restrict__ A = (const T*)p.A;
+  const int t = threadIdx.x, g = blockIdx.x;
+  const int64_t nvec = p.nvec, n = nvec * V;
+  __shared__ double RED[kRkabThreads / kWave];
+
+  double v[VPT][V];
+  raw_t ar[VPT], an[VPT];
+  unsigned target = 0;
+  bool stopped = false;
+  int64_t kl = 0;
+  for (; kl < p.K; ++kl) {
+    const int64_t k = p.k0 + kl;
+    for (int w = g; w < p.q; w += p.G) {
+      // v = x^(k)
+#pragma unroll
+      for (int i = 0; i < VPT; ++i) {
+        const int64_t c = t + (int64_t)kRkabThreads * i;
+#pragma unroll
+        for (int e = 0; e < V; ++e) v[i][e] = (c < nvec) ? load_agent(&p.x[c * V + e]) : 0.0;
+      }
+      const int32_t* rows = p.idx + (kl * p.q + w) * (int64_t)p.bs;
+      int64_t row = rows[0];
+#pragma unroll
+      for (int i = 0; i < VPT; ++i) {
+        const int64_t c = t + (int64_t)kRkabThreads * i;
+        if (c < nvec) ar[i] = load_raw<T, V>(A + row * p.lda + c * V);
+      }
+      for (int jj = 0; jj < p.bs; ++jj) {
+        int64_t row_n = row;
+        if (jj + 1 < p.bs) {
+          row_n = rows[jj + 1];
+#pragma unroll
+          for (int i = 0; i < VPT; ++i) {
+            const int64_t c = t + (int64_t)kRkabThreads * i;
+            if (c < nvec) an[i] = load_raw<T, V>(A + row_n * p.lda + c * V);
+          }
+        }
+        double d = 0.0;
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) {
+          const int64_t c = t + (int64_t)kRkabThreads * i;
+          if (c < nvec) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) d = fma(raw_elem<T, V>(ar[i], e), v[i][e], d);
+          }
+        }
+        const double D = block_sum(d, RED);
+        const double s = p.alpha * (p.b[row] - D) / p.wn[row];
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) {
+          const int64_t c = t + (int64_t)kRkabThreads * i;
+          if (c < nvec) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) v[i][e] = fma(s, raw_elem<T, V>(ar[i], e), v[i][e]);
+          }
+        }
+        if (jj + 1 < p.bs) {
+#pragma unroll
+          for (int i = 0; i < VPT; ++i) ar[i] = an[i];
+          row = row_n;
+        }
+      }
+      double* vw = p.vbuf + (size_t)w * n;
+#pragma unroll
+      for (int i = 0; i < VPT; ++i) {
+        const int64_t c = t + (int64_t)kRkabThreads * i;
+        if (c < nvec) {
+#pragma unroll
+          for (int e = 0; e < V; ++e) vw[c * V + e] = v[i][e];
+        }
+      }
+    }
+    // x^(k+1) = (1/q) sum_w v_w, column slices, fixed worker order
+    sync_grid(p.bar, target, (unsigned)p.G);
+    const bool check = p.check_every > 0 && ((k + 1) % p.check_every) == 0;
+    const int64_t e0 = (int64_t)g * p.ns * V;
+    const int64_t e1 = ((int64_t)(g + 1) * p.ns * V < n) ? (int64_t)(g + 1) * p.ns * V : n;
+    double err = 0.0;
+    for (int64_t ci = e0 + t; ci < e1; ci += kRkabThreads) {
+      double acc = 0.0;
+      for (int w = 0; w < p.q; ++w) acc += load_agent(&p.vbuf[(size_t)w * n + ci]);
+      const double xn = acc / (double)p.q;
+      p.x[ci] = xn;
+      if (check) {
+        const double dd = xn - p.x_ref[ci];
+        err = fma(dd, dd, err);
+      }
+    }
+    if (check) {
+      const double s = block_sum(err, RED);
+      if (t == 0) {
+        if (p.G > 1)
+          store_agent(&p.part[g], s);
+        else
+          p.part[0] = s;
+      }
+    }
+    sync_grid(p.bar, target, (unsigned)p.G);
+    if (check) {
+      double e2 = 0.0;
+      for (int gg = 0; gg < p.G; ++gg) e2 += load_agent(&p.part[gg]);
+      const bool conv = e2 <= p.st->thresh2;
+      const bool div = !isfinite(e2);
+      if (conv || div) {
+        if (g == 0 && t == 0) {
+          p.st->iterations = k + 1;
+          p.st->rel2 = e2 / p.st->ref2;
+          p.st->status = conv ? 0 : -3;
+          p.st->done = 1;
+        }
+        stopped = true;
+        break;
+      }
+    }
+  }
+  if (!stopped && g == 0 && t == 0) p.st->iterations = p.k0 + p.K;
+}
+
+static int vpt_bucket(int64_t need) {
+  static const int b[] = {1, 2, 4, 6, 8, 10, 12, 16, 20};
+  for (int v : b)
+    if (need <= v) return v;
+  return 0;
+}
+
+bool rkab_plan(const SolveShape& sh, RkabGeom* geo) {
+  const int esz = sh.dtype == 0 ? 8 : (sh.dtype == 1 ? 4 : 2);
+  const int V = sh.vec_ok ? 16 / esz : 1;
+  const int64_t nvec = sh.n / V;
+  const int vpt = vpt_bucket((nvec + kRkabThreads - 1) / kRkabThreads);
+  if (vpt == 0) return false;
+  // Per thread: v[VPT][V] doubles plus two raw row buffers; 512-thread groups
+  // allow 256 VGPRs per lane.  Largest bucket per storage type that compiles
+  // without spilling on gfx950.
+  const int vpt_max = V == 1 ? 16 : (sh.dtype == 0 ? 12 : (sh.dtype == 1 ? 6 : 4));
+  if (vpt > vpt_max) return false;
+  const int G = sh.q < sh.num_cu ? sh.q : sh.num_cu;
+  geo->G = G;
+  geo->nt = kRkabThreads;
+  geo->vpt = vpt;
+  geo->ns = (int)((nvec + G - 1) / G);
+  return true;
+}
+
+template <typename T, int V>
+static hipError_t launch_rkab_t(const RkabGeom& geo, RkabArgs& a, hipStream_t s) {
+  void* args[] = {&a};
+  const void* fn = nullptr;
+  switch (geo.vpt) {
+    case 1: fn = (const void*)rkab_kernel<T, V, 1>; break;
+    case 2: fn = (const void*)rkab_kernel<T, V, 2>; break;
+    case 4: fn = (const void*)rkab_kernel<T, V, 4>; break;
+    case 6: fn = (const void*)rkab_kernel<T, V, 6>; break;
+    case 8: fn = (const void*)rkab_kernel<T, V, 8>; break;
+    case 10: fn = (const void*)rkab_kernel<T, V, 10>; break;
+    case 12: fn = (const void*)rkab_kernel<T, V, 12>; break;
+    case 16: fn = (const void*)rkab_kernel<T, V, 16>; break;
+    default: fn = (const void*)rkab_kernel<T, V, 20>; break;
+  }
+  return hipLaunchCooperativeKernel(fn, dim3(geo.G), dim3(geo.nt), args, 0, s);
+}
+
+hipError_t launch_rkab_chunk(const SolveShape& sh, const RkabGeom& geo, const int32_t* idx,
+                             int64_t k0, int64_t K, int64_t check_every, double* vbuf,
+                             double* part, unsigned* bar, DevStatus* st, hipStream_t s) {
+  const int esz = sh.dtype == 0 ? 8 : (sh.dtype == 1 ? 4 : 2);
+  const int V = sh.vec_ok ? 16 / esz : 1;
+  RkabArgs a;
+  a.A = sh.A;
+  a.lda = sh.lda;
+  a.nvec = sh.n / V;
+  a.b = sh.b;
+  a.wn = sh.wn;
+  a.idx = idx;
+  a.x = sh.x;
+  a.x_ref = sh.x_ref;
+  a.alpha = sh.alpha;
+  a.q = sh.q;
+  a.bs = sh.bs;
+  a.G = geo.G;
+  a.ns = geo.ns;
+  a.k0 = k0;
+  a.K = K;
+  a.check_every = check_every;
+  a.vbuf = vbuf;
+  a.part = part;
+  a.bar = bar;
+  a.st = st;
+  if (geo.G > 1) {
+    hipError_t e = hipMemsetAsync(bar, 0, sizeof(unsigned), s);
+    if (e != hipSuccess) return e;
+  }
+  switch (sh.dtype) {
+    case 0:
+      return sh.vec_ok ? launch_rkab_t<double, 2>(geo, a, s) : launch_rkab_t<double, 1>(geo, a, s);
+    case 1:
+      return sh.vec_ok ? launch_rkab_t<float, 4>(geo, a, s) : launch_rkab_t<float, 1>(geo, a, s);
+    default:
+      return sh.vec_ok ? launch_rkab_t<bf16_t, 8>(geo, a, s) : launch_rkab_t<bf16_t, 1>(geo, a, s);
+  }
+}
+
+// ===========================================================================
+// Stopping measures (Sec. 3.1: the error to the solution; without one, the
+// relative residual).  Fixed-order sums; the decision is written to the
+// device status so that later kernels of the solve return immediately.
+// ===========================================================================
+__global__ void status_init_kernel(DevStatus* st, double tol) {
+  st->iterations = 0;
+  st->done = 0;
+  st->status = tol > 0.0 ? 1 : 0;  // RKA_NOT_CONVERGED until the test passes
+  st->rel2 = __builtin_nan("");
+  st->ref2 = 1.0;
+  st->thresh2 = 0.0;
+  st->last_pos = -1;
+}
+
+__global__ __launch_bounds__(1024) void ref_norm_kernel(const double* __restrict__ v, int64_t len,
+                                                         double tol, DevStatus* st) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < len; i += blockDim.x) s = fma(v[i], v[i], s);
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) {
+    st->ref2 = s;
+    st->thresh2 = tol * tol * s;
+  }
+}
+
+__global__ __launch_bounds__(1024) void measure_xref_kernel(const double* __restrict__ x,
+                                                             const double* __restrict__ xr,
+                                                             int64_t n, int64_t k, DevStatus* st) {
+  __shared__ double red[16];
+  if (st->done) return;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const double d = x[i] - xr[i];
+    s = fma(d, d, s);
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) {
+    st->rel2 = s / st->ref2;
+    if (!isfinite(s)) {
+      st->status = -3;
+      st->done = 1;
+      st->iterations = k;
+    } else if (s <= st->thresh2) {
+      st->status = 0;
+      st->done = 1;
+      st->iterations = k;
+    }
+  }
+}
+
+constexpr int kResidRowsPerBlock = 64;
+
+int resid_blocks(int64_t m) { return (int)((m + kResidRowsPerBlock - 1) / kResidRowsPerBlock); }
+
+// One wave per row, 4 waves per block, kResidRowsPerBlock rows per block:
+// partial[blk] = sum over the block's rows of (b_i - <A_i, x>)^2.
+template <typename T>
+__global__ __launch_bounds__(256) void resid_kernel(const T* __restrict__ A, int64_t m, int64_t n,
+                                                    int64_t lda, const double* __restrict__ b,
+                                                    const double* __restrict__ x,
+                                                    double* __restrict__ part,
+                                                    const DevStatus* st) {
+  __shared__ double red[4];
+  if (st->done) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double acc = 0.0;
+  for (int rr = wv; rr < kResidRowsPerBlock; rr += 4) {
+    const int64_t i = (int64_t)blockIdx.x * kResidRowsPerBlock + rr;
+    if (i >= m) break;
+    double d = 0.0;
+    for (int64_t c = lane; c < n; c += 64) d = fma(widen(A[i * lda + c]), x[c], d);
+    d = wave_sum(d);
+    const double r = b[i] - d;
+    acc = fma(r, r, acc);
+  }
+  if (lane == 0) red[wv] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+__global__ __launch_bounds__(1024) void resid_finish_kernel(const double* __restrict__ part,
+                                                             int nb, int64_t k, DevStatus* st) {
+  __shared__ double red[16];
+  if (st->done) return;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) s += part[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) {
+    st->rel2 = s / st->ref2;
+    if (!isfinite(s)) {
+      st->status = -3;
+      st->done = 1;
+      st->iterations = k;
+    } else if (s <= st->thresh2) {
+      st->status = 0;
+      st->done = 1;
+      st->iterations = k;
+    }
+  }
+}
+
+hipError_t launch_status_init(DevStatus* st, double tol, hipStream_t s) {
+  hipLaunchKernelGGL(status_init_kernel, dim3(1), dim3(1), 0, s, st, tol);
+  return hipGetLastError();
+}
+
+hipError_t launch_ref_norm(const double* ref, int64_t len, double tol, DevStatus* st,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(ref_norm_kernel, dim3(1), dim3(1024), 0, s, ref, len, tol, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_measure(const SolveShape& sh, int64_t k, double* part, DevStatus* st,
+                          hipStream_t s) {
+  if (sh.x_ref) {
+    hipLaunchKernelGGL(measure_xref_kernel, dim3(1), dim3(1024), 0, s, sh.x, sh.x_ref, sh.n, k,
+                       st);
+    return hipGetLastError();
+  }
+  const int nb = resid_blocks(sh.m);
+  switch (sh.dtype) {
+    case 0:
+      hipLaunchKernelGGL(resid_kernel<double>, dim3(nb), dim3(256), 0, s, (const double*)sh.A,
+                         sh.m, sh.n, sh.lda, sh.b, sh.x, part, st);
+      break;
+    case 1:
+      hipLaunchKernelGGL(resid_kernel<float>, dim3(nb), dim3(256), 0, s, (const float*)sh.A, sh.m,
+                         sh.n, sh.lda, sh.b, sh.x, part, st);
+      break;
+    default:
+      hipLaunchKernelGGL(resid_kernel<bf16_t>, dim3(nb), dim3(256), 0, s, (const bf16_t*)sh.A,
+                         sh.m, sh.n, sh.lda, sh.b, sh.x, part, st);
+      break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(resid_finish_kernel, dim3(1), dim3(1024), 0, s, part, nb, k, st);
+  return hipGetLastError();
+}
+
+}  // namespace rka
