@@ -112,6 +112,43 @@ int rkab_solve(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, cons
                int64_t max_iter, double tol, uint64_t seed, const double* x_ref,
                int64_t iter_offset, int64_t check_every, void* stream, rka_info* info);
 
+/* Options of rka_solve_ex.  Zero-initialise and set what you need. */
+typedef struct rka_opts {
+    int64_t check_every;    /* stopping-test interval, as in rka_solve (< 1 means 1)     */
+    int32_t grid;           /* workgroups of the iteration kernel; 0 = chosen by the
+                               library.  Changes the summation order (results stay
+                               within rounding of each other), never the method.       */
+    int32_t collect_timing; /* nonzero: time every phase with HIP events recorded on
+                               `stream` and fill the *_ms fields of rka_stats          */
+} rka_opts;
+
+/* Launch facts and phase times of one rka_solve_ex call. */
+typedef struct rka_stats {
+    double norms_ms;          /* squared row norms                                     */
+    double prefix_ms;         /* running sum                                           */
+    double sample_ms;         /* row stream, summed over chunks                        */
+    double iterate_ms;        /* persistent iteration kernel, summed over chunks       */
+    double measure_ms;        /* stopping measures                                     */
+    int64_t iterate_launches; /* chunks (launches of the iteration kernel)             */
+    int32_t kernel;           /* 1 = column-split RKA kernel, 2 = worker-split kernel  */
+    int32_t grid;             /* workgroups of the iteration kernel                    */
+    int32_t threads;          /* threads per workgroup of the iteration kernel         */
+    int32_t bucket;           /* register-tile bucket of the kernel instance: rows per
+                                 thread (kernel 1) or 16-byte vecs per thread (kernel 2) */
+} rka_stats;
+
+/*
+ * rka_solve_ex -- rka_solve (method 0) or rkab_solve (method 1) with extra
+ * options and launch statistics.  opts may be NULL (defaults, check_every =
+ * 1); stats may be NULL.  block_size is ignored for method 0.  Everything
+ * else is as documented for rka_solve / rkab_solve.
+ */
+int rka_solve_ex(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const double* b,
+                 const double* x0, double* x, int32_t method, int32_t q, int32_t block_size,
+                 double alpha, int64_t max_iter, double tol, uint64_t seed, const double* x_ref,
+                 int64_t iter_offset, const rka_opts* opts, void* stream, rka_info* info,
+                 rka_stats* stats);
+
 /*
  * rka_row_norms -- w_l = sum_c A[l,c]^2 for every row (the numerators of
  * Eq. (4)), each summed left to right in FP64 with a rounded square and a

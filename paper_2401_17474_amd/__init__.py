@@ -33,6 +33,19 @@ class _Info(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class _Opts(ctypes.Structure):
+    _fields_ = [("check_every", ctypes.c_int64), ("grid", ctypes.c_int32),
+                ("collect_timing", ctypes.c_int32)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("norms_ms", ctypes.c_double), ("prefix_ms", ctypes.c_double),
+                ("sample_ms", ctypes.c_double), ("iterate_ms", ctypes.c_double),
+                ("measure_ms", ctypes.c_double), ("iterate_launches", ctypes.c_int64),
+                ("kernel", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("threads", ctypes.c_int32), ("bucket", ctypes.c_int32)]
+
+
 @dataclass
 class Info:
     iterations: int
@@ -55,6 +68,9 @@ def lib():
                                 I64, I64, P, ctypes.POINTER(_Info)]
         L.rkab_solve.argtypes = [P, ctypes.c_int, I64, I64, I64, P, P, P, I32, I32, D, I64, D,
                                  U64, P, I64, I64, P, ctypes.POINTER(_Info)]
+        L.rka_solve_ex.argtypes = [P, ctypes.c_int, I64, I64, I64, P, P, P, I32, I32, I32, D,
+                                   I64, D, U64, P, I64, ctypes.POINTER(_Opts), P,
+                                   ctypes.POINTER(_Info), ctypes.POINTER(_Stats)]
         L.rka_row_norms.argtypes = [P, ctypes.c_int, I64, I64, I64, P, P]
         L.rka_prefix.argtypes = [P, I64, P, P, P]
         L.rka_sample_indices.argtypes = [P, P, I64, U64, I64, I64, I32, I32, I32, P, P]
@@ -63,7 +79,7 @@ def lib():
         L.rka_last_error.argtypes = []
         L.rka_last_error.restype = ctypes.c_char_p
         L.rka_version.restype = ctypes.c_int
-        for f in ("rka_solve", "rkab_solve", "rka_row_norms", "rka_prefix",
+        for f in ("rka_solve", "rkab_solve", "rka_solve_ex", "rka_row_norms", "rka_prefix",
                   "rka_sample_indices"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
@@ -166,6 +182,29 @@ def rkab_solve(A, b, *, q, block_size, alpha=1.0, max_iter=1000, tol=0.0, seed=1
     if raise_on_error:
         _raise_if(st)
     return x, Info(info.iterations, info.projections, info.rel_err, st)
+
+
+def solve_ex(A, b, *, method, q, block_size=1, alpha=1.0, max_iter=1000, tol=0.0, seed=1,
+             x0=None, x_ref=None, iter_offset=0, check_every=1, grid=0, timing=False, out=None,
+             stream=None, raise_on_error=True):
+    """rka_solve_ex: method 0 = RKA, 1 = RKAB.  Returns (x, Info, stats dict);
+    with ``timing`` the stats hold per-phase HIP-event times (ms) measured on
+    the stream the kernels run on."""
+    torch = _torch()
+    code, m, n, lda = _matrix(A)
+    b = _vec(b, m, "b", False)
+    x = out if out is not None else torch.empty(n, dtype=torch.float64, device=A.device)
+    _vec(x, n, "out", False)
+    info, stats = _Info(), _Stats()
+    opts = _Opts(check_every, grid, 1 if timing else 0)
+    st = lib().rka_solve_ex(_ptr(A), code, m, n, lda, _ptr(b), _ptr(_vec(x0, n, "x0")), _ptr(x),
+                            method, q, block_size, alpha, max_iter, tol, seed,
+                            _ptr(_vec(x_ref, n, "x_ref")), iter_offset, ctypes.byref(opts),
+                            _stream(stream), ctypes.byref(info), ctypes.byref(stats))
+    if raise_on_error:
+        _raise_if(st)
+    sd = {f: getattr(stats, f) for f, _ in _Stats._fields_}
+    return x, Info(info.iterations, info.projections, info.rel_err, st), sd
 
 
 def row_norms(A, stream=None):

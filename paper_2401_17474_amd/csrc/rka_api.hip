@@ -74,6 +74,54 @@ struct Scratch {
   ~Scratch() { release(); }
 };
 
+// Phase timing with HIP events recorded on the solve's stream.
+enum Phase { kNorms = 0, kPrefix, kSample, kIterate, kMeasure, kPhases };
+struct PhaseTimer {
+  hipStream_t s;
+  bool on;
+  struct Span {
+    int phase;
+    hipEvent_t a, b;
+  };
+  Span spans[4096];
+  int n = 0;
+  int open = -1;
+  PhaseTimer(hipStream_t st, bool enabled) : s(st), on(enabled) {}
+  void begin(int phase) {
+    if (!on || n >= 4096) return;
+    Span& sp = spans[n];
+    if (hipEventCreate(&sp.a) != hipSuccess) return;
+    if (hipEventCreate(&sp.b) != hipSuccess) {
+      (void)hipEventDestroy(sp.a);
+      return;
+    }
+    sp.phase = phase;
+    (void)hipEventRecord(sp.a, s);
+    open = n;
+  }
+  void end() {
+    if (open < 0) return;
+    (void)hipEventRecord(spans[open].b, s);
+    n = open + 1;
+    open = -1;
+  }
+  // after the stream has been synchronized
+  void collect(double out[kPhases]) {
+    for (int i = 0; i < kPhases; ++i) out[i] = 0.0;
+    for (int i = 0; i < n; ++i) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, spans[i].a, spans[i].b) == hipSuccess)
+        out[spans[i].phase] += ms;
+    }
+  }
+  ~PhaseTimer() {
+    for (int i = 0; i < n; ++i) {
+      (void)hipEventDestroy(spans[i].a);
+      (void)hipEventDestroy(spans[i].b);
+    }
+  }
+};
+
 #define HIP_TRY(call)                                                                       \
   do {                                                                                      \
     hipError_t e_ = (call);                                                                 \
@@ -110,8 +158,10 @@ constexpr int64_t kIdxBudget = 16ll << 20;
 int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
                const double* b, const double* x0, double* x, int32_t q, int32_t bs, double alpha,
                int64_t max_iter, double tol, uint64_t seed, const double* x_ref,
-               int64_t iter_offset, int64_t check_every, void* stream, rka_info* info) {
+               int64_t iter_offset, int64_t check_every, int grid, bool timing, void* stream,
+               rka_info* info, rka_stats* stats) {
   g_last_error.clear();
+  if (stats) memset(stats, 0, sizeof *stats);
   if (info) {
     info->iterations = 0;
     info->projections = 0;
@@ -122,6 +172,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   int v = validate(A, dtype, m, n, lda, b, x, q, bs, alpha, max_iter, tol, iter_offset);
   if (v != RKA_OK) return v;
   if (check_every < 1) check_every = 1;
+  if (grid < 0) return fail(RKA_EINVAL, "grid must be >= 0");
   const int ncu = num_cus();
   if (ncu <= 0) return fail(RKA_EDEVICE, "no HIP device available");
   hipStream_t s = (hipStream_t)stream;
@@ -140,6 +191,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   sh.q = q;
   sh.bs = block ? bs : 1;
   sh.num_cu = ncu;
+  sh.grid = grid > ncu ? ncu : grid;
 
   rka::RkaColGeom cgeo{};
   rka::RkabGeom bgeo{};
@@ -181,10 +233,15 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
     HIP_TRY(sc.get(&vbuf, (size_t)q * (size_t)n));
   sh.wn = w;
 
+  PhaseTimer tm(s, timing && stats);
   HIP_TRY(rka::launch_status_init(st, tol, s));
   HIP_TRY(rka::launch_check_finite(b, m, st, s));
+  tm.begin(kNorms);
   HIP_TRY(rka::launch_row_norms(A, dtype, m, n, lda, sh.vec_ok, w, s));
+  tm.end();
+  tm.begin(kPrefix);
   HIP_TRY(rka::launch_prefix(w, m, c, last_pos, st, s));
+  tm.end();
   if (x0) {
     if (x0 != x) HIP_TRY(hipMemcpyAsync(x, x0, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
   } else {
@@ -193,8 +250,11 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   const bool resid_mode = tol > 0.0 && !sh.x_ref;
   if (tol > 0.0) {
     HIP_TRY(rka::launch_ref_norm(sh.x_ref ? sh.x_ref : b, sh.x_ref ? n : m, tol, st, s));
+    tm.begin(kMeasure);
     HIP_TRY(rka::launch_measure(sh, 0, part, st, s));
+    tm.end();
   }
+  int64_t launches = 0;
   const int64_t in_kernel_check = (tol > 0.0 && sh.x_ref) ? check_every : 0;
   for (int64_t k = 0; k < max_iter;) {
     int64_t kc = max_iter - k < kc_max ? max_iter - k : kc_max;
@@ -202,22 +262,48 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
       const int64_t to_check = check_every - (k % check_every);
       if (to_check < kc) kc = to_check;
     }
+    tm.begin(kSample);
     HIP_TRY(rka::launch_sample(c, m, last_pos, seed, k + iter_offset, kc, q, sh.bs, 0, idx, st, s));
+    tm.end();
+    tm.begin(kIterate);
     if (use_col)
       HIP_TRY(rka::launch_rka_chunk(sh, cgeo, idx, k, kc, in_kernel_check, part, scal, bar, st, s));
     else
       HIP_TRY(rka::launch_rkab_chunk(sh, bgeo, idx, k, kc, in_kernel_check, vbuf, part, bar, st, s));
+    tm.end();
+    ++launches;
     k += kc;
-    if (resid_mode && k % check_every == 0 && k < max_iter)
+    if (resid_mode && k % check_every == 0 && k < max_iter) {
+      tm.begin(kMeasure);
       HIP_TRY(rka::launch_measure(sh, k, part, st, s));
+      tm.end();
+    }
   }
-  if (tol > 0.0 && max_iter > 0) HIP_TRY(rka::launch_measure(sh, max_iter, part, st, s));
+  if (tol > 0.0 && max_iter > 0) {
+    tm.begin(kMeasure);
+    HIP_TRY(rka::launch_measure(sh, max_iter, part, st, s));
+    tm.end();
+  }
 
   rka::DevStatus hst;
   HIP_TRY(hipMemcpyAsync(&hst, st, sizeof hst, hipMemcpyDeviceToHost, s));
   sc.release();
   HIP_TRY(hipStreamSynchronize(s));
 
+  if (stats) {
+    double ph[kPhases];
+    tm.collect(ph);
+    stats->norms_ms = ph[kNorms];
+    stats->prefix_ms = ph[kPrefix];
+    stats->sample_ms = ph[kSample];
+    stats->iterate_ms = ph[kIterate];
+    stats->measure_ms = ph[kMeasure];
+    stats->iterate_launches = launches;
+    stats->kernel = use_col ? 1 : 2;
+    stats->grid = use_col ? cgeo.G : bgeo.G;
+    stats->threads = use_col ? cgeo.nt : bgeo.nt;
+    stats->bucket = use_col ? cgeo.rpt : bgeo.vpt;
+  }
   int status = hst.status;
   if (status == RKA_EZERONORM) fail(status, "||A||_F^2 is zero or not finite");
   if (status == RKA_EINVAL) fail(status, "b has a non-finite entry");
@@ -240,7 +326,25 @@ int rka_solve(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const
               uint64_t seed, const double* x_ref, int64_t iter_offset, int64_t check_every,
               void* stream, rka_info* info) {
   return solve_impl(false, A, dtype, m, n, lda, b, x0, x, q, 1, alpha, max_iter, tol, seed, x_ref,
-                    iter_offset, check_every, stream, info);
+                    iter_offset, check_every, 0, false, stream, info, nullptr);
+}
+
+int rka_solve_ex(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const double* b,
+                 const double* x0, double* x, int32_t method, int32_t q, int32_t block_size,
+                 double alpha, int64_t max_iter, double tol, uint64_t seed, const double* x_ref,
+                 int64_t iter_offset, const rka_opts* opts, void* stream, rka_info* info,
+                 rka_stats* stats) {
+  if (method != 0 && method != 1) {
+    g_last_error.clear();
+    if (info) info->status = RKA_EINVAL;
+    return fail(RKA_EINVAL, "method must be 0 (RKA) or 1 (RKAB)");
+  }
+  const int64_t ce = opts ? opts->check_every : 1;
+  const int grid = opts ? opts->grid : 0;
+  const bool timing = opts ? opts->collect_timing != 0 : false;
+  return solve_impl(method == 1, A, dtype, m, n, lda, b, x0, x, q, method == 1 ? block_size : 1,
+                    alpha, max_iter, tol, seed, x_ref, iter_offset, ce, grid, timing, stream, info,
+                    stats);
 }
 
 int rkab_solve(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const double* b,
@@ -248,7 +352,7 @@ int rkab_solve(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, cons
                int64_t max_iter, double tol, uint64_t seed, const double* x_ref,
                int64_t iter_offset, int64_t check_every, void* stream, rka_info* info) {
   return solve_impl(true, A, dtype, m, n, lda, b, x0, x, q, block_size, alpha, max_iter, tol, seed,
-                    x_ref, iter_offset, check_every, stream, info);
+                    x_ref, iter_offset, check_every, 0, false, stream, info, nullptr);
 }
 
 int rka_row_norms(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, double* w,

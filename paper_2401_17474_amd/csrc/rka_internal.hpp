@@ -42,6 +42,7 @@ struct SolveShape {
   double alpha;
   int32_t q, bs;
   int num_cu;
+  int grid;  // requested workgroups of the iteration kernel (0 = automatic)
 };
 
 // Returns false when q rows of a slice do not fit the kernel's register tile.

@@ -255,11 +255,13 @@ bool rka_col_plan(const SolveShape& sh, RkaColGeom* geo) {
   const int64_t nvec = sh.n / V;
   const int64_t bytes_per_iter = (int64_t)sh.q * sh.n * esz;
   int G, nsv;
-  if (bytes_per_iter <= (64 << 10) && nvec <= kMaxColThreads) {
+  const int target = sh.grid > 0 ? sh.grid : sh.num_cu;
+  const bool small = sh.grid == 0 && bytes_per_iter <= (64 << 10);
+  if ((small || target == 1) && nvec <= kMaxColThreads) {
     G = 1;
     nsv = (int)nvec;
   } else {
-    const int64_t g0 = nvec < sh.num_cu ? nvec : sh.num_cu;
+    const int64_t g0 = nvec < target ? nvec : target;
     nsv = (int)((nvec + g0 - 1) / g0);
     G = (int)((nvec + nsv - 1) / nsv);
     if (nsv > kMaxColThreads) return false;
@@ -498,7 +500,8 @@ bool rkab_plan(const SolveShape& sh, RkabGeom* geo) {
   // without spilling on gfx950.
   const int vpt_max = V == 1 ? 16 : (sh.dtype == 0 ? 12 : (sh.dtype == 1 ? 6 : 4));
   if (vpt > vpt_max) return false;
-  const int G = sh.q < sh.num_cu ? sh.q : sh.num_cu;
+  const int target = sh.grid > 0 ? sh.grid : sh.num_cu;
+  const int G = sh.q < target ? sh.q : target;
   geo->G = G;
   geo->nt = kRkabThreads;
   geo->vpt = vpt;
