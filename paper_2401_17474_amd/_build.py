@@ -23,6 +23,7 @@ ARCH = os.environ.get("RKA_OFFLOAD_ARCH", "gfx950")
 SOURCES = {
     "rka_setup.hip": ["-ffp-contract=off"],
     "rka_iter.hip": [],
+    "rka_rkab.hip": [],
     "rka_api.hip": [],
 }
 

@@ -55,10 +55,12 @@ hipError_t launch_rka_chunk(const SolveShape& sh, const RkaColGeom& geo, const i
                             double* scal, unsigned* bar, DevStatus* st, hipStream_t s);
 
 struct RkabGeom {
-  int G;     // workgroups (each runs workers g, g + G, ...)
-  int nt;    // threads per workgroup
-  int vpt;   // vecs per thread (template bucket)
-  int ns;    // vecs per workgroup in the averaging phase
+  int G;       // workgroups (each runs workers g, g + G, ...)
+  int nt;      // threads per workgroup
+  int vpt;     // vecs per thread (template bucket)
+  int ns;      // vecs per workgroup in the averaging phase
+  bool vlds;   // worker iterate kept in LDS instead of registers
+  size_t lds;  // dynamic LDS bytes
 };
 bool rkab_plan(const SolveShape& sh, RkabGeom* geo);
 hipError_t launch_rkab_chunk(const SolveShape& sh, const RkabGeom& geo, const int32_t* idx,

@@ -1,26 +1,20 @@
-// rka_iter.hip -- the iteration side of the hot path on gfx950.
+// rka_iter.hip -- RKA (Eq. (7), arXiv 2401.17474 Sec. 3.3.1) on gfx950, and
+// the stopping measures shared by both solvers.
 //
-// RKA (Eq. (7), arXiv 2401.17474 Sec. 3.3.1) and RKAB (Sec. 3.4.1) are
-// HBM-bound random row gathers: a projection reads one row once and does two
-// flops per element with it (dot product, then update).  Both kernels are
-// persistent and cooperatively launched, so one launch runs a whole chunk of
-// iterations with grid barriers in place of kernel boundaries.
+// RKA is an HBM-bound random row gather: a projection reads one row once and
+// does two flops per element with it (dot product, then update).  The kernel
+// is persistent and cooperatively launched, so one launch runs a whole chunk
+// of iterations with grid barriers in place of kernel boundaries.
 //
-// * RKA, column-split.  Workgroup g owns a fixed slice of the columns of x
-//   and keeps that slice of x on chip for the whole chunk.  Per iteration it
-//   gathers the slice of each of the q sampled rows into registers, forms q
-//   partial dot products, and exchanges only those partials (q doubles per
-//   workgroup) through a two-barrier all-reduce; the scales then update the
-//   slice of x from the row data still in registers.  Each element of A is
-//   read from HBM exactly once per iteration and x never leaves the chip.
-//   This replaces the serial critical section of Algorithm 1 and the q x n
-//   iterate matrix of the averaging alternatives with a fixed-order,
-//   atomic-free reduction.
-// * RKAB, worker-split.  A worker's bs projections depend on each other, so
-//   a worker lives in one workgroup with its private iterate v in registers;
-//   the only grid-wide step per outer iteration is the average of the q
-//   iterates, done column-sliced in fixed worker order (the layout of the
-//   per-thread iterate matrix of Sec. 3.3.1, one row per worker).
+// Column-split: workgroup g owns a fixed slice of the columns of x and keeps
+// that slice of x on chip for the whole chunk.  Per iteration it gathers the
+// slice of each of the q sampled rows into registers, forms q partial dot
+// products, and exchanges only those partials (q doubles per workgroup)
+// through a two-barrier all-reduce; the scales then update the slice of x
+// from the row data still in registers.  Each element of A is read from HBM
+// exactly once per iteration and x never leaves the chip.  This replaces the
+// serial critical section of Algorithm 1 (and the averaging alternatives
+// discussed with it) with a fixed-order, atomic-free reduction.
 //
 // Sums are always taken in a fixed order, so a given launch geometry gives
 // bitwise-reproducible results.
@@ -143,8 +137,10 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
       else
         SC[q] = s;
     }
-    // next iteration's rows are independent of x: start fetching them now,
-    // so that they stream in while the all-reduce below waits
+    // the partials must have landed before arriving; the next iteration's
+    // rows (independent of x) are requested after that wait, so that they
+    // stream in while the all-reduce below is in progress
+    if (p.G > 1) wait_memory();
     if (more) {
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
@@ -154,7 +150,7 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
     }
     const int nr = q + (check ? 1 : 0);
     if (p.G > 1) {
-      grid_barrier(p.bar, target, (unsigned)p.G);
+      grid_arrive_wait(p.bar, target, (unsigned)p.G);
       for (int r = g; r < nr; r += p.G) {
         double v = 0.0;
         for (int gg = t; gg < p.G; gg += NT) v += load_agent(&p.part[(size_t)gg * (q + 1) + r]);
@@ -168,7 +164,8 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
           store_agent(&p.scal[r], s);
         }
       }
-      grid_barrier(p.bar, target, (unsigned)p.G);
+      if (t == 0) wait_memory();
+      grid_arrive_wait(p.bar, target, (unsigned)p.G);
       for (int r = t; r < nr; r += NT) SC[r] = load_agent(&p.scal[r]);
     } else {
       __syncthreads();
@@ -335,235 +332,6 @@ hipError_t launch_rka_chunk(const SolveShape& sh, const RkaColGeom& geo, const i
     case 1: return sh.vec_ok ? launch_col_t<float, 4>(geo, a, s) : launch_col_t<float, 1>(geo, a, s);
     default:
       return sh.vec_ok ? launch_col_t<bf16_t, 8>(geo, a, s) : launch_col_t<bf16_t, 1>(geo, a, s);
-  }
-}
-
-// ===========================================================================
-// RKAB, worker-split persistent kernel.
-// ===========================================================================
-struct RkabArgs {
-  const void* A;
-  int64_t lda, nvec;
-  const double* b;
-  const double* wn;
-  const int32_t* idx;
-  double* x;
-  const double* x_ref;
-  double alpha;
-  int32_t q, bs, G, ns;
-  int64_t k0, K, check_every;
-  double* vbuf;  // q x (nvec * V): the workers' iterates
-  double* part;  // G
-  unsigned* bar;
-  DevStatus* st;
-};
-
-constexpr int kRkabThreads = 512;
-
-template <typename T, int V, int VPT>
-__global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
-  using raw_t = typename Vec<T, V>::raw_t;
-  if (p.st->done) return;
-  const T* __restrict__ A = (const T*)p.A;
-  const int t = threadIdx.x, g = blockIdx.x;
-  const int64_t nvec = p.nvec, n = nvec * V;
-  __shared__ double RED[kRkabThreads / kWave];
-
-  double v[VPT][V];
-  raw_t ar[VPT], an[VPT];
-  unsigned target = 0;
-  bool stopped = false;
-  int64_t kl = 0;
-  for (; kl < p.K; ++kl) {
-    const int64_t k = p.k0 + kl;
-    for (int w = g; w < p.q; w += p.G) {
-      // v = x^(k)
-#pragma unroll
-      for (int i = 0; i < VPT; ++i) {
-        const int64_t c = t + (int64_t)kRkabThreads * i;
-#pragma unroll
-        for (int e = 0; e < V; ++e) v[i][e] = (c < nvec) ? load_agent(&p.x[c * V + e]) : 0.0;
-      }
-      const int32_t* rows = p.idx + (kl * p.q + w) * (int64_t)p.bs;
-      int64_t row = rows[0];
-#pragma unroll
-      for (int i = 0; i < VPT; ++i) {
-        const int64_t c = t + (int64_t)kRkabThreads * i;
-        if (c < nvec) ar[i] = load_raw<T, V>(A + row * p.lda + c * V);
-      }
-      for (int jj = 0; jj < p.bs; ++jj) {
-        int64_t row_n = row;
-        if (jj + 1 < p.bs) {
-          row_n = rows[jj + 1];
-#pragma unroll
-          for (int i = 0; i < VPT; ++i) {
-            const int64_t c = t + (int64_t)kRkabThreads * i;
-            if (c < nvec) an[i] = load_raw<T, V>(A + row_n * p.lda + c * V);
-          }
-        }
-        double d = 0.0;
-#pragma unroll
-        for (int i = 0; i < VPT; ++i) {
-          const int64_t c = t + (int64_t)kRkabThreads * i;
-          if (c < nvec) {
-#pragma unroll
-            for (int e = 0; e < V; ++e) d = fma(raw_elem<T, V>(ar[i], e), v[i][e], d);
-          }
-        }
-        const double D = block_sum(d, RED);
-        const double s = p.alpha * (p.b[row] - D) / p.wn[row];
-#pragma unroll
-        for (int i = 0; i < VPT; ++i) {
-          const int64_t c = t + (int64_t)kRkabThreads * i;
-          if (c < nvec) {
-#pragma unroll
-            for (int e = 0; e < V; ++e) v[i][e] = fma(s, raw_elem<T, V>(ar[i], e), v[i][e]);
-          }
-        }
-        if (jj + 1 < p.bs) {
-#pragma unroll
-          for (int i = 0; i < VPT; ++i) ar[i] = an[i];
-          row = row_n;
-        }
-      }
-      double* vw = p.vbuf + (size_t)w * n;
-#pragma unroll
-      for (int i = 0; i < VPT; ++i) {
-        const int64_t c = t + (int64_t)kRkabThreads * i;
-        if (c < nvec) {
-#pragma unroll
-          for (int e = 0; e < V; ++e) vw[c * V + e] = v[i][e];
-        }
-      }
-    }
-    // x^(k+1) = (1/q) sum_w v_w, column slices, fixed worker order
-    sync_grid(p.bar, target, (unsigned)p.G);
-    const bool check = p.check_every > 0 && ((k + 1) % p.check_every) == 0;
-    const int64_t e0 = (int64_t)g * p.ns * V;
-    const int64_t e1 = ((int64_t)(g + 1) * p.ns * V < n) ? (int64_t)(g + 1) * p.ns * V : n;
-    double err = 0.0;
-    for (int64_t ci = e0 + t; ci < e1; ci += kRkabThreads) {
-      double acc = 0.0;
-      for (int w = 0; w < p.q; ++w) acc += load_agent(&p.vbuf[(size_t)w * n + ci]);
-      const double xn = acc / (double)p.q;
-      p.x[ci] = xn;
-      if (check) {
-        const double dd = xn - p.x_ref[ci];
-        err = fma(dd, dd, err);
-      }
-    }
-    if (check) {
-      const double s = block_sum(err, RED);
-      if (t == 0) {
-        if (p.G > 1)
-          store_agent(&p.part[g], s);
-        else
-          p.part[0] = s;
-      }
-    }
-    sync_grid(p.bar, target, (unsigned)p.G);
-    if (check) {
-      double e2 = 0.0;
-      for (int gg = 0; gg < p.G; ++gg) e2 += load_agent(&p.part[gg]);
-      const bool conv = e2 <= p.st->thresh2;
-      const bool div = !isfinite(e2);
-      if (conv || div) {
-        if (g == 0 && t == 0) {
-          p.st->iterations = k + 1;
-          p.st->rel2 = e2 / p.st->ref2;
-          p.st->status = conv ? 0 : -3;
-          p.st->done = 1;
-        }
-        stopped = true;
-        break;
-      }
-    }
-  }
-  if (!stopped && g == 0 && t == 0) p.st->iterations = p.k0 + p.K;
-}
-
-static int vpt_bucket(int64_t need) {
-  static const int b[] = {1, 2, 4, 6, 8, 10, 12, 16, 20};
-  for (int v : b)
-    if (need <= v) return v;
-  return 0;
-}
-
-bool rkab_plan(const SolveShape& sh, RkabGeom* geo) {
-  const int esz = sh.dtype == 0 ? 8 : (sh.dtype == 1 ? 4 : 2);
-  const int V = sh.vec_ok ? 16 / esz : 1;
-  const int64_t nvec = sh.n / V;
-  const int vpt = vpt_bucket((nvec + kRkabThreads - 1) / kRkabThreads);
-  if (vpt == 0) return false;
-  // Per thread: v[VPT][V] doubles plus two raw row buffers; 512-thread groups
-  // allow 256 VGPRs per lane.  Largest bucket per storage type that compiles
-  // without spilling on gfx950.
-  const int vpt_max = V == 1 ? 16 : (sh.dtype == 0 ? 12 : (sh.dtype == 1 ? 6 : 4));
-  if (vpt > vpt_max) return false;
-  const int target = sh.grid > 0 ? sh.grid : sh.num_cu;
-  const int G = sh.q < target ? sh.q : target;
-  geo->G = G;
-  geo->nt = kRkabThreads;
-  geo->vpt = vpt;
-  geo->ns = (int)((nvec + G - 1) / G);
-  return true;
-}
-
-template <typename T, int V>
-static hipError_t launch_rkab_t(const RkabGeom& geo, RkabArgs& a, hipStream_t s) {
-  void* args[] = {&a};
-  const void* fn = nullptr;
-  switch (geo.vpt) {
-    case 1: fn = (const void*)rkab_kernel<T, V, 1>; break;
-    case 2: fn = (const void*)rkab_kernel<T, V, 2>; break;
-    case 4: fn = (const void*)rkab_kernel<T, V, 4>; break;
-    case 6: fn = (const void*)rkab_kernel<T, V, 6>; break;
-    case 8: fn = (const void*)rkab_kernel<T, V, 8>; break;
-    case 10: fn = (const void*)rkab_kernel<T, V, 10>; break;
-    case 12: fn = (const void*)rkab_kernel<T, V, 12>; break;
-    case 16: fn = (const void*)rkab_kernel<T, V, 16>; break;
-    default: fn = (const void*)rkab_kernel<T, V, 20>; break;
-  }
-  return hipLaunchCooperativeKernel(fn, dim3(geo.G), dim3(geo.nt), args, 0, s);
-}
-
-hipError_t launch_rkab_chunk(const SolveShape& sh, const RkabGeom& geo, const int32_t* idx,
-                             int64_t k0, int64_t K, int64_t check_every, double* vbuf,
-                             double* part, unsigned* bar, DevStatus* st, hipStream_t s) {
-  const int esz = sh.dtype == 0 ? 8 : (sh.dtype == 1 ? 4 : 2);
-  const int V = sh.vec_ok ? 16 / esz : 1;
-  RkabArgs a;
-  a.A = sh.A;
-  a.lda = sh.lda;
-  a.nvec = sh.n / V;
-  a.b = sh.b;
-  a.wn = sh.wn;
-  a.idx = idx;
-  a.x = sh.x;
-  a.x_ref = sh.x_ref;
-  a.alpha = sh.alpha;
-  a.q = sh.q;
-  a.bs = sh.bs;
-  a.G = geo.G;
-  a.ns = geo.ns;
-  a.k0 = k0;
-  a.K = K;
-  a.check_every = check_every;
-  a.vbuf = vbuf;
-  a.part = part;
-  a.bar = bar;
-  a.st = st;
-  if (geo.G > 1) {
-    hipError_t e = hipMemsetAsync(bar, 0, sizeof(unsigned), s);
-    if (e != hipSuccess) return e;
-  }
-  switch (sh.dtype) {
-    case 0:
-      return sh.vec_ok ? launch_rkab_t<double, 2>(geo, a, s) : launch_rkab_t<double, 1>(geo, a, s);
-    case 1:
-      return sh.vec_ok ? launch_rkab_t<float, 4>(geo, a, s) : launch_rkab_t<float, 1>(geo, a, s);
-    default:
-      return sh.vec_ok ? launch_rkab_t<bf16_t, 8>(geo, a, s) : launch_rkab_t<bf16_t, 1>(geo, a, s);
   }
 }
 

@@ -1,0 +1,295 @@
+// rka_rkab.hip -- RKAB (arXiv 2401.17474, Sec. 3.4.1, Algorithm 3) on gfx950:
+// the worker-split persistent kernel.
+//
+// A worker's block of projections is a dependent chain (each projection
+// reads the iterate the previous one produced), so a worker lives in one
+// workgroup with its private iterate v in registers.  Rows are streamed
+// from HBM through a three-deep register ring, so that two rows are always
+// in flight while the third is projected.  The only grid-wide step per outer
+// iteration is the average of the q iterates: every worker publishes v
+// (agent-coherent stores), and after a grid barrier workgroup g averages a
+// fixed slice of the columns over the workers in fixed order -- the layout
+// of the per-thread iterate matrix of Sec. 3.3.1, one row per worker.
+#include <math.h>
+
+#include "rka_device.hpp"
+#include "rka_internal.hpp"
+
+namespace rka {
+
+// ===========================================================================
+// RKAB, worker-split persistent kernel.
+// ===========================================================================
+struct RkabArgs {
+  const void* A;
+  int64_t lda, nvec;
+  const double* b;
+  const double* wn;
+  const int32_t* idx;
+  double* x;
+  const double* x_ref;
+  double alpha;
+  int32_t q, bs, G, ns;
+  int64_t k0, K, check_every;
+  double* vbuf;  // q x (nvec * V): the workers' iterates
+  double* part;  // G
+  unsigned* bar;
+  DevStatus* st;
+};
+
+constexpr int kRkabThreads = 512;
+
+// VLDS = false: the worker's iterate v lives in registers (short rows);
+// VLDS = true: v lives in LDS (nvec * V doubles of dynamic shared memory),
+// leaving the registers to the row ring (long rows).  Each thread only ever
+// touches its own vecs of v, so v needs no extra synchronisation.
+template <typename T, int V, int VPT, bool VLDS>
+__global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
+  using raw_t = typename Vec<T, V>::raw_t;
+  constexpr int NT = kRkabThreads;
+  if (p.st->done) return;
+  const T* __restrict__ A = (const T*)p.A;
+  const int t = threadIdx.x, g = blockIdx.x;
+  const int64_t nvec = p.nvec, n = nvec * V;
+  __shared__ double RED[NT / kWave];
+  extern __shared__ double vlds[];
+
+  double vreg[VLDS ? 1 : VPT][V];
+  auto vat = [&](int i, int e) -> double& {
+    if constexpr (VLDS)
+      return vlds[(t + (int64_t)NT * i) * V + e];
+    else
+      return vreg[i][e];
+  };
+  // three row buffers used as a ring: two rows are in flight while the
+  // third is projected, so a workgroup keeps ~2 rows of HBM reads queued
+  raw_t B0[VPT], B1[VPT], B2[VPT];
+
+  auto load_row = [&](raw_t (&dst)[VPT], int64_t row) {
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const int64_t c = t + (int64_t)NT * i;
+      if (c < nvec) dst[i] = load_raw<T, V>(A + row * p.lda + c * V);
+    }
+  };
+  // v += alpha (b_i - <a_i, v>) / ||a_i||^2 a_i
+  auto project = [&](const raw_t (&src)[VPT], int64_t row) {
+    double d = 0.0;
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const int64_t c = t + (int64_t)NT * i;
+      if (c < nvec) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) d = fma(raw_elem<T, V>(src[i], e), vat(i, e), d);
+      }
+    }
+    const double D = block_sum(d, RED);
+    const double s = p.alpha * (p.b[row] - D) / p.wn[row];
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const int64_t c = t + (int64_t)NT * i;
+      if (c < nvec) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) vat(i, e) = fma(s, raw_elem<T, V>(src[i], e), vat(i, e));
+      }
+    }
+  };
+
+  unsigned target = 0;
+  bool stopped = false;
+  int64_t kl = 0;
+  const int bs = p.bs;
+  for (; kl < p.K; ++kl) {
+    const int64_t k = p.k0 + kl;
+    for (int w = g; w < p.q; w += p.G) {
+      const int32_t* rows = p.idx + (kl * p.q + w) * (int64_t)bs;
+      load_row(B0, rows[0]);
+      if (bs > 1) load_row(B1, rows[1]);
+      // v = x^(k)
+#pragma unroll
+      for (int i = 0; i < VPT; ++i) {
+        const int64_t c = t + (int64_t)NT * i;
+        if (c < nvec) {
+#pragma unroll
+          for (int e = 0; e < V; ++e) vat(i, e) = load_agent(&p.x[c * V + e]);
+        }
+      }
+      int jj = 0;
+      for (; jj + 5 <= bs; jj += 3) {
+        load_row(B2, rows[jj + 2]);
+        project(B0, rows[jj]);
+        load_row(B0, rows[jj + 3]);
+        project(B1, rows[jj + 1]);
+        load_row(B1, rows[jj + 4]);
+        project(B2, rows[jj + 2]);
+      }
+      // at most four rows remain: row jj is in B0, row jj+1 (if any) in B1
+      if (jj + 2 < bs) load_row(B2, rows[jj + 2]);
+      project(B0, rows[jj]);
+      if (jj + 3 < bs) load_row(B0, rows[jj + 3]);
+      if (jj + 1 < bs) project(B1, rows[jj + 1]);
+      if (jj + 2 < bs) project(B2, rows[jj + 2]);
+      if (jj + 3 < bs) project(B0, rows[jj + 3]);
+      double* vw = p.vbuf + (size_t)w * n;
+#pragma unroll
+      for (int i = 0; i < VPT; ++i) {
+        const int64_t c = t + (int64_t)NT * i;
+        if (c < nvec) {
+#pragma unroll
+          for (int e = 0; e < V; ++e) store_agent(&vw[c * V + e], vat(i, e));
+        }
+      }
+    }
+    // x^(k+1) = (1/q) sum_w v_w, column slices, fixed worker order
+    sync_grid(p.bar, target, (unsigned)p.G);
+    const bool check = p.check_every > 0 && ((k + 1) % p.check_every) == 0;
+    const int64_t e0 = (int64_t)g * p.ns * V;
+    const int64_t e1 = ((int64_t)(g + 1) * p.ns * V < n) ? (int64_t)(g + 1) * p.ns * V : n;
+    double err = 0.0;
+    for (int64_t ci = e0 + t; ci < e1; ci += NT) {
+      double acc = 0.0;
+      for (int w = 0; w < p.q; ++w) acc += load_agent(&p.vbuf[(size_t)w * n + ci]);
+      const double xn = acc / (double)p.q;
+      store_agent(&p.x[ci], xn);
+      if (check) {
+        const double dd = xn - p.x_ref[ci];
+        err = fma(dd, dd, err);
+      }
+    }
+    if (check) {
+      const double s = block_sum(err, RED);
+      if (t == 0) store_agent(&p.part[g], s);
+    }
+    sync_grid(p.bar, target, (unsigned)p.G);
+    if (check) {
+      double e2 = 0.0;
+      for (int gg = 0; gg < p.G; ++gg) e2 += load_agent(&p.part[gg]);
+      const bool conv = e2 <= p.st->thresh2;
+      const bool div = !isfinite(e2);
+      if (conv || div) {
+        if (g == 0 && t == 0) {
+          p.st->iterations = k + 1;
+          p.st->rel2 = e2 / p.st->ref2;
+          p.st->status = conv ? 0 : -3;
+          p.st->done = 1;
+        }
+        stopped = true;
+        break;
+      }
+    }
+  }
+  if (!stopped && g == 0 && t == 0) p.st->iterations = p.k0 + p.K;
+}
+
+// Register-tile buckets: 16-byte vecs per thread.  A bucket is offered for a
+// storage type only if its kernel compiles without spilling on gfx950.
+static int vpt_bucket(int64_t need) {
+  static const int b[] = {1, 2, 3, 4, 6, 8, 10, 12, 16, 20};
+  for (int v : b)
+    if (need <= v) return v;
+  return 0;
+}
+
+// largest spill-free bucket with v in registers / with v in LDS
+static int vpt_limit_reg(int dtype, int V) {
+  if (V == 1) return dtype == 0 ? 12 : 16;
+  return dtype == 2 ? 4 : 6;
+}
+static int vpt_limit_lds(int dtype, int V) {
+  if (V == 1) return dtype == 0 ? 16 : 20;
+  return dtype == 0 ? 10 : (dtype == 1 ? 6 : 4);
+}
+constexpr size_t kMaxLds = 160 * 1024 - 1024;
+
+bool rkab_plan(const SolveShape& sh, RkabGeom* geo) {
+  const int esz = sh.dtype == 0 ? 8 : (sh.dtype == 1 ? 4 : 2);
+  const int V = sh.vec_ok ? 16 / esz : 1;
+  const int64_t nvec = sh.n / V;
+  const int vpt = vpt_bucket((nvec + kRkabThreads - 1) / kRkabThreads);
+  if (vpt == 0) return false;
+  bool vlds = vpt > vpt_limit_reg(sh.dtype, V);
+  size_t lds = 0;
+  if (vlds) {
+    if (vpt > vpt_limit_lds(sh.dtype, V)) return false;
+    lds = (size_t)nvec * V * sizeof(double);
+    if (lds > kMaxLds) return false;
+  }
+  const int target = sh.grid > 0 ? sh.grid : sh.num_cu;
+  const int G = sh.q < target ? sh.q : target;
+  geo->G = G;
+  geo->nt = kRkabThreads;
+  geo->vpt = vpt;
+  geo->vlds = vlds;
+  geo->lds = lds;
+  geo->ns = (int)((nvec + G - 1) / G);
+  return true;
+}
+
+template <typename T, int V, bool VLDS>
+static const void* rkab_fn(int vpt) {
+  switch (vpt) {
+    case 1: return (const void*)rkab_kernel<T, V, 1, VLDS>;
+    case 2: return (const void*)rkab_kernel<T, V, 2, VLDS>;
+    case 3: return (const void*)rkab_kernel<T, V, 3, VLDS>;
+    case 4: return (const void*)rkab_kernel<T, V, 4, VLDS>;
+    case 6: return (const void*)rkab_kernel<T, V, 6, VLDS>;
+    case 8: return (const void*)rkab_kernel<T, V, 8, VLDS>;
+    case 10: return (const void*)rkab_kernel<T, V, 10, VLDS>;
+    case 12: return (const void*)rkab_kernel<T, V, 12, VLDS>;
+    case 16: return (const void*)rkab_kernel<T, V, 16, VLDS>;
+    default: return (const void*)rkab_kernel<T, V, 20, VLDS>;
+  }
+}
+
+template <typename T, int V>
+static hipError_t launch_rkab_t(const RkabGeom& geo, RkabArgs& a, hipStream_t s) {
+  void* args[] = {&a};
+  const void* fn = geo.vlds ? rkab_fn<T, V, true>(geo.vpt) : rkab_fn<T, V, false>(geo.vpt);
+  if (geo.lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)geo.lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipLaunchCooperativeKernel(fn, dim3(geo.G), dim3(geo.nt), args, (unsigned)geo.lds, s);
+}
+
+hipError_t launch_rkab_chunk(const SolveShape& sh, const RkabGeom& geo, const int32_t* idx,
+                             int64_t k0, int64_t K, int64_t check_every, double* vbuf,
+                             double* part, unsigned* bar, DevStatus* st, hipStream_t s) {
+  const int esz = sh.dtype == 0 ? 8 : (sh.dtype == 1 ? 4 : 2);
+  const int V = sh.vec_ok ? 16 / esz : 1;
+  RkabArgs a;
+  a.A = sh.A;
+  a.lda = sh.lda;
+  a.nvec = sh.n / V;
+  a.b = sh.b;
+  a.wn = sh.wn;
+  a.idx = idx;
+  a.x = sh.x;
+  a.x_ref = sh.x_ref;
+  a.alpha = sh.alpha;
+  a.q = sh.q;
+  a.bs = sh.bs;
+  a.G = geo.G;
+  a.ns = geo.ns;
+  a.k0 = k0;
+  a.K = K;
+  a.check_every = check_every;
+  a.vbuf = vbuf;
+  a.part = part;
+  a.bar = bar;
+  a.st = st;
+  if (geo.G > 1) {
+    hipError_t e = hipMemsetAsync(bar, 0, sizeof(unsigned), s);
+    if (e != hipSuccess) return e;
+  }
+  switch (sh.dtype) {
+    case 0:
+      return sh.vec_ok ? launch_rkab_t<double, 2>(geo, a, s) : launch_rkab_t<double, 1>(geo, a, s);
+    case 1:
+      return sh.vec_ok ? launch_rkab_t<float, 4>(geo, a, s) : launch_rkab_t<float, 1>(geo, a, s);
+    default:
+      return sh.vec_ok ? launch_rkab_t<bf16_t, 8>(geo, a, s) : launch_rkab_t<bf16_t, 1>(geo, a, s);
+  }
+}
+
+}  // namespace rka

@@ -96,14 +96,23 @@ __global__ __launch_bounds__(kPrefixThreads) void prefix_kernel(const double* __
   for (int64_t base = 0; base < m; base += kPrefixBlock) {
     const int cnt = (int)((m - base) < kPrefixBlock ? (m - base) : kPrefixBlock);
     if (t == 0) {
-      // the sequential chain, on one lane of wave 0
+      // the sequential chain, on one lane of wave 0; weights are read from
+      // LDS a batch at a time so that only the dependent adds are serial
       double run = carry_s;
       long long last = last_s;
-      for (int i = 0; i < cnt; ++i) {
-        const double wi = in[slot][i];
-        run = __dadd_rn(run, wi);
-        out[i] = run;
-        if (wi > 0.0) last = base + i;
+      constexpr int kBatch = 32;
+      for (int i0 = 0; i0 < cnt; i0 += kBatch) {
+        double wv[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) wv[u] = in[slot][i0 + u];  // in-bounds: block of 1024
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+          if (i0 + u < cnt) {
+            run = __dadd_rn(run, wv[u]);
+            out[i0 + u] = run;
+            if (wv[u] > 0.0) last = base + i0 + u;
+          }
+        }
       }
       carry_s = run;
       last_s = last;

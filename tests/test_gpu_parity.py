@@ -144,6 +144,8 @@ RKAB_CASES = [
     (1500, 640, "f32", 16, 5, 10, 1.2),
     (1500, 640, "bf16", 16, 5, 10, 1.0),
     (900, 101, "f64", 6, 3, 15, 0.8),     # scalar path
+    (1200, 8000, "f64", 8, 7, 3, 1.0),    # long rows: worker iterate kept in LDS
+    (600, 5001, "f64", 3, 4, 2, 1.0),     # long odd rows: scalar path, registers
 ]
 
 
