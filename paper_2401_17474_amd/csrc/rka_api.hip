@@ -152,8 +152,8 @@ int validate(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const 
   return RKA_OK;
 }
 
-// Indices per chunk: at most 16 Mi entries (64 MiB).
-constexpr int64_t kIdxBudget = 16ll << 20;
+// Row records per chunk: at most 4 Mi entries (128 MiB).
+constexpr int64_t kRecBudget = 4ll << 20;
 
 int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
                const double* b, const double* x0, double* x, int32_t q, int32_t bs, double alpha,
@@ -208,10 +208,10 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   rka::DevStatus* st;
   double *w, *c, *part, *scal = nullptr, *vbuf = nullptr;
   int64_t* last_pos;
-  int32_t* idx;
+  rka::RowRec* rec;
   unsigned* bar;
   const int64_t per_iter = (int64_t)q * sh.bs;
-  int64_t kc_max = kIdxBudget / per_iter;
+  int64_t kc_max = kRecBudget / per_iter;
   if (kc_max < 1) kc_max = 1;
   if (kc_max > max_iter) kc_max = max_iter > 0 ? max_iter : 1;
   const int G = use_col ? cgeo.G : bgeo.G;
@@ -224,7 +224,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   HIP_TRY(sc.get(&w, (size_t)m));
   HIP_TRY(sc.get(&c, (size_t)m));
   HIP_TRY(sc.get(&last_pos, 1));
-  HIP_TRY(sc.get(&idx, (size_t)(kc_max * per_iter)));
+  HIP_TRY(sc.get(&rec, (size_t)(kc_max * per_iter)));
   HIP_TRY(sc.get(&part, part_len));
   HIP_TRY(sc.get(&bar, 1));
   if (use_col)
@@ -263,13 +263,14 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
       if (to_check < kc) kc = to_check;
     }
     tm.begin(kSample);
-    HIP_TRY(rka::launch_sample(c, m, last_pos, seed, k + iter_offset, kc, q, sh.bs, 0, idx, st, s));
+    HIP_TRY(rka::launch_sample(c, m, last_pos, seed, k + iter_offset, kc, q, sh.bs, 0, nullptr, rec,
+                               b, w, st, s));
     tm.end();
     tm.begin(kIterate);
     if (use_col)
-      HIP_TRY(rka::launch_rka_chunk(sh, cgeo, idx, k, kc, in_kernel_check, part, scal, bar, st, s));
+      HIP_TRY(rka::launch_rka_chunk(sh, cgeo, rec, k, kc, in_kernel_check, part, scal, bar, st, s));
     else
-      HIP_TRY(rka::launch_rkab_chunk(sh, bgeo, idx, k, kc, in_kernel_check, vbuf, part, bar, st, s));
+      HIP_TRY(rka::launch_rkab_chunk(sh, bgeo, rec, k, kc, in_kernel_check, vbuf, part, bar, st, s));
     tm.end();
     ++launches;
     k += kc;
@@ -398,7 +399,8 @@ int rka_sample_indices(const double* w, const double* c, int64_t m, uint64_t see
   hipError_t e = hipMallocAsync((void**)&cscratch, (size_t)m * sizeof(double), s);
   if (e == hipSuccess) e = rka::launch_prefix(w, m, cscratch, last_pos, nullptr, s);
   if (e == hipSuccess)
-    e = rka::launch_sample(c, m, last_pos, seed, iter_offset, K, q, bs, dom, idx, nullptr, s);
+    e = rka::launch_sample(c, m, last_pos, seed, iter_offset, K, q, bs, dom, idx, nullptr, nullptr,
+                           nullptr, nullptr, s);
   if (cscratch) (void)hipFreeAsync(cscratch, s);
   (void)hipFreeAsync(last_pos, s);
   if (e != hipSuccess)

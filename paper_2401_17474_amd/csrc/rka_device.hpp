@@ -122,6 +122,39 @@ __device__ __forceinline__ void store_agent(U* p, U v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Bulk device-coherent access: raw buffer loads/stores carrying the SC1
+// cache-policy bit, which makes them coherent at device scope across XCDs.
+// Unlike atomic loads they are ordinary loads to the compiler, so many can be
+// in flight at once.  Out-of-range offsets read 0 / drop the write.
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+constexpr int kCoherentSC1 = 1 << 4;       // buffer cache policy: device scope
+constexpr int kRawBufferWord3 = 0x00020000;  // gfx9 raw-buffer descriptor word 3
+
+struct CoherentBuf {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ CoherentBuf(const double* base, int64_t count)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0,
+                                            (int)(count * 8), kRawBufferWord3)) {}
+  __device__ __forceinline__ double load(int64_t i) const {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)(i * 8), 0,
+                                                                           kCoherentSC1));
+  }
+  __device__ __forceinline__ void store(int64_t i, double v) const {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, (int)(i * 8), 0,
+                                          kCoherentSC1);
+  }
+};
+
+// One sampled row as the iteration kernels consume it: the sampler writes
+// the right-hand side entry and squared norm next to the index, so that a
+// kernel gets all three with one 32-byte read.
+struct alignas(16) RowRec {
+  double b;
+  double wn;
+  int64_t row;
+  int64_t pad;
+};
+
 // Wait until every memory operation this wave has issued -- in particular
 // its agent-coherent stores -- has completed.  On gfx9 loads and stores
 // share one counter, so this also drains the wave's outstanding loads:

@@ -8,15 +8,19 @@
 namespace rka {
 
 struct DevStatus;
+struct RowRec;
 
 // --- sampler side (rka_setup.hip) ------------------------------------------
 hipError_t launch_row_norms(const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
                             bool vec_ok, double* w, hipStream_t s);
 hipError_t launch_prefix(const double* w, int64_t m, double* c, int64_t* last_pos, DevStatus* st,
                          hipStream_t s);
+// Row stream of K*q*bs draws: indices into idx and/or records (index, b_i,
+// ||a_i||^2) into rec (either may be NULL; b and wn are needed for rec).
 hipError_t launch_sample(const double* c, int64_t m, const int64_t* last_pos, uint64_t seed,
                          int64_t k_base, int64_t K, int32_t q, int32_t bs, int32_t dom,
-                         int32_t* idx, const DevStatus* st, hipStream_t s);
+                         int32_t* idx, RowRec* rec, const double* b, const double* wn,
+                         const DevStatus* st, hipStream_t s);
 hipError_t launch_check_finite(const double* v, int64_t len, DevStatus* st, hipStream_t s);
 
 // --- iterations (rka_iter.hip) ---------------------------------------------
@@ -48,9 +52,9 @@ struct SolveShape {
 // Returns false when q rows of a slice do not fit the kernel's register tile.
 bool rka_col_plan(const SolveShape& sh, RkaColGeom* geo);
 
-// One chunk of iterations [k0, k0 + K) with indices idx[K*q*bs].
+// One chunk of iterations [k0, k0 + K) with row records rec[K*q*bs].
 // check_every = 0 disables the in-kernel stopping test (x_ref mode only).
-hipError_t launch_rka_chunk(const SolveShape& sh, const RkaColGeom& geo, const int32_t* idx,
+hipError_t launch_rka_chunk(const SolveShape& sh, const RkaColGeom& geo, const RowRec* rec,
                             int64_t k0, int64_t K, int64_t check_every, double* part,
                             double* scal, unsigned* bar, DevStatus* st, hipStream_t s);
 
@@ -63,7 +67,7 @@ struct RkabGeom {
   size_t lds;  // dynamic LDS bytes
 };
 bool rkab_plan(const SolveShape& sh, RkabGeom* geo);
-hipError_t launch_rkab_chunk(const SolveShape& sh, const RkabGeom& geo, const int32_t* idx,
+hipError_t launch_rkab_chunk(const SolveShape& sh, const RkabGeom& geo, const RowRec* rec,
                              int64_t k0, int64_t K, int64_t check_every, double* vbuf,
                              double* part, unsigned* bar, DevStatus* st, hipStream_t s);
 

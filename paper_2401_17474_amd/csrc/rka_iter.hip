@@ -31,9 +31,7 @@ namespace rka {
 struct RkaColArgs {
   const void* A;
   int64_t lda, nvec;
-  const double* b;
-  const double* wn;
-  const int32_t* idx;
+  const RowRec* rec;  // K x q row records of the chunk
   double* x;
   const double* x_ref;
   double alpha, inv_q;
@@ -80,7 +78,7 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int r = rgi + rg * i;
-    rows[i] = (active && r < q) ? p.idx[r] : 0;
+    rows[i] = (active && r < q) ? (int)p.rec[r].row : 0;
     if (colv && r < q) a[i] = load_raw<T, V>(A + (int64_t)rows[i] * p.lda + cv * V);
   }
 
@@ -95,7 +93,7 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
         const int r = rgi + rg * i;
-        rows_n[i] = (active && r < q) ? p.idx[(kl + 1) * q + r] : 0;
+        rows_n[i] = (active && r < q) ? (int)p.rec[(kl + 1) * q + r].row : 0;
       }
     }
     // partial dot products of this slice, one per (row, vec)
@@ -152,17 +150,12 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
     if (p.G > 1) {
       grid_arrive_wait(p.bar, target, (unsigned)p.G);
       for (int r = g; r < nr; r += p.G) {
+        RowRec rr;
+        if (t == 0 && r < q) rr = p.rec[kl * q + r];  // in flight with the partials
         double v = 0.0;
         for (int gg = t; gg < p.G; gg += NT) v += load_agent(&p.part[(size_t)gg * (q + 1) + r]);
         const double D = block_sum(v, RED);
-        if (t == 0) {
-          double s = D;
-          if (r < q) {
-            const int64_t ir = p.idx[kl * q + r];
-            s = p.alpha * (p.b[ir] - D) / p.wn[ir];
-          }
-          store_agent(&p.scal[r], s);
-        }
+        if (t == 0) store_agent(&p.scal[r], r < q ? p.alpha * (rr.b - D) / rr.wn : D);
       }
       if (t == 0) wait_memory();
       grid_arrive_wait(p.bar, target, (unsigned)p.G);
@@ -170,8 +163,8 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
     } else {
       __syncthreads();
       for (int r = t; r < q; r += NT) {
-        const int64_t ir = p.idx[kl * q + r];
-        SC[r] = p.alpha * (p.b[ir] - SC[r]) / p.wn[ir];
+        const RowRec rr = p.rec[kl * q + r];
+        SC[r] = p.alpha * (rr.b - SC[r]) / rr.wn;
       }
     }
     __syncthreads();
@@ -242,6 +235,7 @@ static int rpt_bucket(int need) {
   if (need <= 2) return 2;
   if (need <= 4) return 4;
   if (need <= 8) return 8;
+  if (need <= 12) return 12;
   if (need <= 16) return 16;
   return 0;
 }
@@ -268,7 +262,8 @@ bool rka_col_plan(const SolveShape& sh, RkaColGeom* geo) {
   if (rg < 1) rg = 1;
   const int rpt = rpt_bucket((sh.q + rg - 1) / rg);
   if (rpt == 0) return false;
-  if (rpt == 16 && sh.vec_ok && sh.dtype == 2) return false;  // would spill
+  if (rpt == 16) return false;  // would spill; wider q runs on the worker kernel
+  if (rpt == 12 && sh.vec_ok && sh.dtype == 2) return false;
   const int nt = ((nsv * rg + kWave - 1) / kWave) * kWave;
   const size_t lds =
       sizeof(double) * ((size_t)sh.q * nsv + (size_t)nt * V + (size_t)nsv * V + nsv + 16 + sh.q + 1);
@@ -291,12 +286,13 @@ static hipError_t launch_col_t(const RkaColGeom& geo, RkaColArgs& a, hipStream_t
     case 2: fn = (const void*)rka_col_kernel<T, V, 2>; break;
     case 4: fn = (const void*)rka_col_kernel<T, V, 4>; break;
     case 8: fn = (const void*)rka_col_kernel<T, V, 8>; break;
-    default: fn = (const void*)rka_col_kernel<T, V, 16>; break;
+    case 12: fn = (const void*)rka_col_kernel<T, V, 12>; break;
+    default: fn = (const void*)rka_col_kernel<T, V, 12>; break;
   }
   return hipLaunchCooperativeKernel(fn, dim3(geo.G), dim3(geo.nt), args, (unsigned)geo.lds, s);
 }
 
-hipError_t launch_rka_chunk(const SolveShape& sh, const RkaColGeom& geo, const int32_t* idx,
+hipError_t launch_rka_chunk(const SolveShape& sh, const RkaColGeom& geo, const RowRec* rec,
                             int64_t k0, int64_t K, int64_t check_every, double* part,
                             double* scal, unsigned* bar, DevStatus* st, hipStream_t s) {
   const int esz = sh.dtype == 0 ? 8 : (sh.dtype == 1 ? 4 : 2);
@@ -305,9 +301,7 @@ hipError_t launch_rka_chunk(const SolveShape& sh, const RkaColGeom& geo, const i
   a.A = sh.A;
   a.lda = sh.lda;
   a.nvec = sh.n / V;
-  a.b = sh.b;
-  a.wn = sh.wn;
-  a.idx = idx;
+  a.rec = rec;
   a.x = sh.x;
   a.x_ref = sh.x_ref;
   a.alpha = sh.alpha;

@@ -23,9 +23,7 @@ namespace rka {
 struct RkabArgs {
   const void* A;
   int64_t lda, nvec;
-  const double* b;
-  const double* wn;
-  const int32_t* idx;
+  const RowRec* rec;  // K x q x bs row records of the chunk
   double* x;
   const double* x_ref;
   double alpha;
@@ -38,11 +36,17 @@ struct RkabArgs {
 };
 
 constexpr int kRkabThreads = 512;
+constexpr int kStage = 256;  // row records staged in LDS per window slot
 
 // VLDS = false: the worker's iterate v lives in registers (short rows);
 // VLDS = true: v lives in LDS (nvec * V doubles of dynamic shared memory),
 // leaving the registers to the row ring (long rows).  Each thread only ever
 // touches its own vecs of v, so v needs no extra synchronisation.
+//
+// The worker's row records (index, b_i, ||a_i||^2) are staged in LDS in a
+// sliding window of two kStage-entry slots, so that inside the projection
+// loop the only global loads are the row data themselves and a projection
+// never waits for anything but its own row.
 template <typename T, int V, int VPT, bool VLDS>
 __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
   using raw_t = typename Vec<T, V>::raw_t;
@@ -52,6 +56,8 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
   const int t = threadIdx.x, g = blockIdx.x;
   const int64_t nvec = p.nvec, n = nvec * V;
   __shared__ double RED[NT / kWave];
+  __shared__ double Lb[2 * kStage], Lw[2 * kStage];
+  __shared__ int64_t Lr[2 * kStage];
   extern __shared__ double vlds[];
 
   double vreg[VLDS ? 1 : VPT][V];
@@ -65,7 +71,22 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
   // third is projected, so a workgroup keeps ~2 rows of HBM reads queued
   raw_t B0[VPT], B1[VPT], B2[VPT];
 
-  auto load_row = [&](raw_t (&dst)[VPT], int64_t row) {
+  const RowRec* wrec = nullptr;  // this worker's records
+  auto stage = [&](int blk, int bs) {
+    const int j0 = blk * kStage;
+    const int cnt = (bs - j0) < kStage ? (bs - j0) : kStage;
+    const int base = (blk & 1) * kStage;
+    for (int u = t; u < cnt; u += NT) {
+      const RowRec r = wrec[j0 + u];
+      Lb[base + u] = r.b;
+      Lw[base + u] = r.wn;
+      Lr[base + u] = r.row;
+    }
+  };
+  auto slot = [&](int j) { return ((j / kStage) & 1) * kStage + (j % kStage); };
+
+  auto load_row = [&](raw_t (&dst)[VPT], int j) {
+    const int64_t row = Lr[slot(j)];
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
       const int64_t c = t + (int64_t)NT * i;
@@ -73,7 +94,7 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
     }
   };
   // v += alpha (b_i - <a_i, v>) / ||a_i||^2 a_i
-  auto project = [&](const raw_t (&src)[VPT], int64_t row) {
+  auto project = [&](const raw_t (&src)[VPT], int j) {
     double d = 0.0;
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
@@ -84,7 +105,8 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
       }
     }
     const double D = block_sum(d, RED);
-    const double s = p.alpha * (p.b[row] - D) / p.wn[row];
+    const int sl = slot(j);
+    const double s = p.alpha * (Lb[sl] - D) / Lw[sl];
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
       const int64_t c = t + (int64_t)NT * i;
@@ -95,6 +117,7 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
     }
   };
 
+  const CoherentBuf xb(p.x, n);
   unsigned target = 0;
   bool stopped = false;
   int64_t kl = 0;
@@ -102,43 +125,60 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
   for (; kl < p.K; ++kl) {
     const int64_t k = p.k0 + kl;
     for (int w = g; w < p.q; w += p.G) {
-      const int32_t* rows = p.idx + (kl * p.q + w) * (int64_t)bs;
-      load_row(B0, rows[0]);
-      if (bs > 1) load_row(B1, rows[1]);
-      // v = x^(k)
+      wrec = p.rec + (kl * p.q + w) * (int64_t)bs;
+      // v = x^(k) (coherent: x was written by other workgroups)
 #pragma unroll
       for (int i = 0; i < VPT; ++i) {
         const int64_t c = t + (int64_t)NT * i;
         if (c < nvec) {
 #pragma unroll
-          for (int e = 0; e < V; ++e) vat(i, e) = load_agent(&p.x[c * V + e]);
+          for (int e = 0; e < V; ++e) vat(i, e) = xb.load(c * V + e);
         }
       }
+      stage(0, bs);
+      if (bs > kStage) stage(1, bs);
+      int next_blk = 2;
+      __syncthreads();
+      // block b goes into the slot of block b-2 once rows of block b-1 are
+      // being projected; the ring looks at most four rows ahead
+      auto restage = [&](int jj) {
+        if (next_blk * kStage < bs && jj >= (next_blk - 1) * kStage) {
+          __syncthreads();
+          stage(next_blk, bs);
+          __syncthreads();
+          ++next_blk;
+        }
+      };
+      load_row(B0, 0);
+      if (bs > 1) load_row(B1, 1);
       int jj = 0;
       for (; jj + 5 <= bs; jj += 3) {
-        load_row(B2, rows[jj + 2]);
-        project(B0, rows[jj]);
-        load_row(B0, rows[jj + 3]);
-        project(B1, rows[jj + 1]);
-        load_row(B1, rows[jj + 4]);
-        project(B2, rows[jj + 2]);
+        restage(jj);
+        load_row(B2, jj + 2);
+        project(B0, jj);
+        load_row(B0, jj + 3);
+        project(B1, jj + 1);
+        load_row(B1, jj + 4);
+        project(B2, jj + 2);
       }
+      restage(jj);
       // at most four rows remain: row jj is in B0, row jj+1 (if any) in B1
-      if (jj + 2 < bs) load_row(B2, rows[jj + 2]);
-      project(B0, rows[jj]);
-      if (jj + 3 < bs) load_row(B0, rows[jj + 3]);
-      if (jj + 1 < bs) project(B1, rows[jj + 1]);
-      if (jj + 2 < bs) project(B2, rows[jj + 2]);
-      if (jj + 3 < bs) project(B0, rows[jj + 3]);
-      double* vw = p.vbuf + (size_t)w * n;
+      if (jj + 2 < bs) load_row(B2, jj + 2);
+      project(B0, jj);
+      if (jj + 3 < bs) load_row(B0, jj + 3);
+      if (jj + 1 < bs) project(B1, jj + 1);
+      if (jj + 2 < bs) project(B2, jj + 2);
+      if (jj + 3 < bs) project(B0, jj + 3);
+      const CoherentBuf vw(p.vbuf + (size_t)w * n, n);
 #pragma unroll
       for (int i = 0; i < VPT; ++i) {
         const int64_t c = t + (int64_t)NT * i;
         if (c < nvec) {
 #pragma unroll
-          for (int e = 0; e < V; ++e) store_agent(&vw[c * V + e], vat(i, e));
+          for (int e = 0; e < V; ++e) vw.store(c * V + e, vat(i, e));
         }
       }
+      __syncthreads();  // the staged records are reused by the next worker
     }
     // x^(k+1) = (1/q) sum_w v_w, column slices, fixed worker order
     sync_grid(p.bar, target, (unsigned)p.G);
@@ -148,9 +188,17 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
     double err = 0.0;
     for (int64_t ci = e0 + t; ci < e1; ci += NT) {
       double acc = 0.0;
-      for (int w = 0; w < p.q; ++w) acc += load_agent(&p.vbuf[(size_t)w * n + ci]);
+      int w = 0;
+      for (; w + 8 <= p.q; w += 8) {
+        double vv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) vv[u] = CoherentBuf(p.vbuf + (size_t)(w + u) * n, n).load(ci);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += vv[u];
+      }
+      for (; w < p.q; ++w) acc += CoherentBuf(p.vbuf + (size_t)w * n, n).load(ci);
       const double xn = acc / (double)p.q;
-      store_agent(&p.x[ci], xn);
+      xb.store(ci, xn);
       if (check) {
         const double dd = xn - p.x_ref[ci];
         err = fma(dd, dd, err);
@@ -199,7 +247,7 @@ static int vpt_limit_lds(int dtype, int V) {
   if (V == 1) return dtype == 0 ? 16 : 20;
   return dtype == 0 ? 10 : (dtype == 1 ? 6 : 4);
 }
-constexpr size_t kMaxLds = 160 * 1024 - 1024;
+constexpr size_t kMaxLds = 144 * 1024;  // 160 KiB minus the static LDS above
 
 bool rkab_plan(const SolveShape& sh, RkabGeom* geo) {
   const int esz = sh.dtype == 0 ? 8 : (sh.dtype == 1 ? 4 : 2);
@@ -252,7 +300,7 @@ static hipError_t launch_rkab_t(const RkabGeom& geo, RkabArgs& a, hipStream_t s)
   return hipLaunchCooperativeKernel(fn, dim3(geo.G), dim3(geo.nt), args, (unsigned)geo.lds, s);
 }
 
-hipError_t launch_rkab_chunk(const SolveShape& sh, const RkabGeom& geo, const int32_t* idx,
+hipError_t launch_rkab_chunk(const SolveShape& sh, const RkabGeom& geo, const RowRec* rec,
                              int64_t k0, int64_t K, int64_t check_every, double* vbuf,
                              double* part, unsigned* bar, DevStatus* st, hipStream_t s) {
   const int esz = sh.dtype == 0 ? 8 : (sh.dtype == 1 ? 4 : 2);
@@ -261,9 +309,7 @@ hipError_t launch_rkab_chunk(const SolveShape& sh, const RkabGeom& geo, const in
   a.A = sh.A;
   a.lda = sh.lda;
   a.nvec = sh.n / V;
-  a.b = sh.b;
-  a.wn = sh.wn;
-  a.idx = idx;
+  a.rec = rec;
   a.x = sh.x;
   a.x_ref = sh.x_ref;
   a.alpha = sh.alpha;

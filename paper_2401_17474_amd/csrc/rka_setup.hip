@@ -150,6 +150,9 @@ __global__ __launch_bounds__(256) void sample_kernel(const double* __restrict__ 
                                                      uint64_t seed, int64_t k_base, int64_t K,
                                                      int32_t q, int32_t bs, uint32_t dom,
                                                      int32_t* __restrict__ idx,
+                                                     RowRec* __restrict__ rec,
+                                                     const double* __restrict__ b,
+                                                     const double* __restrict__ wn,
                                                      const DevStatus* st) {
   if (st && st->done) return;
   const double W = c[m - 1];
@@ -169,7 +172,16 @@ __global__ __launch_bounds__(256) void sample_kernel(const double* __restrict__ 
       else
         lo = mid + 1;
     }
-    idx[L] = (int32_t)(lo < m ? lo : *last_pos);
+    const int64_t i = lo < m ? lo : *last_pos;
+    if (idx) idx[L] = (int32_t)i;
+    if (rec) {
+      RowRec r;
+      r.b = b[i];
+      r.wn = wn[i];
+      r.row = i;
+      r.pad = 0;
+      rec[L] = r;
+    }
   }
 }
 
@@ -219,13 +231,14 @@ hipError_t launch_prefix(const double* w, int64_t m, double* c, int64_t* last_po
 
 hipError_t launch_sample(const double* c, int64_t m, const int64_t* last_pos, uint64_t seed,
                          int64_t k_base, int64_t K, int32_t q, int32_t bs, int32_t dom,
-                         int32_t* idx, const DevStatus* st, hipStream_t s) {
+                         int32_t* idx, RowRec* rec, const double* b, const double* wn,
+                         const DevStatus* st, hipStream_t s) {
   const int64_t total = K * (int64_t)q * bs;
   if (total <= 0) return hipSuccess;
   int64_t blocks = (total + 255) / 256;
   if (blocks > 8192) blocks = 8192;
   hipLaunchKernelGGL(sample_kernel, dim3((unsigned)blocks), dim3(256), 0, s, c, m, last_pos, seed,
-                     k_base, K, q, bs, (uint32_t)dom, idx, st);
+                     k_base, K, q, bs, (uint32_t)dom, idx, rec, b, wn, st);
   return hipGetLastError();
 }
 
