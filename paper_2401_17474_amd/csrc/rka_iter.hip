@@ -73,13 +73,17 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
     xr[e] = (colv && p.x_ref) ? p.x_ref[cv * V + e] : 0.0;
   }
 
+  // Row loads are unconditional (clamped to a valid row and vec; the surplus
+  // entries are masked in the arithmetic): a branch around a load would make
+  // the compiler drain every in-flight load where the branches join.
+  const int64_t cvl = cv < p.nvec ? cv : p.nvec - 1;
   raw_t a[RPT], an[RPT];
   int rows[RPT], rows_n[RPT];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int r = rgi + rg * i;
-    rows[i] = (active && r < q) ? (int)p.rec[r].row : 0;
-    if (colv && r < q) a[i] = load_raw<T, V>(A + (int64_t)rows[i] * p.lda + cv * V);
+    rows[i] = (int)p.rec[r < q ? r : q - 1].row;
+    a[i] = load_raw<T, V>(A + (int64_t)rows[i] * p.lda + cvl * V);
   }
 
   unsigned target = 0;
@@ -88,26 +92,22 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
   for (; kl < p.K; ++kl) {
     const int64_t k = p.k0 + kl;
     const bool check = p.check_every > 0 && k > 0 && (k % p.check_every) == 0;
-    const bool more = kl + 1 < p.K;
-    if (more) {
+    // next iteration's rows (the last iteration of a chunk re-reads its own:
+    // unconditional loads keep the compiler from draining them at a join)
+    const int64_t kn = kl + 1 < p.K ? kl + 1 : kl;
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) {
-        const int r = rgi + rg * i;
-        rows_n[i] = (active && r < q) ? (int)p.rec[(kl + 1) * q + r].row : 0;
-      }
+    for (int i = 0; i < RPT; ++i) {
+      const int r = rgi + rg * i;
+      rows_n[i] = (int)p.rec[kn * q + (r < q ? r : q - 1)].row;
     }
     // partial dot products of this slice, one per (row, vec)
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int r = rgi + rg * i;
-      if (active && r < q) {
-        double s = 0.0;
-        if (colv) {
+      double s = 0.0;  // xv is 0 past the last column
 #pragma unroll
-          for (int e = 0; e < V; ++e) s = fma(raw_elem<T, V>(a[i], e), xv[e], s);
-        }
-        P[r * nsv + j] = s;
-      }
+      for (int e = 0; e < V; ++e) s = fma(raw_elem<T, V>(a[i], e), xv[e], s);
+      if (active && r < q) P[r * nsv + j] = s;
     }
     if (check && active && rgi == 0) {
       double s = 0.0;
@@ -139,13 +139,8 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
     // rows (independent of x) are requested after that wait, so that they
     // stream in while the all-reduce below is in progress
     if (p.G > 1) wait_memory();
-    if (more) {
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) {
-        const int r = rgi + rg * i;
-        if (colv && r < q) an[i] = load_raw<T, V>(A + (int64_t)rows_n[i] * p.lda + cv * V);
-      }
-    }
+    for (int i = 0; i < RPT; ++i) an[i] = load_raw<T, V>(A + (int64_t)rows_n[i] * p.lda + cvl * V);
     const int nr = q + (check ? 1 : 0);
     if (p.G > 1) {
       grid_arrive_wait(p.bar, target, (unsigned)p.G);
@@ -190,11 +185,9 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int r = rgi + rg * i;
-      if (colv && r < q) {
-        const double s = SC[r];
+      const double s = (colv && r < q) ? SC[r < q ? r : 0] : 0.0;
 #pragma unroll
-        for (int e = 0; e < V; ++e) u[e] = fma(s, raw_elem<T, V>(a[i], e), u[e]);
-      }
+      for (int e = 0; e < V; ++e) u[e] = fma(s, raw_elem<T, V>(a[i], e), u[e]);
     }
     if (active) {
 #pragma unroll
@@ -215,12 +208,10 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
 #pragma unroll
       for (int e = 0; e < V; ++e) xv[e] = XS[j * V + e];
     }
-    if (more) {
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) {
-        a[i] = an[i];
-        rows[i] = rows_n[i];
-      }
+    for (int i = 0; i < RPT; ++i) {
+      a[i] = an[i];
+      rows[i] = rows_n[i];
     }
   }
   if (colv && rgi == 0) {

@@ -39,7 +39,7 @@ constexpr int kRkabThreads = 512;
 constexpr int kStage = 256;  // row records staged in LDS per window slot
 
 // VLDS = false: the worker's iterate v lives in registers (short rows);
-// VLDS = true: v lives in LDS (nvec * V doubles of dynamic shared memory),
+// VLDS = true: v lives in LDS (VPT * NT * V doubles of dynamic shared memory),
 // leaving the registers to the row ring (long rows).  Each thread only ever
 // touches its own vecs of v, so v needs no extra synchronisation.
 //
@@ -85,35 +85,34 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
   };
   auto slot = [&](int j) { return ((j / kStage) & 1) * kStage + (j % kStage); };
 
+  // Loads are unconditional (lanes past the row end re-read its last vec) and
+  // lanes past the end are masked through the scale instead: a branch around
+  // a load would make the compiler drain every in-flight load at the join.
   auto load_row = [&](raw_t (&dst)[VPT], int j) {
     const int64_t row = Lr[slot(j)];
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
       const int64_t c = t + (int64_t)NT * i;
-      if (c < nvec) dst[i] = load_raw<T, V>(A + row * p.lda + c * V);
+      const int64_t cc = c < nvec ? c : nvec - 1;
+      dst[i] = load_raw<T, V>(A + row * p.lda + cc * V);
     }
   };
-  // v += alpha (b_i - <a_i, v>) / ||a_i||^2 a_i
+  // v += alpha (b_i - <a_i, v>) / ||a_i||^2 a_i   (v is 0 on masked lanes)
   auto project = [&](const raw_t (&src)[VPT], int j) {
     double d = 0.0;
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
-      const int64_t c = t + (int64_t)NT * i;
-      if (c < nvec) {
 #pragma unroll
-        for (int e = 0; e < V; ++e) d = fma(raw_elem<T, V>(src[i], e), vat(i, e), d);
-      }
+      for (int e = 0; e < V; ++e) d = fma(raw_elem<T, V>(src[i], e), vat(i, e), d);
     }
     const double D = block_sum(d, RED);
     const int sl = slot(j);
     const double s = p.alpha * (Lb[sl] - D) / Lw[sl];
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
-      const int64_t c = t + (int64_t)NT * i;
-      if (c < nvec) {
+      const double si = (t + (int64_t)NT * i < nvec) ? s : 0.0;
 #pragma unroll
-        for (int e = 0; e < V; ++e) vat(i, e) = fma(s, raw_elem<T, V>(src[i], e), vat(i, e));
-      }
+      for (int e = 0; e < V; ++e) vat(i, e) = fma(si, raw_elem<T, V>(src[i], e), vat(i, e));
     }
   };
 
@@ -126,14 +125,12 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
     const int64_t k = p.k0 + kl;
     for (int w = g; w < p.q; w += p.G) {
       wrec = p.rec + (kl * p.q + w) * (int64_t)bs;
-      // v = x^(k) (coherent: x was written by other workgroups)
+      // v = x^(k) (coherent: x was written by other workgroups; 0 past the end)
 #pragma unroll
       for (int i = 0; i < VPT; ++i) {
         const int64_t c = t + (int64_t)NT * i;
-        if (c < nvec) {
 #pragma unroll
-          for (int e = 0; e < V; ++e) vat(i, e) = xb.load(c * V + e);
-        }
+        for (int e = 0; e < V; ++e) vat(i, e) = xb.load(c * V + e);
       }
       stage(0, bs);
       if (bs > kStage) stage(1, bs);
@@ -150,7 +147,7 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
         }
       };
       load_row(B0, 0);
-      if (bs > 1) load_row(B1, 1);
+      load_row(B1, bs > 1 ? 1 : 0);  // unconditional (see load_row)
       int jj = 0;
       for (; jj + 5 <= bs; jj += 3) {
         restage(jj);
@@ -169,14 +166,12 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
       if (jj + 1 < bs) project(B1, jj + 1);
       if (jj + 2 < bs) project(B2, jj + 2);
       if (jj + 3 < bs) project(B0, jj + 3);
-      const CoherentBuf vw(p.vbuf + (size_t)w * n, n);
+      const CoherentBuf vw(p.vbuf + (size_t)w * n, n);  // stores past the end are dropped
 #pragma unroll
       for (int i = 0; i < VPT; ++i) {
         const int64_t c = t + (int64_t)NT * i;
-        if (c < nvec) {
 #pragma unroll
-          for (int e = 0; e < V; ++e) vw.store(c * V + e, vat(i, e));
-        }
+        for (int e = 0; e < V; ++e) vw.store(c * V + e, vat(i, e));
       }
       __syncthreads();  // the staged records are reused by the next worker
     }
@@ -259,7 +254,7 @@ bool rkab_plan(const SolveShape& sh, RkabGeom* geo) {
   size_t lds = 0;
   if (vlds) {
     if (vpt > vpt_limit_lds(sh.dtype, V)) return false;
-    lds = (size_t)nvec * V * sizeof(double);
+    lds = (size_t)vpt * kRkabThreads * V * sizeof(double);
     if (lds > kMaxLds) return false;
   }
   const int target = sh.grid > 0 ? sh.grid : sh.num_cu;
