@@ -120,6 +120,13 @@ typedef struct rka_opts {
                                within rounding of each other), never the method.       */
     int32_t collect_timing; /* nonzero: time every phase with HIP events recorded on
                                `stream` and fill the *_ms fields of rka_stats          */
+    int32_t allreduce;      /* RKA exchange of the q partial dot products between
+                               workgroups: 0 = chosen by the library, 1 = one barrier
+                               and every workgroup sums all partials, 2 = two barriers
+                               (sums scattered over workgroups).  The two add the
+                               partials in different orders: results agree to
+                               rounding, each is bitwise reproducible.                */
+    int32_t reserved;
 } rka_opts;
 
 /* Launch facts and phase times of one rka_solve_ex call. */

@@ -35,7 +35,8 @@ class _Info(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("check_every", ctypes.c_int64), ("grid", ctypes.c_int32),
-                ("collect_timing", ctypes.c_int32)]
+                ("collect_timing", ctypes.c_int32), ("allreduce", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -185,8 +186,8 @@ def rkab_solve(A, b, *, q, block_size, alpha=1.0, max_iter=1000, tol=0.0, seed=1
 
 
 def solve_ex(A, b, *, method, q, block_size=1, alpha=1.0, max_iter=1000, tol=0.0, seed=1,
-             x0=None, x_ref=None, iter_offset=0, check_every=1, grid=0, timing=False, out=None,
-             stream=None, raise_on_error=True):
+             x0=None, x_ref=None, iter_offset=0, check_every=1, grid=0, allreduce=0,
+             timing=False, out=None, stream=None, raise_on_error=True):
     """rka_solve_ex: method 0 = RKA, 1 = RKAB.  Returns (x, Info, stats dict);
     with ``timing`` the stats hold per-phase HIP-event times (ms) measured on
     the stream the kernels run on."""
@@ -196,7 +197,7 @@ def solve_ex(A, b, *, method, q, block_size=1, alpha=1.0, max_iter=1000, tol=0.0
     x = out if out is not None else torch.empty(n, dtype=torch.float64, device=A.device)
     _vec(x, n, "out", False)
     info, stats = _Info(), _Stats()
-    opts = _Opts(check_every, grid, 1 if timing else 0)
+    opts = _Opts(check_every, grid, 1 if timing else 0, allreduce, 0)
     st = lib().rka_solve_ex(_ptr(A), code, m, n, lda, _ptr(b), _ptr(_vec(x0, n, "x0")), _ptr(x),
                             method, q, block_size, alpha, max_iter, tol, seed,
                             _ptr(_vec(x_ref, n, "x_ref")), iter_offset, ctypes.byref(opts),

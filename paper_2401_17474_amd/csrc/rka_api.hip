@@ -158,8 +158,8 @@ constexpr int64_t kRecBudget = 4ll << 20;
 int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
                const double* b, const double* x0, double* x, int32_t q, int32_t bs, double alpha,
                int64_t max_iter, double tol, uint64_t seed, const double* x_ref,
-               int64_t iter_offset, int64_t check_every, int grid, bool timing, void* stream,
-               rka_info* info, rka_stats* stats) {
+               int64_t iter_offset, int64_t check_every, int grid, int allreduce, bool timing,
+               void* stream, rka_info* info, rka_stats* stats) {
   g_last_error.clear();
   if (stats) memset(stats, 0, sizeof *stats);
   if (info) {
@@ -173,6 +173,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   if (v != RKA_OK) return v;
   if (check_every < 1) check_every = 1;
   if (grid < 0) return fail(RKA_EINVAL, "grid must be >= 0");
+  if (allreduce < 0 || allreduce > 2) return fail(RKA_EINVAL, "allreduce must be 0, 1 or 2");
   const int ncu = num_cus();
   if (ncu <= 0) return fail(RKA_EDEVICE, "no HIP device available");
   hipStream_t s = (hipStream_t)stream;
@@ -192,6 +193,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   sh.bs = block ? bs : 1;
   sh.num_cu = ncu;
   sh.grid = grid > ncu ? ncu : grid;
+  sh.allreduce = allreduce;
 
   rka::RkaColGeom cgeo{};
   rka::RkabGeom bgeo{};
@@ -215,7 +217,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   if (kc_max < 1) kc_max = 1;
   if (kc_max > max_iter) kc_max = max_iter > 0 ? max_iter : 1;
   const int G = use_col ? cgeo.G : bgeo.G;
-  size_t part_len = use_col ? (size_t)G * (q + 1) : (size_t)G;
+  size_t part_len = use_col ? (size_t)(cgeo.gather ? 2 : 1) * G * (q + 1) : (size_t)G;
   if (!sh.x_ref && tol > 0.0) {
     const size_t rb = (size_t)rka::resid_blocks(m);
     if (rb > part_len) part_len = rb;
@@ -327,7 +329,7 @@ int rka_solve(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const
               uint64_t seed, const double* x_ref, int64_t iter_offset, int64_t check_every,
               void* stream, rka_info* info) {
   return solve_impl(false, A, dtype, m, n, lda, b, x0, x, q, 1, alpha, max_iter, tol, seed, x_ref,
-                    iter_offset, check_every, 0, false, stream, info, nullptr);
+                    iter_offset, check_every, 0, 0, false, stream, info, nullptr);
 }
 
 int rka_solve_ex(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const double* b,
@@ -342,10 +344,11 @@ int rka_solve_ex(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, co
   }
   const int64_t ce = opts ? opts->check_every : 1;
   const int grid = opts ? opts->grid : 0;
+  const int allreduce = opts ? opts->allreduce : 0;
   const bool timing = opts ? opts->collect_timing != 0 : false;
   return solve_impl(method == 1, A, dtype, m, n, lda, b, x0, x, q, method == 1 ? block_size : 1,
-                    alpha, max_iter, tol, seed, x_ref, iter_offset, ce, grid, timing, stream, info,
-                    stats);
+                    alpha, max_iter, tol, seed, x_ref, iter_offset, ce, grid, allreduce, timing,
+                    stream, info, stats);
 }
 
 int rkab_solve(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const double* b,
@@ -353,7 +356,7 @@ int rkab_solve(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, cons
                int64_t max_iter, double tol, uint64_t seed, const double* x_ref,
                int64_t iter_offset, int64_t check_every, void* stream, rka_info* info) {
   return solve_impl(true, A, dtype, m, n, lda, b, x0, x, q, block_size, alpha, max_iter, tol, seed,
-                    x_ref, iter_offset, check_every, 0, false, stream, info, nullptr);
+                    x_ref, iter_offset, check_every, 0, 0, false, stream, info, nullptr);
 }
 
 int rka_row_norms(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, double* w,

@@ -32,6 +32,7 @@ struct RkaColGeom {
   int nt;      // threads per workgroup (multiple of 64)
   int rpt;     // rows per thread (template bucket)
   size_t lds;  // dynamic LDS bytes
+  int gather;  // one-barrier all-gather of the partials
 };
 
 struct SolveShape {
@@ -46,7 +47,8 @@ struct SolveShape {
   double alpha;
   int32_t q, bs;
   int num_cu;
-  int grid;  // requested workgroups of the iteration kernel (0 = automatic)
+  int grid;       // requested workgroups of the iteration kernel (0 = automatic)
+  int allreduce;  // RKA partial-dot exchange: 0 automatic, 1 all-gather, 2 two barriers
 };
 
 // Returns false when q rows of a slice do not fit the kernel's register tile.

@@ -36,8 +36,9 @@ struct RkaColArgs {
   const double* x_ref;
   double alpha, inv_q;
   int32_t q, nsv, rg, G;
+  int32_t gather;     // 1: one-barrier all-gather of the partials; 0: two barriers
   int64_t k0, K, check_every;
-  double* part;  // G x (q+1)
+  double* part;  // gather: 2 x G x (q+1) (by iteration parity); else G x (q+1)
   double* scal;  // q+1
   unsigned* bar;
   DevStatus* st;
@@ -51,12 +52,13 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
   if (p.st->done) return;
   const T* __restrict__ A = (const T*)p.A;
   const int t = threadIdx.x, g = blockIdx.x, NT = blockDim.x;
-  const int q = p.q, nsv = p.nsv, rg = p.rg;
+  const int q = p.q, nsv = p.nsv, rg = p.rg, G = p.G;
   const bool active = t < nsv * rg;
   const int j = active ? t % nsv : 0;
   const int rgi = active ? t / nsv : rg;
   const int64_t cv = (int64_t)g * nsv + j;
   const bool colv = active && cv < p.nvec;
+  const bool gather = G > 1 && p.gather;
 
   extern __shared__ double lds[];
   double* P = lds;                    // q * nsv      row partials per vec
@@ -65,6 +67,7 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
   double* E = XS + (size_t)nsv * V;   // nsv          error partials
   double* RED = E + nsv;              // 16           block_sum scratch
   double* SC = RED + 16;              // q + 1        dot totals, then scales
+  double* PG = SC + q + 1;            // G * (q+1)    gathered partials (gather only)
 
   double xv[V], xr[V];
 #pragma unroll
@@ -73,10 +76,11 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
     xr[e] = (colv && p.x_ref) ? p.x_ref[cv * V + e] : 0.0;
   }
 
-  // Row loads are unconditional (clamped to a valid row and vec; the surplus
-  // entries are masked in the arithmetic): a branch around a load would make
+  // Loads are unconditional (indices clamped to valid rows/vecs; the surplus
+  // entries are masked in the arithmetic): a load under a branch would make
   // the compiler drain every in-flight load where the branches join.
   const int64_t cvl = cv < p.nvec ? cv : p.nvec - 1;
+  const int tq = t < q ? t : q - 1;
   raw_t a[RPT], an[RPT];
   int rows[RPT], rows_n[RPT];
 #pragma unroll
@@ -85,6 +89,18 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
     rows[i] = (int)p.rec[r < q ? r : q - 1].row;
     a[i] = load_raw<T, V>(A + (int64_t)rows[i] * p.lda + cvl * V);
   }
+  // records needed one iteration ahead: the next rows (for the prefetch) and
+  // b_i, ||a_i||^2 of row t (used where a workgroup forms every scale itself:
+  // one workgroup, or the all-gather)
+  auto load_next = [&](int64_t kn, int64_t kc) {
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = rgi + rg * i;
+      rows_n[i] = (int)p.rec[kn * q + (r < q ? r : q - 1)].row;
+    }
+    return p.rec[kc * q + tq];
+  };
+  RowRec mine = load_next(p.K > 1 ? 1 : 0, 0);
 
   unsigned target = 0;
   int64_t kl = 0;
@@ -92,14 +108,8 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
   for (; kl < p.K; ++kl) {
     const int64_t k = p.k0 + kl;
     const bool check = p.check_every > 0 && k > 0 && (k % p.check_every) == 0;
-    // next iteration's rows (the last iteration of a chunk re-reads its own:
-    // unconditional loads keep the compiler from draining them at a join)
-    const int64_t kn = kl + 1 < p.K ? kl + 1 : kl;
-#pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-      const int r = rgi + rg * i;
-      rows_n[i] = (int)p.rec[kn * q + (r < q ? r : q - 1)].row;
-    }
+    const int nr = q + (check ? 1 : 0);
+    double* part = p.part + (gather ? (size_t)(kl & 1) * G * (q + 1) : 0);
     // partial dot products of this slice, one per (row, vec)
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
@@ -122,43 +132,58 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
     for (int r = t; r < q; r += NT) {
       double d = 0.0;
       for (int jj = 0; jj < nsv; ++jj) d += P[r * nsv + jj];
-      if (p.G > 1)
-        store_agent(&p.part[(size_t)g * (q + 1) + r], d);
+      if (G > 1)
+        store_agent(&part[(size_t)g * (q + 1) + r], d);
       else
         SC[r] = d;
     }
     if (check && t == 0) {
       double s = 0.0;
       for (int jj = 0; jj < nsv; ++jj) s += E[jj];
-      if (p.G > 1)
-        store_agent(&p.part[(size_t)g * (q + 1) + q], s);
+      if (G > 1)
+        store_agent(&part[(size_t)g * (q + 1) + q], s);
       else
         SC[q] = s;
     }
     // the partials must have landed before arriving; the next iteration's
     // rows (independent of x) are requested after that wait, so that they
     // stream in while the all-reduce below is in progress
-    if (p.G > 1) wait_memory();
+    if (G > 1) wait_memory();
 #pragma unroll
     for (int i = 0; i < RPT; ++i) an[i] = load_raw<T, V>(A + (int64_t)rows_n[i] * p.lda + cvl * V);
-    const int nr = q + (check ? 1 : 0);
-    if (p.G > 1) {
-      grid_arrive_wait(p.bar, target, (unsigned)p.G);
-      for (int r = g; r < nr; r += p.G) {
-        RowRec rr;
-        if (t == 0 && r < q) rr = p.rec[kl * q + r];  // in flight with the partials
-        double v = 0.0;
-        for (int gg = t; gg < p.G; gg += NT) v += load_agent(&p.part[(size_t)gg * (q + 1) + r]);
-        const double D = block_sum(v, RED);
-        if (t == 0) store_agent(&p.scal[r], r < q ? p.alpha * (rr.b - D) / rr.wn : D);
+    if (G > 1) {
+      grid_arrive_wait(p.bar, target, (unsigned)G);
+      if (gather) {
+        // every workgroup sums every row's partials in the same fixed order
+        for (int L = t; L < G * (q + 1); L += NT) PG[L] = load_agent(&part[L]);
+        __syncthreads();
+        for (int r = t; r < nr; r += NT) {
+          double D = 0.0;
+          for (int gg = 0; gg < G; ++gg) D += PG[gg * (q + 1) + r];
+          if (r < q) {
+            const RowRec rr = r == t ? mine : p.rec[kl * q + r];
+            SC[r] = p.alpha * (rr.b - D) / rr.wn;
+          } else {
+            SC[r] = D;
+          }
+        }
+      } else {
+        for (int r = g; r < nr; r += G) {
+          RowRec rr;
+          if (t == 0 && r < q) rr = p.rec[kl * q + r];  // in flight with the partials
+          double v = 0.0;
+          for (int gg = t; gg < G; gg += NT) v += load_agent(&part[(size_t)gg * (q + 1) + r]);
+          const double D = block_sum(v, RED);
+          if (t == 0) store_agent(&p.scal[r], r < q ? p.alpha * (rr.b - D) / rr.wn : D);
+        }
+        if (t == 0) wait_memory();
+        grid_arrive_wait(p.bar, target, (unsigned)G);
+        for (int r = t; r < nr; r += NT) SC[r] = load_agent(&p.scal[r]);
       }
-      if (t == 0) wait_memory();
-      grid_arrive_wait(p.bar, target, (unsigned)p.G);
-      for (int r = t; r < nr; r += NT) SC[r] = load_agent(&p.scal[r]);
     } else {
       __syncthreads();
       for (int r = t; r < q; r += NT) {
-        const RowRec rr = p.rec[kl * q + r];
+        const RowRec rr = r == t ? mine : p.rec[kl * q + r];
         SC[r] = p.alpha * (rr.b - SC[r]) / rr.wn;
       }
     }
@@ -213,6 +238,10 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
       a[i] = an[i];
       rows[i] = rows_n[i];
     }
+    // records for the iterations ahead (clamped at the chunk end)
+    const int64_t k2 = kl + 2 < p.K ? kl + 2 : p.K - 1;
+    const int64_t k1 = kl + 1 < p.K ? kl + 1 : p.K - 1;
+    mine = load_next(k2, k1);
   }
   if (colv && rgi == 0) {
 #pragma unroll
@@ -231,15 +260,25 @@ static int rpt_bucket(int need) {
   return 0;
 }
 
+// Column slices per workgroup: enough workgroups to stream the q rows of an
+// iteration at full bandwidth (about 40 KB of row data per workgroup per
+// iteration), but no more -- every extra workgroup lengthens the barrier.
+constexpr int64_t kColBytesPerGroup = 40 << 10;
+// one-barrier all-gather while every workgroup reads at most this many partials
+constexpr int kGatherMax = 4608;
+
 bool rka_col_plan(const SolveShape& sh, RkaColGeom* geo) {
   const int esz = sh.dtype == 0 ? 8 : (sh.dtype == 1 ? 4 : 2);
   const int V = sh.vec_ok ? 16 / esz : 1;
   const int64_t nvec = sh.n / V;
   const int64_t bytes_per_iter = (int64_t)sh.q * sh.n * esz;
   int G, nsv;
-  const int target = sh.grid > 0 ? sh.grid : sh.num_cu;
-  const bool small = sh.grid == 0 && bytes_per_iter <= (64 << 10);
-  if ((small || target == 1) && nvec <= kMaxColThreads) {
+  int target = sh.grid > 0 ? sh.grid : sh.num_cu;
+  if (sh.grid == 0) {
+    const int64_t want = (bytes_per_iter + kColBytesPerGroup - 1) / kColBytesPerGroup;
+    if (want < target) target = (int)(want < 1 ? 1 : want);
+  }
+  if (target == 1 && nvec <= kMaxColThreads) {
     G = 1;
     nsv = (int)nvec;
   } else {
@@ -253,11 +292,20 @@ bool rka_col_plan(const SolveShape& sh, RkaColGeom* geo) {
   if (rg < 1) rg = 1;
   const int rpt = rpt_bucket((sh.q + rg - 1) / rg);
   if (rpt == 0) return false;
-  if (rpt == 16) return false;  // would spill; wider q runs on the worker kernel
-  if (rpt == 12 && sh.vec_ok && sh.dtype == 2) return false;
+  // largest spill-free bucket per storage type; wider q runs on the worker kernel
+  const int rpt_max = !sh.vec_ok ? 12 : (sh.dtype == 0 ? 12 : (sh.dtype == 1 ? 8 : 4));
+  if (rpt > rpt_max) return false;
   const int nt = ((nsv * rg + kWave - 1) / kWave) * kWave;
-  const size_t lds =
-      sizeof(double) * ((size_t)sh.q * nsv + (size_t)nt * V + (size_t)nsv * V + nsv + 16 + sh.q + 1);
+  int gather = 0;
+  if (G > 1) {
+    if (sh.allreduce == 1)
+      gather = 1;
+    else if (sh.allreduce == 0)
+      gather = (int64_t)G * (sh.q + 1) <= kGatherMax;
+  }
+  const size_t pg = gather ? (size_t)G * (sh.q + 1) : 0;
+  const size_t lds = sizeof(double) * ((size_t)sh.q * nsv + (size_t)nt * V + (size_t)nsv * V +
+                                       nsv + 16 + sh.q + 1 + pg);
   if (lds > 64 * 1024) return false;
   geo->G = G;
   geo->nsv = nsv;
@@ -265,6 +313,7 @@ bool rka_col_plan(const SolveShape& sh, RkaColGeom* geo) {
   geo->nt = nt;
   geo->rpt = rpt;
   geo->lds = lds;
+  geo->gather = gather;
   return true;
 }
 
@@ -301,6 +350,7 @@ hipError_t launch_rka_chunk(const SolveShape& sh, const RkaColGeom& geo, const R
   a.nsv = geo.nsv;
   a.rg = geo.rg;
   a.G = geo.G;
+  a.gather = geo.gather;
   a.k0 = k0;
   a.K = K;
   a.check_every = check_every;

@@ -116,7 +116,7 @@ RKA_CASES = [
     (700, 47, "f64", 8, 60, 1.3),       # odd n: scalar path
     (2000, 1000, "f64", 16, 40, 1.0),   # grid of column slices, 1 row per thread
     (3000, 1024, "f64", 64, 25, 2.0),   # 4 rows per thread
-    (3000, 1536, "f64", 256, 10, 1.0),  # 16 rows per thread
+    (3000, 1536, "f64", 256, 10, 1.0),  # two-barrier exchange
     (2500, 999, "f64", 24, 30, 1.0),    # grid, scalar path, ragged last slice
     (1500, 400, "f32", 16, 40, 1.0),
     (1500, 640, "bf16", 12, 40, 1.0),
@@ -160,6 +160,23 @@ def test_rkab_parity(m, n, dtype, q, bs, K, alpha):
     assert info.status == rka.OK and info.iterations == K
     assert info.projections == K * q * bs
     assert_x_close(host(x), xo, what=f"rkab {m}x{n} q={q} bs={bs}")
+
+
+@pytest.mark.parametrize("q,grid,allreduce", [
+    (16, 0, 1), (16, 0, 2), (16, 7, 1), (16, 64, 2), (64, 40, 1), (64, 0, 2), (100, 16, 1),
+    (200, 20, 2), (5, 2, 0),
+])
+def test_rka_allreduce_modes_and_grids(q, grid, allreduce):
+    """Every exchange mode and launch geometry reaches the oracle's iterate."""
+    say(f"rka modes q={q} grid={grid} allreduce={allreduce}")
+    A, _, b = _system(2500, 1200, seed=q + grid)
+    x, info, st = rka.solve_ex(to_dev(A), vec(b), method=0, q=q, max_iter=30, seed=9,
+                               grid=grid, allreduce=allreduce)
+    xo, _ = oracle.rka(A, b, q=q, max_iter=30, seed=9)
+    assert info.status == rka.OK and st["kernel"] == 1
+    if grid:
+        assert st["grid"] <= grid
+    assert_x_close(host(x), xo, what=f"rka q={q} grid={grid} mode={allreduce}")
 
 
 def test_rka_wide_q_falls_back_to_worker_kernel():
