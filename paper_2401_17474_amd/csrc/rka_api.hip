@@ -208,7 +208,8 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
 
   Scratch sc(s);
   rka::DevStatus* st;
-  double *w, *c, *part, *scal = nullptr, *vbuf = nullptr;
+  double *w, *c, *part, *vbuf = nullptr;
+  uint64_t *slots = nullptr, *sslots = nullptr;  // tagged exchange slots (column kernel)
   int64_t* last_pos;
   rka::RowRec* rec;
   unsigned* bar;
@@ -217,7 +218,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   if (kc_max < 1) kc_max = 1;
   if (kc_max > max_iter) kc_max = max_iter > 0 ? max_iter : 1;
   const int G = use_col ? cgeo.G : bgeo.G;
-  size_t part_len = use_col ? (size_t)(cgeo.gather ? 2 : 1) * G * (q + 1) : (size_t)G;
+  size_t part_len = (size_t)G;
   if (!sh.x_ref && tol > 0.0) {
     const size_t rb = (size_t)rka::resid_blocks(m);
     if (rb > part_len) part_len = rb;
@@ -229,13 +230,23 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   HIP_TRY(sc.get(&rec, (size_t)(kc_max * per_iter)));
   HIP_TRY(sc.get(&part, part_len));
   HIP_TRY(sc.get(&bar, 1));
-  if (use_col)
-    HIP_TRY(sc.get(&scal, (size_t)q + 1));
-  else
+  size_t nslots = 0, nsslots = 0;
+  if (use_col) {
+    // 16-byte slots: 2 words each
+    nslots = (size_t)(cgeo.gather ? 2 : 1) * G * (q + 1);
+    nsslots = (size_t)q + 1;
+    HIP_TRY(sc.get(&slots, 2 * nslots));
+    HIP_TRY(sc.get(&sslots, 2 * nsslots));
+  } else {
     HIP_TRY(sc.get(&vbuf, (size_t)q * (size_t)n));
+  }
   sh.wn = w;
 
   PhaseTimer tm(s, timing && stats);
+  if (use_col) {  // tag 0 never matches: slots start empty for the whole solve
+    HIP_TRY(hipMemsetAsync(slots, 0, 16 * nslots, s));
+    HIP_TRY(hipMemsetAsync(sslots, 0, 16 * nsslots, s));
+  }
   HIP_TRY(rka::launch_status_init(st, tol, s));
   HIP_TRY(rka::launch_check_finite(b, m, st, s));
   tm.begin(kNorms);
@@ -270,7 +281,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
     tm.end();
     tm.begin(kIterate);
     if (use_col)
-      HIP_TRY(rka::launch_rka_chunk(sh, cgeo, rec, k, kc, in_kernel_check, part, scal, bar, st, s));
+      HIP_TRY(rka::launch_rka_chunk(sh, cgeo, rec, k, kc, in_kernel_check, slots, sslots, st, s));
     else
       HIP_TRY(rka::launch_rkab_chunk(sh, bgeo, rec, k, kc, in_kernel_check, vbuf, part, bar, st, s));
     tm.end();
@@ -311,6 +322,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   if (status == RKA_EZERONORM) fail(status, "||A||_F^2 is zero or not finite");
   if (status == RKA_EINVAL) fail(status, "b has a non-finite entry");
   if (status == RKA_EDIVERGED) fail(status, "the stopping measure became non-finite");
+  if (status == RKA_EDEVICE) fail(status, "a grid-wide wait inside a kernel gave up");
   if (info) {
     info->iterations = hst.iterations;
     info->projections = hst.iterations * per_iter;

@@ -145,6 +145,44 @@ struct CoherentBuf {
   }
 };
 
+// Tagged exchange slots: a double travels as two 64-bit words, each holding
+// 32 payload bits and a 32-bit tag (the iteration it belongs to).  A word is
+// written with one aligned 8-byte device-coherent store, which lands
+// whole, so a reader that sees both tags equal to the expected one has the
+// value -- no separate flag, counter or store acknowledgement is needed.
+// Slots start zeroed (tag 0 never matches: tags are iteration + 1).
+struct TagSlots {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ TagSlots(uint64_t* base, int64_t nslots)
+      : r(__builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)(nslots * 16), kRawBufferWord3)) {}
+  __device__ __forceinline__ void put(int64_t i, double v, uint32_t tag) const {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint64_t lo = ((uint64_t)tag << 32) | (b & 0xffffffffull);
+    const uint64_t hi = ((uint64_t)tag << 32) | (b >> 32);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, lo), r, (int)(i * 16), 0,
+                                          kCoherentSC1);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, hi), r, (int)(i * 16 + 8), 0,
+                                          kCoherentSC1);
+  }
+  __device__ __forceinline__ void fetch(int64_t i, uint64_t& lo, uint64_t& hi) const {
+    lo = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(r, (int)(i * 16), 0,
+                                                                          kCoherentSC1));
+    hi = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(r, (int)(i * 16 + 8), 0,
+                                                                          kCoherentSC1));
+  }
+  static __device__ __forceinline__ bool decode(uint64_t lo, uint64_t hi, uint32_t tag, double& v) {
+    if ((uint32_t)(lo >> 32) != tag || (uint32_t)(hi >> 32) != tag) return false;
+    v = __builtin_bit_cast(double, ((hi & 0xffffffffull) << 32) | (lo & 0xffffffffull));
+    return true;
+  }
+};
+
+// Upper bound on polling rounds of any wait (each round sleeps ~64 clocks):
+// a wait that exceeds it records kStatusTimeout and the kernel winds down
+// instead of hanging.
+constexpr unsigned kSpinLimit = 1u << 22;
+constexpr int kStatusTimeout = -5;  // reported as RKA_EDEVICE
+
 // One sampled row as the iteration kernels consume it: the sampler writes
 // the right-hand side entry and squared norm next to the index, so that a
 // kernel gets all three with one 32-byte read.
@@ -173,26 +211,31 @@ __device__ __forceinline__ void wait_memory() {
 // write-back or invalidate is needed (those cost ~40 us per barrier at 256
 // workgroups on MI355X; this barrier costs ~4 us).  `ctr` is zeroed before
 // the launch; `target` advances identically in every workgroup.
-__device__ __forceinline__ void grid_arrive_wait(unsigned* ctr, unsigned& target,
+// Returns false (in every thread of the workgroup) if the wait gave up.
+__device__ __forceinline__ bool grid_arrive_wait(unsigned* ctr, unsigned& target,
                                                  unsigned nblocks) {
+  __shared__ int timed_out;
   target += nblocks;
   __syncthreads();
   if (threadIdx.x == 0) {
     __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target)
+    unsigned spins = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target &&
+           ++spins < kSpinLimit)
       __builtin_amdgcn_s_sleep(1);
+    timed_out = spins >= kSpinLimit;
   }
   __syncthreads();
+  return !timed_out;
 }
 
 // All workgroups of the grid (one workgroup: a block barrier), for callers
 // that have nothing to overlap with the wait.
-__device__ __forceinline__ void sync_grid(unsigned* ctr, unsigned& target, unsigned nblocks) {
+__device__ __forceinline__ bool sync_grid(unsigned* ctr, unsigned& target, unsigned nblocks) {
   wait_memory();
-  if (nblocks > 1)
-    grid_arrive_wait(ctr, target, nblocks);
-  else
-    __syncthreads();
+  if (nblocks > 1) return grid_arrive_wait(ctr, target, nblocks);
+  __syncthreads();
+  return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -207,5 +250,11 @@ struct DevStatus {
   double thresh2;      // tol^2 * ref2
   int64_t last_pos;    // largest row with a positive weight
 };
+
+// Record that a wait gave up (the solve then reports RKA_EDEVICE).
+__device__ __forceinline__ void note_timeout(DevStatus* st) {
+  __hip_atomic_store(&st->status, kStatusTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&st->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 }  // namespace rka

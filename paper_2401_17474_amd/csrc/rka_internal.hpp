@@ -56,9 +56,11 @@ bool rka_col_plan(const SolveShape& sh, RkaColGeom* geo);
 
 // One chunk of iterations [k0, k0 + K) with row records rec[K*q*bs].
 // check_every = 0 disables the in-kernel stopping test (x_ref mode only).
+// part / scal: tagged exchange slots (16 bytes each), zeroed once per solve;
+// rka_col_slots() gives how many.
 hipError_t launch_rka_chunk(const SolveShape& sh, const RkaColGeom& geo, const RowRec* rec,
-                            int64_t k0, int64_t K, int64_t check_every, double* part,
-                            double* scal, unsigned* bar, DevStatus* st, hipStream_t s);
+                            int64_t k0, int64_t K, int64_t check_every, uint64_t* part,
+                            uint64_t* scal, DevStatus* st, hipStream_t s);
 
 struct RkabGeom {
   int G;       // workgroups (each runs workers g, g + G, ...)

@@ -38,15 +38,16 @@ struct RkaColArgs {
   int32_t q, nsv, rg, G;
   int32_t gather;     // 1: one-barrier all-gather of the partials; 0: two barriers
   int64_t k0, K, check_every;
-  double* part;  // gather: 2 x G x (q+1) (by iteration parity); else G x (q+1)
-  double* scal;  // q+1
-  unsigned* bar;
+  uint64_t* part;  // tagged slots: gather 2 x G x (q+1) (by iteration parity); else G x (q+1)
+  uint64_t* scal;  // tagged slots: q+1 scales (two-phase exchange)
   DevStatus* st;
 };
 
+constexpr int kPollMax = 4;  // tagged slots one thread polls per exchange
+
 constexpr int kMaxColThreads = 512;
 
-template <typename T, int V, int RPT>
+template <typename T, int V, int RPT, bool GATHER>
 __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
   using raw_t = typename Vec<T, V>::raw_t;
   if (p.st->done) return;
@@ -58,7 +59,7 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
   const int rgi = active ? t / nsv : rg;
   const int64_t cv = (int64_t)g * nsv + j;
   const bool colv = active && cv < p.nvec;
-  const bool gather = G > 1 && p.gather;
+  const bool gather = GATHER && G > 1;
 
   extern __shared__ double lds[];
   double* P = lds;                    // q * nsv      row partials per vec
@@ -69,12 +70,9 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
   double* SC = RED + 16;              // q + 1        dot totals, then scales
   double* PG = SC + q + 1;            // G * (q+1)    gathered partials (gather only)
 
-  double xv[V], xr[V];
+  double xv[V];
 #pragma unroll
-  for (int e = 0; e < V; ++e) {
-    xv[e] = colv ? p.x[cv * V + e] : 0.0;
-    xr[e] = (colv && p.x_ref) ? p.x_ref[cv * V + e] : 0.0;
-  }
+  for (int e = 0; e < V; ++e) xv[e] = colv ? p.x[cv * V + e] : 0.0;
 
   // Loads are unconditional (indices clamped to valid rows/vecs; the surplus
   // entries are masked in the arithmetic): a load under a branch would make
@@ -92,24 +90,27 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
   // records needed one iteration ahead: the next rows (for the prefetch) and
   // b_i, ||a_i||^2 of row t (used where a workgroup forms every scale itself:
   // one workgroup, or the all-gather)
+  double mine_b, mine_w;
   auto load_next = [&](int64_t kn, int64_t kc) {
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int r = rgi + rg * i;
       rows_n[i] = (int)p.rec[kn * q + (r < q ? r : q - 1)].row;
     }
-    return p.rec[kc * q + tq];
+    mine_b = p.rec[kc * q + tq].b;
+    mine_w = p.rec[kc * q + tq].wn;
   };
-  RowRec mine = load_next(p.K > 1 ? 1 : 0, 0);
+  load_next(p.K > 1 ? 1 : 0, 0);
 
-  unsigned target = 0;
   int64_t kl = 0;
   bool stopped = false;
   for (; kl < p.K; ++kl) {
     const int64_t k = p.k0 + kl;
     const bool check = p.check_every > 0 && k > 0 && (k % p.check_every) == 0;
     const int nr = q + (check ? 1 : 0);
-    double* part = p.part + (gather ? (size_t)(kl & 1) * G * (q + 1) : 0);
+    const uint32_t tag = (uint32_t)(k + 1);
+    const TagSlots part(p.part + (gather ? (size_t)(kl & 1) * G * (q + 1) * 2 : 0),
+                        (int64_t)G * (q + 1));
     // partial dot products of this slice, one per (row, vec)
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
@@ -120,11 +121,15 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
       if (active && r < q) P[r * nsv + j] = s;
     }
     if (check && active && rgi == 0) {
+      // x_ref is read here, before this iteration's prefetch is issued, so
+      // waiting for it cannot drain the prefetch
       double s = 0.0;
+      if (colv) {
 #pragma unroll
-      for (int e = 0; e < V; ++e) {
-        const double d = xv[e] - xr[e];
-        s = fma(d, d, s);
+        for (int e = 0; e < V; ++e) {
+          const double d = xv[e] - p.x_ref[cv * V + e];
+          s = fma(d, d, s);
+        }
       }
       E[j] = s;
     }
@@ -133,7 +138,7 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
       double d = 0.0;
       for (int jj = 0; jj < nsv; ++jj) d += P[r * nsv + jj];
       if (G > 1)
-        store_agent(&part[(size_t)g * (q + 1) + r], d);
+        part.put((int64_t)g * (q + 1) + r, d, tag);
       else
         SC[r] = d;
     }
@@ -141,50 +146,127 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
       double s = 0.0;
       for (int jj = 0; jj < nsv; ++jj) s += E[jj];
       if (G > 1)
-        store_agent(&part[(size_t)g * (q + 1) + q], s);
+        part.put((int64_t)g * (q + 1) + q, s, tag);
       else
         SC[q] = s;
     }
-    // the partials must have landed before arriving; the next iteration's
-    // rows (independent of x) are requested after that wait, so that they
-    // stream in while the all-reduce below is in progress
-    if (G > 1) wait_memory();
+    // the next iteration's rows (independent of x) are requested now, so that
+    // they stream in while the exchange below is in progress
 #pragma unroll
     for (int i = 0; i < RPT; ++i) an[i] = load_raw<T, V>(A + (int64_t)rows_n[i] * p.lda + cvl * V);
+    bool ok = true;
     if (G > 1) {
-      grid_arrive_wait(p.bar, target, (unsigned)G);
-      if (gather) {
-        // every workgroup sums every row's partials in the same fixed order
-        for (int L = t; L < G * (q + 1); L += NT) PG[L] = load_agent(&part[L]);
-        __syncthreads();
+      if constexpr (GATHER) {
+        // every workgroup polls every row's partials and sums them in the
+        // same fixed order (slot L = gg * nr + r of this thread's share)
+        const int total = G * nr;
+        bool have[kPollMax];
+#pragma unroll
+        for (int u = 0; u < kPollMax; ++u) have[u] = t + NT * u >= total;
+        for (unsigned spins = 0;; ++spins) {
+          uint64_t lo[kPollMax], hi[kPollMax];
+#pragma unroll
+          for (int u = 0; u < kPollMax; ++u) {
+            const int L = t + NT * u < total ? t + NT * u : total - 1;
+            part.fetch((int64_t)(L / nr) * (q + 1) + L % nr, lo[u], hi[u]);
+          }
+          bool all = true;
+#pragma unroll
+          for (int u = 0; u < kPollMax; ++u) {
+            double v;
+            if (!have[u] && TagSlots::decode(lo[u], hi[u], tag, v)) {
+              const int L = t + NT * u;
+              PG[(L / nr) * (q + 1) + L % nr] = v;
+              have[u] = true;
+            }
+            all = all && have[u];
+          }
+          if (__syncthreads_and(all)) break;
+          if (spins >= kSpinLimit) {
+            ok = false;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
         for (int r = t; r < nr; r += NT) {
           double D = 0.0;
           for (int gg = 0; gg < G; ++gg) D += PG[gg * (q + 1) + r];
           if (r < q) {
-            const RowRec rr = r == t ? mine : p.rec[kl * q + r];
-            SC[r] = p.alpha * (rr.b - D) / rr.wn;
+            const double rb = r == t ? mine_b : p.rec[kl * q + r].b;
+            const double rw = r == t ? mine_w : p.rec[kl * q + r].wn;
+            SC[r] = p.alpha * (rb - D) / rw;
           } else {
             SC[r] = D;
           }
         }
-      } else {
+      } else if constexpr (!GATHER) {
+        // phase 1: workgroup g sums the partials of rows g, g + G, ...
+        const TagSlots scal(p.scal, q + 1);
         for (int r = g; r < nr; r += G) {
           RowRec rr;
-          if (t == 0 && r < q) rr = p.rec[kl * q + r];  // in flight with the partials
+          if (t == 0 && r < q) rr = p.rec[kl * q + r];  // in flight with the polls
           double v = 0.0;
-          for (int gg = t; gg < G; gg += NT) v += load_agent(&part[(size_t)gg * (q + 1) + r]);
+          bool have = t >= G;
+          for (unsigned spins = 0;; ++spins) {
+            uint64_t lo, hi;
+            part.fetch((int64_t)(t < G ? t : G - 1) * (q + 1) + r, lo, hi);
+            double pv;
+            if (!have && TagSlots::decode(lo, hi, tag, pv)) {
+              v = pv;
+              have = true;
+            }
+            if (__syncthreads_and(have)) break;
+            if (spins >= kSpinLimit) {
+              ok = false;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+          }
+          for (int gg = t + NT; gg < G; gg += NT) {  // only when G > NT
+            uint64_t lo, hi;
+            double pv = 0.0;
+            for (unsigned spins = 0; spins < kSpinLimit; ++spins) {
+              part.fetch((int64_t)gg * (q + 1) + r, lo, hi);
+              if (TagSlots::decode(lo, hi, tag, pv)) break;
+            }
+            v += pv;
+          }
           const double D = block_sum(v, RED);
-          if (t == 0) store_agent(&p.scal[r], r < q ? p.alpha * (rr.b - D) / rr.wn : D);
+          if (t == 0) scal.put(r, r < q ? p.alpha * (rr.b - D) / rr.wn : D, tag);
         }
-        if (t == 0) wait_memory();
-        grid_arrive_wait(p.bar, target, (unsigned)G);
-        for (int r = t; r < nr; r += NT) SC[r] = load_agent(&p.scal[r]);
+        // phase 2: every workgroup polls the q scales (one slot per thread
+        // per round; one round unless q + 1 exceeds the thread count)
+        for (int L0 = 0; L0 < nr && ok; L0 += NT) {
+          const int L = L0 + t;
+          bool have = L >= nr;
+          for (unsigned spins = 0;; ++spins) {
+            uint64_t lo, hi;
+            scal.fetch(L < nr ? L : nr - 1, lo, hi);
+            double v;
+            if (!have && TagSlots::decode(lo, hi, tag, v)) {
+              SC[L] = v;
+              have = true;
+            }
+            if (__syncthreads_and(have)) break;
+            if (spins >= kSpinLimit) {
+              ok = false;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+          }
+        }
+      }
+      if (!__syncthreads_and(ok)) {
+        if (t == 0) note_timeout(p.st);
+        stopped = true;
+        break;
       }
     } else {
       __syncthreads();
       for (int r = t; r < q; r += NT) {
-        const RowRec rr = r == t ? mine : p.rec[kl * q + r];
-        SC[r] = p.alpha * (rr.b - SC[r]) / rr.wn;
+        const double rb = r == t ? mine_b : p.rec[kl * q + r].b;
+        const double rw = r == t ? mine_w : p.rec[kl * q + r].wn;
+        SC[r] = p.alpha * (rb - SC[r]) / rw;
       }
     }
     __syncthreads();
@@ -241,7 +323,7 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
     // records for the iterations ahead (clamped at the chunk end)
     const int64_t k2 = kl + 2 < p.K ? kl + 2 : p.K - 1;
     const int64_t k1 = kl + 1 < p.K ? kl + 1 : p.K - 1;
-    mine = load_next(k2, k1);
+    load_next(k2, k1);
   }
   if (colv && rgi == 0) {
 #pragma unroll
@@ -255,7 +337,7 @@ static int rpt_bucket(int need) {
   if (need <= 2) return 2;
   if (need <= 4) return 4;
   if (need <= 8) return 8;
-  if (need <= 12) return 12;
+  if (need <= 11) return 11;
   if (need <= 16) return 16;
   return 0;
 }
@@ -293,15 +375,23 @@ bool rka_col_plan(const SolveShape& sh, RkaColGeom* geo) {
   const int rpt = rpt_bucket((sh.q + rg - 1) / rg);
   if (rpt == 0) return false;
   // largest spill-free bucket per storage type; wider q runs on the worker kernel
-  const int rpt_max = !sh.vec_ok ? 12 : (sh.dtype == 0 ? 12 : (sh.dtype == 1 ? 8 : 4));
+  const int rpt_max = !sh.vec_ok ? 11 : (sh.dtype == 0 ? 11 : 4);
   if (rpt > rpt_max) return false;
   const int nt = ((nsv * rg + kWave - 1) / kWave) * kWave;
   int gather = 0;
   if (G > 1) {
-    if (sh.allreduce == 1)
+    const bool fits = (int64_t)G * (sh.q + 1) <= (int64_t)kPollMax * nt;
+    if (sh.allreduce == 1) {
+      if (!fits) return false;
       gather = 1;
-    else if (sh.allreduce == 0)
-      gather = (int64_t)G * (sh.q + 1) <= kGatherMax;
+    } else if (sh.allreduce == 0) {
+      gather = fits && (int64_t)G * (sh.q + 1) <= kGatherMax;
+    }
+    if (gather && rpt == 11) {
+      if (sh.allreduce == 1) return false;
+      gather = 0;
+    }
+    if (!gather && sh.q + 1 > kPollMax * nt) return false;
   }
   const size_t pg = gather ? (size_t)G * (sh.q + 1) : 0;
   const size_t lds = sizeof(double) * ((size_t)sh.q * nsv + (size_t)nt * V + (size_t)nsv * V +
@@ -317,24 +407,28 @@ bool rka_col_plan(const SolveShape& sh, RkaColGeom* geo) {
   return true;
 }
 
+template <typename T, int V, bool GATHER>
+static const void* col_fn(int rpt) {
+  switch (rpt) {
+    case 1: return (const void*)rka_col_kernel<T, V, 1, GATHER>;
+    case 2: return (const void*)rka_col_kernel<T, V, 2, GATHER>;
+    case 4: return (const void*)rka_col_kernel<T, V, 4, GATHER>;
+    default: return (const void*)rka_col_kernel<T, V, 8, GATHER>;
+  }
+}
+
 template <typename T, int V>
 static hipError_t launch_col_t(const RkaColGeom& geo, RkaColArgs& a, hipStream_t s) {
   void* args[] = {&a};
-  const void* fn = nullptr;
-  switch (geo.rpt) {
-    case 1: fn = (const void*)rka_col_kernel<T, V, 1>; break;
-    case 2: fn = (const void*)rka_col_kernel<T, V, 2>; break;
-    case 4: fn = (const void*)rka_col_kernel<T, V, 4>; break;
-    case 8: fn = (const void*)rka_col_kernel<T, V, 8>; break;
-    case 12: fn = (const void*)rka_col_kernel<T, V, 12>; break;
-    default: fn = (const void*)rka_col_kernel<T, V, 12>; break;
-  }
+  const void* fn = geo.rpt == 11 ? (const void*)rka_col_kernel<T, V, 11, false>
+                   : geo.gather  ? col_fn<T, V, true>(geo.rpt)
+                                 : col_fn<T, V, false>(geo.rpt);
   return hipLaunchCooperativeKernel(fn, dim3(geo.G), dim3(geo.nt), args, (unsigned)geo.lds, s);
 }
 
 hipError_t launch_rka_chunk(const SolveShape& sh, const RkaColGeom& geo, const RowRec* rec,
-                            int64_t k0, int64_t K, int64_t check_every, double* part,
-                            double* scal, unsigned* bar, DevStatus* st, hipStream_t s) {
+                            int64_t k0, int64_t K, int64_t check_every, uint64_t* part,
+                            uint64_t* scal, DevStatus* st, hipStream_t s) {
   const int esz = sh.dtype == 0 ? 8 : (sh.dtype == 1 ? 4 : 2);
   const int V = sh.vec_ok ? 16 / esz : 1;
   RkaColArgs a;
@@ -356,12 +450,7 @@ hipError_t launch_rka_chunk(const SolveShape& sh, const RkaColGeom& geo, const R
   a.check_every = check_every;
   a.part = part;
   a.scal = scal;
-  a.bar = bar;
   a.st = st;
-  if (geo.G > 1) {
-    hipError_t e = hipMemsetAsync(bar, 0, sizeof(unsigned), s);
-    if (e != hipSuccess) return e;
-  }
   switch (sh.dtype) {
     case 0: return sh.vec_ok ? launch_col_t<double, 2>(geo, a, s) : launch_col_t<double, 1>(geo, a, s);
     case 1: return sh.vec_ok ? launch_col_t<float, 4>(geo, a, s) : launch_col_t<float, 1>(geo, a, s);

@@ -176,7 +176,11 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
       __syncthreads();  // the staged records are reused by the next worker
     }
     // x^(k+1) = (1/q) sum_w v_w, column slices, fixed worker order
-    sync_grid(p.bar, target, (unsigned)p.G);
+    if (!sync_grid(p.bar, target, (unsigned)p.G)) {
+      if (t == 0) note_timeout(p.st);
+      stopped = true;
+      break;
+    }
     const bool check = p.check_every > 0 && ((k + 1) % p.check_every) == 0;
     const int64_t e0 = (int64_t)g * p.ns * V;
     const int64_t e1 = ((int64_t)(g + 1) * p.ns * V < n) ? (int64_t)(g + 1) * p.ns * V : n;
@@ -203,7 +207,11 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
       const double s = block_sum(err, RED);
       if (t == 0) store_agent(&p.part[g], s);
     }
-    sync_grid(p.bar, target, (unsigned)p.G);
+    if (!sync_grid(p.bar, target, (unsigned)p.G)) {
+      if (t == 0) note_timeout(p.st);
+      stopped = true;
+      break;
+    }
     if (check) {
       double e2 = 0.0;
       for (int gg = 0; gg < p.G; ++gg) e2 += load_agent(&p.part[gg]);
