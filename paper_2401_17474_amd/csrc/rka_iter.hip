@@ -347,7 +347,7 @@ static int rpt_bucket(int need) {
 // iteration), but no more -- every extra workgroup lengthens the barrier.
 constexpr int64_t kColBytesPerGroup = 40 << 10;
 // one-barrier all-gather while every workgroup reads at most this many partials
-constexpr int kGatherMax = 4608;
+constexpr int kGatherMax = 2048;
 
 bool rka_col_plan(const SolveShape& sh, RkaColGeom* geo) {
   const int esz = sh.dtype == 0 ? 8 : (sh.dtype == 1 ? 4 : 2);
