@@ -342,10 +342,13 @@ static int rpt_bucket(int need) {
   return 0;
 }
 
-// Column slices per workgroup: enough workgroups to stream the q rows of an
-// iteration at full bandwidth (about 40 KB of row data per workgroup per
-// iteration), but no more -- every extra workgroup lengthens the barrier.
-constexpr int64_t kColBytesPerGroup = 40 << 10;
+// Column slices: one workgroup per CU by default.  Measured on MI355X at
+// 80000 x 10000 FP64, the widest grid is fastest for every q (16, 64, 256):
+// the per-iteration critical path is dominated by the in-workgroup reductions
+// (which shrink with the slice) and the exchange latency, not by the number
+// of participants.  Tiny problems (<= 64 KB of rows per iteration, one slice
+// that fits a workgroup) run in one workgroup with no exchange at all.
+constexpr int64_t kOneGroupBytes = 64 << 10;
 // one-barrier all-gather while every workgroup reads at most this many partials
 constexpr int kGatherMax = 2048;
 
@@ -356,10 +359,7 @@ bool rka_col_plan(const SolveShape& sh, RkaColGeom* geo) {
   const int64_t bytes_per_iter = (int64_t)sh.q * sh.n * esz;
   int G, nsv;
   int target = sh.grid > 0 ? sh.grid : sh.num_cu;
-  if (sh.grid == 0) {
-    const int64_t want = (bytes_per_iter + kColBytesPerGroup - 1) / kColBytesPerGroup;
-    if (want < target) target = (int)(want < 1 ? 1 : want);
-  }
+  if (sh.grid == 0 && bytes_per_iter <= kOneGroupBytes) target = 1;
   if (target == 1 && nvec <= kMaxColThreads) {
     G = 1;
     nsv = (int)nvec;

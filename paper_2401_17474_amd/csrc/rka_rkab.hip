@@ -58,6 +58,7 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
   __shared__ double RED[NT / kWave];
   __shared__ double Lb[2 * kStage], Lw[2 * kStage];
   __shared__ int64_t Lr[2 * kStage];
+  __shared__ double AV[NT];  // partial sums of the average
   extern __shared__ double vlds[];
 
   double vreg[VLDS ? 1 : VPT][V];
@@ -121,10 +122,25 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
   bool stopped = false;
   int64_t kl = 0;
   const int bs = p.bs;
+  // Priming a worker: stage its first record blocks in LDS, then request its
+  // first two rows.  The next worker of a workgroup (in this iteration or the
+  // next) is primed before the current one publishes v and before the grid
+  // barrier, so its rows stream in while the barrier and the average run.
+  auto stage_first = [&](int64_t kp, int wp) {
+    wrec = p.rec + (kp * p.q + wp) * (int64_t)bs;
+    stage(0, bs);
+    if (bs > kStage) stage(1, bs);
+    __syncthreads();
+  };
+  auto issue_first = [&]() {
+    load_row(B0, 0);
+    load_row(B1, bs > 1 ? 1 : 0);  // unconditional (see load_row)
+  };
+  stage_first(0, g);
+  issue_first();
   for (; kl < p.K; ++kl) {
     const int64_t k = p.k0 + kl;
     for (int w = g; w < p.q; w += p.G) {
-      wrec = p.rec + (kl * p.q + w) * (int64_t)bs;
       // v = x^(k) (coherent: x was written by other workgroups; 0 past the end)
 #pragma unroll
       for (int i = 0; i < VPT; ++i) {
@@ -132,10 +148,7 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
 #pragma unroll
         for (int e = 0; e < V; ++e) vat(i, e) = xb.load(c * V + e);
       }
-      stage(0, bs);
-      if (bs > kStage) stage(1, bs);
       int next_blk = 2;
-      __syncthreads();
       // block b goes into the slot of block b-2 once rows of block b-1 are
       // being projected; the ring looks at most four rows ahead
       auto restage = [&](int jj) {
@@ -146,8 +159,6 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
           ++next_blk;
         }
       };
-      load_row(B0, 0);
-      load_row(B1, bs > 1 ? 1 : 0);  // unconditional (see load_row)
       int jj = 0;
       for (; jj + 5 <= bs; jj += 3) {
         restage(jj);
@@ -166,6 +177,12 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
       if (jj + 1 < bs) project(B1, jj + 1);
       if (jj + 2 < bs) project(B2, jj + 2);
       if (jj + 3 < bs) project(B0, jj + 3);
+      const bool same_iter = w + p.G < p.q;
+      __syncthreads();  // every thread is done with the staged records
+      if (same_iter)
+        stage_first(kl, w + p.G);
+      else if (kl + 1 < p.K)
+        stage_first(kl + 1, g);
       const CoherentBuf vw(p.vbuf + (size_t)w * n, n);  // stores past the end are dropped
 #pragma unroll
       for (int i = 0; i < VPT; ++i) {
@@ -173,34 +190,83 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
 #pragma unroll
         for (int e = 0; e < V; ++e) vw.store(c * V + e, vat(i, e));
       }
-      __syncthreads();  // the staged records are reused by the next worker
+      if (same_iter) issue_first();
     }
-    // x^(k+1) = (1/q) sum_w v_w, column slices, fixed worker order
-    if (!sync_grid(p.bar, target, (unsigned)p.G)) {
+    // grid barrier: v's published; then the next iteration's first rows are
+    // requested, to stream in during the barrier and the average
+    wait_memory();
+    if (kl + 1 < p.K) issue_first();
+    bool ok = true;
+    if (p.G > 1)
+      ok = grid_arrive_wait(p.bar, target, (unsigned)p.G);
+    else
+      __syncthreads();
+    if (!ok) {
       if (t == 0) note_timeout(p.st);
       stopped = true;
       break;
     }
+    // x^(k+1) = (1/q) sum_w v_w over this workgroup's column slice.  Each
+    // element's sum over the workers is split over tpe threads (strided
+    // worker subsets, each in increasing order) and the tpe partial sums are
+    // then added in order: a fixed order for a given launch geometry.
     const bool check = p.check_every > 0 && ((k + 1) % p.check_every) == 0;
     const int64_t e0 = (int64_t)g * p.ns * V;
     const int64_t e1 = ((int64_t)(g + 1) * p.ns * V < n) ? (int64_t)(g + 1) * p.ns * V : n;
+    const int E = e1 > e0 ? (int)(e1 - e0) : 0;
+    int tpe = 1;
+    if (E > 0 && E < NT) {
+      tpe = NT / E;
+      if (tpe > p.q) tpe = p.q;
+    }
     double err = 0.0;
-    for (int64_t ci = e0 + t; ci < e1; ci += NT) {
-      double acc = 0.0;
-      int w = 0;
-      for (; w + 8 <= p.q; w += 8) {
-        double vv[8];
+    if (tpe == 1) {
+      for (int64_t ci = e0 + t; ci < e1; ci += NT) {
+        double acc = 0.0;
+        int w = 0;
+        for (; w + 8 <= p.q; w += 8) {
+          double vv[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) vv[u] = CoherentBuf(p.vbuf + (size_t)(w + u) * n, n).load(ci);
+          for (int u = 0; u < 8; ++u) vv[u] = CoherentBuf(p.vbuf + (size_t)(w + u) * n, n).load(ci);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc += vv[u];
+          for (int u = 0; u < 8; ++u) acc += vv[u];
+        }
+        for (; w < p.q; ++w) acc += CoherentBuf(p.vbuf + (size_t)w * n, n).load(ci);
+        const double xn = acc / (double)p.q;
+        xb.store(ci, xn);
+        if (check) {
+          const double dd = xn - p.x_ref[ci];
+          err = fma(dd, dd, err);
+        }
       }
-      for (; w < p.q; ++w) acc += CoherentBuf(p.vbuf + (size_t)w * n, n).load(ci);
-      const double xn = acc / (double)p.q;
-      xb.store(ci, xn);
-      if (check) {
-        const double dd = xn - p.x_ref[ci];
-        err = fma(dd, dd, err);
+    } else {
+      const int le = t / tpe, sub = t % tpe;
+      const int64_t ci = e0 + (le < E ? le : 0);
+      double acc = 0.0;
+      if (le < E) {
+        for (int w0 = sub; w0 < p.q; w0 += 8 * tpe) {
+          double vv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int w = w0 + u * tpe;
+            const double val = CoherentBuf(p.vbuf + (size_t)(w < p.q ? w : p.q - 1) * n, n).load(ci);
+            vv[u] = w < p.q ? val : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc += vv[u];
+        }
+      }
+      AV[t] = acc;
+      __syncthreads();
+      if (t < E) {
+        double sum = 0.0;
+        for (int u = 0; u < tpe; ++u) sum += AV[t * tpe + u];
+        const double xn = sum / (double)p.q;
+        xb.store(e0 + t, xn);
+        if (check) {
+          const double dd = xn - p.x_ref[e0 + t];
+          err = fma(dd, dd, err);
+        }
       }
     }
     if (check) {
@@ -244,11 +310,11 @@ static int vpt_bucket(int64_t need) {
 // largest spill-free bucket with v in registers / with v in LDS
 static int vpt_limit_reg(int dtype, int V) {
   if (V == 1) return dtype == 0 ? 12 : 16;
-  return dtype == 2 ? 4 : 6;
+  return dtype == 2 ? 3 : 6;
 }
 static int vpt_limit_lds(int dtype, int V) {
-  if (V == 1) return dtype == 0 ? 16 : 20;
-  return dtype == 0 ? 10 : (dtype == 1 ? 6 : 4);
+  if (V == 1) return 16;
+  return dtype == 0 ? 10 : (dtype == 1 ? 6 : 3);
 }
 constexpr size_t kMaxLds = 144 * 1024;  // 160 KiB minus the static LDS above
 

@@ -96,10 +96,12 @@ __global__ __launch_bounds__(kPrefixThreads) void prefix_kernel(const double* __
   for (int64_t base = 0; base < m; base += kPrefixBlock) {
     const int cnt = (int)((m - base) < kPrefixBlock ? (m - base) : kPrefixBlock);
     if (t == 0) {
-      // the sequential chain, on one lane of wave 0; weights are read from
-      // LDS a batch at a time so that only the dependent adds are serial
+      // The sequential chain, on one lane of wave 0, branch-free: weights are
+      // read from LDS a batch at a time, the block is zero-padded past m
+      // (adding +0.0 leaves a non-negative running sum unchanged) and the last
+      // positive row is tracked with a select.
       double run = carry_s;
-      long long last = last_s;
+      int lastv = -1;
       constexpr int kBatch = 32;
       for (int i0 = 0; i0 < cnt; i0 += kBatch) {
         double wv[kBatch];
@@ -107,15 +109,13 @@ __global__ __launch_bounds__(kPrefixThreads) void prefix_kernel(const double* __
         for (int u = 0; u < kBatch; ++u) wv[u] = in[slot][i0 + u];  // in-bounds: block of 1024
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
-          if (i0 + u < cnt) {
-            run = __dadd_rn(run, wv[u]);
-            out[i0 + u] = run;
-            if (wv[u] > 0.0) last = base + i0 + u;
-          }
+          run = __dadd_rn(run, wv[u]);
+          out[i0 + u] = run;
+          lastv = wv[u] > 0.0 ? i0 + u : lastv;
         }
       }
       carry_s = run;
-      last_s = last;
+      if (lastv >= 0) last_s = base + lastv;
     } else if (t >= kWave) {
       // waves 1.. stream the next block of w into the other buffer
       const int64_t nb = base + kPrefixBlock;
