@@ -163,7 +163,7 @@ def test_rkab_parity(m, n, dtype, q, bs, K, alpha):
 
 
 @pytest.mark.parametrize("q,grid,allreduce", [
-    (16, 0, 1), (16, 0, 2), (16, 7, 1), (16, 64, 2), (64, 24, 1), (64, 0, 2), (100, 16, 1),
+    (16, 8, 1), (16, 0, 2), (16, 7, 1), (16, 64, 2), (64, 24, 1), (64, 0, 2), (100, 16, 1),
     (200, 25, 2), (5, 2, 0),
 ])
 def test_rka_allreduce_modes_and_grids(q, grid, allreduce):
