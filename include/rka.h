@@ -126,6 +126,13 @@ typedef struct rka_opts {
                                (sums scattered over workgroups).  The two add the
                                partials in different orders: results agree to
                                rounding, each is bitwise reproducible.                */
+    int32_t accumulate;     /* 0 = FP64 arithmetic (default); 1 = FP32: the iterate, the
+                               dot products, the scales and the average are binary32
+                               (the inner solves of the precision form).  FP32 needs
+                               RKA_F32 or RKA_BF16 storage, else RKA_EINVAL.  The
+                               stopping measures stay FP64 either way.               */
+    int32_t stream_id;      /* counter domain `dom` of the row stream, 0..255 (default
+                               0; the column solves of the refinement use 1)          */
     int32_t reserved;
 } rka_opts;
 
@@ -142,6 +149,9 @@ typedef struct rka_stats {
     int32_t threads;          /* threads per workgroup of the iteration kernel         */
     int32_t bucket;           /* register-tile bucket of the kernel instance: rows per
                                  thread (kernel 1) or 16-byte vecs per thread (kernel 2) */
+    int32_t variant;          /* kernel 1: 1 = one-barrier all-gather of the partials;
+                                 kernel 2: 1 = worker iterate kept in LDS               */
+    int32_t accumulate;       /* accumulation type used: 0 = FP64, 1 = FP32             */
 } rka_stats;
 
 /*
@@ -184,6 +194,92 @@ int rka_prefix(const double* w, int64_t m, double* c, int64_t* last_pos, void* s
 int rka_sample_indices(const double* w, const double* c, int64_t m, uint64_t seed,
                        int64_t iter_offset, int64_t K, int32_t q, int32_t bs, int32_t dom,
                        int32_t* idx, void* stream);
+
+/*
+ * rka_gemv -- out_i = (c ? c_i : 0) + gamma * sum_j M[i,j] v_j for i < rows,
+ * in FP64 (narrow storage widens exactly).  M is rows x cols with leading
+ * dimension ld; v: cols doubles; c (nullable) and out: rows doubles (out
+ * may alias c).  With c = b, gamma = -1 this is the residual b - A x; on a
+ * transposed copy it forms A^T r.  Each row's sum has a fixed order.
+ * Enqueue only.
+ */
+int rka_gemv(const void* M, int dtype, int64_t rows, int64_t cols, int64_t ld, const double* v,
+             const double* c, double gamma, double* out, void* stream);
+
+/*
+ * rka_transpose -- At[j, i] = A[i, j] (element bits copied), so that the
+ * columns of A become contiguous rows for the column solves.  At: n rows of
+ * m elements, leading dimension ldat >= m, same dtype; must not overlap A.
+ * m must be below 65535 * 64.  Enqueue only.
+ */
+int rka_transpose(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, void* At,
+                  int64_t ldat, void* stream);
+
+/*
+ * rka_lsq_grad_A -- dA[i, j] = r_i lambda_j - z_i x_j (formed in FP64, stored
+ * as out_dtype = RKA_F64 or RKA_F32, leading dimension ldd >= n): the gradient
+ * of a loss L(x) through the least-squares solution x = argmin ||A x - b||
+ * with respect to A, where r = b - A x, z = dL/db (the minimum-norm solution
+ * of A^T z = dL/dx) and lambda solves A lambda = z.  r, z: m doubles;
+ * lambda, x: n doubles.  Enqueue only.
+ */
+int rka_lsq_grad_A(int64_t m, int64_t n, const double* r, const double* lam, const double* z,
+                   const double* x, void* dA, int out_dtype, int64_t ldd, void* stream);
+
+/* Options of rka_refine_solve. */
+typedef struct rka_refine_opts {
+    int32_t method;       /* inner solver: 0 = RKA (rka_solve), 1 = RKAB (rkab_solve)    */
+    int32_t q;            /* inner workers, >= 1                                         */
+    int32_t block_size;   /* inner RKAB block size (method 1)                            */
+    int32_t accumulate;   /* inner arithmetic: 0 = FP64, 1 = FP32 (narrow storage only)  */
+    double alpha;         /* inner relaxation weight, finite and > 0                     */
+    int64_t inner_iters;  /* outer iterations of every inner row solve, >= 0             */
+    int64_t range_iters;  /* iterations of the column solve that projects the residual
+                             onto range(A) (0: plain refinement, for consistent systems) */
+    int32_t range_q;      /* workers of the column solve                                 */
+    int32_t max_sweeps;   /* refinement sweeps, >= 1                                     */
+    double range_alpha;   /* relaxation weight of the column solve                       */
+    double tol;           /* stop after the first sweep whose measure is <= tol
+                             (0: run max_sweeps)                                         */
+} rka_refine_opts;
+
+typedef struct rka_refine_info {
+    int32_t sweeps;       /* sweeps performed                                            */
+    int32_t status;       /* same as the return value                                    */
+    double rel;           /* measure after the last sweep                                */
+    int64_t projections;  /* row projections of all inner solves                         */
+} rka_refine_info;
+
+/*
+ * rka_refine_solve -- mixed-precision iterative refinement around the
+ * Kaczmarz solves, for the least-squares problem of Eq. (2).  Per sweep s:
+ *     r = b - A x                      (FP64, rka_gemv)
+ *     if range_iters > 0:              (inconsistent systems)
+ *         g = A^T r                    (FP64, on the transposed copy At)
+ *         y = RKA on the columns, A^T y = g from y = 0: range_iters iterations,
+ *             range_q workers, weight range_alpha, row stream dom = 1 with
+ *             iter_offset = s * range_iters -- converges to the projection of
+ *             r onto range(A), so that the next system is consistent
+ *         r = y
+ *     d = RKA / RKAB on A d = r from d = 0: inner_iters iterations, dom = 0,
+ *         iter_offset = s * inner_iters, accumulation as `accumulate`
+ *     x = x + d                        (FP64)
+ * then the measure ||x - x_ref|| / ||x_ref|| (x_ref given) or ||b - A x|| /
+ * ||b|| is written to sweep_measure[s] (host array of max_sweeps doubles,
+ * nullable).  Plain RKA stops at the convergence horizon set by the
+ * least-squares residual (Sec. 2.3.1); the range projection removes that
+ * residual from every correction, so the sweeps converge to the
+ * least-squares solution itself.  With FP32 accumulation every inner solve
+ * is accurate to roughly FP32 rounding and the FP64 residual recovers the
+ * rest.  A, b, x, x0, x_ref as in rka_solve; At: the n x m transpose of A
+ * (rka_transpose), needed only when range_iters > 0.  Waits for the stream
+ * once per sweep.  Returns RKA_OK (converged, or tol == 0),
+ * RKA_NOT_CONVERGED (max_sweeps reached with tol > 0), or an error.
+ */
+int rka_refine_solve(const void* A, const void* At, int dtype, int64_t m, int64_t n, int64_t lda,
+                     int64_t ldat, const double* b, const double* x0, double* x,
+                     const rka_refine_opts* opts, uint64_t seed, const double* x_ref,
+                     double* sweep_measure, void* stream, rka_refine_info* info);
 
 /* Name of a status code (static string). */
 const char* rka_status_string(int status);

@@ -4,8 +4,9 @@ Only the test-suite, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg
 of ``bench.py`` may import this package.  The solver library never does, and
 this package never imports the solver: the two share no code.
 
-The arithmetic lives in ``rka_oracle.c`` (plain C, single thread, compiled
-with ``-O2 -ffp-contract=off``); this module only marshals numpy arrays into
+The arithmetic lives in ``rka_oracle.c`` (the paper's iterations) and
+``forms_oracle.c`` (FP32 iterations, refinement, dense steps) -- plain C,
+single thread, compiled with ``-O2 -ffp-contract=off``; this module only marshals numpy arrays into
 it through ctypes.  Each C function cites the passage of arXiv 2401.17474 it
 follows.
 """
@@ -18,7 +19,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "rka_oracle.c")
+_SRCS = [os.path.join(_HERE, "rka_oracle.c"), os.path.join(_HERE, "forms_oracle.c")]
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 OK, NOT_CONVERGED, EINVAL, EZERONORM, EDIVERGED = 0, 1, -1, -2, -3
@@ -29,7 +30,7 @@ _lib = None
 def build() -> str:
     """Compile the oracle into ``oracle/liboracle.so`` (always recompiles)."""
     cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-           "-shared", "-Wall", "-Wextra", "-o", LIB_PATH + ".tmp", _SRC, "-lm"]
+           "-shared", "-Wall", "-Wextra", "-o", LIB_PATH + ".tmp", *_SRCS, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(LIB_PATH + ".tmp", LIB_PATH)
     return LIB_PATH
@@ -65,6 +66,13 @@ def lib():
         L.oracle_rka_given.argtypes = [P, ctypes.c_int, I64, I64, I64, P, P, I32, D, I64, P]
         L.oracle_rkab_given.argtypes = [P, ctypes.c_int, I64, I64, I64, P, P, I32, I32, D, I64,
                                         P]
+        L.oracle_rka_f32_given.argtypes = [P, ctypes.c_int, I64, I64, I64, P, P, I32, D, I64, P]
+        L.oracle_rkab_f32_given.argtypes = [P, ctypes.c_int, I64, I64, I64, P, P, I32, I32, D,
+                                            I64, P]
+        L.oracle_transpose.argtypes = [P, ctypes.c_int, I64, I64, I64, P]
+        L.oracle_gemv.argtypes = [P, ctypes.c_int, I64, I64, I64, P, P, D, P]
+        L.oracle_refine.argtypes = [P, ctypes.c_int, I64, I64, I64, P, P, P, I32, I32, I32, I32,
+                                    D, I64, I64, I32, D, I32, U64, P, P]
         _lib = L
     return _lib
 
@@ -201,3 +209,69 @@ def rkab_given(A, b, x, idx, *, q, block_size, alpha=1.0, dtype=None):
     if st != OK:
         raise ValueError(f"oracle_rkab_given status {st}")
     return x
+
+
+# -- forms built on the iterations (forms_oracle.c) ----------------------------
+
+def rka_f32_given(A, b, x, idx, *, q, alpha=1.0, dtype=None):
+    """RKA with every iteration quantity in binary32 (A float32 or bf16 bits)."""
+    A, code, lda = _matrix(A, dtype)
+    m, n = A.shape
+    x = np.array(x, dtype=np.float64, copy=True)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    K = idx.size // q
+    st = lib().oracle_rka_f32_given(_ptr(A), code, m, n, lda, _ptr(_vec(b, m)), _ptr(x), q,
+                                    alpha, K, _ptr(idx))
+    if st != OK:
+        raise ValueError(f"oracle_rka_f32_given status {st}")
+    return x
+
+
+def rkab_f32_given(A, b, x, idx, *, q, block_size, alpha=1.0, dtype=None):
+    """RKAB with every iteration quantity in binary32."""
+    A, code, lda = _matrix(A, dtype)
+    m, n = A.shape
+    x = np.array(x, dtype=np.float64, copy=True)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    K = idx.size // (q * block_size)
+    st = lib().oracle_rkab_f32_given(_ptr(A), code, m, n, lda, _ptr(_vec(b, m)), _ptr(x), q,
+                                     block_size, alpha, K, _ptr(idx))
+    if st != OK:
+        raise ValueError(f"oracle_rkab_f32_given status {st}")
+    return x
+
+
+def transpose(A, dtype=None):
+    A, code, lda = _matrix(A, dtype)
+    m, n = A.shape
+    At = np.empty((n, m), dtype=A.dtype)
+    if lib().oracle_transpose(_ptr(A), code, m, n, lda, _ptr(At)) != OK:
+        raise ValueError("oracle_transpose failed")
+    return At
+
+
+def gemv(M, v, *, c=None, gamma=1.0, dtype=None):
+    M, code, ld = _matrix(M, dtype)
+    rows, cols = M.shape
+    out = np.empty(rows, dtype=np.float64)
+    if lib().oracle_gemv(_ptr(M), code, rows, cols, ld, _ptr(_vec(v, cols)),
+                         _ptr(_vec(c, rows)), gamma, _ptr(out)) != OK:
+        raise ValueError("oracle_gemv failed")
+    return out
+
+
+def refine(A, b, *, method=0, q, block_size=1, acc32=1, alpha=1.0, inner_iters,
+           range_iters=0, range_q=1, range_alpha=1.0, sweeps, seed=1, x0=None, x_ref=None,
+           dtype=None):
+    """Refinement sweeps; returns (x, per-sweep measures)."""
+    A, code, lda = _matrix(A, dtype)
+    m, n = A.shape
+    x = np.zeros(n, dtype=np.float64)
+    meas = np.zeros(sweeps, dtype=np.float64)
+    st = lib().oracle_refine(_ptr(A), code, m, n, lda, _ptr(_vec(b, m)), _ptr(_vec(x0, n)),
+                             _ptr(x), method, q, block_size, acc32, alpha, inner_iters,
+                             range_iters, range_q, range_alpha, sweeps, seed,
+                             _ptr(_vec(x_ref, n)), _ptr(meas))
+    if st != OK:
+        raise ValueError(f"oracle_refine status {st}")
+    return x, meas

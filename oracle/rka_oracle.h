@@ -93,6 +93,41 @@ int oracle_rkab_given(const void* A, int dtype, int64_t m, int64_t n, int64_t ld
                       const double* b, double* x, int32_t q, int32_t bs, double alpha,
                       int64_t K, const int32_t* idx);
 
+/* ------------------------------------------------------------------ */
+/* Forms built on the iterations (forms_oracle.c).                      */
+/* ------------------------------------------------------------------ */
+
+/* The two iterations above with every iteration quantity in binary32
+ * ("FP32 accumulation", the inner solves of the precision form): A widened
+ * exactly to binary32 (dtype 1 or 2 only), x rounded to binary32 on entry and
+ * widened on exit, b_i and ||A^(i)||^2 (binary64 norms as above) rounded to
+ * binary32 once per use; dot products left to right; RKA adds the scaled rows
+ * in worker order and multiplies by (1/q) rounded to binary32; RKAB divides
+ * the worker sum by q. */
+int oracle_rka_f32_given(const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
+                         const double* b, double* x, int32_t q, double alpha, int64_t K,
+                         const int32_t* idx);
+int oracle_rkab_f32_given(const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
+                          const double* b, double* x, int32_t q, int32_t bs, double alpha,
+                          int64_t K, const int32_t* idx);
+
+/* At (n x m, leading dimension m) = A^T, element bits copied. */
+int oracle_transpose(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, void* At);
+
+/* out_i = (c ? c_i : 0) + gamma * sum_j M[i,j] v_j, binary64, left to right. */
+int oracle_gemv(const void* M, int dtype, int64_t rows, int64_t cols, int64_t ld,
+                const double* v, const double* c, double gamma, double* out);
+
+/* Iterative refinement sweeps around inner RKA / RKAB solves (binary32 if
+ * acc32), with the residual projected onto range(A) by a column solve when
+ * range_iters > 0; measures[s] = the relative error (x_ref) or residual after
+ * sweep s.  The steps are listed above the definition. */
+int oracle_refine(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const double* b,
+                  const double* x0, double* x, int32_t method, int32_t q, int32_t bs,
+                  int32_t acc32, double alpha, int64_t inner_iters, int64_t range_iters,
+                  int32_t range_q, double range_alpha, int32_t sweeps, uint64_t seed,
+                  const double* x_ref, double* measures);
+
 #ifdef __cplusplus
 }
 #endif

@@ -36,6 +36,7 @@ class _Info(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("check_every", ctypes.c_int64), ("grid", ctypes.c_int32),
                 ("collect_timing", ctypes.c_int32), ("allreduce", ctypes.c_int32),
+                ("accumulate", ctypes.c_int32), ("stream_id", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
 
 
@@ -44,7 +45,22 @@ class _Stats(ctypes.Structure):
                 ("sample_ms", ctypes.c_double), ("iterate_ms", ctypes.c_double),
                 ("measure_ms", ctypes.c_double), ("iterate_launches", ctypes.c_int64),
                 ("kernel", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("threads", ctypes.c_int32), ("bucket", ctypes.c_int32)]
+                ("threads", ctypes.c_int32), ("bucket", ctypes.c_int32),
+                ("variant", ctypes.c_int32), ("accumulate", ctypes.c_int32)]
+
+
+class _RefineOpts(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("q", ctypes.c_int32),
+                ("block_size", ctypes.c_int32), ("accumulate", ctypes.c_int32),
+                ("alpha", ctypes.c_double), ("inner_iters", ctypes.c_int64),
+                ("range_iters", ctypes.c_int64), ("range_q", ctypes.c_int32),
+                ("max_sweeps", ctypes.c_int32), ("range_alpha", ctypes.c_double),
+                ("tol", ctypes.c_double)]
+
+
+class _RefineInfo(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("rel", ctypes.c_double), ("projections", ctypes.c_int64)]
 
 
 @dataclass
@@ -75,13 +91,20 @@ def lib():
         L.rka_row_norms.argtypes = [P, ctypes.c_int, I64, I64, I64, P, P]
         L.rka_prefix.argtypes = [P, I64, P, P, P]
         L.rka_sample_indices.argtypes = [P, P, I64, U64, I64, I64, I32, I32, I32, P, P]
+        L.rka_gemv.argtypes = [P, ctypes.c_int, I64, I64, I64, P, P, D, P, P]
+        L.rka_transpose.argtypes = [P, ctypes.c_int, I64, I64, I64, P, I64, P]
+        L.rka_lsq_grad_A.argtypes = [I64, I64, P, P, P, P, P, ctypes.c_int, I64, P]
+        L.rka_refine_solve.argtypes = [P, P, ctypes.c_int, I64, I64, I64, I64, P, P, P,
+                                       ctypes.POINTER(_RefineOpts), U64, P, P, P,
+                                       ctypes.POINTER(_RefineInfo)]
         L.rka_status_string.argtypes = [ctypes.c_int]
         L.rka_status_string.restype = ctypes.c_char_p
         L.rka_last_error.argtypes = []
         L.rka_last_error.restype = ctypes.c_char_p
         L.rka_version.restype = ctypes.c_int
         for f in ("rka_solve", "rkab_solve", "rka_solve_ex", "rka_row_norms", "rka_prefix",
-                  "rka_sample_indices"):
+                  "rka_sample_indices", "rka_gemv", "rka_transpose", "rka_lsq_grad_A",
+                  "rka_refine_solve"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -187,17 +210,19 @@ def rkab_solve(A, b, *, q, block_size, alpha=1.0, max_iter=1000, tol=0.0, seed=1
 
 def solve_ex(A, b, *, method, q, block_size=1, alpha=1.0, max_iter=1000, tol=0.0, seed=1,
              x0=None, x_ref=None, iter_offset=0, check_every=1, grid=0, allreduce=0,
-             timing=False, out=None, stream=None, raise_on_error=True):
+             timing=False, accumulate=0, stream_id=0, out=None, stream=None,
+             raise_on_error=True):
     """rka_solve_ex: method 0 = RKA, 1 = RKAB.  Returns (x, Info, stats dict);
     with ``timing`` the stats hold per-phase HIP-event times (ms) measured on
-    the stream the kernels run on."""
+    the stream the kernels run on.  ``accumulate=1`` computes in FP32 (narrow
+    storage only); ``stream_id`` is the row stream's counter domain."""
     torch = _torch()
     code, m, n, lda = _matrix(A)
     b = _vec(b, m, "b", False)
     x = out if out is not None else torch.empty(n, dtype=torch.float64, device=A.device)
     _vec(x, n, "out", False)
     info, stats = _Info(), _Stats()
-    opts = _Opts(check_every, grid, 1 if timing else 0, allreduce, 0)
+    opts = _Opts(check_every, grid, 1 if timing else 0, allreduce, accumulate, stream_id, 0)
     st = lib().rka_solve_ex(_ptr(A), code, m, n, lda, _ptr(b), _ptr(_vec(x0, n, "x0")), _ptr(x),
                             method, q, block_size, alpha, max_iter, tol, seed,
                             _ptr(_vec(x_ref, n, "x_ref")), iter_offset, ctypes.byref(opts),
@@ -238,6 +263,85 @@ def sample_indices(w, c, *, seed, iter_offset=0, K, q, bs=1, dom=0, stream=None)
     _raise_if(lib().rka_sample_indices(_ptr(w), _ptr(c), m, seed, iter_offset, K, q, bs, dom,
                                        _ptr(idx), _stream(stream)))
     return idx
+
+
+# -- dense steps and refinement --------------------------------------------------
+
+def gemv(M, v, *, c=None, gamma=1.0, out=None, stream=None):
+    """out = (c or 0) + gamma * M v in FP64 (rka_gemv)."""
+    torch = _torch()
+    code, rows, cols, ld = _matrix(M)
+    _vec(v, cols, "v", False)
+    _vec(c, rows, "c")
+    y = out if out is not None else torch.empty(rows, dtype=torch.float64, device=M.device)
+    _vec(y, rows, "out", False)
+    _raise_if(lib().rka_gemv(_ptr(M), code, rows, cols, ld, _ptr(v), _ptr(c), gamma, _ptr(y),
+                             _stream(stream)))
+    return y
+
+
+def transpose(A, stream=None):
+    """A contiguous transposed copy of A made by the library's kernel."""
+    torch = _torch()
+    code, m, n, lda = _matrix(A)
+    At = torch.empty((n, m), dtype=A.dtype, device=A.device)
+    _raise_if(lib().rka_transpose(_ptr(A), code, m, n, lda, _ptr(At), m, _stream(stream)))
+    return At
+
+
+def lsq_grad_A(r, lam, z, x, *, dtype=None, stream=None):
+    """dA = r lam^T - z x^T (rka_lsq_grad_A), float64 or float32."""
+    torch = _torch()
+    m, n = r.shape[0], x.shape[0]
+    for v, k, nm in ((r, m, "r"), (z, m, "z"), (lam, n, "lam"), (x, n, "x")):
+        _vec(v, k, nm, False)
+    dt = dtype or torch.float64
+    if dt not in (torch.float64, torch.float32):
+        raise TypeError("dtype must be float64 or float32")
+    dA = torch.empty((m, n), dtype=dt, device=r.device)
+    _raise_if(lib().rka_lsq_grad_A(m, n, _ptr(r), _ptr(lam), _ptr(z), _ptr(x), _ptr(dA),
+                                   0 if dt == torch.float64 else 1, n, _stream(stream)))
+    return dA
+
+
+@dataclass
+class RefineInfo:
+    sweeps: int
+    status: int
+    rel: float
+    projections: int
+    measures: list
+
+
+def refine_solve(A, b, *, At=None, method=0, q, block_size=1, accumulate=1, alpha=1.0,
+                 inner_iters, range_iters=0, range_q=1, range_alpha=1.0, max_sweeps=4,
+                 tol=0.0, seed=1, x0=None, x_ref=None, out=None, stream=None,
+                 raise_on_error=True):
+    """rka_refine_solve: FP64 refinement sweeps around inner RKA/RKAB solves
+    (optionally FP32), with the residual projected onto range(A) by a column
+    solve on ``At`` when ``range_iters`` > 0.  Returns (x, RefineInfo)."""
+    torch = _torch()
+    code, m, n, lda = _matrix(A)
+    ldat = 0
+    if At is not None:
+        ct, nt, mt, ldat = _matrix(At)
+        if ct != code or nt != n or mt != m:
+            raise ValueError("At must be the n x m transpose of A, same dtype")
+    b = _vec(b, m, "b", False)
+    x = out if out is not None else torch.empty(n, dtype=torch.float64, device=A.device)
+    _vec(x, n, "out", False)
+    o = _RefineOpts(method, q, block_size, accumulate, alpha, inner_iters, range_iters, range_q,
+                    max_sweeps, range_alpha, tol)
+    meas = (ctypes.c_double * max_sweeps)()
+    info = _RefineInfo()
+    st = lib().rka_refine_solve(_ptr(A), _ptr(At), code, m, n, lda, ldat, _ptr(b),
+                                _ptr(_vec(x0, n, "x0")), _ptr(x), ctypes.byref(o), seed,
+                                _ptr(_vec(x_ref, n, "x_ref")), meas, _stream(stream),
+                                ctypes.byref(info))
+    if raise_on_error:
+        _raise_if(st)
+    return x, RefineInfo(info.sweeps, st, info.rel, info.projections,
+                         [meas[i] for i in range(info.sweeps)])
 
 
 # -- host helpers --------------------------------------------------------------

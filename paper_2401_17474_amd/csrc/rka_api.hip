@@ -159,7 +159,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
                const double* b, const double* x0, double* x, int32_t q, int32_t bs, double alpha,
                int64_t max_iter, double tol, uint64_t seed, const double* x_ref,
                int64_t iter_offset, int64_t check_every, int grid, int allreduce, bool timing,
-               void* stream, rka_info* info, rka_stats* stats) {
+               int acc, int dom, void* stream, rka_info* info, rka_stats* stats) {
   g_last_error.clear();
   if (stats) memset(stats, 0, sizeof *stats);
   if (info) {
@@ -174,6 +174,10 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   if (check_every < 1) check_every = 1;
   if (grid < 0) return fail(RKA_EINVAL, "grid must be >= 0");
   if (allreduce < 0 || allreduce > 2) return fail(RKA_EINVAL, "allreduce must be 0, 1 or 2");
+  if (acc < 0 || acc > 1) return fail(RKA_EINVAL, "accumulate must be 0 (FP64) or 1 (FP32)");
+  if (acc == 1 && dtype == RKA_F64)
+    return fail(RKA_EINVAL, "FP32 accumulation needs RKA_F32 or RKA_BF16 storage");
+  if (dom < 0 || dom > 255) return fail(RKA_EINVAL, "stream_id must be in [0, 255]");
   const int ncu = num_cus();
   if (ncu <= 0) return fail(RKA_EDEVICE, "no HIP device available");
   hipStream_t s = (hipStream_t)stream;
@@ -194,6 +198,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   sh.num_cu = ncu;
   sh.grid = grid > ncu ? ncu : grid;
   sh.allreduce = allreduce;
+  sh.acc = acc;
 
   rka::RkaColGeom cgeo{};
   rka::RkabGeom bgeo{};
@@ -208,7 +213,8 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
 
   Scratch sc(s);
   rka::DevStatus* st;
-  double *w, *c, *part, *vbuf = nullptr;
+  double *w, *c, *part;
+  void* vbuf = nullptr;
   uint64_t *slots = nullptr, *sslots = nullptr;  // tagged exchange slots (column kernel)
   int64_t* last_pos;
   rka::RowRec* rec;
@@ -238,7 +244,8 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
     HIP_TRY(sc.get(&slots, 2 * nslots));
     HIP_TRY(sc.get(&sslots, 2 * nsslots));
   } else {
-    HIP_TRY(sc.get(&vbuf, (size_t)q * (size_t)n));
+    const size_t vb = (size_t)q * (size_t)n * (acc == 1 ? sizeof(float) : sizeof(double));
+    HIP_TRY(sc.get((char**)&vbuf, vb));
   }
   sh.wn = w;
 
@@ -276,7 +283,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
       if (to_check < kc) kc = to_check;
     }
     tm.begin(kSample);
-    HIP_TRY(rka::launch_sample(c, m, last_pos, seed, k + iter_offset, kc, q, sh.bs, 0, nullptr, rec,
+    HIP_TRY(rka::launch_sample(c, m, last_pos, seed, k + iter_offset, kc, q, sh.bs, dom, nullptr, rec,
                                b, w, st, s));
     tm.end();
     tm.begin(kIterate);
@@ -317,6 +324,8 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
     stats->grid = use_col ? cgeo.G : bgeo.G;
     stats->threads = use_col ? cgeo.nt : bgeo.nt;
     stats->bucket = use_col ? cgeo.rpt : bgeo.vpt;
+    stats->variant = use_col ? cgeo.gather : (bgeo.vlds ? 1 : 0);
+    stats->accumulate = acc;
   }
   int status = hst.status;
   if (status == RKA_EZERONORM) fail(status, "||A||_F^2 is zero or not finite");
@@ -341,7 +350,7 @@ int rka_solve(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const
               uint64_t seed, const double* x_ref, int64_t iter_offset, int64_t check_every,
               void* stream, rka_info* info) {
   return solve_impl(false, A, dtype, m, n, lda, b, x0, x, q, 1, alpha, max_iter, tol, seed, x_ref,
-                    iter_offset, check_every, 0, 0, false, stream, info, nullptr);
+                    iter_offset, check_every, 0, 0, false, 0, 0, stream, info, nullptr);
 }
 
 int rka_solve_ex(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const double* b,
@@ -358,9 +367,11 @@ int rka_solve_ex(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, co
   const int grid = opts ? opts->grid : 0;
   const int allreduce = opts ? opts->allreduce : 0;
   const bool timing = opts ? opts->collect_timing != 0 : false;
+  const int acc = opts ? opts->accumulate : 0;
+  const int dom = opts ? opts->stream_id : 0;
   return solve_impl(method == 1, A, dtype, m, n, lda, b, x0, x, q, method == 1 ? block_size : 1,
                     alpha, max_iter, tol, seed, x_ref, iter_offset, ce, grid, allreduce, timing,
-                    stream, info, stats);
+                    acc, dom, stream, info, stats);
 }
 
 int rkab_solve(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const double* b,
@@ -368,7 +379,7 @@ int rkab_solve(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, cons
                int64_t max_iter, double tol, uint64_t seed, const double* x_ref,
                int64_t iter_offset, int64_t check_every, void* stream, rka_info* info) {
   return solve_impl(true, A, dtype, m, n, lda, b, x0, x, q, block_size, alpha, max_iter, tol, seed,
-                    x_ref, iter_offset, check_every, 0, 0, false, stream, info, nullptr);
+                    x_ref, iter_offset, check_every, 0, 0, false, 0, 0, stream, info, nullptr);
 }
 
 int rka_row_norms(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, double* w,
@@ -422,6 +433,166 @@ int rka_sample_indices(const double* w, const double* c, int64_t m, uint64_t see
     return fail(e == hipErrorOutOfMemory ? RKA_ENOMEM : RKA_EDEVICE, "sampling: %s",
                 hipGetErrorString(e));
   return RKA_OK;
+}
+
+int rka_gemv(const void* M, int dtype, int64_t rows, int64_t cols, int64_t ld, const double* v,
+             const double* c, double gamma, double* out, void* stream) {
+  g_last_error.clear();
+  if (!M || !v || !out) return fail(RKA_EINVAL, "M, v and out must be non-null");
+  if (bad_dtype(dtype)) return fail(RKA_EINVAL, "dtype %d is not an rka_dtype", dtype);
+  if (rows < 1 || cols < 1 || ld < cols) return fail(RKA_EINVAL, "need rows, cols >= 1, ld >= cols");
+  if (!isfinite(gamma)) return fail(RKA_EINVAL, "gamma must be finite");
+  if (num_cus() <= 0) return fail(RKA_EDEVICE, "no HIP device available");
+  HIP_TRY(rka::launch_gemv(M, dtype, rows, cols, ld, vector_path_ok(M, dtype, cols, ld), v, c, gamma,
+                           out, (hipStream_t)stream));
+  return RKA_OK;
+}
+
+int rka_transpose(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, void* At,
+                  int64_t ldat, void* stream) {
+  g_last_error.clear();
+  if (!A || !At) return fail(RKA_EINVAL, "A and At must be non-null");
+  if (bad_dtype(dtype)) return fail(RKA_EINVAL, "dtype %d is not an rka_dtype", dtype);
+  if (m < 1 || n < 1 || lda < n || ldat < m)
+    return fail(RKA_EINVAL, "need m, n >= 1, lda >= n, ldat >= m");
+  if ((m + 63) / 64 > 65535) return fail(RKA_EINVAL, "m must be < 65535 * 64");
+  if (num_cus() <= 0) return fail(RKA_EDEVICE, "no HIP device available");
+  HIP_TRY(rka::launch_transpose(A, dtype, m, n, lda, At, ldat, (hipStream_t)stream));
+  return RKA_OK;
+}
+
+int rka_lsq_grad_A(int64_t m, int64_t n, const double* r, const double* lam, const double* z,
+                   const double* x, void* dA, int out_dtype, int64_t ldd, void* stream) {
+  g_last_error.clear();
+  if (!r || !lam || !z || !x || !dA) return fail(RKA_EINVAL, "every array must be non-null");
+  if (m < 1 || n < 1 || ldd < n) return fail(RKA_EINVAL, "need m, n >= 1 and ldd >= n");
+  if (out_dtype != RKA_F64 && out_dtype != RKA_F32)
+    return fail(RKA_EINVAL, "out_dtype must be RKA_F64 or RKA_F32");
+  if (num_cus() <= 0) return fail(RKA_EDEVICE, "no HIP device available");
+  HIP_TRY(rka::launch_rank2(m, n, r, lam, z, x, dA, out_dtype, ldd, (hipStream_t)stream));
+  return RKA_OK;
+}
+
+int rka_refine_solve(const void* A, const void* At, int dtype, int64_t m, int64_t n, int64_t lda,
+                     int64_t ldat, const double* b, const double* x0, double* x,
+                     const rka_refine_opts* o, uint64_t seed, const double* x_ref,
+                     double* sweep_measure, void* stream, rka_refine_info* info) {
+  g_last_error.clear();
+  if (info) {
+    info->sweeps = 0;
+    info->status = RKA_EINVAL;
+    info->rel = NAN;
+    info->projections = 0;
+  }
+  if (!o) return fail(RKA_EINVAL, "opts must be non-null");
+  if (!A || !b || !x) return fail(RKA_EINVAL, "A, b and x must be non-null");
+  if (bad_dtype(dtype)) return fail(RKA_EINVAL, "dtype %d is not an rka_dtype", dtype);
+  if (m < 1 || n < 1 || lda < n) return fail(RKA_EINVAL, "need m, n >= 1 and lda >= n");
+  if (m > INT32_MAX || n > INT32_MAX) return fail(RKA_EINVAL, "m and n must be < 2^31");
+  if (o->method != 0 && o->method != 1) return fail(RKA_EINVAL, "method must be 0 or 1");
+  if (o->q < 1 || o->inner_iters < 0 || o->max_sweeps < 1)
+    return fail(RKA_EINVAL, "need q >= 1, inner_iters >= 0, max_sweeps >= 1");
+  if (o->method == 1 && (o->block_size < 1 || o->block_size >= (1 << 24)))
+    return fail(RKA_EINVAL, "block_size must be in [1, 2^24)");
+  if (!(o->alpha > 0.0) || !isfinite(o->alpha)) return fail(RKA_EINVAL, "alpha must be finite and > 0");
+  if (!(o->tol >= 0.0) || !isfinite(o->tol)) return fail(RKA_EINVAL, "tol must be finite and >= 0");
+  if (o->accumulate < 0 || o->accumulate > 1 || (o->accumulate == 1 && dtype == RKA_F64))
+    return fail(RKA_EINVAL, "accumulate must be 0, or 1 with RKA_F32 / RKA_BF16 storage");
+  const bool range = o->range_iters > 0;
+  if (o->range_iters < 0) return fail(RKA_EINVAL, "range_iters must be >= 0");
+  if (range) {
+    if (!At || ldat < m) return fail(RKA_EINVAL, "the range projection needs At (n x m, ldat >= m)");
+    if (o->range_q < 1 || !(o->range_alpha > 0.0) || !isfinite(o->range_alpha))
+      return fail(RKA_EINVAL, "need range_q >= 1 and a finite range_alpha > 0");
+  }
+  if (num_cus() <= 0) return fail(RKA_EDEVICE, "no HIP device available");
+  hipStream_t s = (hipStream_t)stream;
+  const bool vec_a = vector_path_ok(A, dtype, n, lda);
+  const bool vec_t = range && vector_path_ok(At, dtype, m, ldat);
+
+  Scratch sc(s);
+  double *r, *d, *part, *acc2, *y = nullptr, *g = nullptr;
+  HIP_TRY(sc.get(&r, (size_t)m));
+  HIP_TRY(sc.get(&d, (size_t)n));
+  HIP_TRY(sc.get(&part, (size_t)rka::sumsq_part_len()));
+  HIP_TRY(sc.get(&acc2, 2));
+  if (range) {
+    HIP_TRY(sc.get(&y, (size_t)m));
+    HIP_TRY(sc.get(&g, (size_t)n));
+  }
+  if (x0) {
+    if (x0 != x) HIP_TRY(hipMemcpyAsync(x, x0, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  } else {
+    HIP_TRY(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), s));
+  }
+  // denominator of the sweep measure
+  HIP_TRY(rka::launch_sumsq(x_ref ? x_ref : b, nullptr, x_ref ? n : m, part, acc2 + 1, s));
+  double ref2 = 0.0;
+  HIP_TRY(hipMemcpyAsync(&ref2, acc2 + 1, sizeof ref2, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (!(ref2 > 0.0)) ref2 = 1.0;
+
+  int status = o->tol > 0.0 ? RKA_NOT_CONVERGED : RKA_OK;
+  int64_t projections = 0;
+  double rel = NAN;
+  int sweeps = 0;
+  for (int sw = 0; sw < o->max_sweeps; ++sw) {
+    // r = b - A x in FP64
+    HIP_TRY(rka::launch_gemv(A, dtype, m, n, lda, vec_a, x, b, -1.0, r, s));
+    const double* rhs = r;
+    rka_info ii;
+    if (range) {
+      // y = the projection of r onto range(A): the minimum-norm solution of
+      // A^T y = A^T r, by Kaczmarz on the columns of A from y = 0
+      HIP_TRY(rka::launch_gemv(At, dtype, n, m, ldat, vec_t, r, nullptr, 1.0, g, s));
+      const int st = solve_impl(false, At, dtype, n, m, ldat, g, nullptr, y, o->range_q, 1,
+                                o->range_alpha, o->range_iters, 0.0, seed, nullptr,
+                                (int64_t)sw * o->range_iters, 1, 0, 0, false, o->accumulate, 1, stream,
+                                &ii, nullptr);
+      if (st < 0) return st;
+      projections += ii.projections;
+      rhs = y;
+    }
+    // d ~ argmin ||A d - rhs||, by the inner RKA / RKAB solve from d = 0
+    const int st = solve_impl(o->method == 1, A, dtype, m, n, lda, rhs, nullptr, d, o->q,
+                              o->method == 1 ? o->block_size : 1, o->alpha, o->inner_iters, 0.0,
+                              seed, nullptr, (int64_t)sw * o->inner_iters, 1, 0, 0, false,
+                              o->accumulate, 0, stream, &ii, nullptr);
+    if (st < 0) return st;
+    projections += ii.projections;
+    HIP_TRY(rka::launch_axpy(x, d, n, s));
+    // sweep measure: ||x - x_ref|| / ||x_ref||, else ||b - A x|| / ||b||
+    if (x_ref) {
+      HIP_TRY(rka::launch_sumsq(x, x_ref, n, part, acc2, s));
+    } else {
+      HIP_TRY(rka::launch_gemv(A, dtype, m, n, lda, vec_a, x, b, -1.0, r, s));
+      HIP_TRY(rka::launch_sumsq(r, nullptr, m, part, acc2, s));
+    }
+    double e2 = 0.0;
+    HIP_TRY(hipMemcpyAsync(&e2, acc2, sizeof e2, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    rel = sqrt(e2 / ref2);
+    if (sweep_measure) sweep_measure[sw] = rel;
+    sweeps = sw + 1;
+    if (!isfinite(rel)) {
+      status = RKA_EDIVERGED;
+      fail(status, "the sweep measure became non-finite");
+      break;
+    }
+    if (o->tol > 0.0 && rel <= o->tol) {
+      status = RKA_OK;
+      break;
+    }
+  }
+  sc.release();
+  HIP_TRY(hipStreamSynchronize(s));
+  if (info) {
+    info->sweeps = sweeps;
+    info->status = status;
+    info->rel = rel;
+    info->projections = projections;
+  }
+  return status;
 }
 
 const char* rka_status_string(int status) {

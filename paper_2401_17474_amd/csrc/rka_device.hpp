@@ -27,6 +27,21 @@ __device__ __forceinline__ double widen(bf16_t v) {
   return (double)__uint_as_float((uint32_t)v.bits << 16);
 }
 
+// Widening to an accumulation type C (double, or float for narrow storage):
+// exact for every storage type a C instance accepts.
+template <typename C>
+__device__ __forceinline__ C widen_c(double v) {
+  return (C)v;
+}
+template <typename C>
+__device__ __forceinline__ C widen_c(float v) {
+  return (C)v;
+}
+template <typename C>
+__device__ __forceinline__ C widen_c(bf16_t v) {
+  return (C)__uint_as_float((uint32_t)v.bits << 16);
+}
+
 // A "vec" is the unit one lane loads from a row: V elements of T, which is
 // 16 bytes on the vector path and one element on the scalar path.
 template <typename T, int V>
@@ -54,6 +69,17 @@ __device__ __forceinline__ double raw_elem(const typename Vec<T, V>::raw_t& r, i
   } u;
   u.raw = r;
   return widen(u.el[e]);
+}
+
+// Element e of a raw vec, widened to the accumulation type C.
+template <typename C, typename T, int V>
+__device__ __forceinline__ C raw_elem_c(const typename Vec<T, V>::raw_t& r, int e) {
+  union {
+    typename Vec<T, V>::raw_t raw;
+    T el[V];
+  } u;
+  u.raw = r;
+  return widen_c<C>(u.el[e]);
 }
 
 // ---------------------------------------------------------------------------
@@ -89,21 +115,23 @@ __device__ __forceinline__ double draw_uniform(uint64_t seed, uint64_t k, uint32
 // the same tree on every lane, so every lane ends with the bitwise-same sum.
 // Blocks must be a whole number of waves.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
+template <typename U>
+__device__ __forceinline__ U wave_sum(U v) {
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
   return v;
 }
 
 // Sum over the block; every thread receives the same value.  `scratch` holds
-// at least blockDim.x / 64 doubles of LDS and is free for reuse on return.
-__device__ __forceinline__ double block_sum(double v, double* scratch) {
+// at least blockDim.x / 64 values of LDS and is free for reuse on return.
+template <typename U>
+__device__ __forceinline__ U block_sum(U v, U* scratch) {
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const int nw = blockDim.x / kWave;
   v = wave_sum(v);
   if (lane == 0) scratch[wid] = v;
   __syncthreads();
-  double s = 0.0;
+  U s = 0;
   for (int i = 0; i < nw; ++i) s += scratch[i];
   __syncthreads();
   return s;
@@ -144,6 +172,24 @@ struct CoherentBuf {
                                           kCoherentSC1);
   }
 };
+
+// The same for 4-byte elements (FP32 worker iterates).
+struct CoherentBuf32 {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ CoherentBuf32(const float* base, int64_t count)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, (int)(count * 4),
+                                            kRawBufferWord3)) {}
+  __device__ __forceinline__ float load(int64_t i) const {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)(i * 4), 0,
+                                                                         kCoherentSC1));
+  }
+  __device__ __forceinline__ void store(int64_t i, float v) const {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)(i * 4), 0,
+                                          kCoherentSC1);
+  }
+};
+template <typename U>
+using CoherentOf = typename std::conditional<sizeof(U) == 8, CoherentBuf, CoherentBuf32>::type;
 
 // Tagged exchange slots: a double travels as two 64-bit words, each holding
 // 32 payload bits and a 32-bit tag (the iteration it belongs to).  A word is

@@ -49,6 +49,7 @@ struct SolveShape {
   int num_cu;
   int grid;       // requested workgroups of the iteration kernel (0 = automatic)
   int allreduce;  // RKA partial-dot exchange: 0 automatic, 1 all-gather, 2 two barriers
+  int acc;        // accumulation type: 0 FP64, 1 FP32 (narrow storage only)
 };
 
 // Returns false when q rows of a slice do not fit the kernel's register tile.
@@ -71,8 +72,9 @@ struct RkabGeom {
   size_t lds;  // dynamic LDS bytes
 };
 bool rkab_plan(const SolveShape& sh, RkabGeom* geo);
+// vbuf: q x n worker iterates in the accumulation type.
 hipError_t launch_rkab_chunk(const SolveShape& sh, const RkabGeom& geo, const RowRec* rec,
-                             int64_t k0, int64_t K, int64_t check_every, double* vbuf,
+                             int64_t k0, int64_t K, int64_t check_every, void* vbuf,
                              double* part, unsigned* bar, DevStatus* st, hipStream_t s);
 
 // --- stopping measures (rka_iter.hip) ---------------------------------------
@@ -86,5 +88,21 @@ hipError_t launch_ref_norm(const double* ref, int64_t len, double tol, DevStatus
 hipError_t launch_measure(const SolveShape& sh, int64_t k, double* part, DevStatus* st,
                           hipStream_t s);
 int resid_blocks(int64_t m);
+
+// --- dense FP64 steps (rka_dense.hip) --------------------------------------
+// out_i = (c ? c_i : 0) + gamma * <M_i, v>, rows x cols, FP64 accumulation.
+hipError_t launch_gemv(const void* M, int dtype, int64_t rows, int64_t cols, int64_t ld,
+                       bool vec_ok, const double* v, const double* c, double gamma, double* out,
+                       hipStream_t s);
+hipError_t launch_transpose(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, void* At,
+                            int64_t ldat, hipStream_t s);
+hipError_t launch_axpy(double* x, const double* d, int64_t n, hipStream_t s);
+// out[0] = sum (a - b)^2 (b may be NULL); part holds sumsq_part_len() doubles
+int sumsq_part_len();
+hipError_t launch_sumsq(const double* a, const double* b, int64_t len, double* part, double* out,
+                        hipStream_t s);
+// out[i, j] = r_i lam_j - z_i x_j; out_dtype 0 = FP64, 1 = FP32
+hipError_t launch_rank2(int64_t m, int64_t n, const double* r, const double* lam, const double* z,
+                        const double* x, void* out, int out_dtype, int64_t ldo, hipStream_t s);
 
 }  // namespace rka

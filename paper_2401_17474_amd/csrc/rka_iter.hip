@@ -47,7 +47,11 @@ constexpr int kPollMax = 4;  // tagged slots one thread polls per exchange
 
 constexpr int kMaxColThreads = 512;
 
-template <typename T, int V, int RPT, bool GATHER>
+// C is the accumulation type: double, or float for narrow storage (the
+// inner solves of the precision form).  With C = float the slice of x, the
+// products and the in-workgroup sums are FP32; the per-workgroup partial
+// sums are combined across workgroups in FP64 and rounded once.
+template <typename T, typename C, int V, int RPT, bool GATHER>
 __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
   using raw_t = typename Vec<T, V>::raw_t;
   if (p.st->done) return;
@@ -62,17 +66,22 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
   const bool gather = GATHER && G > 1;
 
   extern __shared__ double lds[];
-  double* P = lds;                    // q * nsv      row partials per vec
-  double* U = P + (size_t)q * nsv;    // NT * V       update partials per thread
-  double* XS = U + (size_t)NT * V;    // nsv * V      new slice of x
-  double* E = XS + (size_t)nsv * V;   // nsv          error partials
+  double* E = lds;                    // nsv          error partials
   double* RED = E + nsv;              // 16           block_sum scratch
   double* SC = RED + 16;              // q + 1        dot totals, then scales
   double* PG = SC + q + 1;            // G * (q+1)    gathered partials (gather only)
+  C* P = (C*)(PG + (gather ? (size_t)G * (q + 1) : 0));  // q * nsv   row partials per vec
+  C* U = P + (size_t)q * nsv;         // NT * V       update partials per thread
+  C* XS = U + (size_t)NT * V;         // nsv * V      new slice of x
 
-  double xv[V];
+  // the scale alpha (b_i - <a_i, x>) / ||a_i||^2 in the accumulation type
+  auto scale_of = [&](double bi, double wi, double D) -> double {
+    return (double)((C)p.alpha * ((C)bi - (C)D) / (C)wi);
+  };
+
+  C xv[V];
 #pragma unroll
-  for (int e = 0; e < V; ++e) xv[e] = colv ? p.x[cv * V + e] : 0.0;
+  for (int e = 0; e < V; ++e) xv[e] = colv ? (C)p.x[cv * V + e] : (C)0;
 
   // Loads are unconditional (indices clamped to valid rows/vecs; the surplus
   // entries are masked in the arithmetic): a load under a branch would make
@@ -115,9 +124,9 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int r = rgi + rg * i;
-      double s = 0.0;  // xv is 0 past the last column
+      C s = 0;  // xv is 0 past the last column
 #pragma unroll
-      for (int e = 0; e < V; ++e) s = fma(raw_elem<T, V>(a[i], e), xv[e], s);
+      for (int e = 0; e < V; ++e) s = fma(raw_elem_c<C, T, V>(a[i], e), xv[e], s);
       if (active && r < q) P[r * nsv + j] = s;
     }
     if (check && active && rgi == 0) {
@@ -127,7 +136,7 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
       if (colv) {
 #pragma unroll
         for (int e = 0; e < V; ++e) {
-          const double d = xv[e] - p.x_ref[cv * V + e];
+          const double d = (double)xv[e] - p.x_ref[cv * V + e];
           s = fma(d, d, s);
         }
       }
@@ -135,12 +144,12 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
     }
     __syncthreads();
     for (int r = t; r < q; r += NT) {
-      double d = 0.0;
+      C d = 0;
       for (int jj = 0; jj < nsv; ++jj) d += P[r * nsv + jj];
       if (G > 1)
-        part.put((int64_t)g * (q + 1) + r, d, tag);
+        part.put((int64_t)g * (q + 1) + r, (double)d, tag);
       else
-        SC[r] = d;
+        SC[r] = (double)d;
     }
     if (check && t == 0) {
       double s = 0.0;
@@ -194,7 +203,7 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
           if (r < q) {
             const double rb = r == t ? mine_b : p.rec[kl * q + r].b;
             const double rw = r == t ? mine_w : p.rec[kl * q + r].wn;
-            SC[r] = p.alpha * (rb - D) / rw;
+            SC[r] = scale_of(rb, rw, D);
           } else {
             SC[r] = D;
           }
@@ -232,7 +241,7 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
             v += pv;
           }
           const double D = block_sum(v, RED);
-          if (t == 0) scal.put(r, r < q ? p.alpha * (rr.b - D) / rr.wn : D, tag);
+          if (t == 0) scal.put(r, r < q ? scale_of(rr.b, rr.wn, D) : D, tag);
         }
         // phase 2: every workgroup polls the q scales (one slot per thread
         // per round; one round unless q + 1 exceeds the thread count)
@@ -266,7 +275,7 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
       for (int r = t; r < q; r += NT) {
         const double rb = r == t ? mine_b : p.rec[kl * q + r].b;
         const double rw = r == t ? mine_w : p.rec[kl * q + r].wn;
-        SC[r] = p.alpha * (rb - SC[r]) / rw;
+        SC[r] = scale_of(rb, rw, SC[r]);
       }
     }
     __syncthreads();
@@ -286,15 +295,15 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
       }
     }
     // x_slice += (1/q) sum_r s_r * A[i_r, slice]   (fixed row order)
-    double u[V];
+    C u[V];
 #pragma unroll
-    for (int e = 0; e < V; ++e) u[e] = 0.0;
+    for (int e = 0; e < V; ++e) u[e] = 0;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int r = rgi + rg * i;
-      const double s = (colv && r < q) ? SC[r < q ? r : 0] : 0.0;
+      const C s = (colv && r < q) ? (C)SC[r < q ? r : 0] : (C)0;
 #pragma unroll
-      for (int e = 0; e < V; ++e) u[e] = fma(s, raw_elem<T, V>(a[i], e), u[e]);
+      for (int e = 0; e < V; ++e) u[e] = fma(s, raw_elem_c<C, T, V>(a[i], e), u[e]);
     }
     if (active) {
 #pragma unroll
@@ -304,9 +313,9 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
     if (colv && rgi == 0) {
 #pragma unroll
       for (int e = 0; e < V; ++e) {
-        double acc = 0.0;
+        C acc = 0;
         for (int gg = 0; gg < rg; ++gg) acc += U[(gg * nsv + j) * V + e];
-        xv[e] = fma(acc, p.inv_q, xv[e]);
+        xv[e] = fma(acc, (C)p.inv_q, xv[e]);
         XS[j * V + e] = xv[e];
       }
     }
@@ -327,7 +336,7 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
   }
   if (colv && rgi == 0) {
 #pragma unroll
-    for (int e = 0; e < V; ++e) p.x[cv * V + e] = xv[e];
+    for (int e = 0; e < V; ++e) p.x[cv * V + e] = (double)xv[e];
   }
   if (!stopped && g == 0 && t == 0) p.st->iterations = p.k0 + p.K;
 }
@@ -375,7 +384,7 @@ bool rka_col_plan(const SolveShape& sh, RkaColGeom* geo) {
   const int rpt = rpt_bucket((sh.q + rg - 1) / rg);
   if (rpt == 0) return false;
   // largest spill-free bucket per storage type; wider q runs on the worker kernel
-  const int rpt_max = !sh.vec_ok ? 11 : (sh.dtype == 0 ? 11 : 4);
+  const int rpt_max = !sh.vec_ok ? 11 : ((sh.dtype == 0 || (sh.acc == 1 && sh.dtype == 1)) ? 11 : 4);
   if (rpt > rpt_max) return false;
   const int nt = ((nsv * rg + kWave - 1) / kWave) * kWave;
   int gather = 0;
@@ -394,8 +403,9 @@ bool rka_col_plan(const SolveShape& sh, RkaColGeom* geo) {
     if (!gather && sh.q + 1 > kPollMax * nt) return false;
   }
   const size_t pg = gather ? (size_t)G * (sh.q + 1) : 0;
-  const size_t lds = sizeof(double) * ((size_t)sh.q * nsv + (size_t)nt * V + (size_t)nsv * V +
-                                       nsv + 16 + sh.q + 1 + pg);
+  const size_t csz = sh.acc == 1 ? sizeof(float) : sizeof(double);
+  const size_t lds = sizeof(double) * (nsv + 16 + sh.q + 1 + pg) +
+                     csz * ((size_t)sh.q * nsv + (size_t)nt * V + (size_t)nsv * V);
   if (lds > 64 * 1024) return false;
   geo->G = G;
   geo->nsv = nsv;
@@ -407,22 +417,22 @@ bool rka_col_plan(const SolveShape& sh, RkaColGeom* geo) {
   return true;
 }
 
-template <typename T, int V, bool GATHER>
+template <typename T, typename C, int V, bool GATHER>
 static const void* col_fn(int rpt) {
   switch (rpt) {
-    case 1: return (const void*)rka_col_kernel<T, V, 1, GATHER>;
-    case 2: return (const void*)rka_col_kernel<T, V, 2, GATHER>;
-    case 4: return (const void*)rka_col_kernel<T, V, 4, GATHER>;
-    default: return (const void*)rka_col_kernel<T, V, 8, GATHER>;
+    case 1: return (const void*)rka_col_kernel<T, C, V, 1, GATHER>;
+    case 2: return (const void*)rka_col_kernel<T, C, V, 2, GATHER>;
+    case 4: return (const void*)rka_col_kernel<T, C, V, 4, GATHER>;
+    default: return (const void*)rka_col_kernel<T, C, V, 8, GATHER>;
   }
 }
 
-template <typename T, int V>
+template <typename T, typename C, int V>
 static hipError_t launch_col_t(const RkaColGeom& geo, RkaColArgs& a, hipStream_t s) {
   void* args[] = {&a};
-  const void* fn = geo.rpt == 11 ? (const void*)rka_col_kernel<T, V, 11, false>
-                   : geo.gather  ? col_fn<T, V, true>(geo.rpt)
-                                 : col_fn<T, V, false>(geo.rpt);
+  const void* fn = geo.rpt == 11 ? (const void*)rka_col_kernel<T, C, V, 11, false>
+                   : geo.gather  ? col_fn<T, C, V, true>(geo.rpt)
+                                 : col_fn<T, C, V, false>(geo.rpt);
   return hipLaunchCooperativeKernel(fn, dim3(geo.G), dim3(geo.nt), args, (unsigned)geo.lds, s);
 }
 
@@ -451,11 +461,23 @@ hipError_t launch_rka_chunk(const SolveShape& sh, const RkaColGeom& geo, const R
   a.part = part;
   a.scal = scal;
   a.st = st;
+  if (sh.acc == 1) {
+    if (sh.dtype == 1)
+      return sh.vec_ok ? launch_col_t<float, float, 4>(geo, a, s)
+                       : launch_col_t<float, float, 1>(geo, a, s);
+    return sh.vec_ok ? launch_col_t<bf16_t, float, 8>(geo, a, s)
+                     : launch_col_t<bf16_t, float, 1>(geo, a, s);
+  }
   switch (sh.dtype) {
-    case 0: return sh.vec_ok ? launch_col_t<double, 2>(geo, a, s) : launch_col_t<double, 1>(geo, a, s);
-    case 1: return sh.vec_ok ? launch_col_t<float, 4>(geo, a, s) : launch_col_t<float, 1>(geo, a, s);
+    case 0:
+      return sh.vec_ok ? launch_col_t<double, double, 2>(geo, a, s)
+                       : launch_col_t<double, double, 1>(geo, a, s);
+    case 1:
+      return sh.vec_ok ? launch_col_t<float, double, 4>(geo, a, s)
+                       : launch_col_t<float, double, 1>(geo, a, s);
     default:
-      return sh.vec_ok ? launch_col_t<bf16_t, 8>(geo, a, s) : launch_col_t<bf16_t, 1>(geo, a, s);
+      return sh.vec_ok ? launch_col_t<bf16_t, double, 8>(geo, a, s)
+                       : launch_col_t<bf16_t, double, 1>(geo, a, s);
   }
 }
 

@@ -29,7 +29,7 @@ struct RkabArgs {
   double alpha;
   int32_t q, bs, G, ns;
   int64_t k0, K, check_every;
-  double* vbuf;  // q x (nvec * V): the workers' iterates
+  void* vbuf;    // q x (nvec * V): the workers' iterates (accumulation type)
   double* part;  // G
   unsigned* bar;
   DevStatus* st;
@@ -47,7 +47,11 @@ constexpr int kStage = 256;  // row records staged in LDS per window slot
 // sliding window of two kStage-entry slots, so that inside the projection
 // loop the only global loads are the row data themselves and a projection
 // never waits for anything but its own row.
-template <typename T, int V, int VPT, bool VLDS>
+//
+// C is the accumulation type: double, or float for narrow storage (the inner
+// solves of the precision form), in which case v, the dot products, the
+// scales and the average are FP32.
+template <typename T, typename C, int V, int VPT, bool VLDS>
 __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
   using raw_t = typename Vec<T, V>::raw_t;
   constexpr int NT = kRkabThreads;
@@ -56,13 +60,16 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
   const int t = threadIdx.x, g = blockIdx.x;
   const int64_t nvec = p.nvec, n = nvec * V;
   __shared__ double RED[NT / kWave];
+  __shared__ C REDC[NT / kWave];
   __shared__ double Lb[2 * kStage], Lw[2 * kStage];
   __shared__ int64_t Lr[2 * kStage];
-  __shared__ double AV[NT];  // partial sums of the average
-  extern __shared__ double vlds[];
+  __shared__ C AV[NT];  // partial sums of the average
+  extern __shared__ double vlds_raw[];
+  C* vlds = (C*)vlds_raw;
+  C* vbuf = (C*)p.vbuf;
 
-  double vreg[VLDS ? 1 : VPT][V];
-  auto vat = [&](int i, int e) -> double& {
+  C vreg[VLDS ? 1 : VPT][V];
+  auto vat = [&](int i, int e) -> C& {
     if constexpr (VLDS)
       return vlds[(t + (int64_t)NT * i) * V + e];
     else
@@ -100,20 +107,20 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
   };
   // v += alpha (b_i - <a_i, v>) / ||a_i||^2 a_i   (v is 0 on masked lanes)
   auto project = [&](const raw_t (&src)[VPT], int j) {
-    double d = 0.0;
+    C d = 0;
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
 #pragma unroll
-      for (int e = 0; e < V; ++e) d = fma(raw_elem<T, V>(src[i], e), vat(i, e), d);
+      for (int e = 0; e < V; ++e) d = fma(raw_elem_c<C, T, V>(src[i], e), vat(i, e), d);
     }
-    const double D = block_sum(d, RED);
+    const C D = block_sum(d, REDC);
     const int sl = slot(j);
-    const double s = p.alpha * (Lb[sl] - D) / Lw[sl];
+    const C s = (C)p.alpha * ((C)Lb[sl] - D) / (C)Lw[sl];
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
-      const double si = (t + (int64_t)NT * i < nvec) ? s : 0.0;
+      const C si = (t + (int64_t)NT * i < nvec) ? s : (C)0;
 #pragma unroll
-      for (int e = 0; e < V; ++e) vat(i, e) = fma(si, raw_elem<T, V>(src[i], e), vat(i, e));
+      for (int e = 0; e < V; ++e) vat(i, e) = fma(si, raw_elem_c<C, T, V>(src[i], e), vat(i, e));
     }
   };
 
@@ -146,7 +153,7 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
       for (int i = 0; i < VPT; ++i) {
         const int64_t c = t + (int64_t)NT * i;
 #pragma unroll
-        for (int e = 0; e < V; ++e) vat(i, e) = xb.load(c * V + e);
+        for (int e = 0; e < V; ++e) vat(i, e) = (C)xb.load(c * V + e);
       }
       int next_blk = 2;
       // block b goes into the slot of block b-2 once rows of block b-1 are
@@ -183,7 +190,7 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
         stage_first(kl, w + p.G);
       else if (kl + 1 < p.K)
         stage_first(kl + 1, g);
-      const CoherentBuf vw(p.vbuf + (size_t)w * n, n);  // stores past the end are dropped
+      const CoherentOf<C> vw(vbuf + (size_t)w * n, n);  // stores past the end are dropped
 #pragma unroll
       for (int i = 0; i < VPT; ++i) {
         const int64_t c = t + (int64_t)NT * i;
@@ -222,35 +229,35 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
     double err = 0.0;
     if (tpe == 1) {
       for (int64_t ci = e0 + t; ci < e1; ci += NT) {
-        double acc = 0.0;
+        C acc = 0;
         int w = 0;
         for (; w + 8 <= p.q; w += 8) {
-          double vv[8];
+          C vv[8];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) vv[u] = CoherentBuf(p.vbuf + (size_t)(w + u) * n, n).load(ci);
+          for (int u = 0; u < 8; ++u) vv[u] = CoherentOf<C>(vbuf + (size_t)(w + u) * n, n).load(ci);
 #pragma unroll
           for (int u = 0; u < 8; ++u) acc += vv[u];
         }
-        for (; w < p.q; ++w) acc += CoherentBuf(p.vbuf + (size_t)w * n, n).load(ci);
-        const double xn = acc / (double)p.q;
-        xb.store(ci, xn);
+        for (; w < p.q; ++w) acc += CoherentOf<C>(vbuf + (size_t)w * n, n).load(ci);
+        const C xn = acc / (C)p.q;
+        xb.store(ci, (double)xn);
         if (check) {
-          const double dd = xn - p.x_ref[ci];
+          const double dd = (double)xn - p.x_ref[ci];
           err = fma(dd, dd, err);
         }
       }
     } else {
       const int le = t / tpe, sub = t % tpe;
       const int64_t ci = e0 + (le < E ? le : 0);
-      double acc = 0.0;
+      C acc = 0;
       if (le < E) {
         for (int w0 = sub; w0 < p.q; w0 += 8 * tpe) {
-          double vv[8];
+          C vv[8];
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
             const int w = w0 + u * tpe;
-            const double val = CoherentBuf(p.vbuf + (size_t)(w < p.q ? w : p.q - 1) * n, n).load(ci);
-            vv[u] = w < p.q ? val : 0.0;
+            const C val = CoherentOf<C>(vbuf + (size_t)(w < p.q ? w : p.q - 1) * n, n).load(ci);
+            vv[u] = w < p.q ? val : (C)0;
           }
 #pragma unroll
           for (int u = 0; u < 8; ++u) acc += vv[u];
@@ -259,12 +266,12 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
       AV[t] = acc;
       __syncthreads();
       if (t < E) {
-        double sum = 0.0;
+        C sum = 0;
         for (int u = 0; u < tpe; ++u) sum += AV[t * tpe + u];
-        const double xn = sum / (double)p.q;
-        xb.store(e0 + t, xn);
+        const C xn = sum / (C)p.q;
+        xb.store(e0 + t, (double)xn);
         if (check) {
-          const double dd = xn - p.x_ref[e0 + t];
+          const double dd = (double)xn - p.x_ref[e0 + t];
           err = fma(dd, dd, err);
         }
       }
@@ -307,13 +314,16 @@ static int vpt_bucket(int64_t need) {
   return 0;
 }
 
-// largest spill-free bucket with v in registers / with v in LDS
-static int vpt_limit_reg(int dtype, int V) {
+// largest spill-free bucket with v in registers / with v in LDS, per storage
+// type and accumulation type
+static int vpt_limit_reg(int dtype, int V, int acc) {
   if (V == 1) return dtype == 0 ? 12 : 16;
+  if (acc == 1) return dtype == 2 ? 4 : 6;
   return dtype == 2 ? 3 : 6;
 }
-static int vpt_limit_lds(int dtype, int V) {
+static int vpt_limit_lds(int dtype, int V, int acc) {
   if (V == 1) return 16;
+  if (acc == 1) return dtype == 2 ? 4 : 8;
   return dtype == 0 ? 10 : (dtype == 1 ? 6 : 3);
 }
 constexpr size_t kMaxLds = 144 * 1024;  // 160 KiB minus the static LDS above
@@ -324,11 +334,11 @@ bool rkab_plan(const SolveShape& sh, RkabGeom* geo) {
   const int64_t nvec = sh.n / V;
   const int vpt = vpt_bucket((nvec + kRkabThreads - 1) / kRkabThreads);
   if (vpt == 0) return false;
-  bool vlds = vpt > vpt_limit_reg(sh.dtype, V);
+  bool vlds = vpt > vpt_limit_reg(sh.dtype, V, sh.acc);
   size_t lds = 0;
   if (vlds) {
-    if (vpt > vpt_limit_lds(sh.dtype, V)) return false;
-    lds = (size_t)vpt * kRkabThreads * V * sizeof(double);
+    if (vpt > vpt_limit_lds(sh.dtype, V, sh.acc)) return false;
+    lds = (size_t)vpt * kRkabThreads * V * (sh.acc == 1 ? sizeof(float) : sizeof(double));
     if (lds > kMaxLds) return false;
   }
   const int target = sh.grid > 0 ? sh.grid : sh.num_cu;
@@ -342,26 +352,27 @@ bool rkab_plan(const SolveShape& sh, RkabGeom* geo) {
   return true;
 }
 
-template <typename T, int V, bool VLDS>
+template <typename T, typename C, int V, bool VLDS>
 static const void* rkab_fn(int vpt) {
   switch (vpt) {
-    case 1: return (const void*)rkab_kernel<T, V, 1, VLDS>;
-    case 2: return (const void*)rkab_kernel<T, V, 2, VLDS>;
-    case 3: return (const void*)rkab_kernel<T, V, 3, VLDS>;
-    case 4: return (const void*)rkab_kernel<T, V, 4, VLDS>;
-    case 6: return (const void*)rkab_kernel<T, V, 6, VLDS>;
-    case 8: return (const void*)rkab_kernel<T, V, 8, VLDS>;
-    case 10: return (const void*)rkab_kernel<T, V, 10, VLDS>;
-    case 12: return (const void*)rkab_kernel<T, V, 12, VLDS>;
-    case 16: return (const void*)rkab_kernel<T, V, 16, VLDS>;
-    default: return (const void*)rkab_kernel<T, V, 20, VLDS>;
+    case 1: return (const void*)rkab_kernel<T, C, V, 1, VLDS>;
+    case 2: return (const void*)rkab_kernel<T, C, V, 2, VLDS>;
+    case 3: return (const void*)rkab_kernel<T, C, V, 3, VLDS>;
+    case 4: return (const void*)rkab_kernel<T, C, V, 4, VLDS>;
+    case 6: return (const void*)rkab_kernel<T, C, V, 6, VLDS>;
+    case 8: return (const void*)rkab_kernel<T, C, V, 8, VLDS>;
+    case 10: return (const void*)rkab_kernel<T, C, V, 10, VLDS>;
+    case 12: return (const void*)rkab_kernel<T, C, V, 12, VLDS>;
+    case 16: return (const void*)rkab_kernel<T, C, V, 16, VLDS>;
+    default: return (const void*)rkab_kernel<T, C, V, 20, VLDS>;
   }
 }
 
-template <typename T, int V>
+template <typename T, typename C, int V>
 static hipError_t launch_rkab_t(const RkabGeom& geo, RkabArgs& a, hipStream_t s) {
   void* args[] = {&a};
-  const void* fn = geo.vlds ? rkab_fn<T, V, true>(geo.vpt) : rkab_fn<T, V, false>(geo.vpt);
+  const void* fn =
+      geo.vlds ? rkab_fn<T, C, V, true>(geo.vpt) : rkab_fn<T, C, V, false>(geo.vpt);
   if (geo.lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)geo.lds);
     if (e != hipSuccess) return e;
@@ -370,7 +381,7 @@ static hipError_t launch_rkab_t(const RkabGeom& geo, RkabArgs& a, hipStream_t s)
 }
 
 hipError_t launch_rkab_chunk(const SolveShape& sh, const RkabGeom& geo, const RowRec* rec,
-                             int64_t k0, int64_t K, int64_t check_every, double* vbuf,
+                             int64_t k0, int64_t K, int64_t check_every, void* vbuf,
                              double* part, unsigned* bar, DevStatus* st, hipStream_t s) {
   const int esz = sh.dtype == 0 ? 8 : (sh.dtype == 1 ? 4 : 2);
   const int V = sh.vec_ok ? 16 / esz : 1;
@@ -397,13 +408,23 @@ hipError_t launch_rkab_chunk(const SolveShape& sh, const RkabGeom& geo, const Ro
     hipError_t e = hipMemsetAsync(bar, 0, sizeof(unsigned), s);
     if (e != hipSuccess) return e;
   }
+  if (sh.acc == 1) {
+    if (sh.dtype == 1)
+      return sh.vec_ok ? launch_rkab_t<float, float, 4>(geo, a, s)
+                       : launch_rkab_t<float, float, 1>(geo, a, s);
+    return sh.vec_ok ? launch_rkab_t<bf16_t, float, 8>(geo, a, s)
+                     : launch_rkab_t<bf16_t, float, 1>(geo, a, s);
+  }
   switch (sh.dtype) {
     case 0:
-      return sh.vec_ok ? launch_rkab_t<double, 2>(geo, a, s) : launch_rkab_t<double, 1>(geo, a, s);
+      return sh.vec_ok ? launch_rkab_t<double, double, 2>(geo, a, s)
+                       : launch_rkab_t<double, double, 1>(geo, a, s);
     case 1:
-      return sh.vec_ok ? launch_rkab_t<float, 4>(geo, a, s) : launch_rkab_t<float, 1>(geo, a, s);
+      return sh.vec_ok ? launch_rkab_t<float, double, 4>(geo, a, s)
+                       : launch_rkab_t<float, double, 1>(geo, a, s);
     default:
-      return sh.vec_ok ? launch_rkab_t<bf16_t, 8>(geo, a, s) : launch_rkab_t<bf16_t, 1>(geo, a, s);
+      return sh.vec_ok ? launch_rkab_t<bf16_t, double, 8>(geo, a, s)
+                       : launch_rkab_t<bf16_t, double, 1>(geo, a, s);
   }
 }
 

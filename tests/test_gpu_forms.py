@@ -1,0 +1,231 @@
+"""GPU parity of the precision-form building blocks, through the C ABI:
+FP32-accumulation inner solves, the FP64 GEMV / transpose / rank-2 steps, and
+the refinement sweeps, each against the oracle on the same seeded inputs.
+
+Bars:
+  * transpose: bit-exact;
+  * FP64 GEMV: every entry within 2 n u64 sum_j |M_ij v_j| of the oracle's
+    (the two sum in different orders; each partial sum errs by at most that);
+  * FP32 inner solves (same index stream): norm-wise within 4 K bs n u32 of
+    the oracle's binary32 iteration -- each of the K bs projections perturbs
+    the iterate by at most a few n u32 relative on either side, and the
+    averaged projections do not expand the difference (alpha <= 1);
+  * refinement: the final x within 1e-12 of the oracle's refined x, and both
+    within 1e-12 of the exact solution (planted x*, or numpy's x_LS).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import DEV, assert_x_close, host, say, to_dev, vec
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+rka = pytest.importorskip("paper_2401_17474_amd")
+
+U32 = 2.0 ** -24
+U64 = 2.0 ** -53
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rka.lib()
+
+
+def _system(m, n, dtype, seed=1, noise=0.0):
+    A, xs, b = workloads.gaussian_system(m, n, seed=seed, noise_var=noise, dtype=dtype)
+    return np.array(A), xs, b
+
+
+def _odt(dtype):
+    return "bf16" if dtype == "bf16" else None
+
+
+def _widen(A, dtype):
+    return workloads.bf16_bits_to_f64(A) if dtype == "bf16" else A.astype(np.float64)
+
+
+# -- FP32-accumulation inner solves --------------------------------------------
+
+RKA32_CASES = [  # m, n, q, K, dtype, grid, allreduce
+    (600, 96, 8, 60, "f32", 0, 0),        # one workgroup
+    (700, 97, 4, 40, "f32", 0, 0),        # scalar path
+    (900, 4096, 8, 25, "f32", 0, 0),      # many workgroups
+    (900, 4096, 16, 20, "bf16", 0, 0),
+    (800, 2000, 11, 20, "f32", 16, 1),    # all-gather exchange
+    (800, 2000, 11, 20, "bf16", 16, 2),   # two-phase exchange
+    (500, 3000, 40, 10, "f32", 0, 0),     # 11-row bucket
+]
+
+
+@pytest.mark.parametrize("m,n,q,K,dtype,grid,ar", RKA32_CASES)
+def test_rka_fp32_inner_vs_oracle(m, n, q, K, dtype, grid, ar):
+    say(f"rka fp32 {dtype} {m}x{n} q={q} K={K} grid={grid} ar={ar}")
+    A, _, b = _system(m, n, dtype, seed=3, noise=0.01)
+    x, info, st = rka.solve_ex(to_dev(A, dtype), vec(b), method=0, q=q, max_iter=K, seed=5,
+                               grid=grid, allreduce=ar, accumulate=1)
+    assert info.status == rka.OK and st["accumulate"] == 1 and st["kernel"] == 1
+    w = oracle.row_norms(A, dtype=_odt(dtype))
+    idx = oracle.indices(w, 5, 0, K, q)
+    xo = oracle.rka_f32_given(A, b, np.zeros(n), idx, q=q, dtype=_odt(dtype))
+    xg = host(x)
+    gap = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+    assert gap <= 4 * K * n * U32, gap
+    # binary32 iterate, widened on the way out
+    assert np.array_equal(xg.astype(np.float32).astype(np.float64), xg)
+
+
+RKAB32_CASES = [  # m, n, q, bs, K, dtype
+    (600, 96, 4, 5, 10, "f32"),
+    (600, 97, 3, 4, 8, "bf16"),          # scalar path
+    (400, 8192, 8, 6, 4, "bf16"),
+    (300, 16000, 4, 5, 3, "f32"),        # iterate in LDS
+    (500, 2048, 300, 2, 2, "f32"),       # more workers than workgroups
+]
+
+
+@pytest.mark.parametrize("m,n,q,bs,K,dtype", RKAB32_CASES)
+def test_rkab_fp32_inner_vs_oracle(m, n, q, bs, K, dtype):
+    say(f"rkab fp32 {dtype} {m}x{n} q={q} bs={bs} K={K}")
+    A, _, b = _system(m, n, dtype, seed=4, noise=0.01)
+    x, info, st = rka.solve_ex(to_dev(A, dtype), vec(b), method=1, q=q, block_size=bs,
+                               max_iter=K, seed=6, accumulate=1)
+    assert info.status == rka.OK and st["accumulate"] == 1 and st["kernel"] == 2
+    w = oracle.row_norms(A, dtype=_odt(dtype))
+    idx = oracle.indices(w, 6, 0, K, q, bs)
+    xo = oracle.rkab_f32_given(A, b, np.zeros(n), idx, q=q, block_size=bs, dtype=_odt(dtype))
+    gap = np.linalg.norm(host(x) - xo) / np.linalg.norm(xo)
+    assert gap <= 4 * K * bs * n * U32, gap
+    if n == 16000:
+        assert st["variant"] == 1  # iterate kept in LDS
+
+
+def test_fp32_accumulation_needs_narrow_storage():
+    A, _, b = _system(50, 8, "f64")
+    with pytest.raises(rka.RKAError) as e:
+        rka.solve_ex(to_dev(A), vec(b), method=0, q=2, max_iter=3, accumulate=1)
+    assert e.value.status == rka.EINVAL
+
+
+def test_stream_id_selects_the_row_stream():
+    # dom = 1 draws the oracle's dom-1 stream (the refinement's column solves)
+    A, _, b = _system(500, 64, "f32", seed=7)
+    x, info, _ = rka.solve_ex(to_dev(A, "f32"), vec(b), method=0, q=4, max_iter=30, seed=9,
+                              accumulate=1, stream_id=1)
+    w = oracle.row_norms(A)
+    xo = oracle.rka_f32_given(A, b, np.zeros(64), oracle.indices(w, 9, 0, 30, 4, dom=1), q=4)
+    assert np.linalg.norm(host(x) - xo) <= 4 * 30 * 64 * U32 * np.linalg.norm(xo)
+
+
+# -- dense steps ---------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("rows,cols", [(1, 1), (5, 7), (513, 1000), (130, 4099), (64, 16)])
+def test_gemv_vs_oracle(dtype, rows, cols):
+    say(f"gemv {dtype} {rows}x{cols}")
+    M, _, _ = _system(rows, cols, dtype, seed=8)
+    rng = np.random.default_rng(8)
+    v, c = rng.standard_normal(cols), rng.standard_normal(rows)
+    y = host(rka.gemv(to_dev(M, dtype), vec(v), c=vec(c), gamma=-1.0))
+    yo = oracle.gemv(M, v, c=c, gamma=-1.0, dtype=_odt(dtype))
+    bound = 2 * cols * U64 * (np.abs(_widen(M, dtype)) @ np.abs(v)) + 4 * U64 * np.abs(c)
+    assert np.all(np.abs(y - yo) <= bound)
+    y2 = host(rka.gemv(to_dev(M, dtype), vec(v)))
+    yo2 = oracle.gemv(M, v, dtype=_odt(dtype))
+    assert np.all(np.abs(y2 - yo2) <= bound)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("m,n", [(1, 1), (63, 65), (200, 130), (64, 64), (1000, 3)])
+def test_transpose_bitwise(dtype, m, n):
+    say(f"transpose {dtype} {m}x{n}")
+    A, _, _ = _system(m, n, dtype, seed=9)
+    At = rka.transpose(to_dev(A, dtype))
+    got = host(At.view(torch.int16) if dtype == "bf16" else At)
+    want = oracle.transpose(A, dtype=_odt(dtype))
+    if dtype == "bf16":
+        want = want.view(np.int16)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("out", ["f64", "f32"])
+def test_lsq_grad_A_vs_numpy(out):
+    rng = np.random.default_rng(10)
+    m, n = 333, 77
+    r, z = rng.standard_normal(m), rng.standard_normal(m)
+    lam, x = rng.standard_normal(n), rng.standard_normal(n)
+    dA = host(rka.lsq_grad_A(vec(r), vec(lam), vec(z), vec(x),
+                             dtype=torch.float64 if out == "f64" else torch.float32))
+    want = np.outer(r, lam) - np.outer(z, x)
+    scale = np.abs(np.outer(r, lam)) + np.abs(np.outer(z, x))
+    u = U64 if out == "f64" else U32
+    assert np.all(np.abs(dA - want) <= 4 * u * scale + 1e-300)
+
+
+# -- refinement ----------------------------------------------------------------
+
+REFINE_CASES = [  # m, n, dtype, method, bs, q, inner, sweeps, noise, range_iters
+    (1500, 96, "f32", 0, 1, 8, 2000, 4, 0.0, 0),
+    (1500, 96, "bf16", 0, 1, 8, 2000, 4, 0.0, 0),
+    (1500, 96, "f32", 1, 8, 8, 500, 4, 0.0, 0),
+    (1200, 80, "f32", 0, 1, 8, 2000, 4, 0.01, 2000),
+    (1200, 80, "bf16", 1, 5, 8, 400, 4, 0.01, 2000),
+    (20000, 512, "f32", 0, 1, 64, 600, 3, 0.0, 0),     # many workgroups, alpha*
+]
+
+
+@pytest.mark.parametrize("m,n,dtype,method,bs,q,inner,sweeps,noise,riters", REFINE_CASES)
+def test_refine_vs_oracle(m, n, dtype, method, bs, q, inner, sweeps, noise, riters):
+    say(f"refine {dtype} {m}x{n} method={method} bs={bs} q={q} inner={inner} "
+        f"sweeps={sweeps} noise={noise} range={riters}")
+    A, xs, b = _system(m, n, dtype, seed=11, noise=noise)
+    Aw = _widen(A, dtype)
+    xt = xs if noise == 0.0 else np.linalg.lstsq(Aw, b, rcond=None)[0]
+    alpha = 1.0
+    if q == 64:  # Eq. (6) from the extreme singular values
+        sv = np.linalg.svd(Aw, compute_uv=False)
+        F = np.sum(sv ** 2)
+        alpha = rka.alpha_star(sv[-1] ** 2 / F, sv[0] ** 2 / F, q)
+    Ad = to_dev(A, dtype)
+    At = rka.transpose(Ad) if riters else None
+    x, info = rka.refine_solve(Ad, vec(b), At=At, method=method, q=q, block_size=bs,
+                               accumulate=1, alpha=alpha, inner_iters=inner, range_iters=riters,
+                               range_q=q, max_sweeps=sweeps, seed=13, x_ref=vec(xt))
+    xo, mo = oracle.refine(A, b, method=method, q=q, block_size=bs, acc32=1, alpha=alpha,
+                           inner_iters=inner, range_iters=riters, range_q=q, sweeps=sweeps,
+                           seed=13, x_ref=xt, dtype=_odt(dtype))
+    xg = host(x)
+    assert info.status == rka.OK and info.sweeps == sweeps
+    # the first sweep's measure agrees up to binary32 rounding of the inner
+    # solve (relative, or absolute once the inner solve reaches its floor)
+    assert abs(info.measures[0] - mo[0]) <= 1e-3 * mo[0] + 1e-5
+    assert_x_close(xg, xo, 1e-12, "refined x vs oracle")
+    assert_x_close(xg, xt, 1e-12, "refined x vs exact")
+
+
+def test_refine_stops_at_tol_and_reports_residual():
+    A, xs, b = _system(1500, 96, "f32", seed=12)
+    x, info = rka.refine_solve(to_dev(A, "f32"), vec(b), q=8, inner_iters=1000, max_sweeps=8,
+                               tol=1e-9, seed=2)
+    assert info.status == rka.OK and info.sweeps < 8 and info.measures[-1] <= 1e-9
+    Aw = A.astype(np.float64)
+    res = np.linalg.norm(b - Aw @ host(x)) / np.linalg.norm(b)
+    assert abs(res - info.measures[-1]) <= 1e-3 * max(res, 1e-14) + 1e-15
+
+
+def test_refine_errors():
+    A, _, b = _system(100, 10, "f32")
+    Ad = to_dev(A, "f32")
+    for kw in (dict(range_iters=10), dict(q=0), dict(max_sweeps=0), dict(alpha=-1.0)):
+        args = dict(q=2, inner_iters=5, max_sweeps=1)
+        args.update(kw)
+        with pytest.raises(rka.RKAError) as e:
+            rka.refine_solve(Ad, vec(b), **args)
+        assert e.value.status == rka.EINVAL
+    with pytest.raises(rka.RKAError):  # FP32 accumulation on FP64 storage
+        rka.refine_solve(to_dev(A.astype(np.float64)), vec(b), q=2, inner_iters=5,
+                         max_sweeps=1, accumulate=1)
