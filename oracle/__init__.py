@@ -6,7 +6,8 @@ this package never imports the solver: the two share no code.
 
 The arithmetic lives in ``rka_oracle.c`` (the paper's iterations) and
 ``forms_oracle.c`` (FP32 iterations, refinement, dense steps) -- plain C,
-single thread, compiled with ``-O2 -ffp-contract=off``; this module only marshals numpy arrays into
+single thread, compiled with ``-O2 -ffp-contract=off`` -- and in
+``lsq_grad.py`` (least-squares solution and gradient by FP64 QR); this module only marshals numpy arrays into
 it through ctypes.  Each C function cites the passage of arXiv 2401.17474 it
 follows.
 """
