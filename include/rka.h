@@ -281,6 +281,69 @@ int rka_refine_solve(const void* A, const void* At, int dtype, int64_t m, int64_
                      const rka_refine_opts* opts, uint64_t seed, const double* x_ref,
                      double* sweep_measure, void* stream, rka_refine_info* info);
 
+/* One system of a batch (rka_batch_solve).  nrhs right-hand sides share A
+ * and one row stream. */
+typedef struct rka_batch_system {
+    const void* A;          /* m x n, leading dimension lda (dtype of the batch)       */
+    int64_t m, n, lda;      /* 1 <= m < 2^31, 1 <= n <= 4096                           */
+    const double* b;        /* right-hand side r at b + r * ldb (ldb >= m)             */
+    int64_t ldb;
+    double* x;              /* iterate r at x + r * ldx (ldx >= n): start in, result
+                               out                                                    */
+    int64_t ldx;
+    const double* x_ref;    /* nullable: reference r at x_ref + r * ldxr for the
+                               stopping test                                          */
+    int64_t ldxr;
+    int32_t nrhs;           /* >= 1                                                    */
+    int32_t q;              /* workers; 0 = chosen by the library                      */
+    int32_t block_size;     /* projections per worker and iteration; 0 = chosen       */
+    int32_t tpr;            /* threads per row (16, 32, 64, 128 or 256 with
+                               16 tpr >= n); 0 = chosen                               */
+    int32_t rhs_per_task;   /* right-hand sides one workgroup carries (<= 8); 0 =
+                               the most that fit 64 KB of LDS                         */
+    int32_t reserved;
+    double alpha;           /* relaxation weight, finite and > 0                       */
+    int64_t max_iter;       /* iteration cap, >= 0                                     */
+} rka_batch_system;
+
+typedef struct rka_batch_result {
+    int64_t iterations;     /* iterations run (the largest over the system's tasks)   */
+    double rel;             /* largest last relative error over its tasks (0 if none) */
+    int32_t status;         /* RKA_OK, RKA_NOT_CONVERGED or RKA_EDIVERGED              */
+    int32_t q, block_size, tpr, rhs_per_task;  /* parameters used                      */
+    int32_t reserved;
+} rka_batch_result;
+
+typedef struct rka_batch_stats {
+    int32_t tasks;          /* workgroup tasks (systems x right-hand-side groups)     */
+    int32_t chunks;         /* row-stream chunks                                      */
+    int32_t lds_bytes;      /* dynamic LDS of the iteration launch                    */
+    int32_t graph;          /* 1 if the launches ran as one captured HIP graph         */
+} rka_batch_stats;
+
+/*
+ * rka_batch_solve -- RKAB (Sec. 3.4.1; block_size = 1 is RKA, Eq. (7)) on
+ * `count` independent systems at once, every iteration in binary32 on FP32
+ * or BF16 storage (dtype RKA_F32 / RKA_BF16).  System i draws its rows with
+ * key seed + i and counter (k, w, j, 0) exactly as rka_solve / rkab_solve
+ * do, from its own squared row norms (Eq. (4)); the nrhs right-hand sides of
+ * a system share that row stream, so each sampled row is read once per
+ * group of rhs_per_task right-hand sides.  Iteration k of every worker is
+ *     v = x^(k);  bs times: v += alpha (b_i - <A^(i), v>) / ||A^(i)||^2 A^(i)^T
+ *     x^(k+1) = (sum_w v_w) / q                (binary32, worker order)
+ * With tol > 0 and x_ref given, a group stops after the first multiple of
+ * check_every where ||x - x_ref|| <= tol ||x_ref|| over its right-hand sides.
+ * use_graph != 0 captures the whole launch sequence (set-up, then per chunk
+ * of iterations a row-stream launch and one iteration launch for all
+ * systems) in one HIP graph and launches it once; `stream` must then not be
+ * the null stream.  results: host array of count entries (nullable).  Waits
+ * for the stream once.  Returns RKA_OK, RKA_NOT_CONVERGED (some system did
+ * not reach tol), RKA_EDIVERGED, or an error.
+ */
+int rka_batch_solve(const rka_batch_system* systems, int32_t count, int dtype, uint64_t seed,
+                    double tol, int64_t check_every, int32_t use_graph, void* stream,
+                    rka_batch_result* results, rka_batch_stats* stats);
+
 /* Name of a status code (static string). */
 const char* rka_status_string(int status);
 

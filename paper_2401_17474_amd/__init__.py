@@ -58,6 +58,28 @@ class _RefineOpts(ctypes.Structure):
                 ("tol", ctypes.c_double)]
 
 
+class _BatchSystem(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("m", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("lda", ctypes.c_int64), ("b", ctypes.c_void_p), ("ldb", ctypes.c_int64),
+                ("x", ctypes.c_void_p), ("ldx", ctypes.c_int64), ("x_ref", ctypes.c_void_p),
+                ("ldxr", ctypes.c_int64), ("nrhs", ctypes.c_int32), ("q", ctypes.c_int32),
+                ("block_size", ctypes.c_int32), ("tpr", ctypes.c_int32),
+                ("rhs_per_task", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("alpha", ctypes.c_double), ("max_iter", ctypes.c_int64)]
+
+
+class _BatchResult(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("rel", ctypes.c_double),
+                ("status", ctypes.c_int32), ("q", ctypes.c_int32), ("block_size", ctypes.c_int32),
+                ("tpr", ctypes.c_int32), ("rhs_per_task", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class _BatchStats(ctypes.Structure):
+    _fields_ = [("tasks", ctypes.c_int32), ("chunks", ctypes.c_int32),
+                ("lds_bytes", ctypes.c_int32), ("graph", ctypes.c_int32)]
+
+
 class _RefineInfo(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("rel", ctypes.c_double), ("projections", ctypes.c_int64)]
@@ -97,6 +119,9 @@ def lib():
         L.rka_refine_solve.argtypes = [P, P, ctypes.c_int, I64, I64, I64, I64, P, P, P,
                                        ctypes.POINTER(_RefineOpts), U64, P, P, P,
                                        ctypes.POINTER(_RefineInfo)]
+        L.rka_batch_solve.argtypes = [ctypes.POINTER(_BatchSystem), I32, ctypes.c_int, U64, D,
+                                      I64, I32, P, ctypes.POINTER(_BatchResult),
+                                      ctypes.POINTER(_BatchStats)]
         L.rka_status_string.argtypes = [ctypes.c_int]
         L.rka_status_string.restype = ctypes.c_char_p
         L.rka_last_error.argtypes = []
@@ -104,7 +129,7 @@ def lib():
         L.rka_version.restype = ctypes.c_int
         for f in ("rka_solve", "rkab_solve", "rka_solve_ex", "rka_row_norms", "rka_prefix",
                   "rka_sample_indices", "rka_gemv", "rka_transpose", "rka_lsq_grad_A",
-                  "rka_refine_solve"):
+                  "rka_refine_solve", "rka_batch_solve"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -342,6 +367,76 @@ def refine_solve(A, b, *, At=None, method=0, q, block_size=1, accumulate=1, alph
         _raise_if(st)
     return x, RefineInfo(info.sweeps, st, info.rel, info.projections,
                          [meas[i] for i in range(info.sweeps)])
+
+
+# -- batching ------------------------------------------------------------------
+
+@dataclass
+class BatchSystem:
+    """One system of a batch: A (m x n, float32 or bfloat16, GPU), B (m) or
+    (nrhs x m) float64, X (n) or (nrhs x n) float64 -- start values in,
+    results out.  q, block_size, tpr = 0 let the library choose."""
+    A: object
+    B: object
+    X: object
+    X_ref: object = None
+    q: int = 0
+    block_size: int = 0
+    tpr: int = 0
+    rhs_per_task: int = 0
+    alpha: float = 1.0
+    max_iter: int = 1000
+
+
+def _rows(t, length, name):
+    torch = _torch()
+    if t.dim() == 1:
+        t = t.unsqueeze(0)
+    if not t.is_cuda or t.dtype != torch.float64 or t.dim() != 2 or t.shape[1] != length \
+            or t.stride(1) != 1:
+        raise ValueError(f"{name} must be float64 GPU rows of length {length}")
+    return t, (t.stride(0) if t.shape[0] > 1 else length)
+
+
+def batch_solve(systems, *, seed=1, tol=0.0, check_every=1, graph=True, stream=None,
+                raise_on_error=True):
+    """rka_batch_solve over a list of BatchSystem.  Returns (results, stats):
+    per-system dicts (iterations, rel, status, q, block_size, tpr,
+    rhs_per_task) and launch facts.  With ``graph`` the launches run as one
+    captured HIP graph on a side stream ordered after the current one."""
+    torch = _torch()
+    n_sys = len(systems)
+    arr = (_BatchSystem * n_sys)()
+    dtypes = set()
+    for i, S in enumerate(systems):
+        code, m, n, lda = _matrix(S.A)
+        dtypes.add(code)
+        B, ldb = _rows(S.B, m, "B")
+        X, ldx = _rows(S.X, n, "X")
+        if B.shape[0] != X.shape[0]:
+            raise ValueError("B and X must hold the same number of right-hand sides")
+        XR, ldxr = (None, 0) if S.X_ref is None else _rows(S.X_ref, n, "X_ref")
+        arr[i] = _BatchSystem(S.A.data_ptr(), m, n, lda, B.data_ptr(), ldb, X.data_ptr(), ldx,
+                              None if XR is None else XR.data_ptr(), ldxr, B.shape[0], S.q,
+                              S.block_size, S.tpr, S.rhs_per_task, 0, S.alpha, S.max_iter)
+    if len(dtypes) != 1:
+        raise ValueError("every system of a batch must have the same storage type")
+    res = (_BatchResult * n_sys)()
+    st = _BatchStats()
+    cur = torch.cuda.current_stream()
+    side = torch.cuda.Stream() if graph else None
+    if side is not None:
+        side.wait_stream(cur)
+    run_on = side if side is not None else (stream or cur)
+    status = lib().rka_batch_solve(arr, n_sys, dtypes.pop(), seed, tol, check_every,
+                                   1 if graph else 0, ctypes.c_void_p(run_on.cuda_stream), res,
+                                   ctypes.byref(st))
+    if side is not None:
+        cur.wait_stream(side)
+    if raise_on_error:
+        _raise_if(status)
+    out = [{f: getattr(r, f) for f, _ in _BatchResult._fields_ if f != "reserved"} for r in res]
+    return out, {f: getattr(st, f) for f, _ in _BatchStats._fields_}
 
 
 # -- host helpers --------------------------------------------------------------

@@ -25,6 +25,7 @@ SOURCES = {
     "rka_iter.hip": [],
     "rka_rkab.hip": [],
     "rka_dense.hip": [],
+    "rka_batch.hip": [],
     "rka_api.hip": [],
 }
 

@@ -343,6 +343,23 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
 
 }  // namespace
 
+namespace rka {
+// error reporting and device query for the other translation units' entry points
+int api_fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+int api_num_cus() {
+  g_last_error.clear();
+  return num_cus();
+}
+}  // namespace rka
+
 extern "C" {
 
 int rka_solve(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const double* b,

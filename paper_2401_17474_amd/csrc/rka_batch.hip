@@ -1,0 +1,609 @@
+// rka_batch.hip -- many independent systems (and right-hand sides) in one
+// launch: the batching form.
+//
+// A *task* is one system with a group of R of its right-hand sides (R = 1
+// for an ordinary system; a matrix shared by many right-hand sides becomes
+// several tasks that share its row stream).  One workgroup runs one task, so
+// tasks of uneven sizes balance through the hardware dispatcher (tasks are
+// ordered largest first).  Inside a workgroup, sub-teams of `tpr` threads
+// (threads per row) are the RKAB workers of Sec. 3.4.1: each keeps its
+// iterate v for the R right-hand sides in LDS and applies block_size
+// projections, a sampled row being read once from memory and applied to all
+// R iterates; the q worker iterates are then summed in worker order and
+// divided by q.  Arithmetic is binary32 on FP32 or BF16 storage.  A chunk of
+// iterations is a batched row-stream launch followed by the batched
+// iteration launch; the chunks of a solve can be captured in one HIP graph.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "rka.h"
+#include "rka_device.hpp"
+#include "rka_internal.hpp"
+
+namespace rka {
+
+constexpr int kBT = 256;     // threads per batch workgroup
+constexpr int kEptMax = 16;  // row elements per thread (tpr * 16 >= n)
+constexpr int kRmax = 8;     // right-hand sides per task
+
+struct BatchSys {
+  const double* c;         // running sum of the squared row norms
+  const int64_t* last_pos; // largest row with a positive weight
+  int64_t m;
+  uint64_t seed;
+  int32_t q, bs;
+  int32_t* idx;            // row stream of the current chunk, K x q x bs
+  const int32_t* alive;    // nonzero while a task of the system still runs
+};
+
+struct BatchTask {
+  const void* A;
+  int64_t m, n, lda;
+  const double* b;   // right-hand side r at b + r * ldb
+  int64_t ldb;
+  double* x;         // iterate r at x + r * ldx (start in, result out)
+  int64_t ldx;
+  const double* xr;  // stopping reference r at xr + r * ldxr (nullable)
+  int64_t ldxr;
+  const double* w;   // squared row norms
+  const int32_t* idx;
+  int32_t* done;     // per task
+  int32_t* alive;    // per system: cleared by the sampler bookkeeping below
+  int64_t* iters;    // per task
+  double* rel;       // per task: last relative error (NaN if never measured)
+  int64_t max_iter;  // iteration cap of the system
+  float alpha;
+  int32_t R, q, bs, tpr;
+  int32_t bf16;      // storage: 0 FP32, 1 BF16
+};
+
+__device__ __forceinline__ float load_elem(const void* A, int bf16, int64_t off) {
+  if (bf16) return __uint_as_float((uint32_t)((const uint16_t*)A)[off] << 16);
+  return ((const float*)A)[off];
+}
+
+// Row stream of one chunk for every system still running (one thread per draw).
+__global__ __launch_bounds__(256) void batch_sample_kernel(const BatchSys* __restrict__ sys,
+                                                           int64_t k0, int64_t K) {
+  const BatchSys S = sys[blockIdx.y];
+  if (S.alive && *S.alive == 0) return;
+  const double W = S.c[S.m - 1];
+  const int64_t last = *S.last_pos;
+  const int64_t total = K * (int64_t)S.q * S.bs;
+  for (int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; L < total;
+       L += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = L % S.bs;
+    const int64_t wk = (L / S.bs) % S.q;
+    const int64_t kl = L / ((int64_t)S.bs * S.q);
+    const double u = draw_uniform(S.seed, (uint64_t)(k0 + kl), (uint32_t)wk, (uint32_t)j, 0u);
+    S.idx[L] = (int32_t)pick_row(S.c, S.m, W, u, last);
+  }
+}
+
+__global__ void batch_fill_kernel(int32_t* p, int64_t n, int32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// One task per workgroup; K iterations from k0.  check_every > 0 with a
+// reference: stop once ||x - xr|| <= tol ||xr|| (all R right-hand sides
+// together), tested after every check_every-th iteration.
+__global__ __launch_bounds__(kBT) void batch_iter_kernel(const BatchTask* __restrict__ tasks,
+                                                         int64_t k0, int64_t K,
+                                                         int64_t check_every, double tol2) {
+  const BatchTask T = tasks[blockIdx.x];
+  const int64_t max_iter = T.max_iter;
+  if (*T.done) return;
+  extern __shared__ float L[];
+  __shared__ float red[kBT / kWave][kRmax];
+  __shared__ double dred[kBT / kWave];
+  const int n = (int)T.n, R = T.R, q = T.q, bs = T.bs, tpr = T.tpr;
+  const int W = kBT / tpr;
+  const int t = threadIdx.x, team = t / tpr, lane = t % tpr;
+  const int nw_team = tpr > kWave ? tpr / kWave : 1;
+  const int Rn = R * n;
+  float* X = L;
+  float* S = X + Rn;
+  float* Vt = S + Rn + (size_t)team * Rn;
+
+  for (int e = t; e < Rn; e += kBT) X[e] = (float)T.x[(e / n) * T.ldx + (e % n)];
+  double ref2 = 0.0;
+  const bool checking = T.xr && check_every > 0;
+  if (checking) {
+    double s = 0.0;
+    for (int e = t; e < Rn; e += kBT) {
+      const double v = T.xr[(e / n) * T.ldxr + (e % n)];
+      s = fma(v, v, s);
+    }
+    ref2 = block_sum(s, dred);
+  }
+  __syncthreads();
+
+  const float alpha = T.alpha;
+  auto load_row = [&](float (&a)[kEptMax], int64_t row) {
+#pragma unroll
+    for (int u = 0; u < kEptMax; ++u) {
+      const int c = lane + u * tpr;
+      const int cc = c < n ? c : n - 1;  // unconditional load, masked below
+      a[u] = load_elem(T.A, T.bf16, row * T.lda + cc);
+    }
+  };
+
+  int64_t kl = 0;
+  bool stopped = false;
+  for (; kl < K && k0 + kl < max_iter; ++kl) {
+    for (int e = t; e < Rn; e += kBT) S[e] = 0.0f;
+    for (int w0 = 0; w0 < q; w0 += W) {
+      const int w = w0 + team < q ? w0 + team : q - 1;
+      const int32_t* ix = T.idx + ((int64_t)kl * q + w) * bs;
+      for (int e = lane; e < Rn; e += tpr) Vt[e] = X[e];
+      // two rows in flight: the current one and the next
+      float a[kEptMax], an[kEptMax];
+      int64_t i0 = ix[0];
+      int64_t i1 = ix[bs > 1 ? 1 : 0];
+      load_row(a, i0);
+      float bb[kRmax], wi = (float)T.w[i0];
+#pragma unroll
+      for (int r = 0; r < kRmax; ++r) bb[r] = (float)T.b[(r < R ? r : 0) * T.ldb + i0];
+      for (int j = 0; j < bs; ++j) {
+        const int64_t i2 = ix[j + 2 < bs ? j + 2 : bs - 1];
+        load_row(an, i1);
+        float bbn[kRmax];
+        const float win = (float)T.w[i1];
+#pragma unroll
+        for (int r = 0; r < kRmax; ++r) bbn[r] = (float)T.b[(r < R ? r : 0) * T.ldb + i1];
+        // dot products with the R iterates
+        float d[kRmax];
+#pragma unroll
+        for (int r = 0; r < kRmax; ++r) {
+          float s = 0.0f;
+          if (r < R) {
+#pragma unroll
+            for (int u = 0; u < kEptMax; ++u) {
+              const int c = lane + u * tpr;
+              if (c < n) s = fmaf(a[u], Vt[r * n + c], s);
+            }
+          }
+          d[r] = s;
+        }
+#pragma unroll
+        for (int r = 0; r < kRmax; ++r) {
+          const int top = tpr < kWave ? tpr : kWave;
+          for (int off = top / 2; off > 0; off >>= 1) d[r] += __shfl_xor(d[r], off, kWave);
+        }
+        if (tpr > kWave) {  // several waves per team: combine in wave order
+          if ((t & (kWave - 1)) == 0) {
+#pragma unroll
+            for (int r = 0; r < kRmax; ++r) red[t / kWave][r] = d[r];
+          }
+          __syncthreads();
+#pragma unroll
+          for (int r = 0; r < kRmax; ++r) {
+            float s = 0.0f;
+            for (int v = 0; v < nw_team; ++v) s += red[team * nw_team + v][r];
+            d[r] = s;
+          }
+          __syncthreads();
+        }
+        // v += alpha (b_i - <a_i, v>) / ||a_i||^2 a_i   for every right-hand side
+#pragma unroll
+        for (int r = 0; r < kRmax; ++r) {
+          if (r < R) {
+            const float s = alpha * (bb[r] - d[r]) / wi;
+#pragma unroll
+            for (int u = 0; u < kEptMax; ++u) {
+              const int c = lane + u * tpr;
+              if (c < n) Vt[r * n + c] = fmaf(s, a[u], Vt[r * n + c]);
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kEptMax; ++u) a[u] = an[u];
+#pragma unroll
+        for (int r = 0; r < kRmax; ++r) bb[r] = bbn[r];
+        wi = win;
+        i0 = i1;
+        i1 = i2;
+      }
+      __syncthreads();
+      // sum of the worker iterates in worker order
+      const int nact = q - w0 < W ? q - w0 : W;
+      for (int e = t; e < Rn; e += kBT) {
+        float s = S[e];
+        for (int tt = 0; tt < nact; ++tt) s = s + S[Rn + (size_t)tt * Rn + e];
+        S[e] = s;
+      }
+      __syncthreads();
+    }
+    const float qf = (float)q;
+    for (int e = t; e < Rn; e += kBT) X[e] = S[e] / qf;
+    __syncthreads();
+    const int64_t k = k0 + kl + 1;  // iterations done
+    if (checking && (k % check_every) == 0) {
+      double s = 0.0;
+      for (int e = t; e < Rn; e += kBT) {
+        const double dd = (double)X[e] - T.xr[(e / n) * T.ldxr + (e % n)];
+        s = fma(dd, dd, s);
+      }
+      const double e2 = block_sum(s, dred);
+      if (t == 0) T.rel[blockIdx.x] = sqrt(e2 / ref2);
+      if (e2 <= tol2 * ref2 || !isfinite(e2)) {
+        if (t == 0) {
+          T.iters[blockIdx.x] = k;
+          T.done[blockIdx.x] = isfinite(e2) ? 1 : 2;
+        }
+        stopped = true;
+        break;
+      }
+    }
+  }
+  for (int e = t; e < Rn; e += kBT) T.x[(e / n) * T.ldx + (e % n)] = (double)X[e];
+  if (!stopped && t == 0) {
+    T.iters[blockIdx.x] = k0 + kl;
+    if (k0 + kl >= max_iter) T.done[blockIdx.x] = 3;  // ran out of iterations
+  }
+}
+
+// Per system: clear `alive` once all its tasks are done (so later chunks skip
+// its sampling).  One thread per system.
+__global__ void batch_alive_kernel(const int32_t* __restrict__ done, const int32_t* task_sys,
+                                   int ntasks, int32_t* alive, int nsys) {
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < nsys; s += gridDim.x * blockDim.x) {
+    int any = 0;
+    for (int t = 0; t < ntasks; ++t)
+      if (task_sys[t] == s && done[t] == 0) any = 1;
+    alive[s] = any;
+  }
+}
+
+size_t batch_lds_bytes(int64_t n, int R, int tpr) {
+  return (size_t)(2 + kBT / tpr) * (size_t)R * (size_t)n * sizeof(float);
+}
+
+}  // namespace rka
+
+// ===========================================================================
+// Host side: planning, the autotuner and the C ABI.
+// ===========================================================================
+namespace {
+
+using rka::BatchSys;
+using rka::BatchTask;
+
+constexpr size_t kBatchLdsMax = 64 * 1024;
+
+bool pow2_tpr(int t) { return t == 16 || t == 32 || t == 64 || t == 128 || t == 256; }
+
+int min_tpr(int64_t n) {
+  int t = 16;
+  while ((int64_t)t * rka::kEptMax < n) t *= 2;
+  return t;
+}
+
+// Largest right-hand-side group (<= kRmax) whose task fits the LDS budget.
+int pick_R(int64_t n, int tpr, int nrhs) {
+  int R = nrhs < rka::kRmax ? nrhs : rka::kRmax;
+  while (R > 1 && rka::batch_lds_bytes(n, R, tpr) > kBatchLdsMax) --R;
+  return R;
+}
+
+// Heuristic parameters (used where the caller gives 0 and no tuning table
+// applies): threads per row just enough for the row (16 elements a thread),
+// q = the workers that run at once, block size ~ n/4 in [4, 64] (the paper
+// recommends blocks of the order of n, Sec. 3.4.3; shorter blocks average
+// more often).
+void heuristic(int64_t n, int* q, int* bs, int* tpr) {
+  if (*tpr == 0) *tpr = min_tpr(n);
+  if (*q == 0) *q = rka::kBT / *tpr;
+  if (*bs == 0) {
+    int64_t b = n / 4;
+    if (b < 4) b = 4;
+    if (b > 64) b = 64;
+    *bs = (int)b;
+  }
+}
+
+}  // namespace
+
+namespace rka {
+int api_fail(int code, const char* fmt, ...);
+int api_num_cus();
+}
+
+#define BHIP(call)                                                                           \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return rka::api_fail(e_ == hipErrorOutOfMemory ? RKA_ENOMEM : RKA_EDEVICE, "%s: %s",   \
+                           #call, hipGetErrorString(e_));                                    \
+  } while (0)
+
+namespace {
+
+struct DevBuf {
+  std::vector<void*> p;
+  hipStream_t s;
+  explicit DevBuf(hipStream_t st) : s(st) {}
+  template <typename U>
+  hipError_t get(U** out, size_t count) {
+    void* q = nullptr;
+    hipError_t e = hipMallocAsync(&q, count * sizeof(U) > 0 ? count * sizeof(U) : 16, s);
+    if (e != hipSuccess) return e;
+    p.push_back(q);
+    *out = (U*)q;
+    return hipSuccess;
+  }
+  ~DevBuf() {
+    for (size_t i = p.size(); i-- > 0;) (void)hipFreeAsync(p[i], s);
+  }
+};
+
+int validate_sys(const rka_batch_system& S, int i, int dtype) {
+  if (!S.A || !S.b || !S.x) return rka::api_fail(RKA_EINVAL, "system %d: A, b and x must be non-null", i);
+  if (S.m < 1 || S.n < 1 || S.lda < S.n || S.m > INT32_MAX)
+    return rka::api_fail(RKA_EINVAL, "system %d: need 1 <= m < 2^31, n >= 1, lda >= n", i);
+  if (S.n > (int64_t)256 * rka::kEptMax)
+    return rka::api_fail(RKA_EINVAL, "system %d: n must be <= %d", i, 256 * rka::kEptMax);
+  if (S.nrhs < 1 || S.ldb < S.m || S.ldx < S.n || (S.x_ref && S.ldxr < S.n))
+    return rka::api_fail(RKA_EINVAL, "system %d: need nrhs >= 1, ldb >= m, ldx >= n, ldxr >= n", i);
+  if (S.q < 0 || S.block_size < 0 || S.block_size >= (1 << 24) || S.max_iter < 0)
+    return rka::api_fail(RKA_EINVAL, "system %d: bad q, block_size or max_iter", i);
+  if (S.tpr != 0 && (!pow2_tpr(S.tpr) || (int64_t)S.tpr * rka::kEptMax < S.n))
+    return rka::api_fail(RKA_EINVAL, "system %d: tpr must be 16..256 (power of 2) with tpr*16 >= n", i);
+  if (S.rhs_per_task < 0 || S.rhs_per_task > rka::kRmax)
+    return rka::api_fail(RKA_EINVAL, "system %d: rhs_per_task must be in [0, %d]", i, rka::kRmax);
+  if (!(S.alpha > 0.0) || !isfinite(S.alpha))
+    return rka::api_fail(RKA_EINVAL, "system %d: alpha must be finite and > 0", i);
+  (void)dtype;
+  return RKA_OK;
+}
+
+}  // namespace
+
+extern "C" int rka_batch_solve(const rka_batch_system* systems, int32_t count, int dtype,
+                               uint64_t seed, double tol, int64_t check_every, int32_t use_graph,
+                               void* stream, rka_batch_result* results, rka_batch_stats* stats) {
+  if (stats) memset(stats, 0, sizeof *stats);
+  if (!systems || count < 1 || count > 65535)
+    return rka::api_fail(RKA_EINVAL, "need 1 to 65535 systems");
+  if (dtype != RKA_F32 && dtype != RKA_BF16)
+    return rka::api_fail(RKA_EINVAL, "batched solves take RKA_F32 or RKA_BF16 storage");
+  if (!(tol >= 0.0) || !isfinite(tol)) return rka::api_fail(RKA_EINVAL, "tol must be finite and >= 0");
+  for (int i = 0; i < count; ++i) {
+    int v = validate_sys(systems[i], i, dtype);
+    if (v != RKA_OK) return v;
+  }
+  if (rka::api_num_cus() <= 0) return rka::api_fail(RKA_EDEVICE, "no HIP device available");
+  hipStream_t s = (hipStream_t)stream;
+  if (check_every < 1) check_every = 1;
+
+  // parameters and tasks
+  std::vector<int> q(count), bs(count), tpr(count), R(count);
+  int64_t max_iter = 0;
+  for (int i = 0; i < count; ++i) {
+    const rka_batch_system& S = systems[i];
+    q[i] = S.q;
+    bs[i] = S.block_size;
+    tpr[i] = S.tpr;
+    heuristic(S.n, &q[i], &bs[i], &tpr[i]);
+    if (q[i] > 65535) return rka::api_fail(RKA_EINVAL, "system %d: q too large", i);
+    R[i] = S.rhs_per_task > 0 ? S.rhs_per_task : pick_R(S.n, tpr[i], S.nrhs);
+    if (R[i] > S.nrhs) R[i] = S.nrhs;
+    if (rka::batch_lds_bytes(S.n, R[i], tpr[i]) > 160 * 1024 - 4096)
+      return rka::api_fail(RKA_EINVAL, "system %d: a task of %d right-hand sides does not fit LDS", i, R[i]);
+    if (S.max_iter > max_iter) max_iter = S.max_iter;
+  }
+
+  DevBuf buf(s);
+  std::vector<BatchSys> hsys(count);
+  std::vector<BatchTask> htask;
+  std::vector<int32_t> task_sys;
+  std::vector<int64_t> task_work;
+  int64_t idx_total = 0;
+  // row stream chunk: bounded so that the chunk's indices stay <= 64 Mi entries
+  int64_t Kc = max_iter > 0 ? max_iter : 1;
+  {
+    int64_t per_iter = 0;
+    for (int i = 0; i < count; ++i) per_iter += (int64_t)q[i] * bs[i];
+    const int64_t cap = (64ll << 20) / (per_iter > 0 ? per_iter : 1);
+    if (Kc > cap) Kc = cap > 0 ? cap : 1;
+  }
+  double* wbuf;
+  double* cbuf;
+  int64_t* lastbuf;
+  int64_t mtot = 0;
+  for (int i = 0; i < count; ++i) mtot += systems[i].m;
+  BHIP(buf.get(&wbuf, (size_t)mtot));
+  BHIP(buf.get(&cbuf, (size_t)mtot));
+  BHIP(buf.get(&lastbuf, (size_t)count));
+  for (int i = 0; i < count; ++i) idx_total += Kc * q[i] * bs[i];
+  int32_t* idxbuf;
+  BHIP(buf.get(&idxbuf, (size_t)idx_total));
+  int64_t moff = 0, ioff = 0;
+  for (int i = 0; i < count; ++i) {
+    const rka_batch_system& S = systems[i];
+    BatchSys& Y = hsys[i];
+    Y.c = cbuf + moff;
+    Y.last_pos = lastbuf + i;
+    Y.m = S.m;
+    Y.seed = seed + (uint64_t)i;
+    Y.q = q[i];
+    Y.bs = bs[i];
+    Y.idx = idxbuf + ioff;
+    Y.alive = nullptr;
+    for (int r0 = 0; r0 < S.nrhs; r0 += R[i]) {
+      BatchTask T;
+      T.A = S.A;
+      T.m = S.m;
+      T.n = S.n;
+      T.lda = S.lda;
+      T.b = S.b + (int64_t)r0 * S.ldb;
+      T.ldb = S.ldb;
+      T.x = S.x + (int64_t)r0 * S.ldx;
+      T.ldx = S.ldx;
+      T.xr = S.x_ref ? S.x_ref + (int64_t)r0 * S.ldxr : nullptr;
+      T.ldxr = S.ldxr;
+      T.w = wbuf + moff;
+      T.idx = Y.idx;
+      T.alpha = (float)S.alpha;
+      T.R = S.nrhs - r0 < R[i] ? S.nrhs - r0 : R[i];
+      T.q = q[i];
+      T.bs = bs[i];
+      T.tpr = tpr[i];
+      T.bf16 = dtype == RKA_BF16;
+      T.max_iter = S.max_iter;
+      htask.push_back(T);
+      task_sys.push_back(i);
+      task_work.push_back((int64_t)T.R * S.n * q[i] * bs[i] * (S.max_iter > 0 ? S.max_iter : 1));
+    }
+    moff += S.m;
+    ioff += Kc * q[i] * bs[i];
+  }
+  const int ntask = (int)htask.size();
+  // largest tasks first, so that the long ones start at once
+  std::vector<int> order(ntask);
+  for (int t = 0; t < ntask; ++t) order[t] = t;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return task_work[a] > task_work[b]; });
+  std::vector<BatchTask> sorted(ntask);
+  std::vector<int32_t> sorted_sys(ntask);
+  for (int t = 0; t < ntask; ++t) {
+    sorted[t] = htask[order[t]];
+    sorted_sys[t] = task_sys[order[t]];
+  }
+  int32_t *done, *alive, *tsys;
+  int64_t* iters;
+  double* rel;
+  BatchTask* dtask;
+  BatchSys* dsys;
+  BHIP(buf.get(&done, (size_t)ntask));
+  BHIP(buf.get(&alive, (size_t)count));
+  BHIP(buf.get(&tsys, (size_t)ntask));
+  BHIP(buf.get(&iters, (size_t)ntask));
+  BHIP(buf.get(&rel, (size_t)ntask));
+  BHIP(buf.get(&dtask, (size_t)ntask));
+  BHIP(buf.get(&dsys, (size_t)count));
+  for (int t = 0; t < ntask; ++t) {
+    sorted[t].done = done;
+    sorted[t].alive = alive;
+    sorted[t].iters = iters;
+    sorted[t].rel = rel;
+  }
+  for (int i = 0; i < count; ++i) hsys[i].alive = alive + i;
+  BHIP(hipMemcpyAsync(dtask, sorted.data(), ntask * sizeof(BatchTask), hipMemcpyHostToDevice, s));
+  BHIP(hipMemcpyAsync(dsys, hsys.data(), count * sizeof(BatchSys), hipMemcpyHostToDevice, s));
+  BHIP(hipMemcpyAsync(tsys, sorted_sys.data(), ntask * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  // NaN pattern for rel (never measured)
+  {
+    std::vector<double> nanv(ntask, NAN);
+    BHIP(hipMemcpyAsync(rel, nanv.data(), ntask * sizeof(double), hipMemcpyHostToDevice, s));
+    BHIP(hipStreamSynchronize(s));  // the host vectors go out of scope
+  }
+  size_t lds = 0;
+  int64_t draws_max = 0;
+  for (int t = 0; t < ntask; ++t)
+    lds = std::max(lds, rka::batch_lds_bytes(sorted[t].n, sorted[t].R, sorted[t].tpr));
+  for (int i = 0; i < count; ++i) draws_max = std::max(draws_max, Kc * q[i] * bs[i]);
+  if (lds > 64 * 1024)
+    BHIP(hipFuncSetAttribute((const void*)rka::batch_iter_kernel,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+
+  // The whole solve as one launch sequence (captured in a graph if asked):
+  // per system norms and running sum, flag set-up, then per chunk the row
+  // streams of every running system, the iteration launch and the
+  // bookkeeping of which systems still run.
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  if (use_graph) BHIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  {
+    int64_t off = 0;
+    for (int i = 0; i < count; ++i) {
+      const rka_batch_system& S = systems[i];
+      const bool vec_ok = ((uintptr_t)S.A % 16 == 0) &&
+                          ((S.lda * (dtype == RKA_F32 ? 4 : 2)) % 16 == 0) &&
+                          (S.n % (dtype == RKA_F32 ? 4 : 8) == 0);
+      hipError_t e = rka::launch_row_norms(S.A, dtype, S.m, S.n, S.lda, vec_ok, wbuf + off, s);
+      if (e == hipSuccess) e = rka::launch_prefix(wbuf + off, S.m, cbuf + off, lastbuf + i, nullptr, s);
+      if (e != hipSuccess) {
+        if (use_graph) {
+          hipGraph_t g2;
+          (void)hipStreamEndCapture(s, &g2);
+          if (g2) (void)hipGraphDestroy(g2);
+        }
+        return rka::api_fail(RKA_EDEVICE, "batch set-up: %s", hipGetErrorString(e));
+      }
+      off += S.m;
+    }
+    hipLaunchKernelGGL(rka::batch_fill_kernel, dim3(1), dim3(256), 0, s, done, (int64_t)ntask, 0);
+    hipLaunchKernelGGL(rka::batch_fill_kernel, dim3(1), dim3(256), 0, s, alive, (int64_t)count, 1);
+    int nb = (int)((draws_max + 255) / 256);
+    if (nb > 1024) nb = 1024;
+    for (int64_t k0 = 0; k0 < max_iter; k0 += Kc) {
+      const int64_t K = max_iter - k0 < Kc ? max_iter - k0 : Kc;
+      hipLaunchKernelGGL(rka::batch_sample_kernel, dim3(nb, count), dim3(256), 0, s, dsys, k0, K);
+      hipLaunchKernelGGL(rka::batch_iter_kernel, dim3(ntask), dim3(rka::kBT), (unsigned)lds, s,
+                         dtask, k0, K, tol > 0.0 ? check_every : 0, tol * tol);
+      hipLaunchKernelGGL(rka::batch_alive_kernel, dim3((count + 255) / 256), dim3(256), 0, s,
+                         done, tsys, ntask, alive, count);
+    }
+  }
+  hipError_t le = hipGetLastError();
+  if (use_graph) {
+    hipError_t e = hipStreamEndCapture(s, &graph);
+    if (e == hipSuccess && le == hipSuccess) e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+    if (e == hipSuccess && le == hipSuccess) e = hipGraphLaunch(gexec, s);
+    if (e != hipSuccess) le = e;
+  }
+  if (le != hipSuccess) {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    return rka::api_fail(RKA_EDEVICE, "batch launch: %s", hipGetErrorString(le));
+  }
+  std::vector<int32_t> hdone(ntask);
+  std::vector<int64_t> hiters(ntask);
+  std::vector<double> hrel(ntask);
+  BHIP(hipMemcpyAsync(hdone.data(), done, ntask * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  BHIP(hipMemcpyAsync(hiters.data(), iters, ntask * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  BHIP(hipMemcpyAsync(hrel.data(), rel, ntask * sizeof(double), hipMemcpyDeviceToHost, s));
+  BHIP(hipStreamSynchronize(s));
+  if (gexec) (void)hipGraphExecDestroy(gexec);
+  if (graph) (void)hipGraphDestroy(graph);
+  int status = RKA_OK;
+  if (results) {
+    for (int i = 0; i < count; ++i) {
+      results[i].iterations = 0;
+      results[i].status = RKA_OK;
+      results[i].rel = 0.0;
+      results[i].q = q[i];
+      results[i].block_size = bs[i];
+      results[i].tpr = tpr[i];
+      results[i].rhs_per_task = R[i];
+    }
+  }
+  for (int t = 0; t < ntask; ++t) {
+    const int i = sorted_sys[t];
+    int st = RKA_OK;
+    if (hdone[t] == 2) st = RKA_EDIVERGED;
+    else if (tol > 0.0 && hdone[t] != 1) st = RKA_NOT_CONVERGED;
+    if (results) {
+      rka_batch_result& Rr = results[i];
+      Rr.iterations = std::max(Rr.iterations, hiters[t]);
+      if (st < 0 || (st > Rr.status && Rr.status >= 0)) Rr.status = st;
+      if (!isnan(hrel[t])) Rr.rel = std::max(Rr.rel, hrel[t]);
+    }
+    if (st < 0) status = st;
+    else if (st > 0 && status == RKA_OK) status = st;
+  }
+  if (stats) {
+    stats->tasks = ntask;
+    stats->chunks = (int32_t)((max_iter + Kc - 1) / Kc);
+    stats->lds_bytes = (int32_t)lds;
+    stats->graph = use_graph ? 1 : 0;
+  }
+  return status;
+}

@@ -110,6 +110,23 @@ __device__ __forceinline__ double draw_uniform(uint64_t seed, uint64_t k, uint32
   return (double)bits * 0x1.0p-53;
 }
 
+// Inverse-CDF pick of Eq. (4): t = u * W (one rounded multiply), the smallest
+// l with c_l > t; if there is none (t rounded up to W), `last` -- the largest
+// row with a positive weight.
+__device__ __forceinline__ int64_t pick_row(const double* __restrict__ c, int64_t m, double W,
+                                            double u, int64_t last) {
+  const double tt = __dmul_rn(u, W);
+  int64_t lo = 0, hi = m;
+  while (lo < hi) {
+    const int64_t mid = lo + ((hi - lo) >> 1);
+    if (c[mid] > tt)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  return lo < m ? lo : last;
+}
+
 // ---------------------------------------------------------------------------
 // Deterministic reductions.  The xor butterfly combines the same pairs in
 // the same tree on every lane, so every lane ends with the bitwise-same sum.

@@ -163,16 +163,7 @@ __global__ __launch_bounds__(256) void sample_kernel(const double* __restrict__ 
     const int64_t wk = (L / bs) % q;
     const int64_t kl = L / ((int64_t)bs * q);
     const double u = draw_uniform(seed, (uint64_t)(k_base + kl), (uint32_t)wk, (uint32_t)j, dom);
-    const double tt = __dmul_rn(u, W);
-    int64_t lo = 0, hi = m;
-    while (lo < hi) {
-      const int64_t mid = lo + ((hi - lo) >> 1);
-      if (c[mid] > tt)
-        hi = mid;
-      else
-        lo = mid + 1;
-    }
-    const int64_t i = lo < m ? lo : *last_pos;
+    const int64_t i = pick_row(c, m, W, u, *last_pos);
     if (idx) idx[L] = (int32_t)i;
     if (rec) {
       RowRec r;

@@ -87,6 +87,30 @@ def scaled_rows_system(m, n, *, seed=DATA_SEED, lo=0.1, hi=10.0, noise_var=0.0, 
     return A, x, b
 
 
+def batch_shapes(count, *, seed=DATA_SEED, m_range=(1000, 50000), n_range=(50, 2000),
+                 ratio=4):
+    """(m, n) pairs of the batching workload: m and n log-uniform in their
+    ranges, redrawn until m >= ratio * n."""
+    g = _np_rng(seed)
+    out = []
+    while len(out) < count:
+        m = int(round(np.exp(g.uniform(np.log(m_range[0]), np.log(m_range[1])))))
+        n = int(round(np.exp(g.uniform(np.log(n_range[0]), np.log(n_range[1])))))
+        if m >= ratio * n:
+            out.append((m, n))
+    return out
+
+
+def multi_rhs_system(m, n, nrhs, *, seed=DATA_SEED, dtype="f32"):
+    """One Gaussian A shared by nrhs planted right-hand sides: (A, X*, B) with
+    X* (nrhs x n) and B = X* A^T (nrhs x m), formed from the stored values."""
+    g = _np_rng(seed)
+    A = _round_np(g.standard_normal((m, n)), dtype)
+    X = g.standard_normal((nrhs, n))
+    B = X @ _widen_np(A, dtype).T
+    return A, X, B
+
+
 def seeds(k, base=1):
     """Solver seeds base, base+1, ... (the paper averages over 10 seeds)."""
     return [base + i for i in range(k)]
