@@ -319,6 +319,9 @@ typedef struct rka_batch_stats {
     int32_t chunks;         /* row-stream chunks                                      */
     int32_t lds_bytes;      /* dynamic LDS of the iteration launch                    */
     int32_t graph;          /* 1 if the launches ran as one captured HIP graph         */
+    double setup_ms;        /* plain launches: row norms and running sums (HIP events) */
+    double iterate_ms;      /* plain launches: the chunks of iterations; graph: the
+                               whole graph (set-up included)                          */
 } rka_batch_stats;
 
 /*
@@ -343,6 +346,21 @@ typedef struct rka_batch_stats {
 int rka_batch_solve(const rka_batch_system* systems, int32_t count, int dtype, uint64_t seed,
                     double tol, int64_t check_every, int32_t use_graph, void* stream,
                     rka_batch_result* results, rka_batch_stats* stats);
+
+/*
+ * rka_batch_tune -- the batching form's autotuner.  Groups the systems by
+ * size class (n rounded up to a power of two), runs candidate (tpr, q,
+ * block_size) triples -- tpr from the smallest that covers a row to four
+ * times it, q one or two rounds of the workers a workgroup holds, block_size
+ * in {n/16, n/4, n} clipped to [1, 256] -- on each class's median system for
+ * the same number of projections (8 m), and keeps the triple with the
+ * fastest residual reduction per second (HIP-event time of the iterations).
+ * Writes q, block_size and tpr into every system of the class where they are
+ * 0; x is not touched.  Meant for consistent systems (the residual is the
+ * progress measure).  *trials (nullable) = candidates timed.
+ */
+int rka_batch_tune(rka_batch_system* systems, int32_t count, int dtype, uint64_t seed,
+                   void* stream, int32_t* trials);
 
 /* Name of a status code (static string). */
 const char* rka_status_string(int status);

@@ -77,7 +77,8 @@ class _BatchResult(ctypes.Structure):
 
 class _BatchStats(ctypes.Structure):
     _fields_ = [("tasks", ctypes.c_int32), ("chunks", ctypes.c_int32),
-                ("lds_bytes", ctypes.c_int32), ("graph", ctypes.c_int32)]
+                ("lds_bytes", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("setup_ms", ctypes.c_double), ("iterate_ms", ctypes.c_double)]
 
 
 class _RefineInfo(ctypes.Structure):
@@ -122,6 +123,8 @@ def lib():
         L.rka_batch_solve.argtypes = [ctypes.POINTER(_BatchSystem), I32, ctypes.c_int, U64, D,
                                       I64, I32, P, ctypes.POINTER(_BatchResult),
                                       ctypes.POINTER(_BatchStats)]
+        L.rka_batch_tune.argtypes = [ctypes.POINTER(_BatchSystem), I32, ctypes.c_int, U64, P,
+                                     ctypes.POINTER(I32)]
         L.rka_status_string.argtypes = [ctypes.c_int]
         L.rka_status_string.restype = ctypes.c_char_p
         L.rka_last_error.argtypes = []
@@ -129,7 +132,7 @@ def lib():
         L.rka_version.restype = ctypes.c_int
         for f in ("rka_solve", "rkab_solve", "rka_solve_ex", "rka_row_norms", "rka_prefix",
                   "rka_sample_indices", "rka_gemv", "rka_transpose", "rka_lsq_grad_A",
-                  "rka_refine_solve", "rka_batch_solve"):
+                  "rka_refine_solve", "rka_batch_solve", "rka_batch_tune"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -398,13 +401,7 @@ def _rows(t, length, name):
     return t, (t.stride(0) if t.shape[0] > 1 else length)
 
 
-def batch_solve(systems, *, seed=1, tol=0.0, check_every=1, graph=True, stream=None,
-                raise_on_error=True):
-    """rka_batch_solve over a list of BatchSystem.  Returns (results, stats):
-    per-system dicts (iterations, rel, status, q, block_size, tpr,
-    rhs_per_task) and launch facts.  With ``graph`` the launches run as one
-    captured HIP graph on a side stream ordered after the current one."""
-    torch = _torch()
+def _batch_array(systems):
     n_sys = len(systems)
     arr = (_BatchSystem * n_sys)()
     dtypes = set()
@@ -421,6 +418,30 @@ def batch_solve(systems, *, seed=1, tol=0.0, check_every=1, graph=True, stream=N
                               S.block_size, S.tpr, S.rhs_per_task, 0, S.alpha, S.max_iter)
     if len(dtypes) != 1:
         raise ValueError("every system of a batch must have the same storage type")
+    return arr, dtypes.pop()
+
+
+def batch_tune(systems, *, seed=1, stream=None):
+    """rka_batch_tune: fill q, block_size and tpr (where 0) of every
+    BatchSystem from timed candidates; returns the number of candidates."""
+    arr, code = _batch_array(systems)
+    trials = ctypes.c_int32(0)
+    _raise_if(lib().rka_batch_tune(arr, len(systems), code, seed, _stream(stream),
+                                   ctypes.byref(trials)))
+    for S, a in zip(systems, arr):
+        S.q, S.block_size, S.tpr = a.q, a.block_size, a.tpr
+    return trials.value
+
+
+def batch_solve(systems, *, seed=1, tol=0.0, check_every=1, graph=True, stream=None,
+                raise_on_error=True):
+    """rka_batch_solve over a list of BatchSystem.  Returns (results, stats):
+    per-system dicts (iterations, rel, status, q, block_size, tpr,
+    rhs_per_task) and launch facts.  With ``graph`` the launches run as one
+    captured HIP graph on a side stream ordered after the current one."""
+    torch = _torch()
+    n_sys = len(systems)
+    arr, code = _batch_array(systems)
     res = (_BatchResult * n_sys)()
     st = _BatchStats()
     cur = torch.cuda.current_stream()
@@ -428,7 +449,7 @@ def batch_solve(systems, *, seed=1, tol=0.0, check_every=1, graph=True, stream=N
     if side is not None:
         side.wait_stream(cur)
     run_on = side if side is not None else (stream or cur)
-    status = lib().rka_batch_solve(arr, n_sys, dtypes.pop(), seed, tol, check_every,
+    status = lib().rka_batch_solve(arr, n_sys, code, seed, tol, check_every,
                                    1 if graph else 0, ctypes.c_void_p(run_on.cuda_stream), res,
                                    ctypes.byref(st))
     if side is not None:

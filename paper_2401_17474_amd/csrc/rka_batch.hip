@@ -519,7 +519,19 @@ extern "C" int rka_batch_solve(const rka_batch_system* systems, int32_t count, i
   // bookkeeping of which systems still run.
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
-  if (use_graph) BHIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  for (auto& e : ev) BHIP(hipEventCreate(&e));
+  struct EvFree {
+    hipEvent_t* e;
+    ~EvFree() {
+      for (int i = 0; i < 3; ++i)
+        if (e[i]) (void)hipEventDestroy(e[i]);
+    }
+  } ev_free{ev};
+  if (use_graph)
+    BHIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  else
+    BHIP(hipEventRecord(ev[0], s));
   {
     int64_t off = 0;
     for (int i = 0; i < count; ++i) {
@@ -541,6 +553,7 @@ extern "C" int rka_batch_solve(const rka_batch_system* systems, int32_t count, i
     }
     hipLaunchKernelGGL(rka::batch_fill_kernel, dim3(1), dim3(256), 0, s, done, (int64_t)ntask, 0);
     hipLaunchKernelGGL(rka::batch_fill_kernel, dim3(1), dim3(256), 0, s, alive, (int64_t)count, 1);
+    if (!use_graph) (void)hipEventRecord(ev[1], s);
     int nb = (int)((draws_max + 255) / 256);
     if (nb > 1024) nb = 1024;
     for (int64_t k0 = 0; k0 < max_iter; k0 += Kc) {
@@ -556,9 +569,11 @@ extern "C" int rka_batch_solve(const rka_batch_system* systems, int32_t count, i
   if (use_graph) {
     hipError_t e = hipStreamEndCapture(s, &graph);
     if (e == hipSuccess && le == hipSuccess) e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+    if (e == hipSuccess && le == hipSuccess) e = hipEventRecord(ev[0], s);
     if (e == hipSuccess && le == hipSuccess) e = hipGraphLaunch(gexec, s);
     if (e != hipSuccess) le = e;
   }
+  if (le == hipSuccess) le = hipEventRecord(ev[2], s);
   if (le != hipSuccess) {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -600,10 +615,135 @@ extern "C" int rka_batch_solve(const rka_batch_system* systems, int32_t count, i
     else if (st > 0 && status == RKA_OK) status = st;
   }
   if (stats) {
+    float ms = 0.f;
+    if (use_graph) {
+      if (hipEventElapsedTime(&ms, ev[0], ev[2]) == hipSuccess) stats->iterate_ms = ms;
+    } else {
+      if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) stats->setup_ms = ms;
+      if (hipEventElapsedTime(&ms, ev[1], ev[2]) == hipSuccess) stats->iterate_ms = ms;
+    }
     stats->tasks = ntask;
     stats->chunks = (int32_t)((max_iter + Kc - 1) / Kc);
     stats->lds_bytes = (int32_t)lds;
     stats->graph = use_graph ? 1 : 0;
   }
   return status;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: per size class of n (powers of two), time candidate (tpr, q,
+// block_size) triples on the class's median system and keep the one that
+// reduces the residual fastest: score = ln(||b|| / ||b - A x_K||) / time of
+// the K iterations, with K set so that every candidate spends the same
+// number of projections (8 m).  Only parameters the caller left at 0 are
+// filled in.  The progress measure is the residual, so the tuner is meant
+// for consistent systems (inconsistent ones stall at the least-squares
+// residual, Sec. 2.3.1).
+// ---------------------------------------------------------------------------
+extern "C" int rka_batch_tune(rka_batch_system* systems, int32_t count, int dtype, uint64_t seed,
+                              void* stream, int32_t* trials) {
+  if (trials) *trials = 0;
+  if (!systems || count < 1 || count > 65535)
+    return rka::api_fail(RKA_EINVAL, "need 1 to 65535 systems");
+  if (dtype != RKA_F32 && dtype != RKA_BF16)
+    return rka::api_fail(RKA_EINVAL, "batched solves take RKA_F32 or RKA_BF16 storage");
+  for (int i = 0; i < count; ++i) {
+    int v = validate_sys(systems[i], i, dtype);
+    if (v != RKA_OK) return v;
+  }
+  if (rka::api_num_cus() <= 0) return rka::api_fail(RKA_EDEVICE, "no HIP device available");
+  hipStream_t s = (hipStream_t)stream;
+  // size classes
+  std::vector<std::vector<int>> cls(16);
+  for (int i = 0; i < count; ++i) {
+    int c = 0;
+    while ((int64_t)1 << c < systems[i].n) ++c;
+    cls[c].push_back(i);
+  }
+  int64_t mmax = 0, nmax = 0;
+  for (int i = 0; i < count; ++i) {
+    mmax = std::max(mmax, systems[i].m);
+    nmax = std::max(nmax, systems[i].n);
+  }
+  DevBuf buf(s);
+  double *x, *r, *part, *acc;
+  BHIP(buf.get(&x, (size_t)nmax));
+  BHIP(buf.get(&r, (size_t)mmax));
+  BHIP(buf.get(&part, (size_t)rka::sumsq_part_len()));
+  BHIP(buf.get(&acc, 2));
+  int ntrials = 0;
+  for (auto& members : cls) {
+    if (members.empty()) continue;
+    std::vector<int> byw(members);
+    std::sort(byw.begin(), byw.end(), [&](int a, int b) {
+      return systems[a].m * systems[a].n < systems[b].m * systems[b].n;
+    });
+    const rka_batch_system& Rp = systems[byw[byw.size() / 2]];
+    const int64_t n = Rp.n;
+    // ||b|| of the first right-hand side
+    BHIP(rka::launch_sumsq(Rp.b, nullptr, Rp.m, part, acc + 1, s));
+    double b2 = 0.0;
+    BHIP(hipMemcpyAsync(&b2, acc + 1, sizeof b2, hipMemcpyDeviceToHost, s));
+    BHIP(hipStreamSynchronize(s));
+    if (!(b2 > 0.0)) continue;
+    const int t0 = min_tpr(n);
+    double best = -1.0;
+    int bq = 0, bbs = 0, btpr = 0;
+    for (int tpr = t0; tpr <= 256 && tpr <= 4 * t0; tpr *= 2) {
+      const int W = rka::kBT / tpr;
+      for (int qm = 1; qm <= 2; ++qm) {
+        const int q = W * qm;
+        int64_t cands[3] = {n / 16, n / 4, n};
+        for (int ci = 0; ci < 3; ++ci) {
+          int64_t bsl = cands[ci] < 1 ? 1 : (cands[ci] > 256 ? 256 : cands[ci]);
+          if (ci > 0) {
+            int64_t prev = cands[ci - 1] < 1 ? 1 : (cands[ci - 1] > 256 ? 256 : cands[ci - 1]);
+            if (prev == bsl) continue;
+          }
+          const int bs = (int)bsl;
+          const int64_t K = std::max<int64_t>(1, 8 * Rp.m / ((int64_t)q * bs));
+          rka_batch_system T = Rp;
+          T.nrhs = 1;
+          T.x = x;
+          T.ldx = n;
+          T.x_ref = nullptr;
+          T.q = q;
+          T.block_size = bs;
+          T.tpr = tpr;
+          T.rhs_per_task = 1;
+          T.max_iter = K;
+          BHIP(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), s));
+          rka_batch_stats st;
+          int rc = rka_batch_solve(&T, 1, dtype, seed, 0.0, 1, 0, stream, nullptr, &st);
+          if (rc < 0) return rc;
+          BHIP(rka::launch_gemv(Rp.A, dtype, Rp.m, n, Rp.lda, false, x, Rp.b, -1.0, r, s));
+          BHIP(rka::launch_sumsq(r, nullptr, Rp.m, part, acc, s));
+          double r2 = 0.0;
+          BHIP(hipMemcpyAsync(&r2, acc, sizeof r2, hipMemcpyDeviceToHost, s));
+          BHIP(hipStreamSynchronize(s));
+          ++ntrials;
+          double rho = sqrt(r2 / b2);
+          if (!(rho > 1e-30)) rho = 1e-30;
+          const double ms = st.iterate_ms > 1e-3 ? st.iterate_ms : 1e-3;
+          const double score = isfinite(rho) ? -log(rho) / ms : -1.0;
+          if (score > best) {
+            best = score;
+            bq = q;
+            bbs = bs;
+            btpr = tpr;
+          }
+        }
+      }
+    }
+    if (btpr == 0) continue;
+    for (int i : members) {
+      if (systems[i].tpr == 0) systems[i].tpr = btpr;
+      if (systems[i].q == 0) systems[i].q = bq;
+      if (systems[i].block_size == 0) systems[i].block_size = bbs;
+      // a caller-fixed tpr must still cover the row
+      if ((int64_t)systems[i].tpr * rka::kEptMax < systems[i].n) systems[i].tpr = min_tpr(systems[i].n);
+    }
+  }
+  if (trials) *trials = ntrials;
+  return RKA_OK;
 }

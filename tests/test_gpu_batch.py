@@ -130,3 +130,32 @@ def test_batch_errors():
                         X=torch.zeros(5000, dtype=torch.float64, device=DEV))
     with pytest.raises(rka.RKAError):  # n above 16 x 256
         rka.batch_solve([S])
+
+
+def test_autotuner_fills_parameters_and_tuned_batch_converges():
+    shapes = [(1000, 50), (1200, 60), (3000, 300), (2500, 280), (6000, 1000)]
+    hs, systems = [], []
+    for s, (m, n) in enumerate(shapes):
+        A, xs, b = workloads.scaled_rows_system(m, n, seed=300 + s, dtype="f32")
+        A = np.array(A)
+        hs.append((A, xs))
+        X = torch.full((n,), 7.0, dtype=torch.float64, device=DEV)
+        systems.append(rka.BatchSystem(A=to_dev(A, "f32"), B=vec(b), X=X, X_ref=vec(xs),
+                                       max_iter=50000))
+    systems[1].block_size = 3  # a caller's choice is kept
+    trials = rka.batch_tune(systems, seed=2)
+    assert trials > 0
+    for S in systems:
+        assert np.all(host(S.X) == 7.0)  # untouched
+        n = S.A.shape[1]
+        assert S.tpr in (16, 32, 64, 128, 256) and S.tpr * 16 >= n
+        assert S.q % (256 // S.tpr) == 0 and 1 <= S.block_size <= 256
+    assert systems[1].block_size == 3
+    # same size class, same choice
+    assert (systems[2].tpr, systems[2].q) == (systems[3].tpr, systems[3].q)
+    for S in systems:
+        S.X.zero_()
+    res, _ = rka.batch_solve(systems, seed=5, tol=1e-5, check_every=5)
+    for (A, xs), S, r in zip(hs, systems, res):
+        assert r["status"] == rka.OK
+        assert np.linalg.norm(host(S.X) - xs) <= 1e-5 * np.linalg.norm(xs)
