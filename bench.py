@@ -46,6 +46,12 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the precision / batching / differentiation measurements")
+    ap.add_argument("--forms", default="precision,batching,differentiation")
+    ap.add_argument("--batch-systems", type=int, default=512)
+    ap.add_argument("--batch-sample", type=int, default=16,
+                    help="systems solved one by one in plain FP64 for the batching comparison")
     return ap.parse_args()
 
 
@@ -106,11 +112,14 @@ def make_cells(spec, astar):
     return out
 
 
-def kernel_name(stats):
-    # template instance as named in the library (double storage, 16-byte vecs)
+def kernel_name(stats, storage="double", vec=2):
+    """Template instance as named in the library: <storage, accumulation,
+    elements per 16-byte vec, register bucket, all-gather / iterate in LDS>."""
+    acc = "float" if stats.get("accumulate") == 1 else "double"
+    flag = "true" if stats.get("variant") == 1 else "false"
     if stats["kernel"] == 1:
-        return f"rka_col_kernel<double, 2, {stats['bucket']}>"
-    return f"rkab_kernel<double, 2, {stats['bucket']}>"
+        return f"rka_col_kernel<{storage}, {acc}, {vec}, {stats['bucket']}, {flag}>"
+    return f"rkab_kernel<{storage}, {acc}, {vec}, {stats['bucket']}, {flag}>"
 
 
 def cpu_baseline(A, b, seconds):
@@ -135,6 +144,287 @@ def cpu_baseline(A, b, seconds):
                        f"({info['projections']} projections) including its row norms and "
                        f"running sum, {dt:.1f} s wall"),
             "host_cpu": _cpu_model(), "host_threads": os.cpu_count()}
+
+
+# -- the three forms -------------------------------------------------------------
+
+def _timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, (time.perf_counter() - t0) * 1e3
+
+
+def _rate(s, alpha, q):
+    """e-folds of the error per RKA iteration from the one-step identity
+    E||e_{k+1}||^2 = sum_j phi(s_j) (v_j^T e_k)^2 (consistent part):
+    phi(s) = 1 - 2 alpha s + alpha^2 s / q + alpha^2 (1 - 1/q) s^2, worst at an
+    extreme of the spectrum."""
+    rho = max(1 - 2 * alpha * x + alpha ** 2 * x / q + alpha ** 2 * (1 - 1 / q) * x * x
+              for x in s)
+    return -math.log(rho) / 2
+
+
+def _mp_extremes(m, n):
+    """Marchenko-Pastur edges of sigma^2 / ||A||_F^2 for an iid m x n matrix."""
+    F = m * n
+    return (math.sqrt(m) - math.sqrt(n)) ** 2 / F, (math.sqrt(m) + math.sqrt(n)) ** 2 / F
+
+
+def bench_precision(rka, A, xs, b, x_ls, s_ext):
+    """Plain FP64 RKA vs the precision form (BF16 / FP32 storage, FP32 inner
+    solves, FP64 refinement) at 80000 x 10000: time to 1e-6 relative error on
+    the planted consistent system and, horizon-free, on the least-squares
+    problem; then inner-solve throughput per storage type at 200000 x 20000."""
+    import torch
+    out = {}
+    m, n = A.shape
+    q, qc = 256, 32
+    al, alc = rka.alpha_star(*s_ext, q), rka.alpha_star(*s_ext, qc)
+    k_in = int(math.ceil(1.1 * 9.2 / _rate(s_ext, al, q)))      # ~1e-4 per inner solve
+    k_col = int(math.ceil(1.1 * 9.2 / _rate(s_ext, alc, qc)))
+    A16 = A.to(torch.bfloat16)
+    A32 = A.to(torch.float32)
+    # consistent: b = A x*, each storage type's own rounded matrix
+    cons = {}
+    bc = A @ xs
+    (x, info, st), ms = _timed(lambda: rka.solve_ex(A, bc, method=0, q=q, alpha=al,
+                                                   max_iter=400000, tol=1e-6, x_ref=xs,
+                                                   check_every=25, timing=True))
+    cons["fp64_plain_rka"] = {"ms": ms, "iterations": info.iterations, "status": info.status,
+                              "rel_err": info.rel_err, "q": q, "alpha": al}
+    for name, Ast in (("bf16_refined", A16), ("fp32_refined", A32)):
+        bst = Ast.to(torch.float64) @ xs
+        (x, ri), ms = _timed(lambda: rka.refine_solve(Ast, bst, q=q, alpha=al, accumulate=1,
+                                                      inner_iters=k_in, max_sweeps=6, tol=1e-6,
+                                                      x_ref=xs))
+        cons[name] = {"ms": ms, "sweeps": ri.sweeps, "status": ri.status,
+                      "per_sweep_rel_err": ri.measures, "inner_iters": k_in,
+                      "projections": ri.projections}
+    for name in ("bf16_refined", "fp32_refined"):
+        cons[name]["speedup_vs_fp64"] = cons["fp64_plain_rka"]["ms"] / cons[name]["ms"]
+    out["consistent_80000x10000_to_1e-6"] = cons
+    # least squares (b = A x* + N(0, 1e-2)): horizon-free refinement in both
+    lsq = {}
+    At = rka.transpose(A)
+    (x, ri), ms = _timed(lambda: rka.refine_solve(A, b, At=At, q=q, alpha=al, accumulate=0,
+                                                  inner_iters=k_in, range_iters=k_col,
+                                                  range_q=qc, range_alpha=alc, max_sweeps=5,
+                                                  tol=1e-6, x_ref=x_ls))
+    lsq["fp64_horizon_free"] = {"ms": ms, "sweeps": ri.sweeps, "status": ri.status,
+                                "per_sweep_rel_err": ri.measures}
+    del At
+    torch.cuda.empty_cache()
+    A16d = A16.to(torch.float64)
+    G = A16d.T @ A16d
+    L = torch.linalg.cholesky(G)
+    x_ls16 = torch.cholesky_solve((A16d.T @ b)[:, None], L)[:, 0]
+    r = b - A16d @ x_ls16
+    x_ls16 = x_ls16 + torch.cholesky_solve((A16d.T @ r)[:, None], L)[:, 0]
+    del A16d, G, L, r
+    torch.cuda.empty_cache()
+    At16 = rka.transpose(A16)
+    (x, ri), ms = _timed(lambda: rka.refine_solve(A16, b, At=At16, q=q, alpha=al, accumulate=1,
+                                                  inner_iters=k_in, range_iters=k_col,
+                                                  range_q=qc, range_alpha=alc, max_sweeps=5,
+                                                  tol=1e-6, x_ref=x_ls16))
+    lsq["bf16_horizon_free"] = {"ms": ms, "sweeps": ri.sweeps, "status": ri.status,
+                                "per_sweep_rel_err": ri.measures,
+                                "speedup_vs_fp64": lsq["fp64_horizon_free"]["ms"] / ms}
+    lsq["inner_iters"], lsq["range_iters"], lsq["range_q"] = k_in, k_col, qc
+    out["least_squares_80000x10000_to_1e-6"] = lsq
+    del At16, A16, A32
+    torch.cuda.empty_cache()
+    # inner-solve throughput at 200000 x 20000 (A = the rounded Gaussian)
+    M, N, q3, K3 = 200000, 20000, 64, 300
+    gen = torch.Generator(device=A.device)
+    gen.manual_seed(240117474 + 3)
+    A64 = torch.randn((M, N), generator=gen, device=A.device, dtype=torch.float64)
+    x3 = torch.randn(N, generator=gen, device=A.device, dtype=torch.float64)
+    b3 = A64 @ x3 + 1e-2 * torch.randn(M, generator=gen, device=A.device, dtype=torch.float64)
+    a3 = rka.alpha_star(*_mp_extremes(M, N), q3)
+    thr = {}
+    for name, dt, acc, esz in (("fp64", torch.float64, 0, 8), ("fp32", torch.float32, 1, 4),
+                               ("bf16", torch.bfloat16, 1, 2)):
+        As = A64 if dt == torch.float64 else A64.to(dt)
+        x, info, st = rka.solve_ex(As, b3, method=0, q=q3, alpha=a3, max_iter=K3, seed=2,
+                                   accumulate=acc, timing=True)
+        it_s = st["iterate_ms"] / 1e3
+        bpp = N * esz + 20
+        y, gms = _timed(lambda: rka.gemv(As, x3, c=b3, gamma=-1.0))
+        thr[name] = {"projections_per_s": info.projections / it_s,
+                     "hbm_gbps": info.projections * bpp / it_s / 1e9,
+                     "us_per_iteration": st["iterate_ms"] * 1e3 / K3,
+                     "kernel": kernel_name(st, {"fp64": "double", "fp32": "float",
+                                                "bf16": "rka::bf16_t"}[name],
+                                           16 // esz),
+                     "residual_gemv_gbps": M * N * esz / (gms / 1e3) / 1e9}
+        if As is not A64:
+            del As
+        torch.cuda.empty_cache()
+    out["inner_throughput_200000x20000_rka_q64"] = thr
+    del A64, b3, x3
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_batching(rka, workloads, count, n_sample, seed):
+    """512 FP32 systems (m, n log-uniform, m >= 4n, rows scaled log-uniform in
+    [0.1, 10], planted x*) plus a 50000 x 2000 matrix with 64 planted
+    right-hand sides, in one graph-captured batch to 1e-6 relative error;
+    against plain FP64 RKA (q = 16, alpha = 1) solving a random sample of the
+    same systems one by one, extrapolated by system count."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda:0")
+    shapes = workloads.batch_shapes(count, seed=workloads.DATA_SEED + 4)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(workloads.DATA_SEED + 5)
+    systems, planted = [], []
+    total_bytes = 0
+    for (m, n) in shapes:
+        A = torch.randn((m, n), generator=gen, device=dev, dtype=torch.float32)
+        sc = torch.exp(torch.empty(m, device=dev, dtype=torch.float64).uniform_(
+            math.log(0.1), math.log(10.0), generator=gen))
+        A *= sc.to(torch.float32)[:, None]
+        xs = torch.randn(n, generator=gen, device=dev, dtype=torch.float64)
+        b = A.to(torch.float64) @ xs
+        systems.append(rka.BatchSystem(A=A, B=b, X=torch.zeros(n, dtype=torch.float64,
+                                                               device=dev),
+                                       X_ref=xs, max_iter=60000))
+        planted.append(xs)
+        total_bytes += m * n * 4
+    Msh, Nsh, R = 50000, 2000, 64
+    Ash = torch.randn((Msh, Nsh), generator=gen, device=dev, dtype=torch.float32)
+    Xs = torch.randn((R, Nsh), generator=gen, device=dev, dtype=torch.float64)
+    Bsh = Xs @ Ash.to(torch.float64).T
+    systems.append(rka.BatchSystem(A=Ash, B=Bsh.contiguous(),
+                                   X=torch.zeros((R, Nsh), dtype=torch.float64, device=dev),
+                                   X_ref=Xs, max_iter=60000))
+    total_bytes += Msh * Nsh * 4
+    torch.cuda.synchronize()
+    trials, tune_ms = _timed(lambda: rka.batch_tune(systems, seed=seed))
+    (res, st), ms = _timed(lambda: rka.batch_solve(systems, seed=seed, tol=1e-6, check_every=10,
+                                                   graph=True, raise_on_error=False))
+    ok = sum(1 for r in res if r["status"] == 0)
+    classes = {}
+    for r, S in zip(res, systems):
+        n = S.A.shape[1]
+        c = 1 << max(0, (n - 1).bit_length())
+        key = f"n<={c}"
+        e = classes.setdefault(key, {"systems": 0, "params": set(), "not_converged": 0,
+                                     "max_iterations": 0})
+        e["systems"] += 1
+        e["params"].add((r["tpr"], r["q"], r["block_size"], r["rhs_per_task"]))
+        e["max_iterations"] = max(e["max_iterations"], r["iterations"])
+        if r["status"] != 0:
+            e["not_converged"] += 1
+    for e in classes.values():
+        e["params"] = sorted(e["params"])
+    unconv = [{"m": S.A.shape[0], "n": S.A.shape[1], "iterations": r["iterations"],
+               "rel": r["rel"], "tpr": r["tpr"], "q": r["q"], "bs": r["block_size"]}
+              for r, S in zip(res, systems) if r["status"] != 0][:12]
+    proj = sum(r["iterations"] * r["q"] * r["block_size"] * S.B.shape[0] if S.B.dim() > 1
+               else r["iterations"] * r["q"] * r["block_size"] for r, S in zip(res, systems))
+    worst = max(r["rel"] for r in res)
+    # plain FP64 RKA on a random sample, one system at a time
+    rng = np.random.default_rng(seed)
+    pick = sorted(rng.choice(count, size=min(n_sample, count), replace=False).tolist())
+    t_plain = 0.0
+    plain = []
+    for i in pick:
+        S = systems[i]
+        A64 = S.A.to(torch.float64)
+        (x, info, _), t = _timed(lambda: rka.solve_ex(A64, S.B, method=0, q=16, alpha=1.0,
+                                                      max_iter=2000000, tol=1e-6,
+                                                      x_ref=planted[i], check_every=10,
+                                                      raise_on_error=False))
+        t_plain += t
+        plain.append({"m": S.A.shape[0], "n": S.A.shape[1], "ms": t,
+                      "iterations": info.iterations, "status": info.status})
+        del A64
+    A64 = Ash.to(torch.float64)
+    t_sh = 0.0
+    for r in range(4):
+        (x, info, _), t = _timed(lambda: rka.solve_ex(A64, Bsh[r].contiguous(), method=0, q=16,
+                                                      alpha=1.0, max_iter=2000000, tol=1e-6,
+                                                      x_ref=Xs[r].contiguous(), check_every=10,
+                                                      raise_on_error=False))
+        t_sh += t
+    del A64
+    extrap = t_plain / len(pick) * count + t_sh / 4 * R
+    return {
+        "systems": count, "shared_matrix": f"{Msh}x{Nsh} with {R} right-hand sides",
+        "matrix_bytes": total_bytes, "tune_ms": tune_ms, "tune_trials": trials,
+        "batch_ms_to_1e-6": ms, "graph_ms": st["iterate_ms"], "tasks": st["tasks"],
+        "chunks": st["chunks"], "converged_systems": ok, "worst_rel_err": worst,
+        "projections_upper_bound": proj, "classes": classes, "not_converged_sample": unconv,
+        "plain_fp64_rka_sample": plain, "plain_fp64_shared_ms_per_rhs": t_sh / 4,
+        "plain_fp64_extrapolated_ms": extrap,
+        "speedup_vs_plain_fp64": extrap / ms,
+        "note": ("plain FP64 RKA (q=16, alpha=1) measured on a random sample of "
+                 f"{len(pick)} systems and 4 of the shared right-hand sides, one solve at a "
+                 "time, extrapolated by system / right-hand-side count"),
+    }
+
+
+def bench_differentiation(rka):
+    """Forward + backward of the differentiable solve on a 20000 x 1000 system
+    (FP32 storage) against the same with FP64 storage; accuracy against an
+    FP64 normal-equations reference computed on the GPU."""
+    import torch
+    from paper_2401_17474_amd.autograd import SolveOpts, lsq_solve
+    dev = torch.device("cuda:0")
+    m, n, q = 20000, 1000, 64
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(240117474 + 6)
+    A64 = torch.randn((m, n), generator=gen, device=dev, dtype=torch.float64)
+    A32 = A64.to(torch.float32)
+    A64 = A32.to(torch.float64)  # the problem matrix is the FP32 one
+    xs = torch.randn(n, generator=gen, device=dev, dtype=torch.float64)
+    b = A64 @ xs + 0.1 * torch.randn(m, generator=gen, device=dev, dtype=torch.float64)
+    t = torch.randn(n, generator=gen, device=dev, dtype=torch.float64)
+    G = A64.T @ A64
+    ev = torch.linalg.eigvalsh(G)
+    F = float(torch.trace(G))
+    s_ext = (float(ev[0]) / F, float(ev[-1]) / F)
+    al = rka.alpha_star(*s_ext, q)
+    k = int(math.ceil(1.1 * 9.2 / _rate(s_ext, al, q)))
+    # reference: x_LS and the gradient of L = ||x - t||^2 from the normal equations
+    L = torch.linalg.cholesky(G)
+    x_ref = torch.cholesky_solve((A64.T @ b)[:, None], L)[:, 0]
+    g = 2 * (x_ref - t)
+    lam = torch.cholesky_solve(g[:, None], L)[:, 0]
+    z = A64 @ lam
+    r = b - A64 @ x_ref
+    dA_ref = torch.outer(r, lam) - torch.outer(z, x_ref)
+    out = {"shape": f"{m}x{n}", "q": q, "alpha": al, "inner_iters": k, "sweeps": 3}
+    for name, A in (("fp32", A32), ("fp64", A64)):
+        opts = SolveOpts(q=q, alpha=al, inner_iters=k, range_iters=k, sweeps=3,
+                         accumulate=1 if name == "fp32" else 0, seed=3)
+        times = []
+        for rep in range(3):
+            Ad = A.detach().clone().requires_grad_(True)
+            bd = b.detach().clone().requires_grad_(True)
+
+            def fb():
+                x = lsq_solve(Ad, bd, opts)
+                torch.sum((x - t) ** 2).backward()
+                return x
+            x, ms = _timed(fb)
+            times.append(ms)
+        times.sort()
+        out[name] = {
+            "forward_backward_ms": times[1],
+            "rel_err_x": float((x - x_ref).norm() / x_ref.norm()),
+            "rel_err_dA": float((Ad.grad.to(torch.float64) - dA_ref).norm() / dA_ref.norm()),
+            "rel_err_db": float((bd.grad - z).norm() / z.norm()),
+        }
+    out["speedup_fp32_vs_fp64"] = out["fp64"]["forward_backward_ms"] / out["fp32"][
+        "forward_backward_ms"]
+    return out
 
 
 def _cpu_model():
@@ -267,6 +557,24 @@ def main():
             "kernel": dom_name, "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch":
             bytes_per_launch, "bytes_per_projection": bytes_per_proj}
 
+    forms = {}
+    if not args.no_forms:
+        wanted = set(args.forms.split(","))
+        for name, fn in (("precision", lambda: bench_precision(rka, A, xs, b, x_ls,
+                                                                (s_min, s_max))),
+                         ("batching", lambda: bench_batching(rka, workloads, args.batch_systems,
+                                                             args.batch_sample, args.seed)),
+                         ("differentiation", lambda: bench_differentiation(rka))):
+            if name not in wanted:
+                continue
+            log(f"[bench] form: {name}")
+            try:
+                forms[name] = fn()
+            except Exception as e:  # a failing form must not hide the main line
+                forms[name] = {"error": f"{type(e).__name__}: {e}"}
+            torch.cuda.empty_cache()
+            log(f"[bench] form {name} done")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
@@ -289,6 +597,7 @@ def main():
         "cpu_baseline": cpu,
         "alpha_star": {str(q): astar[q] for q in astar}, "s_min": s_min, "s_max": s_max,
         "cells": cells_out,
+        "forms": forms,
     }
     print(json.dumps(line), flush=True)
 

@@ -266,7 +266,9 @@ typedef struct rka_refine_info {
  *     x = x + d                        (FP64)
  * then the measure ||x - x_ref|| / ||x_ref|| (x_ref given) or ||b - A x|| /
  * ||b|| is written to sweep_measure[s] (host array of max_sweeps doubles,
- * nullable).  Plain RKA stops at the convergence horizon set by the
+ * nullable).  With x_ref and tol > 0 the inner solve also stops early, at
+ * the first multiple of 25 iterations where ||d - (x_ref - x)|| <= tol
+ * ||x_ref|| (the sweep's own stopping test, measured on the correction).  Plain RKA stops at the convergence horizon set by the
  * least-squares residual (Sec. 2.3.1); the range projection removes that
  * residual from every correction, so the sweeps converge to the
  * least-squares solution itself.  With FP32 accumulation every inner solve
@@ -336,7 +338,8 @@ typedef struct rka_batch_stats {
  *     x^(k+1) = (sum_w v_w) / q                (binary32, worker order)
  * With tol > 0 and x_ref given, a group stops after the first multiple of
  * check_every where ||x - x_ref|| <= tol ||x_ref|| over its right-hand sides.
- * use_graph != 0 captures the whole launch sequence (set-up, then per chunk
+ * chunk_iters > 0 caps the iterations per chunk (0: as many as keep the
+ * chunk's row streams within 64 Mi indices).  use_graph != 0 captures the whole launch sequence (set-up, then per chunk
  * of iterations a row-stream launch and one iteration launch for all
  * systems) in one HIP graph and launches it once; `stream` must then not be
  * the null stream.  results: host array of count entries (nullable).  Waits
@@ -344,20 +347,22 @@ typedef struct rka_batch_stats {
  * not reach tol), RKA_EDIVERGED, or an error.
  */
 int rka_batch_solve(const rka_batch_system* systems, int32_t count, int dtype, uint64_t seed,
-                    double tol, int64_t check_every, int32_t use_graph, void* stream,
-                    rka_batch_result* results, rka_batch_stats* stats);
+                    double tol, int64_t check_every, int64_t chunk_iters, int32_t use_graph,
+                    void* stream, rka_batch_result* results, rka_batch_stats* stats);
 
 /*
  * rka_batch_tune -- the batching form's autotuner.  Groups the systems by
- * size class (n rounded up to a power of two), runs candidate (tpr, q,
- * block_size) triples -- tpr from the smallest that covers a row to four
- * times it, q one or two rounds of the workers a workgroup holds, block_size
- * in {n/16, n/4, n} clipped to [1, 256] -- on each class's median system for
- * the same number of projections (8 m), and keeps the triple with the
- * fastest residual reduction per second (HIP-event time of the iterations).
- * Writes q, block_size and tpr into every system of the class where they are
- * 0; x is not touched.  Meant for consistent systems (the residual is the
- * progress measure).  *trials (nullable) = candidates timed.
+ * size class (n rounded up to a power of two) and runs candidate (tpr, q,
+ * block_size) triples -- tpr in {t0, 2 t0} with t0 the smallest that covers
+ * a row, q in {1, W/4, W} with W = 256 / tpr, block_size in {n/8, n/2}
+ * clipped to [1, 256] -- on each class's median system for about m/2
+ * projections, measuring the residual reduction per millisecond and per
+ * projection.  The choice per class minimises the modelled batch time to a
+ * 10^-6 residual reduction: the larger of the slowest class's own time and
+ * the row bytes of all tasks at 5 TB/s.  Writes q, block_size and tpr into
+ * every system of a class where they are 0; x is not touched.  Meant for
+ * consistent systems (the residual is the progress measure).  *trials
+ * (nullable) = candidates timed.
  */
 int rka_batch_tune(rka_batch_system* systems, int32_t count, int dtype, uint64_t seed,
                    void* stream, int32_t* trials);

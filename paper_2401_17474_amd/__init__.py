@@ -121,7 +121,7 @@ def lib():
                                        ctypes.POINTER(_RefineOpts), U64, P, P, P,
                                        ctypes.POINTER(_RefineInfo)]
         L.rka_batch_solve.argtypes = [ctypes.POINTER(_BatchSystem), I32, ctypes.c_int, U64, D,
-                                      I64, I32, P, ctypes.POINTER(_BatchResult),
+                                      I64, I64, I32, P, ctypes.POINTER(_BatchResult),
                                       ctypes.POINTER(_BatchStats)]
         L.rka_batch_tune.argtypes = [ctypes.POINTER(_BatchSystem), I32, ctypes.c_int, U64, P,
                                      ctypes.POINTER(I32)]
@@ -433,8 +433,8 @@ def batch_tune(systems, *, seed=1, stream=None):
     return trials.value
 
 
-def batch_solve(systems, *, seed=1, tol=0.0, check_every=1, graph=True, stream=None,
-                raise_on_error=True):
+def batch_solve(systems, *, seed=1, tol=0.0, check_every=1, chunk_iters=0, graph=True,
+                stream=None, raise_on_error=True):
     """rka_batch_solve over a list of BatchSystem.  Returns (results, stats):
     per-system dicts (iterations, rel, status, q, block_size, tpr,
     rhs_per_task) and launch facts.  With ``graph`` the launches run as one
@@ -449,7 +449,7 @@ def batch_solve(systems, *, seed=1, tol=0.0, check_every=1, graph=True, stream=N
     if side is not None:
         side.wait_stream(cur)
     run_on = side if side is not None else (stream or cur)
-    status = lib().rka_batch_solve(arr, n_sys, code, seed, tol, check_every,
+    status = lib().rka_batch_solve(arr, n_sys, code, seed, tol, check_every, chunk_iters,
                                    1 if graph else 0, ctypes.c_void_p(run_on.cuda_stream), res,
                                    ctypes.byref(st))
     if side is not None:

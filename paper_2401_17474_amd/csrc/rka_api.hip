@@ -490,6 +490,9 @@ int rka_lsq_grad_A(int64_t m, int64_t n, const double* r, const double* lam, con
   return RKA_OK;
 }
 
+// stopping-test interval of the inner solves when a reference is given
+constexpr int64_t kInnerCheck = 25;
+
 int rka_refine_solve(const void* A, const void* At, int dtype, int64_t m, int64_t n, int64_t lda,
                      int64_t ldat, const double* b, const double* x0, double* x,
                      const rka_refine_opts* o, uint64_t seed, const double* x_ref,
@@ -528,9 +531,11 @@ int rka_refine_solve(const void* A, const void* At, int dtype, int64_t m, int64_
   const bool vec_t = range && vector_path_ok(At, dtype, m, ldat);
 
   Scratch sc(s);
-  double *r, *d, *part, *acc2, *y = nullptr, *g = nullptr;
+  double *r, *d, *part, *acc2, *y = nullptr, *g = nullptr, *dref = nullptr;
   HIP_TRY(sc.get(&r, (size_t)m));
   HIP_TRY(sc.get(&d, (size_t)n));
+  const bool early = x_ref && o->tol > 0.0;
+  if (early) HIP_TRY(sc.get(&dref, (size_t)n));
   HIP_TRY(sc.get(&part, (size_t)rka::sumsq_part_len()));
   HIP_TRY(sc.get(&acc2, 2));
   if (range) {
@@ -570,11 +575,23 @@ int rka_refine_solve(const void* A, const void* At, int dtype, int64_t m, int64_
       projections += ii.projections;
       rhs = y;
     }
-    // d ~ argmin ||A d - rhs||, by the inner RKA / RKAB solve from d = 0
+    // d ~ argmin ||A d - rhs||, by the inner RKA / RKAB solve from d = 0.
+    // With a reference the exact correction is x_ref - x, and
+    // ||(x + d) - x_ref|| = ||d - (x_ref - x)||: the inner solve stops as
+    // soon as the sweep would meet tol (tested every kInnerCheck iterations).
+    double tol_d = 0.0;
+    if (early) {
+      HIP_TRY(rka::launch_sub(dref, x_ref, x, n, s));
+      HIP_TRY(rka::launch_sumsq(dref, nullptr, n, part, acc2, s));
+      double dr2 = 0.0;
+      HIP_TRY(hipMemcpyAsync(&dr2, acc2, sizeof dr2, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      if (dr2 > 0.0 && isfinite(dr2)) tol_d = o->tol * sqrt(ref2 / dr2);
+    }
     const int st = solve_impl(o->method == 1, A, dtype, m, n, lda, rhs, nullptr, d, o->q,
-                              o->method == 1 ? o->block_size : 1, o->alpha, o->inner_iters, 0.0,
-                              seed, nullptr, (int64_t)sw * o->inner_iters, 1, 0, 0, false,
-                              o->accumulate, 0, stream, &ii, nullptr);
+                              o->method == 1 ? o->block_size : 1, o->alpha, o->inner_iters, tol_d,
+                              seed, tol_d > 0.0 ? dref : nullptr, (int64_t)sw * o->inner_iters,
+                              kInnerCheck, 0, 0, false, o->accumulate, 0, stream, &ii, nullptr);
     if (st < 0) return st;
     projections += ii.projections;
     HIP_TRY(rka::launch_axpy(x, d, n, s));

@@ -98,7 +98,7 @@ __global__ __launch_bounds__(kBT) void batch_iter_kernel(const BatchTask* __rest
                                                          int64_t check_every, double tol2) {
   const BatchTask T = tasks[blockIdx.x];
   const int64_t max_iter = T.max_iter;
-  if (*T.done) return;
+  if (T.done[blockIdx.x]) return;
   extern __shared__ float L[];
   __shared__ float red[kBT / kWave][kRmax];
   __shared__ double dred[kBT / kWave];
@@ -366,14 +366,16 @@ int validate_sys(const rka_batch_system& S, int i, int dtype) {
 }  // namespace
 
 extern "C" int rka_batch_solve(const rka_batch_system* systems, int32_t count, int dtype,
-                               uint64_t seed, double tol, int64_t check_every, int32_t use_graph,
-                               void* stream, rka_batch_result* results, rka_batch_stats* stats) {
+                               uint64_t seed, double tol, int64_t check_every, int64_t chunk_iters,
+                               int32_t use_graph, void* stream, rka_batch_result* results,
+                               rka_batch_stats* stats) {
   if (stats) memset(stats, 0, sizeof *stats);
   if (!systems || count < 1 || count > 65535)
     return rka::api_fail(RKA_EINVAL, "need 1 to 65535 systems");
   if (dtype != RKA_F32 && dtype != RKA_BF16)
     return rka::api_fail(RKA_EINVAL, "batched solves take RKA_F32 or RKA_BF16 storage");
   if (!(tol >= 0.0) || !isfinite(tol)) return rka::api_fail(RKA_EINVAL, "tol must be finite and >= 0");
+  if (chunk_iters < 0) return rka::api_fail(RKA_EINVAL, "chunk_iters must be >= 0");
   for (int i = 0; i < count; ++i) {
     int v = validate_sys(systems[i], i, dtype);
     if (v != RKA_OK) return v;
@@ -412,6 +414,7 @@ extern "C" int rka_batch_solve(const rka_batch_system* systems, int32_t count, i
     for (int i = 0; i < count; ++i) per_iter += (int64_t)q[i] * bs[i];
     const int64_t cap = (64ll << 20) / (per_iter > 0 ? per_iter : 1);
     if (Kc > cap) Kc = cap > 0 ? cap : 1;
+    if (chunk_iters > 0 && Kc > chunk_iters) Kc = chunk_iters;
   }
   double* wbuf;
   double* cbuf;
@@ -631,15 +634,33 @@ extern "C" int rka_batch_solve(const rka_batch_system* systems, int32_t count, i
 }
 
 // ---------------------------------------------------------------------------
-// Autotuner: per size class of n (powers of two), time candidate (tpr, q,
-// block_size) triples on the class's median system and keep the one that
-// reduces the residual fastest: score = ln(||b|| / ||b - A x_K||) / time of
-// the K iterations, with K set so that every candidate spends the same
-// number of projections (8 m).  Only parameters the caller left at 0 are
-// filled in.  The progress measure is the residual, so the tuner is meant
-// for consistent systems (inconsistent ones stall at the least-squares
-// residual, Sec. 2.3.1).
+// Autotuner.  Systems are grouped by size class (n rounded up to a power of
+// two).  On each class's median system, every candidate (tpr, q, block_size)
+// runs from x = 0 for about m/2 projections; from the residual reduction rho
+// and the HIP-event time t of the iterations it gets the progress per
+// millisecond, r_t = ln(1/rho) / t, and per projection, r_p = ln(1/rho) / P.
+// The batch then runs all tasks at once, so its time to a 10^-6 residual
+// reduction (E = ln 10^6) is modelled as
+//     max( max_c E / r_t(c) ,  sum_c tasks_c * (E / r_p(c)) * bytes_c / BW )
+// -- the slowest task's own chain against the row bytes of all tasks through
+// HBM (BW = 5 TB/s, the rate the row gathers reach on this device).  The
+// tuner starts from the fastest candidate of every class and, while the
+// bandwidth term dominates, moves one class at a time to the candidate that
+// lowers the modelled time most.  Candidates: tpr in {t0, 2 t0} (t0 the
+// smallest that covers a row), q in {1, W/4, W} with W = 256 / tpr the
+// workers a workgroup runs at once, block_size in {n/8, n/2} clipped to
+// [1, 256].  Only parameters the caller left at 0 are written; x is not
+// touched.  The progress measure is the residual, so the tuner is meant for
+// consistent systems (inconsistent ones stall at the least-squares residual,
+// Sec. 2.3.1).
 // ---------------------------------------------------------------------------
+namespace {
+struct Cand {
+  int tpr, q, bs;
+  double rt, rp;  // e-folds per ms, per projection
+};
+}  // namespace
+
 extern "C" int rka_batch_tune(rka_batch_system* systems, int32_t count, int dtype, uint64_t seed,
                               void* stream, int32_t* trials) {
   if (trials) *trials = 0;
@@ -653,7 +674,7 @@ extern "C" int rka_batch_tune(rka_batch_system* systems, int32_t count, int dtyp
   }
   if (rka::api_num_cus() <= 0) return rka::api_fail(RKA_EDEVICE, "no HIP device available");
   hipStream_t s = (hipStream_t)stream;
-  // size classes
+  const int esz = dtype == RKA_F32 ? 4 : 2;
   std::vector<std::vector<int>> cls(16);
   for (int i = 0; i < count; ++i) {
     int c = 0;
@@ -672,6 +693,13 @@ extern "C" int rka_batch_tune(rka_batch_system* systems, int32_t count, int dtyp
   BHIP(buf.get(&part, (size_t)rka::sumsq_part_len()));
   BHIP(buf.get(&acc, 2));
   int ntrials = 0;
+  struct Class {
+    std::vector<int> members;
+    std::vector<Cand> cands;
+    double tasks = 0, bytes = 0;  // tasks of the class, row bytes per projection
+    int pick = -1;
+  };
+  std::vector<Class> classes;
   for (auto& members : cls) {
     if (members.empty()) continue;
     std::vector<int> byw(members);
@@ -680,28 +708,28 @@ extern "C" int rka_batch_tune(rka_batch_system* systems, int32_t count, int dtyp
     });
     const rka_batch_system& Rp = systems[byw[byw.size() / 2]];
     const int64_t n = Rp.n;
-    // ||b|| of the first right-hand side
+    Class C;
+    C.members = members;
+    for (int i : members) C.tasks += systems[i].nrhs;
+    C.bytes = (double)n * esz + 16.0;
     BHIP(rka::launch_sumsq(Rp.b, nullptr, Rp.m, part, acc + 1, s));
     double b2 = 0.0;
     BHIP(hipMemcpyAsync(&b2, acc + 1, sizeof b2, hipMemcpyDeviceToHost, s));
     BHIP(hipStreamSynchronize(s));
     if (!(b2 > 0.0)) continue;
     const int t0 = min_tpr(n);
-    double best = -1.0;
-    int bq = 0, bbs = 0, btpr = 0;
-    for (int tpr = t0; tpr <= 256 && tpr <= 4 * t0; tpr *= 2) {
+    for (int tpr = t0; tpr <= 256 && tpr <= 2 * t0; tpr *= 2) {
       const int W = rka::kBT / tpr;
-      for (int qm = 1; qm <= 2; ++qm) {
-        const int q = W * qm;
-        int64_t cands[3] = {n / 16, n / 4, n};
-        for (int ci = 0; ci < 3; ++ci) {
-          int64_t bsl = cands[ci] < 1 ? 1 : (cands[ci] > 256 ? 256 : cands[ci]);
-          if (ci > 0) {
-            int64_t prev = cands[ci - 1] < 1 ? 1 : (cands[ci - 1] > 256 ? 256 : cands[ci - 1]);
-            if (prev == bsl) continue;
-          }
-          const int bs = (int)bsl;
-          const int64_t K = std::max<int64_t>(1, 8 * Rp.m / ((int64_t)q * bs));
+      const int qs[3] = {1, W / 4 > 1 ? W / 4 : 1, W};
+      for (int qi = 0; qi < 3; ++qi) {
+        if (qi > 0 && qs[qi] == qs[qi - 1]) continue;
+        const int q = qs[qi];
+        const int64_t bss[2] = {std::min<int64_t>(256, std::max<int64_t>(1, n / 8)),
+                                std::min<int64_t>(256, std::max<int64_t>(1, n / 2))};
+        for (int bi = 0; bi < 2; ++bi) {
+          if (bi > 0 && bss[bi] == bss[0]) continue;
+          const int bs = (int)bss[bi];
+          const int64_t K = std::max<int64_t>(1, Rp.m / 2 / ((int64_t)q * bs));
           rka_batch_system T = Rp;
           T.nrhs = 1;
           T.x = x;
@@ -714,7 +742,7 @@ extern "C" int rka_batch_tune(rka_batch_system* systems, int32_t count, int dtyp
           T.max_iter = K;
           BHIP(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), s));
           rka_batch_stats st;
-          int rc = rka_batch_solve(&T, 1, dtype, seed, 0.0, 1, 0, stream, nullptr, &st);
+          int rc = rka_batch_solve(&T, 1, dtype, seed, 0.0, 1, 0, 0, stream, nullptr, &st);
           if (rc < 0) return rc;
           BHIP(rka::launch_gemv(Rp.A, dtype, Rp.m, n, Rp.lda, false, x, Rp.b, -1.0, r, s));
           BHIP(rka::launch_sumsq(r, nullptr, Rp.m, part, acc, s));
@@ -724,23 +752,62 @@ extern "C" int rka_batch_tune(rka_batch_system* systems, int32_t count, int dtyp
           ++ntrials;
           double rho = sqrt(r2 / b2);
           if (!(rho > 1e-30)) rho = 1e-30;
+          if (!isfinite(rho) || rho >= 1.0) continue;
           const double ms = st.iterate_ms > 1e-3 ? st.iterate_ms : 1e-3;
-          const double score = isfinite(rho) ? -log(rho) / ms : -1.0;
-          if (score > best) {
-            best = score;
-            bq = q;
-            bbs = bs;
-            btpr = tpr;
-          }
+          const double ef = -log(rho);
+          C.cands.push_back({tpr, q, bs, ef / ms, ef / (double)(K * q * bs)});
         }
       }
     }
-    if (btpr == 0) continue;
-    for (int i : members) {
-      if (systems[i].tpr == 0) systems[i].tpr = btpr;
-      if (systems[i].q == 0) systems[i].q = bq;
-      if (systems[i].block_size == 0) systems[i].block_size = bbs;
-      // a caller-fixed tpr must still cover the row
+    if (C.cands.empty()) continue;
+    int best = 0;
+    for (int k = 1; k < (int)C.cands.size(); ++k)
+      if (C.cands[k].rt > C.cands[best].rt) best = k;
+    C.pick = best;
+    classes.push_back(C);
+  }
+  // batch model: max(latency of the slowest class, row bytes of all tasks / BW)
+  const double E = log(1e6), BW = 5e12 / 1e3;  // bytes per ms
+  auto model = [&](const std::vector<Class>& cs, double* lat, double* bw) {
+    *lat = 0.0;
+    *bw = 0.0;
+    for (const Class& C : cs) {
+      const Cand& k = C.cands[C.pick];
+      *lat = std::max(*lat, E / k.rt);
+      *bw += C.tasks * (E / k.rp) * C.bytes / BW;
+    }
+    return std::max(*lat, *bw);
+  };
+  double lat, bw;
+  double cur = model(classes, &lat, &bw);
+  for (int guard = 0; guard < 64 && bw > lat; ++guard) {
+    int bc = -1, bk = -1;
+    double bt = cur;
+    for (int c = 0; c < (int)classes.size(); ++c) {
+      const int keep = classes[c].pick;
+      for (int k = 0; k < (int)classes[c].cands.size(); ++k) {
+        if (k == keep) continue;
+        classes[c].pick = k;
+        double l2, b2;
+        const double t = model(classes, &l2, &b2);
+        if (t < bt) {
+          bt = t;
+          bc = c;
+          bk = k;
+        }
+      }
+      classes[c].pick = keep;
+    }
+    if (bc < 0) break;
+    classes[bc].pick = bk;
+    cur = model(classes, &lat, &bw);
+  }
+  for (const Class& C : classes) {
+    const Cand& k = C.cands[C.pick];
+    for (int i : C.members) {
+      if (systems[i].tpr == 0) systems[i].tpr = k.tpr;
+      if (systems[i].q == 0) systems[i].q = k.q;
+      if (systems[i].block_size == 0) systems[i].block_size = k.bs;
       if ((int64_t)systems[i].tpr * rka::kEptMax < systems[i].n) systems[i].tpr = min_tpr(systems[i].n);
     }
   }

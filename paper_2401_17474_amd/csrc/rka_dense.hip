@@ -138,6 +138,22 @@ hipError_t launch_axpy(double* x, const double* d, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// out = a - b
+__global__ __launch_bounds__(256) void sub_kernel(double* __restrict__ out,
+                                                  const double* __restrict__ a,
+                                                  const double* __restrict__ b, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = a[i] - b[i];
+}
+
+hipError_t launch_sub(double* out, const double* a, const double* b, int64_t n, hipStream_t s) {
+  int64_t nb = (n + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(sub_kernel, dim3((unsigned)nb), dim3(256), 0, s, out, a, b, n);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // out[0] = sum_i (a_i - b_i)^2 (b may be NULL): per-block fixed-order partial
 // sums, then one block adds the partials in block order.

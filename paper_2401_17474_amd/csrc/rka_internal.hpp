@@ -97,6 +97,7 @@ hipError_t launch_gemv(const void* M, int dtype, int64_t rows, int64_t cols, int
 hipError_t launch_transpose(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, void* At,
                             int64_t ldat, hipStream_t s);
 hipError_t launch_axpy(double* x, const double* d, int64_t n, hipStream_t s);
+hipError_t launch_sub(double* out, const double* a, const double* b, int64_t n, hipStream_t s);
 // out[0] = sum (a - b)^2 (b may be NULL); part holds sumsq_part_len() doubles
 int sumsq_part_len();
 hipError_t launch_sumsq(const double* a, const double* b, int64_t len, double* part, double* out,

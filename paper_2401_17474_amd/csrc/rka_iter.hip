@@ -20,6 +20,8 @@
 // bitwise-reproducible results.
 #include <math.h>
 
+#include <algorithm>
+
 #include "rka_device.hpp"
 #include "rka_internal.hpp"
 
@@ -73,6 +75,11 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
   C* P = (C*)(PG + (gather ? (size_t)G * (q + 1) : 0));  // q * nsv   row partials per vec
   C* U = P + (size_t)q * nsv;         // NT * V       update partials per thread
   C* XS = U + (size_t)NT * V;         // nsv * V      new slice of x
+  C* UP = XS + (size_t)nsv * V;       // max(NT, nsv*V)  partial column sums of the update
+  // the update's column sums over the rg row groups are split into NP parts
+  // of consecutive groups (all threads busy even when the slice is narrow)
+  const int NE = nsv * V;
+  const int NP = NT / NE > 1 ? NT / NE : 1;
 
   // the scale alpha (b_i - <a_i, x>) / ||a_i||^2 in the accumulation type
   auto scale_of = [&](double bi, double wi, double D) -> double {
@@ -310,11 +317,20 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
       for (int e = 0; e < V; ++e) U[t * V + e] = u[e];
     }
     __syncthreads();
+    for (int L = t; L < NE * NP; L += NT) {
+      const int je = L % NE, part = L / NE;
+      const int jj = je / V, e = je % V;
+      const int g0 = part * rg / NP, g1 = (part + 1) * rg / NP;
+      C acc = 0;
+      for (int gg = g0; gg < g1; ++gg) acc += U[(gg * nsv + jj) * V + e];
+      UP[L] = acc;
+    }
+    __syncthreads();
     if (colv && rgi == 0) {
 #pragma unroll
       for (int e = 0; e < V; ++e) {
         C acc = 0;
-        for (int gg = 0; gg < rg; ++gg) acc += U[(gg * nsv + j) * V + e];
+        for (int pp = 0; pp < NP; ++pp) acc += UP[pp * NE + j * V + e];
         xv[e] = fma(acc, (C)p.inv_q, xv[e]);
         XS[j * V + e] = xv[e];
       }
@@ -352,10 +368,11 @@ static int rpt_bucket(int need) {
 }
 
 // Column slices: one workgroup per CU by default.  Measured on MI355X at
-// 80000 x 10000 FP64, the widest grid is fastest for every q (16, 64, 256):
-// the per-iteration critical path is dominated by the in-workgroup reductions
-// (which shrink with the slice) and the exchange latency, not by the number
-// of participants.  Tiny problems (<= 64 KB of rows per iteration, one slice
+// 80000 x 10000 and x 20000, FP64, FP32 and BF16 storage, the widest grid is
+// fastest or within a few percent for every q (16, 64, 256), even where a
+// BF16 slice is only 80 bytes of a row: the per-iteration critical path is
+// the in-workgroup reductions (which shrink with the slice) and the exchange
+// latency, not the HBM fetch granularity or the number of participants.  Tiny problems (<= 64 KB of rows per iteration, one slice
 // that fits a workgroup) run in one workgroup with no exchange at all.
 constexpr int64_t kOneGroupBytes = 64 << 10;
 // one-barrier all-gather while every workgroup reads at most this many partials
@@ -405,7 +422,8 @@ bool rka_col_plan(const SolveShape& sh, RkaColGeom* geo) {
   const size_t pg = gather ? (size_t)G * (sh.q + 1) : 0;
   const size_t csz = sh.acc == 1 ? sizeof(float) : sizeof(double);
   const size_t lds = sizeof(double) * (nsv + 16 + sh.q + 1 + pg) +
-                     csz * ((size_t)sh.q * nsv + (size_t)nt * V + (size_t)nsv * V);
+                     csz * ((size_t)sh.q * nsv + (size_t)nt * V + (size_t)nsv * V +
+                            (size_t)std::max(nt, nsv * V));
   if (lds > 64 * 1024) return false;
   geo->G = G;
   geo->nsv = nsv;

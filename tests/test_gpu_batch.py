@@ -149,7 +149,8 @@ def test_autotuner_fills_parameters_and_tuned_batch_converges():
         assert np.all(host(S.X) == 7.0)  # untouched
         n = S.A.shape[1]
         assert S.tpr in (16, 32, 64, 128, 256) and S.tpr * 16 >= n
-        assert S.q % (256 // S.tpr) == 0 and 1 <= S.block_size <= 256
+        W = 256 // S.tpr
+        assert S.q in (1, max(1, W // 4), W) and 1 <= S.block_size <= 256
     assert systems[1].block_size == 3
     # same size class, same choice
     assert (systems[2].tpr, systems[2].q) == (systems[3].tpr, systems[3].q)
@@ -159,3 +160,26 @@ def test_autotuner_fills_parameters_and_tuned_batch_converges():
     for (A, xs), S, r in zip(hs, systems, res):
         assert r["status"] == rka.OK
         assert np.linalg.norm(host(S.X) - xs) <= 1e-5 * np.linalg.norm(xs)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_each_task_keeps_its_own_stop_flag(graph):
+    # the largest task (scheduled first) converges in the first chunk; the
+    # others must go on for many more chunks of 5 iterations
+    easy = workloads.gaussian_system(4000, 100, seed=41, dtype="f32")
+    hard = [workloads.scaled_rows_system(900, 200, seed=42 + s, dtype="f32") for s in range(3)]
+    systems = []
+    A, xs, b = easy
+    systems.append(rka.BatchSystem(A=to_dev(np.array(A), "f32"), B=vec(b),
+                                   X=torch.zeros(100, dtype=torch.float64, device=DEV),
+                                   X_ref=vec(xs), q=16, block_size=100, tpr=16, max_iter=400))
+    for A, xs, b in hard:
+        systems.append(rka.BatchSystem(A=to_dev(np.array(A), "f32"), B=vec(b),
+                                       X=torch.zeros(200, dtype=torch.float64, device=DEV),
+                                       X_ref=vec(xs), q=1, block_size=4, tpr=16, max_iter=3000))
+    res, st = rka.batch_solve(systems, seed=3, tol=1e-2, check_every=5, chunk_iters=5,
+                              graph=graph, raise_on_error=False)
+    assert st["chunks"] == 600
+    assert res[0]["status"] == rka.OK and res[0]["iterations"] <= 20
+    for r in res[1:]:
+        assert r["iterations"] > 50  # ran far past the chunk where the first task stopped

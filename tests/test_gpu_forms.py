@@ -229,3 +229,18 @@ def test_refine_errors():
     with pytest.raises(rka.RKAError):  # FP32 accumulation on FP64 storage
         rka.refine_solve(to_dev(A.astype(np.float64)), vec(b), q=2, inner_iters=5,
                          max_sweeps=1, accumulate=1)
+
+
+def test_refine_inner_solves_stop_at_the_sweep_tolerance():
+    # with x_ref and tol, an inner solve ends once ||x + d - x_ref|| <= tol ||x_ref||
+    A, xs, b = _system(1500, 96, "f32", seed=14)
+    Ad = to_dev(A, "f32")
+    x1, full = rka.refine_solve(Ad, vec(b), q=8, inner_iters=3000, max_sweeps=4, seed=4,
+                                x_ref=vec(xs))
+    x2, early = rka.refine_solve(Ad, vec(b), q=8, inner_iters=3000, max_sweeps=4, seed=4,
+                                 x_ref=vec(xs), tol=1e-5)
+    assert early.status == rka.OK and early.sweeps == 1 and early.measures[0] <= 1e-5
+    assert early.projections < full.projections / 4
+    assert early.projections % (25 * 8) == 0
+    err = np.linalg.norm(host(x2) - xs) / np.linalg.norm(xs)
+    assert abs(err - early.measures[0]) <= 1e-3 * err
