@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--batch-systems", type=int, default=512)
     ap.add_argument("--batch-sample", type=int, default=16,
                     help="systems solved one by one in plain FP64 for the batching comparison")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run one device-to-device copy of MIB MiB (the reference for "
+                         "scaling the FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
 
 
@@ -427,6 +430,26 @@ def bench_differentiation(rka):
     return out
 
 
+def pmc_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE
+    counter runs (profiles/pmc_traffic.json, scaled by a copy of known size),
+    or None when they were taken on another kernel or on other kernel sources."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        h = hashlib.sha256()
+        for p in d["sources"]:
+            with open(os.path.join(ROOT, p), "rb") as f:
+                h.update(f.read())
+    except (OSError, KeyError, ValueError):
+        return None
+    if d.get("kernel") != kernel or h.hexdigest() != d.get("sources_sha256"):
+        return None
+    return d["traffic_bytes_per_launch"]
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -449,6 +472,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes": nbytes}), flush=True)
+        return
 
     import paper_2401_17474_amd as rka
     import workloads
@@ -553,7 +586,7 @@ def main():
     bytes_per_launch = dom["bytes"] / dom["launches"]
     achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None,
+            "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": pmc_traffic(dom_name),
             "kernel": dom_name, "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch":
             bytes_per_launch, "bytes_per_projection": bytes_per_proj}
 
