@@ -276,7 +276,9 @@ def bench_precision(rka, A, xs, b, x_ls, s_ext):
 def bench_batching(rka, workloads, count, n_sample, seed):
     """512 FP32 systems (m, n log-uniform, m >= 4n, rows scaled log-uniform in
     [0.1, 10], planted x*) plus a 50000 x 2000 matrix with 64 planted
-    right-hand sides, in one graph-captured batch to 1e-6 relative error;
+    right-hand sides, to 1e-6 relative error in graph-captured batch solves
+    (binary32, with FP64 refinement sweeps for the systems whose binary32
+    iteration stalls above 1e-6);
     against plain FP64 RKA (q = 16, alpha = 1) solving a random sample of the
     same systems one by one, extrapolated by system count."""
     import numpy as np
@@ -296,7 +298,7 @@ def bench_batching(rka, workloads, count, n_sample, seed):
         b = A.to(torch.float64) @ xs
         systems.append(rka.BatchSystem(A=A, B=b, X=torch.zeros(n, dtype=torch.float64,
                                                                device=dev),
-                                       X_ref=xs, max_iter=60000))
+                                       X_ref=xs, alpha=0.0, max_iter=60000))
         planted.append(xs)
         total_bytes += m * n * 4
     Msh, Nsh, R = 50000, 2000, 64
@@ -305,12 +307,17 @@ def bench_batching(rka, workloads, count, n_sample, seed):
     Bsh = Xs @ Ash.to(torch.float64).T
     systems.append(rka.BatchSystem(A=Ash, B=Bsh.contiguous(),
                                    X=torch.zeros((R, Nsh), dtype=torch.float64, device=dev),
-                                   X_ref=Xs, max_iter=60000))
+                                   X_ref=Xs, alpha=0.0, max_iter=60000))
     total_bytes += Msh * Nsh * 4
     torch.cuda.synchronize()
     trials, tune_ms = _timed(lambda: rka.batch_tune(systems, seed=seed))
+    # iteration caps as a budget of 4e6 dependent projection steps per worker
+    # (an iteration is block_size steps plus the average)
+    for S in systems:
+        S.max_iter = int(4e6 // (S.block_size + 2))
     (res, st), ms = _timed(lambda: rka.batch_solve(systems, seed=seed, tol=1e-6, check_every=10,
-                                                   graph=True, raise_on_error=False))
+                                                   graph=True, refine_sweeps=3,
+                                                   raise_on_error=False))
     ok = sum(1 for r in res if r["status"] == 0)
     classes = {}
     for r, S in zip(res, systems):
@@ -320,7 +327,8 @@ def bench_batching(rka, workloads, count, n_sample, seed):
         e = classes.setdefault(key, {"systems": 0, "params": set(), "not_converged": 0,
                                      "max_iterations": 0})
         e["systems"] += 1
-        e["params"].add((r["tpr"], r["q"], r["block_size"], r["rhs_per_task"]))
+        e["params"].add((r["tpr"], r["q"], r["block_size"], round(r["alpha"], 3),
+                         r["rhs_per_task"]))
         e["max_iterations"] = max(e["max_iterations"], r["iterations"])
         if r["status"] != 0:
             e["not_converged"] += 1
@@ -332,22 +340,39 @@ def bench_batching(rka, workloads, count, n_sample, seed):
     proj = sum(r["iterations"] * r["q"] * r["block_size"] * S.B.shape[0] if S.B.dim() > 1
                else r["iterations"] * r["q"] * r["block_size"] for r, S in zip(res, systems))
     worst = max(r["rel"] for r in res)
-    # plain FP64 RKA on a random sample, one system at a time
+    # plain FP64 RKA on a sample, one system at a time, stratified by how much
+    # work the batch needed (row bytes to convergence): the hardest 5 % form
+    # one stratum, the rest another; each stratum's mean time is scaled by its
+    # size
     rng = np.random.default_rng(seed)
-    pick = sorted(rng.choice(count, size=min(n_sample, count), replace=False).tolist())
+    work = np.array([r["iterations"] * r["q"] * r["block_size"] * S.A.shape[1]
+                     for r, S in zip(res[:count], systems[:count])], dtype=np.float64)
+    order = np.argsort(-work)
+    n_hard = max(1, count // 20)
+    hard, rest = order[:n_hard], order[n_hard:]
+    k_hard = min(len(hard), max(1, n_sample // 4))
+    k_rest = min(len(rest), max(1, n_sample - k_hard))
+    strata = [(rng.choice(hard, size=k_hard, replace=False), len(hard)),
+              (rng.choice(rest, size=k_rest, replace=False), len(rest))]
     t_plain = 0.0
+    extrap = 0.0
     plain = []
-    for i in pick:
-        S = systems[i]
-        A64 = S.A.to(torch.float64)
-        (x, info, _), t = _timed(lambda: rka.solve_ex(A64, S.B, method=0, q=16, alpha=1.0,
-                                                      max_iter=2000000, tol=1e-6,
-                                                      x_ref=planted[i], check_every=10,
-                                                      raise_on_error=False))
-        t_plain += t
-        plain.append({"m": S.A.shape[0], "n": S.A.shape[1], "ms": t,
-                      "iterations": info.iterations, "status": info.status})
-        del A64
+    for members, size in strata:
+        t_stratum = 0.0
+        for i in sorted(int(v) for v in members):
+            S = systems[i]
+            A64 = S.A.to(torch.float64)
+            (x, info, _), t = _timed(lambda: rka.solve_ex(A64, S.B, method=0, q=16, alpha=1.0,
+                                                          max_iter=2000000, tol=1e-6,
+                                                          x_ref=planted[i], check_every=10,
+                                                          raise_on_error=False))
+            t_stratum += t
+            plain.append({"m": S.A.shape[0], "n": S.A.shape[1], "ms": t,
+                          "iterations": info.iterations, "status": info.status,
+                          "stratum": "hardest 5%" if size == len(hard) else "rest"})
+            del A64
+        t_plain += t_stratum
+        extrap += t_stratum / len(members) * size
     A64 = Ash.to(torch.float64)
     t_sh = 0.0
     for r in range(4):
@@ -357,7 +382,7 @@ def bench_batching(rka, workloads, count, n_sample, seed):
                                                       raise_on_error=False))
         t_sh += t
     del A64
-    extrap = t_plain / len(pick) * count + t_sh / 4 * R
+    extrap += t_sh / 4 * R
     return {
         "systems": count, "shared_matrix": f"{Msh}x{Nsh} with {R} right-hand sides",
         "matrix_bytes": total_bytes, "tune_ms": tune_ms, "tune_trials": trials,
@@ -367,9 +392,10 @@ def bench_batching(rka, workloads, count, n_sample, seed):
         "plain_fp64_rka_sample": plain, "plain_fp64_shared_ms_per_rhs": t_sh / 4,
         "plain_fp64_extrapolated_ms": extrap,
         "speedup_vs_plain_fp64": extrap / ms,
-        "note": ("plain FP64 RKA (q=16, alpha=1) measured on a random sample of "
-                 f"{len(pick)} systems and 4 of the shared right-hand sides, one solve at a "
-                 "time, extrapolated by system / right-hand-side count"),
+        "note": ("plain FP64 RKA (q=16, alpha=1) measured one solve at a time on a sample "
+                 f"stratified by the batch's work to convergence ({k_hard} of the hardest "
+                 f"{len(hard)} systems, {k_rest} of the other {len(rest)}) and on 4 of the "
+                 "shared right-hand sides; each stratum's mean scaled by its size"),
     }
 
 

@@ -304,13 +304,15 @@ typedef struct rka_batch_system {
     int32_t rhs_per_task;   /* right-hand sides one workgroup carries (<= 8); 0 =
                                the most that fit 64 KB of LDS                         */
     int32_t reserved;
-    double alpha;           /* relaxation weight, finite and > 0                       */
+    double alpha;           /* relaxation weight, finite and > 0; 0 = chosen by the
+                               tuner (1 if the batch is not tuned)                    */
     int64_t max_iter;       /* iteration cap, >= 0                                     */
 } rka_batch_system;
 
 typedef struct rka_batch_result {
     int64_t iterations;     /* iterations run (the largest over the system's tasks)   */
     double rel;             /* largest last relative error over its tasks (0 if none) */
+    double alpha;           /* relaxation weight used                                  */
     int32_t status;         /* RKA_OK, RKA_NOT_CONVERGED or RKA_EDIVERGED              */
     int32_t q, block_size, tpr, rhs_per_task;  /* parameters used                      */
     int32_t reserved;
@@ -337,7 +339,11 @@ typedef struct rka_batch_stats {
  *     v = x^(k);  bs times: v += alpha (b_i - <A^(i), v>) / ||A^(i)||^2 A^(i)^T
  *     x^(k+1) = (sum_w v_w) / q                (binary32, worker order)
  * With tol > 0 and x_ref given, a group stops after the first multiple of
- * check_every where ||x - x_ref|| <= tol ||x_ref|| over its right-hand sides.
+ * check_every where ||x - x_ref|| <= tol ||x_ref|| over its right-hand sides,
+ * or (status RKA_NOT_CONVERGED) once its squared error has not halved for
+ * 60000 dependent projection steps (iterations x (block_size + 2)) -- the
+ * rounding floor of a binary32 iteration, which rka_batch_refine_solve goes
+ * below.
  * chunk_iters > 0 caps the iterations per chunk (0: as many as keep the
  * chunk's row streams within 64 Mi indices).  use_graph != 0 captures the whole launch sequence (set-up, then per chunk
  * of iterations a row-stream launch and one iteration launch for all
@@ -351,16 +357,34 @@ int rka_batch_solve(const rka_batch_system* systems, int32_t count, int dtype, u
                     void* stream, rka_batch_result* results, rka_batch_stats* stats);
 
 /*
+ * rka_batch_refine_solve -- the batch with FP64 iterative refinement (the
+ * precision form of rka_refine_solve, for consistent systems): per sweep s,
+ * r = b - A x in FP64 for every system and right-hand side, then one batch
+ * solve as rka_batch_solve (binary32) of A d = r from d = 0 with keys
+ * seed + s * 65536 + i, then x += d in FP64.  With x_ref and tol > 0 a task
+ * stops once ||x + d - x_ref|| <= tol ||x_ref|| and the sweeps end when every
+ * system has; this reaches accuracies below the binary32 rounding floor of
+ * one batch solve.  results: iterations summed over sweeps, rel and status of
+ * the last sweep.  Other arguments as rka_batch_solve (chunk length chosen
+ * by the library).
+ */
+int rka_batch_refine_solve(const rka_batch_system* systems, int32_t count, int dtype,
+                           uint64_t seed, double tol, int64_t check_every, int32_t sweeps,
+                           int32_t use_graph, void* stream, rka_batch_result* results,
+                           rka_batch_stats* stats);
+
+/*
  * rka_batch_tune -- the batching form's autotuner.  Groups the systems by
- * size class (n rounded up to a power of two) and runs candidate (tpr, q,
- * block_size) triples -- tpr in {t0, 2 t0} with t0 the smallest that covers
- * a row, q in {1, W/4, W} with W = 256 / tpr, block_size in {n/8, n/2}
- * clipped to [1, 256] -- on each class's median system for about m/2
- * projections, measuring the residual reduction per millisecond and per
- * projection.  The choice per class minimises the modelled batch time to a
+ * size class (n rounded up to a power of two) and runs candidates on each
+ * class's median system for about m/2 projections, measuring the residual
+ * reduction per millisecond and per projection.  Candidates: tpr in {t0,
+ * 2 t0} with t0 the smallest that covers a row and W = 256 / tpr workers per
+ * workgroup; RKAB with alpha = 1, q in {1, W/4, W}, block_size in {n/8, n/2}
+ * clipped to [1, 256]; and RKA (block size 1) with q = W, alpha in {W/4,
+ * W/2}.  The choice per class minimises the modelled batch time to a
  * 10^-6 residual reduction: the larger of the slowest class's own time and
- * the row bytes of all tasks at 5 TB/s.  Writes q, block_size and tpr into
- * every system of a class where they are 0; x is not touched.  Meant for
+ * the row bytes of all tasks at 5 TB/s.  Writes q, block_size, tpr and alpha
+ * into every system of a class where they are 0; x is not touched.  Meant for
  * consistent systems (the residual is the progress measure).  *trials
  * (nullable) = candidates timed.
  */

@@ -70,6 +70,7 @@ class _BatchSystem(ctypes.Structure):
 
 class _BatchResult(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int64), ("rel", ctypes.c_double),
+                ("alpha", ctypes.c_double),
                 ("status", ctypes.c_int32), ("q", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("tpr", ctypes.c_int32), ("rhs_per_task", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
@@ -123,6 +124,10 @@ def lib():
         L.rka_batch_solve.argtypes = [ctypes.POINTER(_BatchSystem), I32, ctypes.c_int, U64, D,
                                       I64, I64, I32, P, ctypes.POINTER(_BatchResult),
                                       ctypes.POINTER(_BatchStats)]
+        L.rka_batch_refine_solve.argtypes = [ctypes.POINTER(_BatchSystem), I32, ctypes.c_int,
+                                             U64, D, I64, I32, I32, P,
+                                             ctypes.POINTER(_BatchResult),
+                                             ctypes.POINTER(_BatchStats)]
         L.rka_batch_tune.argtypes = [ctypes.POINTER(_BatchSystem), I32, ctypes.c_int, U64, P,
                                      ctypes.POINTER(I32)]
         L.rka_status_string.argtypes = [ctypes.c_int]
@@ -132,7 +137,8 @@ def lib():
         L.rka_version.restype = ctypes.c_int
         for f in ("rka_solve", "rkab_solve", "rka_solve_ex", "rka_row_norms", "rka_prefix",
                   "rka_sample_indices", "rka_gemv", "rka_transpose", "rka_lsq_grad_A",
-                  "rka_refine_solve", "rka_batch_solve", "rka_batch_tune"):
+                  "rka_refine_solve", "rka_batch_solve", "rka_batch_tune",
+                  "rka_batch_refine_solve"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -378,7 +384,8 @@ def refine_solve(A, b, *, At=None, method=0, q, block_size=1, accumulate=1, alph
 class BatchSystem:
     """One system of a batch: A (m x n, float32 or bfloat16, GPU), B (m) or
     (nrhs x m) float64, X (n) or (nrhs x n) float64 -- start values in,
-    results out.  q, block_size, tpr = 0 let the library choose."""
+    results out.  q, block_size, tpr, alpha = 0 let the library (its tuner)
+    choose."""
     A: object
     B: object
     X: object
@@ -429,13 +436,14 @@ def batch_tune(systems, *, seed=1, stream=None):
     _raise_if(lib().rka_batch_tune(arr, len(systems), code, seed, _stream(stream),
                                    ctypes.byref(trials)))
     for S, a in zip(systems, arr):
-        S.q, S.block_size, S.tpr = a.q, a.block_size, a.tpr
+        S.q, S.block_size, S.tpr, S.alpha = a.q, a.block_size, a.tpr, a.alpha
     return trials.value
 
 
 def batch_solve(systems, *, seed=1, tol=0.0, check_every=1, chunk_iters=0, graph=True,
-                stream=None, raise_on_error=True):
-    """rka_batch_solve over a list of BatchSystem.  Returns (results, stats):
+                refine_sweeps=0, stream=None, raise_on_error=True):
+    """rka_batch_solve (or, with refine_sweeps > 0, rka_batch_refine_solve)
+    over a list of BatchSystem.  Returns (results, stats):
     per-system dicts (iterations, rel, status, q, block_size, tpr,
     rhs_per_task) and launch facts.  With ``graph`` the launches run as one
     captured HIP graph on a side stream ordered after the current one."""
@@ -449,9 +457,15 @@ def batch_solve(systems, *, seed=1, tol=0.0, check_every=1, chunk_iters=0, graph
     if side is not None:
         side.wait_stream(cur)
     run_on = side if side is not None else (stream or cur)
-    status = lib().rka_batch_solve(arr, n_sys, code, seed, tol, check_every, chunk_iters,
-                                   1 if graph else 0, ctypes.c_void_p(run_on.cuda_stream), res,
-                                   ctypes.byref(st))
+    if refine_sweeps > 0:
+        status = lib().rka_batch_refine_solve(arr, n_sys, code, seed, tol, check_every,
+                                              refine_sweeps, 1 if graph else 0,
+                                              ctypes.c_void_p(run_on.cuda_stream), res,
+                                              ctypes.byref(st))
+    else:
+        status = lib().rka_batch_solve(arr, n_sys, code, seed, tol, check_every, chunk_iters,
+                                       1 if graph else 0, ctypes.c_void_p(run_on.cuda_stream),
+                                       res, ctypes.byref(st))
     if side is not None:
         cur.wait_stream(side)
     if raise_on_error:

@@ -29,14 +29,22 @@ namespace rka {
 constexpr int kBT = 256;     // threads per batch workgroup
 constexpr int kEptMax = 16;  // row elements per thread (tpr * 16 >= n)
 constexpr int kRmax = 8;     // right-hand sides per task
+// dependent projection steps (block size + 2 for the average) per chunk
+constexpr double kChunkSteps = 4096.0;
+// a task whose squared error has not halved for this many dependent
+// projection steps (iterations x (block size + 2)) has reached the rounding
+// floor of its binary32 iteration and stops (done = 4)
+constexpr int64_t kStallSteps = 60000;
 
 struct BatchSys {
   const double* c;         // running sum of the squared row norms
   const int64_t* last_pos; // largest row with a positive weight
   int64_t m;
   uint64_t seed;
+  int64_t kc;              // iterations of this system per chunk
+  int64_t max_iter;
   int32_t q, bs;
-  int32_t* idx;            // row stream of the current chunk, K x q x bs
+  int32_t* idx;            // row stream of the current chunk, kc x q x bs
   const int32_t* alive;    // nonzero while a task of the system still runs
 };
 
@@ -55,7 +63,11 @@ struct BatchTask {
   int32_t* alive;    // per system: cleared by the sampler bookkeeping below
   int64_t* iters;    // per task
   double* rel;       // per task: last relative error (NaN if never measured)
+  double* best;      // per task: smallest squared error seen at a halving
+  int64_t* best_k;   // per task: iteration of that halving
   int64_t max_iter;  // iteration cap of the system
+  int64_t kc;        // iterations per chunk (shared with its system's sampler)
+  double ref2;       // > 0: denominator of the stopping test (else ||xr||^2)
   float alpha;
   int32_t R, q, bs, tpr;
   int32_t bf16;      // storage: 0 FP32, 1 BF16
@@ -66,11 +78,15 @@ __device__ __forceinline__ float load_elem(const void* A, int bf16, int64_t off)
   return ((const float*)A)[off];
 }
 
-// Row stream of one chunk for every system still running (one thread per draw).
+// Row stream of chunk `chunk` for every system still running (one thread per
+// draw): system s covers iterations [chunk kc_s, (chunk + 1) kc_s).
 __global__ __launch_bounds__(256) void batch_sample_kernel(const BatchSys* __restrict__ sys,
-                                                           int64_t k0, int64_t K) {
+                                                           int64_t chunk) {
   const BatchSys S = sys[blockIdx.y];
   if (S.alive && *S.alive == 0) return;
+  const int64_t k0 = chunk * S.kc;
+  if (k0 >= S.max_iter) return;
+  const int64_t K = S.max_iter - k0 < S.kc ? S.max_iter - k0 : S.kc;
   const double W = S.c[S.m - 1];
   const int64_t last = *S.last_pos;
   const int64_t total = K * (int64_t)S.q * S.bs;
@@ -84,21 +100,30 @@ __global__ __launch_bounds__(256) void batch_sample_kernel(const BatchSys* __res
   }
 }
 
+__global__ void batch_fill64_kernel(double* p, int64_t n, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
 __global__ void batch_fill_kernel(int32_t* p, int64_t n, int32_t v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
 }
 
-// One task per workgroup; K iterations from k0.  check_every > 0 with a
-// reference: stop once ||x - xr|| <= tol ||xr|| (all R right-hand sides
-// together), tested after every check_every-th iteration.
+// One task per workgroup; chunk `chunk` covers its iterations
+// [chunk kc, (chunk + 1) kc).  check_every > 0 with a reference: stop once
+// ||x - xr|| <= tol ||xr|| (all R right-hand sides together), tested after
+// every check_every-th iteration.
 __global__ __launch_bounds__(kBT) void batch_iter_kernel(const BatchTask* __restrict__ tasks,
-                                                         int64_t k0, int64_t K,
-                                                         int64_t check_every, double tol2) {
+                                                         int64_t chunk, int64_t check_every,
+                                                         double tol2) {
   const BatchTask T = tasks[blockIdx.x];
   const int64_t max_iter = T.max_iter;
   if (T.done[blockIdx.x]) return;
+  const int64_t k0 = chunk * T.kc, K = T.kc;
+  if (k0 >= max_iter) return;
   extern __shared__ float L[];
   __shared__ float red[kBT / kWave][kRmax];
   __shared__ double dred[kBT / kWave];
@@ -120,7 +145,7 @@ __global__ __launch_bounds__(kBT) void batch_iter_kernel(const BatchTask* __rest
       const double v = T.xr[(e / n) * T.ldxr + (e % n)];
       s = fma(v, v, s);
     }
-    ref2 = block_sum(s, dred);
+    ref2 = T.ref2 > 0.0 ? T.ref2 : block_sum(s, dred);
   }
   __syncthreads();
 
@@ -232,10 +257,18 @@ __global__ __launch_bounds__(kBT) void batch_iter_kernel(const BatchTask* __rest
       }
       const double e2 = block_sum(s, dred);
       if (t == 0) T.rel[blockIdx.x] = sqrt(e2 / ref2);
-      if (e2 <= tol2 * ref2 || !isfinite(e2)) {
+      const double best = T.best[blockIdx.x];
+      const bool halved = e2 <= 0.5 * best;
+      const bool stalled = !halved && (k - T.best_k[blockIdx.x]) * (bs + 2) >= kStallSteps;
+      __syncthreads();  // every thread has read best before it changes
+      if (halved && t == 0) {
+        T.best[blockIdx.x] = e2;
+        T.best_k[blockIdx.x] = k;
+      }
+      if (e2 <= tol2 * ref2 || !isfinite(e2) || stalled) {
         if (t == 0) {
           T.iters[blockIdx.x] = k;
-          T.done[blockIdx.x] = isfinite(e2) ? 1 : 2;
+          T.done[blockIdx.x] = !isfinite(e2) ? 2 : (e2 <= tol2 * ref2 ? 1 : 4);
         }
         stopped = true;
         break;
@@ -357,18 +390,21 @@ int validate_sys(const rka_batch_system& S, int i, int dtype) {
     return rka::api_fail(RKA_EINVAL, "system %d: tpr must be 16..256 (power of 2) with tpr*16 >= n", i);
   if (S.rhs_per_task < 0 || S.rhs_per_task > rka::kRmax)
     return rka::api_fail(RKA_EINVAL, "system %d: rhs_per_task must be in [0, %d]", i, rka::kRmax);
-  if (!(S.alpha > 0.0) || !isfinite(S.alpha))
-    return rka::api_fail(RKA_EINVAL, "system %d: alpha must be finite and > 0", i);
+  if (!(S.alpha >= 0.0) || !isfinite(S.alpha))
+    return rka::api_fail(RKA_EINVAL, "system %d: alpha must be finite and >= 0 (0: chosen)", i);
   (void)dtype;
   return RKA_OK;
 }
 
 }  // namespace
 
-extern "C" int rka_batch_solve(const rka_batch_system* systems, int32_t count, int dtype,
-                               uint64_t seed, double tol, int64_t check_every, int64_t chunk_iters,
-                               int32_t use_graph, void* stream, rka_batch_result* results,
-                               rka_batch_stats* stats) {
+// The batch solve; ref2_rhs (nullable): per system and right-hand side (in
+// system order), the squared norm that stands for ||x_ref||^2 in the
+// stopping test (the refinement measures corrections against x_ref - x).
+static int batch_core(const rka_batch_system* systems, int32_t count, int dtype, uint64_t seed,
+                      double tol, int64_t check_every, int64_t chunk_iters, int32_t use_graph,
+                      void* stream, rka_batch_result* results, rka_batch_stats* stats,
+                      const double* ref2_rhs) {
   if (stats) memset(stats, 0, sizeof *stats);
   if (!systems || count < 1 || count > 65535)
     return rka::api_fail(RKA_EINVAL, "need 1 to 65535 systems");
@@ -407,15 +443,29 @@ extern "C" int rka_batch_solve(const rka_batch_system* systems, int32_t count, i
   std::vector<int32_t> task_sys;
   std::vector<int64_t> task_work;
   int64_t idx_total = 0;
-  // row stream chunk: bounded so that the chunk's indices stay <= 64 Mi entries
-  int64_t Kc = max_iter > 0 ? max_iter : 1;
+  // Chunks are balanced in time, not in iterations: an iteration of system s
+  // is a chain of bs_s dependent projections plus the average, so system s
+  // advances kc_s ~ kChunkSteps / (bs_s + 2) iterations per chunk and no task
+  // holds a chunk open for the others.  The chunk's row streams stay within
+  // 64 Mi indices (the budget is scaled down if needed).
+  std::vector<int64_t> kc(count);
   {
-    int64_t per_iter = 0;
-    for (int i = 0; i < count; ++i) per_iter += (int64_t)q[i] * bs[i];
-    const int64_t cap = (64ll << 20) / (per_iter > 0 ? per_iter : 1);
-    if (Kc > cap) Kc = cap > 0 ? cap : 1;
-    if (chunk_iters > 0 && Kc > chunk_iters) Kc = chunk_iters;
+    double steps = rka::kChunkSteps;
+    double idx_need = 0.0;
+    for (int i = 0; i < count; ++i)
+      idx_need += steps / (bs[i] + 2.0) * (double)q[i] * bs[i];
+    if (idx_need > (double)(64ll << 20)) steps *= (double)(64ll << 20) / idx_need;
+    for (int i = 0; i < count; ++i) {
+      int64_t k = (int64_t)(steps / (bs[i] + 2.0));
+      if (k < 1) k = 1;
+      if (chunk_iters > 0 && k > chunk_iters) k = chunk_iters;
+      const int64_t cap = systems[i].max_iter > 0 ? systems[i].max_iter : 1;
+      kc[i] = k < cap ? k : cap;
+    }
   }
+  int64_t nchunks = 0;
+  for (int i = 0; i < count; ++i)
+    nchunks = std::max(nchunks, (systems[i].max_iter + kc[i] - 1) / kc[i]);
   double* wbuf;
   double* cbuf;
   int64_t* lastbuf;
@@ -424,10 +474,10 @@ extern "C" int rka_batch_solve(const rka_batch_system* systems, int32_t count, i
   BHIP(buf.get(&wbuf, (size_t)mtot));
   BHIP(buf.get(&cbuf, (size_t)mtot));
   BHIP(buf.get(&lastbuf, (size_t)count));
-  for (int i = 0; i < count; ++i) idx_total += Kc * q[i] * bs[i];
+  for (int i = 0; i < count; ++i) idx_total += kc[i] * q[i] * bs[i];
   int32_t* idxbuf;
   BHIP(buf.get(&idxbuf, (size_t)idx_total));
-  int64_t moff = 0, ioff = 0;
+  int64_t moff = 0, ioff = 0, roff = 0;
   for (int i = 0; i < count; ++i) {
     const rka_batch_system& S = systems[i];
     BatchSys& Y = hsys[i];
@@ -435,6 +485,8 @@ extern "C" int rka_batch_solve(const rka_batch_system* systems, int32_t count, i
     Y.last_pos = lastbuf + i;
     Y.m = S.m;
     Y.seed = seed + (uint64_t)i;
+    Y.kc = kc[i];
+    Y.max_iter = S.max_iter;
     Y.q = q[i];
     Y.bs = bs[i];
     Y.idx = idxbuf + ioff;
@@ -453,19 +505,24 @@ extern "C" int rka_batch_solve(const rka_batch_system* systems, int32_t count, i
       T.ldxr = S.ldxr;
       T.w = wbuf + moff;
       T.idx = Y.idx;
-      T.alpha = (float)S.alpha;
+      T.alpha = (float)(S.alpha > 0.0 ? S.alpha : 1.0);
       T.R = S.nrhs - r0 < R[i] ? S.nrhs - r0 : R[i];
       T.q = q[i];
       T.bs = bs[i];
       T.tpr = tpr[i];
       T.bf16 = dtype == RKA_BF16;
       T.max_iter = S.max_iter;
+      T.kc = kc[i];
+      T.ref2 = 0.0;
+      if (ref2_rhs)
+        for (int r = 0; r < T.R; ++r) T.ref2 += ref2_rhs[roff + r0 + r];
       htask.push_back(T);
       task_sys.push_back(i);
       task_work.push_back((int64_t)T.R * S.n * q[i] * bs[i] * (S.max_iter > 0 ? S.max_iter : 1));
     }
     moff += S.m;
-    ioff += Kc * q[i] * bs[i];
+    ioff += kc[i] * q[i] * bs[i];
+    roff += S.nrhs;
   }
   const int ntask = (int)htask.size();
   // largest tasks first, so that the long ones start at once
@@ -480,8 +537,8 @@ extern "C" int rka_batch_solve(const rka_batch_system* systems, int32_t count, i
     sorted_sys[t] = task_sys[order[t]];
   }
   int32_t *done, *alive, *tsys;
-  int64_t* iters;
-  double* rel;
+  int64_t *iters, *best_k;
+  double *rel, *best;
   BatchTask* dtask;
   BatchSys* dsys;
   BHIP(buf.get(&done, (size_t)ntask));
@@ -489,6 +546,8 @@ extern "C" int rka_batch_solve(const rka_batch_system* systems, int32_t count, i
   BHIP(buf.get(&tsys, (size_t)ntask));
   BHIP(buf.get(&iters, (size_t)ntask));
   BHIP(buf.get(&rel, (size_t)ntask));
+  BHIP(buf.get(&best, (size_t)ntask));
+  BHIP(buf.get(&best_k, (size_t)ntask));
   BHIP(buf.get(&dtask, (size_t)ntask));
   BHIP(buf.get(&dsys, (size_t)count));
   for (int t = 0; t < ntask; ++t) {
@@ -496,6 +555,8 @@ extern "C" int rka_batch_solve(const rka_batch_system* systems, int32_t count, i
     sorted[t].alive = alive;
     sorted[t].iters = iters;
     sorted[t].rel = rel;
+    sorted[t].best = best;
+    sorted[t].best_k = best_k;
   }
   for (int i = 0; i < count; ++i) hsys[i].alive = alive + i;
   BHIP(hipMemcpyAsync(dtask, sorted.data(), ntask * sizeof(BatchTask), hipMemcpyHostToDevice, s));
@@ -511,7 +572,7 @@ extern "C" int rka_batch_solve(const rka_batch_system* systems, int32_t count, i
   int64_t draws_max = 0;
   for (int t = 0; t < ntask; ++t)
     lds = std::max(lds, rka::batch_lds_bytes(sorted[t].n, sorted[t].R, sorted[t].tpr));
-  for (int i = 0; i < count; ++i) draws_max = std::max(draws_max, Kc * q[i] * bs[i]);
+  for (int i = 0; i < count; ++i) draws_max = std::max(draws_max, kc[i] * q[i] * bs[i]);
   if (lds > 64 * 1024)
     BHIP(hipFuncSetAttribute((const void*)rka::batch_iter_kernel,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -555,15 +616,20 @@ extern "C" int rka_batch_solve(const rka_batch_system* systems, int32_t count, i
       off += S.m;
     }
     hipLaunchKernelGGL(rka::batch_fill_kernel, dim3(1), dim3(256), 0, s, done, (int64_t)ntask, 0);
+    hipLaunchKernelGGL(rka::batch_fill_kernel, dim3(1), dim3(256), 0, s, (int32_t*)iters,
+                       (int64_t)ntask * 2, 0);
+    hipLaunchKernelGGL(rka::batch_fill_kernel, dim3(1), dim3(256), 0, s, (int32_t*)best_k,
+                       (int64_t)ntask * 2, 0);
+    hipLaunchKernelGGL(rka::batch_fill64_kernel, dim3(1), dim3(256), 0, s, best, (int64_t)ntask,
+                       (double)INFINITY);
     hipLaunchKernelGGL(rka::batch_fill_kernel, dim3(1), dim3(256), 0, s, alive, (int64_t)count, 1);
     if (!use_graph) (void)hipEventRecord(ev[1], s);
     int nb = (int)((draws_max + 255) / 256);
     if (nb > 1024) nb = 1024;
-    for (int64_t k0 = 0; k0 < max_iter; k0 += Kc) {
-      const int64_t K = max_iter - k0 < Kc ? max_iter - k0 : Kc;
-      hipLaunchKernelGGL(rka::batch_sample_kernel, dim3(nb, count), dim3(256), 0, s, dsys, k0, K);
+    for (int64_t c = 0; c < nchunks; ++c) {
+      hipLaunchKernelGGL(rka::batch_sample_kernel, dim3(nb, count), dim3(256), 0, s, dsys, c);
       hipLaunchKernelGGL(rka::batch_iter_kernel, dim3(ntask), dim3(rka::kBT), (unsigned)lds, s,
-                         dtask, k0, K, tol > 0.0 ? check_every : 0, tol * tol);
+                         dtask, c, tol > 0.0 ? check_every : 0, tol * tol);
       hipLaunchKernelGGL(rka::batch_alive_kernel, dim3((count + 255) / 256), dim3(256), 0, s,
                          done, tsys, ntask, alive, count);
     }
@@ -601,6 +667,7 @@ extern "C" int rka_batch_solve(const rka_batch_system* systems, int32_t count, i
       results[i].block_size = bs[i];
       results[i].tpr = tpr[i];
       results[i].rhs_per_task = R[i];
+      results[i].alpha = systems[i].alpha > 0.0 ? systems[i].alpha : 1.0;
     }
   }
   for (int t = 0; t < ntask; ++t) {
@@ -626,10 +693,136 @@ extern "C" int rka_batch_solve(const rka_batch_system* systems, int32_t count, i
       if (hipEventElapsedTime(&ms, ev[1], ev[2]) == hipSuccess) stats->iterate_ms = ms;
     }
     stats->tasks = ntask;
-    stats->chunks = (int32_t)((max_iter + Kc - 1) / Kc);
+    stats->chunks = (int32_t)nchunks;
     stats->lds_bytes = (int32_t)lds;
     stats->graph = use_graph ? 1 : 0;
   }
+  return status;
+}
+
+extern "C" int rka_batch_solve(const rka_batch_system* systems, int32_t count, int dtype,
+                               uint64_t seed, double tol, int64_t check_every, int64_t chunk_iters,
+                               int32_t use_graph, void* stream, rka_batch_result* results,
+                               rka_batch_stats* stats) {
+  return batch_core(systems, count, dtype, seed, tol, check_every, chunk_iters, use_graph, stream,
+                    results, stats, nullptr);
+}
+
+// Refinement of a batch: every sweep solves, for all systems at once and in
+// binary32, for the corrections d with A d = b - A x (FP64 residuals), then
+// x += d in FP64 -- the batch form of rka_refine_solve.  Sweep s draws its
+// rows with keys seed + s * 65536 + i.
+extern "C" int rka_batch_refine_solve(const rka_batch_system* systems, int32_t count, int dtype,
+                                      uint64_t seed, double tol, int64_t check_every,
+                                      int32_t sweeps, int32_t use_graph, void* stream,
+                                      rka_batch_result* results, rka_batch_stats* stats) {
+  if (stats) memset(stats, 0, sizeof *stats);
+  if (!systems || count < 1 || count > 65535)
+    return rka::api_fail(RKA_EINVAL, "need 1 to 65535 systems");
+  if (sweeps < 1) return rka::api_fail(RKA_EINVAL, "sweeps must be >= 1");
+  if (dtype != RKA_F32 && dtype != RKA_BF16)
+    return rka::api_fail(RKA_EINVAL, "batched solves take RKA_F32 or RKA_BF16 storage");
+  if (!(tol >= 0.0) || !isfinite(tol)) return rka::api_fail(RKA_EINVAL, "tol must be finite and >= 0");
+  for (int i = 0; i < count; ++i) {
+    int v = validate_sys(systems[i], i, dtype);
+    if (v != RKA_OK) return v;
+  }
+  if (rka::api_num_cus() <= 0) return rka::api_fail(RKA_EDEVICE, "no HIP device available");
+  hipStream_t s = (hipStream_t)stream;
+  const int es = dtype == RKA_F32 ? 4 : 2;
+  // scratch: per system and right-hand side a residual (m), a correction (n)
+  // and, with a reference, its target x_ref - x (n)
+  int64_t nr = 0, rtot = 0, ntot = 0;
+  for (int i = 0; i < count; ++i) {
+    nr += systems[i].nrhs;
+    rtot += systems[i].nrhs * systems[i].m;
+    ntot += systems[i].nrhs * systems[i].n;
+  }
+  bool have_ref = true;
+  for (int i = 0; i < count; ++i) have_ref = have_ref && systems[i].x_ref;
+  DevBuf buf(s);
+  double *rbuf, *dbuf, *drbuf = nullptr, *part, *n2;
+  BHIP(buf.get(&rbuf, (size_t)rtot));
+  BHIP(buf.get(&dbuf, (size_t)ntot));
+  BHIP(buf.get(&part, (size_t)rka::sumsq_part_len()));
+  BHIP(buf.get(&n2, (size_t)nr));
+  if (have_ref) BHIP(buf.get(&drbuf, (size_t)ntot));
+  std::vector<double> ref2(nr, 0.0);
+  if (have_ref) {
+    int64_t k = 0;
+    for (int i = 0; i < count; ++i)
+      for (int r = 0; r < systems[i].nrhs; ++r, ++k)
+        BHIP(rka::launch_sumsq(systems[i].x_ref + r * systems[i].ldxr, nullptr, systems[i].n,
+                               part, n2 + k, s));
+    BHIP(hipMemcpyAsync(ref2.data(), n2, nr * sizeof(double), hipMemcpyDeviceToHost, s));
+    BHIP(hipStreamSynchronize(s));
+  }
+  std::vector<rka_batch_system> sub(systems, systems + count);
+  std::vector<rka_batch_result> res(count), acc(count);
+  for (int i = 0; i < count; ++i) {
+    acc[i] = rka_batch_result{};
+    acc[i].status = RKA_OK;
+  }
+  int status = RKA_OK;
+  for (int sw = 0; sw < sweeps; ++sw) {
+    int64_t ro = 0, no = 0;
+    for (int i = 0; i < count; ++i) {
+      const rka_batch_system& S = systems[i];
+      const bool vec = ((uintptr_t)S.A % 16 == 0) && ((S.lda * es) % 16 == 0) &&
+                       (S.n % (16 / es) == 0);
+      for (int r = 0; r < S.nrhs; ++r) {
+        BHIP(rka::launch_gemv(S.A, dtype, S.m, S.n, S.lda, vec, S.x + r * S.ldx, S.b + r * S.ldb,
+                              -1.0, rbuf + ro + r * S.m, s));
+        if (have_ref)
+          BHIP(rka::launch_sub(drbuf + no + r * S.n, S.x_ref + r * S.ldxr, S.x + r * S.ldx, S.n,
+                               s));
+      }
+      BHIP(hipMemsetAsync(dbuf + no, 0, (size_t)S.nrhs * S.n * sizeof(double), s));
+      sub[i].b = rbuf + ro;
+      sub[i].ldb = S.m;
+      sub[i].x = dbuf + no;
+      sub[i].ldx = S.n;
+      sub[i].x_ref = have_ref ? drbuf + no : nullptr;
+      sub[i].ldxr = S.n;
+      ro += S.nrhs * S.m;
+      no += S.nrhs * S.n;
+    }
+    rka_batch_stats st;
+    const int rc = batch_core(sub.data(), count, dtype, seed + (uint64_t)sw * 65536u, tol,
+                              check_every, 0, use_graph, stream, res.data(), &st,
+                              have_ref ? ref2.data() : nullptr);
+    if (rc < 0 && rc != RKA_EDIVERGED) return rc;
+    no = 0;
+    bool all_ok = true;
+    for (int i = 0; i < count; ++i) {
+      const rka_batch_system& S = systems[i];
+      for (int r = 0; r < S.nrhs; ++r)
+        BHIP(rka::launch_axpy(S.x + r * S.ldx, dbuf + no + r * S.n, S.n, s));
+      no += S.nrhs * S.n;
+      acc[i].iterations += res[i].iterations;
+      acc[i].rel = res[i].rel;
+      acc[i].status = res[i].status;
+      acc[i].q = res[i].q;
+      acc[i].block_size = res[i].block_size;
+      acc[i].tpr = res[i].tpr;
+      acc[i].rhs_per_task = res[i].rhs_per_task;
+      acc[i].alpha = res[i].alpha;
+      all_ok = all_ok && res[i].status == RKA_OK;
+    }
+    if (stats) {
+      stats->tasks = st.tasks;
+      stats->chunks += st.chunks;
+      stats->lds_bytes = st.lds_bytes;
+      stats->graph = st.graph;
+      stats->setup_ms += st.setup_ms;
+      stats->iterate_ms += st.iterate_ms;
+    }
+    status = rc;
+    if (tol > 0.0 && all_ok) break;
+  }
+  BHIP(hipStreamSynchronize(s));
+  if (results)
+    for (int i = 0; i < count; ++i) results[i] = acc[i];
   return status;
 }
 
@@ -647,16 +840,20 @@ extern "C" int rka_batch_solve(const rka_batch_system* systems, int32_t count, i
 // tuner starts from the fastest candidate of every class and, while the
 // bandwidth term dominates, moves one class at a time to the candidate that
 // lowers the modelled time most.  Candidates: tpr in {t0, 2 t0} (t0 the
-// smallest that covers a row), q in {1, W/4, W} with W = 256 / tpr the
-// workers a workgroup runs at once, block_size in {n/8, n/2} clipped to
-// [1, 256].  Only parameters the caller left at 0 are written; x is not
-// touched.  The progress measure is the residual, so the tuner is meant for
+// smallest that covers a row) with W = 256 / tpr the workers a workgroup
+// runs at once; RKAB with alpha = 1, q in {1, W/4, W} and block_size in
+// {n/8, n/2} clipped to [1, 256]; RKA (block size 1) with q = W and alpha in
+// {W/4, W/2} -- a weight above 1 is what makes averaging pay (Eq. (6)), and
+// these stay well inside the range where it contracts when sigma_max^2 /
+// ||A||_F^2 is small next to 1/q.  Only parameters the caller left at 0 are
+// written; x is not touched.  The progress measure is the residual, so the tuner is meant for
 // consistent systems (inconsistent ones stall at the least-squares residual,
 // Sec. 2.3.1).
 // ---------------------------------------------------------------------------
 namespace {
 struct Cand {
   int tpr, q, bs;
+  double alpha;
   double rt, rp;  // e-folds per ms, per projection
 };
 }  // namespace
@@ -718,46 +915,60 @@ extern "C" int rka_batch_tune(rka_batch_system* systems, int32_t count, int dtyp
     BHIP(hipStreamSynchronize(s));
     if (!(b2 > 0.0)) continue;
     const int t0 = min_tpr(n);
+    // (tpr, q, block_size, alpha) candidates: RKAB with alpha = 1, and RKA
+    // (block size 1) with alpha = q/4 and q/2 (inside the range where Eq. (6)'s
+    // weight contracts for these spectra, sigma_max^2 / ||A||_F^2 << 1 / q)
+    std::vector<Cand> trial;
     for (int tpr = t0; tpr <= 256 && tpr <= 2 * t0; tpr *= 2) {
       const int W = rka::kBT / tpr;
       const int qs[3] = {1, W / 4 > 1 ? W / 4 : 1, W};
       for (int qi = 0; qi < 3; ++qi) {
         if (qi > 0 && qs[qi] == qs[qi - 1]) continue;
-        const int q = qs[qi];
         const int64_t bss[2] = {std::min<int64_t>(256, std::max<int64_t>(1, n / 8)),
                                 std::min<int64_t>(256, std::max<int64_t>(1, n / 2))};
         for (int bi = 0; bi < 2; ++bi) {
           if (bi > 0 && bss[bi] == bss[0]) continue;
-          const int bs = (int)bss[bi];
-          const int64_t K = std::max<int64_t>(1, Rp.m / 2 / ((int64_t)q * bs));
-          rka_batch_system T = Rp;
-          T.nrhs = 1;
-          T.x = x;
-          T.ldx = n;
-          T.x_ref = nullptr;
-          T.q = q;
-          T.block_size = bs;
-          T.tpr = tpr;
-          T.rhs_per_task = 1;
-          T.max_iter = K;
-          BHIP(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), s));
-          rka_batch_stats st;
-          int rc = rka_batch_solve(&T, 1, dtype, seed, 0.0, 1, 0, 0, stream, nullptr, &st);
-          if (rc < 0) return rc;
-          BHIP(rka::launch_gemv(Rp.A, dtype, Rp.m, n, Rp.lda, false, x, Rp.b, -1.0, r, s));
-          BHIP(rka::launch_sumsq(r, nullptr, Rp.m, part, acc, s));
-          double r2 = 0.0;
-          BHIP(hipMemcpyAsync(&r2, acc, sizeof r2, hipMemcpyDeviceToHost, s));
-          BHIP(hipStreamSynchronize(s));
-          ++ntrials;
-          double rho = sqrt(r2 / b2);
-          if (!(rho > 1e-30)) rho = 1e-30;
-          if (!isfinite(rho) || rho >= 1.0) continue;
-          const double ms = st.iterate_ms > 1e-3 ? st.iterate_ms : 1e-3;
-          const double ef = -log(rho);
-          C.cands.push_back({tpr, q, bs, ef / ms, ef / (double)(K * q * bs)});
+          trial.push_back({tpr, qs[qi], (int)bss[bi], 1.0, 0.0, 0.0});
         }
       }
+      if (W >= 4) {
+        trial.push_back({tpr, W, 1, W / 4.0, 0.0, 0.0});
+        trial.push_back({tpr, W, 1, W / 2.0, 0.0, 0.0});
+      }
+    }
+    for (const Cand& cd : trial) {
+      const int q = cd.q, bs = cd.bs, tpr = cd.tpr;
+      const int64_t K = std::max<int64_t>(1, Rp.m / 2 / ((int64_t)q * bs));
+      rka_batch_system T = Rp;
+      T.nrhs = 1;
+      T.x = x;
+      T.ldx = n;
+      T.x_ref = nullptr;
+      T.q = q;
+      T.block_size = bs;
+      T.tpr = tpr;
+      T.alpha = cd.alpha;
+      T.rhs_per_task = 1;
+      T.max_iter = K;
+      BHIP(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), s));
+      rka_batch_stats st;
+      int rc = rka_batch_solve(&T, 1, dtype, seed, 0.0, 1, 0, 0, stream, nullptr, &st);
+      if (rc < 0) return rc;
+      BHIP(rka::launch_gemv(Rp.A, dtype, Rp.m, n, Rp.lda, false, x, Rp.b, -1.0, r, s));
+      BHIP(rka::launch_sumsq(r, nullptr, Rp.m, part, acc, s));
+      double r2 = 0.0;
+      BHIP(hipMemcpyAsync(&r2, acc, sizeof r2, hipMemcpyDeviceToHost, s));
+      BHIP(hipStreamSynchronize(s));
+      ++ntrials;
+      double rho = sqrt(r2 / b2);
+      if (!(rho > 1e-30)) rho = 1e-30;
+      if (!isfinite(rho) || rho >= 1.0) continue;
+      const double ms = st.iterate_ms > 1e-3 ? st.iterate_ms : 1e-3;
+      const double ef = -log(rho);
+      Cand c = cd;
+      c.rt = ef / ms;
+      c.rp = ef / (double)(K * q * bs);
+      C.cands.push_back(c);
     }
     if (C.cands.empty()) continue;
     int best = 0;
@@ -808,6 +1019,7 @@ extern "C" int rka_batch_tune(rka_batch_system* systems, int32_t count, int dtyp
       if (systems[i].tpr == 0) systems[i].tpr = k.tpr;
       if (systems[i].q == 0) systems[i].q = k.q;
       if (systems[i].block_size == 0) systems[i].block_size = k.bs;
+      if (systems[i].alpha == 0.0) systems[i].alpha = k.alpha;
       if ((int64_t)systems[i].tpr * rka::kEptMax < systems[i].n) systems[i].tpr = min_tpr(systems[i].n);
     }
   }

@@ -143,6 +143,8 @@ def test_autotuner_fills_parameters_and_tuned_batch_converges():
         systems.append(rka.BatchSystem(A=to_dev(A, "f32"), B=vec(b), X=X, X_ref=vec(xs),
                                        max_iter=50000))
     systems[1].block_size = 3  # a caller's choice is kept
+    for S in systems[2:]:
+        S.alpha = 0.0  # chosen by the tuner
     trials = rka.batch_tune(systems, seed=2)
     assert trials > 0
     for S in systems:
@@ -151,7 +153,8 @@ def test_autotuner_fills_parameters_and_tuned_batch_converges():
         assert S.tpr in (16, 32, 64, 128, 256) and S.tpr * 16 >= n
         W = 256 // S.tpr
         assert S.q in (1, max(1, W // 4), W) and 1 <= S.block_size <= 256
-    assert systems[1].block_size == 3
+        assert S.alpha > 0 and (S.alpha == 1.0 or (S.block_size == 1 and S.q == W))
+    assert systems[1].block_size == 3 and systems[0].alpha == 1.0
     # same size class, same choice
     assert (systems[2].tpr, systems[2].q) == (systems[3].tpr, systems[3].q)
     for S in systems:
@@ -183,3 +186,27 @@ def test_each_task_keeps_its_own_stop_flag(graph):
     assert res[0]["status"] == rka.OK and res[0]["iterations"] <= 20
     for r in res[1:]:
         assert r["iterations"] > 50  # ran far past the chunk where the first task stopped
+
+
+def test_batch_refinement_goes_below_the_fp32_floor():
+    # one binary32 batch solve stalls near its rounding floor; FP64 refinement
+    # sweeps (batch solves for the corrections) reach 1e-10 on every system
+    shapes = [(1500, 120), (2500, 300), (3000, 64)]
+    hs, mk = [], []
+    for s, (m, n) in enumerate(shapes):
+        A, xs, b = workloads.scaled_rows_system(m, n, seed=500 + s, dtype="f32")
+        hs.append((np.array(A), xs, b))
+
+    def systems():
+        return [rka.BatchSystem(A=to_dev(A, "f32"), B=vec(b),
+                                X=torch.zeros(A.shape[1], dtype=torch.float64, device=DEV),
+                                X_ref=vec(xs), q=8, block_size=1, tpr=32, alpha=4.0,
+                                max_iter=400000) for A, xs, b in hs]
+    plain = systems()
+    res, _ = rka.batch_solve(plain, seed=2, tol=1e-10, check_every=50, raise_on_error=False)
+    assert any(r["status"] != rka.OK for r in res)  # the binary32 floor
+    ref = systems()
+    res, st = rka.batch_solve(ref, seed=2, tol=1e-10, check_every=50, refine_sweeps=4)
+    for (A, xs, b), S, r in zip(hs, ref, res):
+        assert r["status"] == rka.OK
+        assert np.linalg.norm(host(S.X) - xs) <= 1e-10 * np.linalg.norm(xs)
