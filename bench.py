@@ -62,38 +62,6 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def lanczos_extremes(G, steps=160):
-    """Extreme eigenvalues of the SPD matrix G (torch, FP64) by Lanczos with
-    full reorthogonalization; used only to set alpha* (Eq. (6))."""
-    import numpy as np
-    import torch
-    n = G.shape[0]
-    gen = torch.Generator(device=G.device)
-    gen.manual_seed(7)
-    v = torch.randn(n, generator=gen, device=G.device, dtype=torch.float64)
-    v /= v.norm()
-    V = torch.zeros((steps, n), device=G.device, dtype=torch.float64)
-    al, be = [], []
-    b_prev = 0.0
-    v_prev = torch.zeros_like(v)
-    for j in range(steps):
-        V[j] = v
-        w = G @ v - b_prev * v_prev
-        a = float(w @ v)
-        w -= a * v
-        w -= V[: j + 1].T @ (V[: j + 1] @ w)
-        b = float(w.norm())
-        al.append(a)
-        be.append(b)
-        if b < 1e-12:
-            break
-        v_prev, v, b_prev = v, w / b, b
-    k = len(al)
-    T = np.diag(al) + np.diag(be[: k - 1], 1) + np.diag(be[: k - 1], -1)
-    ev = np.linalg.eigvalsh(T)
-    return float(ev[0]), float(ev[-1])
-
-
 def make_cells(spec, astar):
     cells = []
     for q in (16, 64, 256):
@@ -524,15 +492,16 @@ def main():
     torch.cuda.synchronize()
 
     # least-squares reference (normal equations, well conditioned here, plus one
-    # refinement step) and alpha*(q) from the extreme singular values
+    # refinement step -- a measurement aid) and alpha*(q) from the extreme
+    # singular values
     log("[bench] least-squares reference and alpha*")
     G = A.T @ A
     L = torch.linalg.cholesky(G)
     x_ls = torch.cholesky_solve((A.T @ b)[:, None], L)[:, 0]
     r = b - A @ x_ls
     x_ls = x_ls + torch.cholesky_solve((A.T @ r)[:, None], L)[:, 0]
-    F = float((A * A).sum())
-    lmin, lmax = lanczos_extremes(G)
+    # alpha* (Eq. (6)) from the extreme eigenvalues of A^T A, on the device
+    (lmin, lmax, F), astar_ms = _timed(lambda: rka.spectral_bounds(A, steps=160, seed=7))
     s_min, s_max = lmin / F, lmax / F
     astar = {q: rka.alpha_star(s_min, s_max, q) for q in (16, 64, 256)}
     del G, L, r
@@ -655,6 +624,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "alpha_star": {str(q): astar[q] for q in astar}, "s_min": s_min, "s_max": s_max,
+        "alpha_star_device_ms": astar_ms,
         "cells": cells_out,
         "forms": forms,
     }

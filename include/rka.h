@@ -207,6 +207,31 @@ int rka_gemv(const void* M, int dtype, int64_t rows, int64_t cols, int64_t ld, c
              const double* c, double gamma, double* out, void* stream);
 
 /*
+ * rka_gemv_t -- out_c = (c ? c_c : 0) + gamma * sum_i M[i,c] t_i for c < cols
+ * (A^T t without a transposed copy), FP64: blocks of 512 rows form partial
+ * column sums, added in block order (bitwise reproducible).  t: rows doubles;
+ * c (nullable) and out: cols doubles (out may alias c).  rows must be below
+ * 65535 * 512.  Allocates and frees its partial sums on the stream.
+ */
+int rka_gemv_t(const void* M, int dtype, int64_t rows, int64_t cols, int64_t ld, const double* t,
+               const double* c, double gamma, double* out, void* stream);
+
+/*
+ * rka_spectral_bounds -- the extreme eigenvalues of A^T A (sigma_min^2 and
+ * sigma_max^2 of A), which alpha* of Eq. (6) needs as s = sigma^2 /
+ * ||A||_F^2.  Lanczos on A^T A with full reorthogonalisation from a Philox
+ * start vector (key seed, stream dom 2), min(steps, n) steps, two streaming
+ * passes over A per step; the extreme Ritz values by Sturm bisection.  Ritz
+ * values lie inside the spectrum: *lam_min >= sigma_min^2 and
+ * *lam_max <= sigma_max^2, both converging with steps (exact at steps = n in
+ * exact arithmetic).  *fro2 (nullable) = ||A||_F^2 from the squared row norms.
+ * Host outputs; waits for the stream.  m must be below 65535 * 512.
+ */
+int rka_spectral_bounds(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, int32_t steps,
+                        uint64_t seed, void* stream, double* lam_min, double* lam_max,
+                        double* fro2);
+
+/*
  * rka_transpose -- At[j, i] = A[i, j] (element bits copied), so that the
  * columns of A become contiguous rows for the column solves.  At: n rows of
  * m elements, leading dimension ldat >= m, same dtype; must not overlap A.

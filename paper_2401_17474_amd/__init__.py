@@ -130,6 +130,10 @@ def lib():
                                              ctypes.POINTER(_BatchStats)]
         L.rka_batch_tune.argtypes = [ctypes.POINTER(_BatchSystem), I32, ctypes.c_int, U64, P,
                                      ctypes.POINTER(I32)]
+        L.rka_gemv_t.argtypes = [P, ctypes.c_int, I64, I64, I64, P, P, D, P, P]
+        L.rka_spectral_bounds.argtypes = [P, ctypes.c_int, I64, I64, I64, I32, U64, P,
+                                          ctypes.POINTER(D), ctypes.POINTER(D),
+                                          ctypes.POINTER(D)]
         L.rka_status_string.argtypes = [ctypes.c_int]
         L.rka_status_string.restype = ctypes.c_char_p
         L.rka_last_error.argtypes = []
@@ -138,7 +142,7 @@ def lib():
         for f in ("rka_solve", "rkab_solve", "rka_solve_ex", "rka_row_norms", "rka_prefix",
                   "rka_sample_indices", "rka_gemv", "rka_transpose", "rka_lsq_grad_A",
                   "rka_refine_solve", "rka_batch_solve", "rka_batch_tune",
-                  "rka_batch_refine_solve"):
+                  "rka_batch_refine_solve", "rka_gemv_t", "rka_spectral_bounds"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -312,6 +316,29 @@ def gemv(M, v, *, c=None, gamma=1.0, out=None, stream=None):
     _raise_if(lib().rka_gemv(_ptr(M), code, rows, cols, ld, _ptr(v), _ptr(c), gamma, _ptr(y),
                              _stream(stream)))
     return y
+
+
+def gemv_t(M, t, *, c=None, gamma=1.0, out=None, stream=None):
+    """out = (c or 0) + gamma * M^T t in FP64 (rka_gemv_t), without a transposed copy."""
+    torch = _torch()
+    code, rows, cols, ld = _matrix(M)
+    _vec(t, rows, "t", False)
+    _vec(c, cols, "c")
+    y = out if out is not None else torch.empty(cols, dtype=torch.float64, device=M.device)
+    _vec(y, cols, "out", False)
+    _raise_if(lib().rka_gemv_t(_ptr(M), code, rows, cols, ld, _ptr(t), _ptr(c), gamma, _ptr(y),
+                               _stream(stream)))
+    return y
+
+
+def spectral_bounds(A, *, steps=120, seed=1, stream=None):
+    """(lam_min, lam_max, ||A||_F^2): extreme Ritz values of A^T A by Lanczos on
+    the device (rka_spectral_bounds); s = lam / ||A||_F^2 feeds alpha_star."""
+    code, m, n, lda = _matrix(A)
+    lo, hi, f = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _raise_if(lib().rka_spectral_bounds(_ptr(A), code, m, n, lda, steps, seed, _stream(stream),
+                                        ctypes.byref(lo), ctypes.byref(hi), ctypes.byref(f)))
+    return lo.value, hi.value, f.value
 
 
 def transpose(A, stream=None):

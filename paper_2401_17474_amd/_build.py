@@ -26,6 +26,7 @@ SOURCES = {
     "rka_rkab.hip": [],
     "rka_dense.hip": [],
     "rka_batch.hip": [],
+    "rka_spectral.hip": [],
     "rka_api.hip": [],
 }
 

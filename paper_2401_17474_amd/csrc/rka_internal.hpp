@@ -98,6 +98,12 @@ hipError_t launch_transpose(const void* A, int dtype, int64_t m, int64_t n, int6
                             int64_t ldat, hipStream_t s);
 hipError_t launch_axpy(double* x, const double* d, int64_t n, hipStream_t s);
 hipError_t launch_sub(double* out, const double* a, const double* b, int64_t n, hipStream_t s);
+// out_c = (cin ? cin_c : 0) + gamma * sum_i M[i, c] t_i (FP64, fixed order); part holds
+// gemvt_part_len(rows, cols) doubles (rka_spectral.hip)
+int64_t gemvt_part_len(int64_t rows, int64_t cols);
+hipError_t launch_gemvt(const void* M, int dtype, int64_t rows, int64_t cols, int64_t ld,
+                        const double* t, const double* cin, double gamma, double* out,
+                        double* part, hipStream_t s);
 // out[0] = sum (a - b)^2 (b may be NULL); part holds sumsq_part_len() doubles
 int sumsq_part_len();
 hipError_t launch_sumsq(const double* a, const double* b, int64_t len, double* part, double* out,
