@@ -133,7 +133,13 @@ typedef struct rka_opts {
                                stopping measures stay FP64 either way.               */
     int32_t stream_id;      /* counter domain `dom` of the row stream, 0..255 (default
                                0; the column solves of the refinement use 1)          */
-    int32_t reserved;
+    int32_t sampling;       /* 0 = every worker samples all rows (default); 1 = the
+                               Distributed Approach of Sec. 3.3.2: worker w samples
+                               only rows floor(w m / q) .. floor((w+1) m / q) - 1, by
+                               their norms within that block (q <= m)                 */
+    const double* worker_alpha; /* NULL (every worker uses alpha) or q doubles on the
+                               device: worker w's weight (the partial-matrix alpha of
+                               Sec. 3.3.2, rka_partial_alpha)                         */
 } rka_opts;
 
 /* Launch facts and phase times of one rka_solve_ex call. */
@@ -217,19 +223,32 @@ int rka_gemv_t(const void* M, int dtype, int64_t rows, int64_t cols, int64_t ld,
                const double* c, double gamma, double* out, void* stream);
 
 /*
- * rka_spectral_bounds -- the extreme eigenvalues of A^T A (sigma_min^2 and
- * sigma_max^2 of A), which alpha* of Eq. (6) needs as s = sigma^2 /
- * ||A||_F^2.  Lanczos on A^T A with full reorthogonalisation from a Philox
- * start vector (key seed, stream dom 2), min(steps, n) steps, two streaming
+ * rka_spectral_bounds -- the extreme squared singular values sigma_min^2 and
+ * sigma_max^2 of A (over its min(m, n) singular values), which alpha* of
+ * Eq. (6) needs as s = sigma^2 / ||A||_F^2.  Lanczos with full
+ * reorthogonalisation on the smaller of A^T A and A A^T, from a Philox start
+ * vector (key seed, stream dom 2), min(steps, min(m, n)) steps, two streaming
  * passes over A per step; the extreme Ritz values by Sturm bisection.  Ritz
  * values lie inside the spectrum: *lam_min >= sigma_min^2 and
- * *lam_max <= sigma_max^2, both converging with steps (exact at steps = n in
- * exact arithmetic).  *fro2 (nullable) = ||A||_F^2 from the squared row norms.
- * Host outputs; waits for the stream.  m must be below 65535 * 512.
+ * *lam_max <= sigma_max^2, both converging with steps (exact at steps =
+ * min(m, n) in exact arithmetic).  *fro2 (nullable) = ||A||_F^2 from the
+ * squared row norms.  Host outputs; waits for the stream.  m must be below
+ * 65535 * 512.
  */
 int rka_spectral_bounds(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, int32_t steps,
                         uint64_t seed, void* stream, double* lam_min, double* lam_max,
                         double* fro2);
+
+/*
+ * rka_partial_alpha -- the partial-matrix weights of Sec. 3.3.2: for every
+ * worker w, Eq. (6) evaluated with q and the extreme squared singular values
+ * of its own row block A[floor(w m / q) .. floor((w+1) m / q) - 1, :] over
+ * that block's squared Frobenius norm (rka_spectral_bounds on the block, key
+ * seed + w).  alpha_out: q doubles on the host.  Use them with
+ * rka_opts.worker_alpha (copied to the device).  Waits for the stream.
+ */
+int rka_partial_alpha(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, int32_t q,
+                      int32_t steps, uint64_t seed, void* stream, double* alpha_out);
 
 /*
  * rka_transpose -- At[j, i] = A[i, j] (element bits copied), so that the
@@ -415,6 +434,19 @@ int rka_batch_refine_solve(const rka_batch_system* systems, int32_t count, int d
  */
 int rka_batch_tune(rka_batch_system* systems, int32_t count, int dtype, uint64_t seed,
                    void* stream, int32_t* trials);
+
+/*
+ * rka_sample_blocks -- the row stream of the Distributed Approach (Sec. 3.3.2):
+ * draw (k, w, j) with counter (k + iter_offset, w, j, dom) picks, within
+ * worker w's block of rows floor(w m / q) .. floor((w+1) m / q) - 1, the
+ * smallest row whose running sum restarted at the block exceeds u times the
+ * block's total (falling back to the block's last row of positive weight).
+ * w: the m squared row norms (rka_row_norms); idx: K*q*bs int32, layout as
+ * rka_sample_indices.  Waits for the stream; RKA_EZERONORM if a block has
+ * zero weight.
+ */
+int rka_sample_blocks(const double* w, int64_t m, uint64_t seed, int64_t iter_offset, int64_t K,
+                      int32_t q, int32_t bs, int32_t dom, int32_t* idx, void* stream);
 
 /* Name of a status code (static string). */
 const char* rka_status_string(int status);

@@ -74,6 +74,11 @@ def lib():
         L.oracle_gemv.argtypes = [P, ctypes.c_int, I64, I64, I64, P, P, D, P]
         L.oracle_refine.argtypes = [P, ctypes.c_int, I64, I64, I64, P, P, P, I32, I32, I32, I32,
                                     D, I64, I64, I32, D, I32, U64, P, P]
+        L.oracle_indices_blocks.argtypes = [P, I64, U64, I64, I64, I32, I32, I32, P]
+        L.oracle_rka_walpha_given.argtypes = [P, ctypes.c_int, I64, I64, I64, P, P, I32, P, I64,
+                                              P]
+        L.oracle_rkab_walpha_given.argtypes = [P, ctypes.c_int, I64, I64, I64, P, P, I32, I32,
+                                               P, I64, P]
         _lib = L
     return _lib
 
@@ -276,3 +281,42 @@ def refine(A, b, *, method=0, q, block_size=1, acc32=1, alpha=1.0, inner_iters,
     if st != OK:
         raise ValueError(f"oracle_refine status {st}")
     return x, meas
+
+
+# -- the Distributed Approach and per-worker weights (Sec. 3.3.2) ---------------
+
+def indices_blocks(w, seed, iter_offset, K, q, bs=1, dom=0):
+    """Row stream with worker w restricted to its own row block."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    idx = np.empty(K * q * bs, dtype=np.int32)
+    st = lib().oracle_indices_blocks(_ptr(w), w.size, seed, iter_offset, K, q, bs, dom, _ptr(idx))
+    if st != OK:
+        raise ValueError(f"oracle_indices_blocks status {st}")
+    return idx
+
+
+def rka_walpha_given(A, b, x, idx, walpha, *, q, dtype=None):
+    A, code, lda = _matrix(A, dtype)
+    m, n = A.shape
+    x = np.array(x, dtype=np.float64, copy=True)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    wa = np.ascontiguousarray(walpha, dtype=np.float64)
+    st = lib().oracle_rka_walpha_given(_ptr(A), code, m, n, lda, _ptr(_vec(b, m)), _ptr(x), q,
+                                       _ptr(wa), idx.size // q, _ptr(idx))
+    if st != OK:
+        raise ValueError(f"oracle_rka_walpha_given status {st}")
+    return x
+
+
+def rkab_walpha_given(A, b, x, idx, walpha, *, q, block_size, dtype=None):
+    A, code, lda = _matrix(A, dtype)
+    m, n = A.shape
+    x = np.array(x, dtype=np.float64, copy=True)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    wa = np.ascontiguousarray(walpha, dtype=np.float64)
+    st = lib().oracle_rkab_walpha_given(_ptr(A), code, m, n, lda, _ptr(_vec(b, m)), _ptr(x), q,
+                                        block_size, _ptr(wa), idx.size // (q * block_size),
+                                        _ptr(idx))
+    if st != OK:
+        raise ValueError(f"oracle_rkab_walpha_given status {st}")
+    return x

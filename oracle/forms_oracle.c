@@ -295,3 +295,129 @@ done:
     free(At);
     return st;
 }
+
+/* ------------------------------------------------------------------ */
+/* The Distributed Approach and partial-matrix weights (Sec. 3.3.2).    */
+/* ------------------------------------------------------------------ */
+
+/* Worker w draws only from its block of rows floor(w m / q) .. floor((w+1)
+ * m / q) - 1: the running sum restarted at the block, t = u * (block total),
+ * the smallest row of the block whose running sum exceeds t, else the
+ * block's last row of positive weight. */
+int oracle_indices_blocks(const double* w, int64_t m, uint64_t seed, int64_t iter_offset,
+                          int64_t K, int32_t q, int32_t bs, int32_t dom, int32_t* idx)
+{
+    if (!w || !idx || m < 1 || q < 1 || q > m || bs < 1 || K < 0 || iter_offset < 0 || dom < 0 ||
+        dom > 255)
+        return ORACLE_EINVAL;
+    double* c = (double*)malloc((size_t)m * sizeof(double));
+    if (!c) return ORACLE_EINVAL;
+    int st = ORACLE_OK;
+    for (int32_t wk = 0; wk < q && st == ORACLE_OK; ++wk) {
+        int64_t lo = (int64_t)wk * m / q, hi = ((int64_t)wk + 1) * m / q;
+        st = oracle_prefix(w + lo, hi - lo, c + lo);
+    }
+    for (int64_t k = 0; k < K && st == ORACLE_OK; ++k)
+        for (int32_t wk = 0; wk < q; ++wk) {
+            int64_t lo = (int64_t)wk * m / q, hi = ((int64_t)wk + 1) * m / q;
+            for (int32_t j = 0; j < bs; ++j) {
+                double u = oracle_uniform(seed, (uint64_t)(k + iter_offset), (uint32_t)wk,
+                                          (uint32_t)j, (uint32_t)dom);
+                idx[(k * q + wk) * (int64_t)bs + j] =
+                    (int32_t)(lo + oracle_pick_row(c + lo, w + lo, hi - lo, u));
+            }
+        }
+    free(c);
+    return st;
+}
+
+/* RKA, Eq. (7), with a weight per worker (the partial-matrix alpha of
+ * Sec. 3.3.2): x^(k+1) = x^(k) + (1/q) sum_w alpha_w (b_i - <A^(i), x^(k)>) /
+ * ||A^(i)||^2 A^(i)^T, every dot product against x^(k). */
+int oracle_rka_walpha_given(const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
+                            const double* b, double* x, int32_t q, const double* walpha,
+                            int64_t K, const int32_t* idx)
+{
+    if (!A || !b || !x || !walpha || !idx || m < 1 || n < 1 || lda < n || q < 1 || K < 0)
+        return ORACLE_EINVAL;
+    double* wn = (double*)malloc((size_t)m * sizeof(double));
+    double* s = (double*)malloc((size_t)q * sizeof(double));
+    double* acc = (double*)malloc((size_t)n * sizeof(double));
+    if (!wn || !s || !acc) {
+        free(wn);
+        free(s);
+        free(acc);
+        return ORACLE_EINVAL;
+    }
+    oracle_row_norms(A, dtype, m, n, lda, wn);
+    for (int64_t k = 0; k < K; ++k) {
+        const int32_t* rows = idx + k * q;
+        for (int32_t wk = 0; wk < q; ++wk) {
+            int64_t i = rows[wk];
+            double d = 0.0;
+            for (int64_t c = 0; c < n; ++c) {
+                double p = elem64(A, dtype, lda, i, c) * x[c];
+                d = d + p;
+            }
+            s[wk] = walpha[wk] * ((b[i] - d) / wn[i]);
+        }
+        for (int64_t c = 0; c < n; ++c) {
+            double a = 0.0;
+            for (int32_t wk = 0; wk < q; ++wk) {
+                double t = s[wk] * elem64(A, dtype, lda, rows[wk], c);
+                a = a + t;
+            }
+            acc[c] = a;
+        }
+        for (int64_t c = 0; c < n; ++c) x[c] = x[c] + acc[c] / (double)q;
+    }
+    free(wn);
+    free(s);
+    free(acc);
+    return ORACLE_OK;
+}
+
+/* RKAB (Sec. 3.4.1) with worker w projecting with its own weight alpha_w. */
+int oracle_rkab_walpha_given(const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
+                             const double* b, double* x, int32_t q, int32_t bs,
+                             const double* walpha, int64_t K, const int32_t* idx)
+{
+    if (!A || !b || !x || !walpha || !idx || m < 1 || n < 1 || lda < n || q < 1 || bs < 1 ||
+        K < 0)
+        return ORACLE_EINVAL;
+    double* wn = (double*)malloc((size_t)m * sizeof(double));
+    double* v = (double*)malloc((size_t)n * sizeof(double));
+    double* sum = (double*)malloc((size_t)n * sizeof(double));
+    if (!wn || !v || !sum) {
+        free(wn);
+        free(v);
+        free(sum);
+        return ORACLE_EINVAL;
+    }
+    oracle_row_norms(A, dtype, m, n, lda, wn);
+    for (int64_t k = 0; k < K; ++k) {
+        for (int64_t c = 0; c < n; ++c) sum[c] = 0.0;
+        for (int32_t wk = 0; wk < q; ++wk) {
+            for (int64_t c = 0; c < n; ++c) v[c] = x[c];
+            for (int32_t j = 0; j < bs; ++j) {
+                int64_t i = idx[(k * q + wk) * (int64_t)bs + j];
+                double d = 0.0;
+                for (int64_t c = 0; c < n; ++c) {
+                    double p = elem64(A, dtype, lda, i, c) * v[c];
+                    d = d + p;
+                }
+                double s = walpha[wk] * ((b[i] - d) / wn[i]);
+                for (int64_t c = 0; c < n; ++c) {
+                    double t = s * elem64(A, dtype, lda, i, c);
+                    v[c] = v[c] + t;
+                }
+            }
+            for (int64_t c = 0; c < n; ++c) sum[c] = sum[c] + v[c];
+        }
+        for (int64_t c = 0; c < n; ++c) x[c] = sum[c] / (double)q;
+    }
+    free(wn);
+    free(v);
+    free(sum);
+    return ORACLE_OK;
+}

@@ -128,6 +128,21 @@ int oracle_refine(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, c
                   int32_t range_q, double range_alpha, int32_t sweeps, uint64_t seed,
                   const double* x_ref, double* measures);
 
+/* The Distributed Approach of Sec. 3.3.2: worker w samples only its block of
+ * rows floor(w m / q) .. floor((w+1) m / q) - 1 (running sum restarted at the
+ * block); layout as oracle_indices. */
+int oracle_indices_blocks(const double* w, int64_t m, uint64_t seed, int64_t iter_offset,
+                          int64_t K, int32_t q, int32_t bs, int32_t dom, int32_t* idx);
+
+/* RKA / RKAB on a given stream with a weight per worker (the partial-matrix
+ * alpha of Sec. 3.3.2); walpha: q doubles. */
+int oracle_rka_walpha_given(const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
+                            const double* b, double* x, int32_t q, const double* walpha,
+                            int64_t K, const int32_t* idx);
+int oracle_rkab_walpha_given(const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
+                             const double* b, double* x, int32_t q, int32_t bs,
+                             const double* walpha, int64_t K, const int32_t* idx);
+
 #ifdef __cplusplus
 }
 #endif

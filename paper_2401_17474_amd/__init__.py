@@ -37,7 +37,7 @@ class _Opts(ctypes.Structure):
     _fields_ = [("check_every", ctypes.c_int64), ("grid", ctypes.c_int32),
                 ("collect_timing", ctypes.c_int32), ("allreduce", ctypes.c_int32),
                 ("accumulate", ctypes.c_int32), ("stream_id", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("sampling", ctypes.c_int32), ("worker_alpha", ctypes.c_void_p)]
 
 
 class _Stats(ctypes.Structure):
@@ -134,6 +134,8 @@ def lib():
         L.rka_spectral_bounds.argtypes = [P, ctypes.c_int, I64, I64, I64, I32, U64, P,
                                           ctypes.POINTER(D), ctypes.POINTER(D),
                                           ctypes.POINTER(D)]
+        L.rka_partial_alpha.argtypes = [P, ctypes.c_int, I64, I64, I64, I32, I32, U64, P, P]
+        L.rka_sample_blocks.argtypes = [P, I64, U64, I64, I64, I32, I32, I32, P, P]
         L.rka_status_string.argtypes = [ctypes.c_int]
         L.rka_status_string.restype = ctypes.c_char_p
         L.rka_last_error.argtypes = []
@@ -142,7 +144,8 @@ def lib():
         for f in ("rka_solve", "rkab_solve", "rka_solve_ex", "rka_row_norms", "rka_prefix",
                   "rka_sample_indices", "rka_gemv", "rka_transpose", "rka_lsq_grad_A",
                   "rka_refine_solve", "rka_batch_solve", "rka_batch_tune",
-                  "rka_batch_refine_solve", "rka_gemv_t", "rka_spectral_bounds"):
+                  "rka_batch_refine_solve", "rka_gemv_t", "rka_spectral_bounds",
+                  "rka_partial_alpha", "rka_sample_blocks"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -248,19 +251,24 @@ def rkab_solve(A, b, *, q, block_size, alpha=1.0, max_iter=1000, tol=0.0, seed=1
 
 def solve_ex(A, b, *, method, q, block_size=1, alpha=1.0, max_iter=1000, tol=0.0, seed=1,
              x0=None, x_ref=None, iter_offset=0, check_every=1, grid=0, allreduce=0,
-             timing=False, accumulate=0, stream_id=0, out=None, stream=None,
-             raise_on_error=True):
+             timing=False, accumulate=0, stream_id=0, sampling=0, worker_alpha=None, out=None,
+             stream=None, raise_on_error=True):
     """rka_solve_ex: method 0 = RKA, 1 = RKAB.  Returns (x, Info, stats dict);
     with ``timing`` the stats hold per-phase HIP-event times (ms) measured on
     the stream the kernels run on.  ``accumulate=1`` computes in FP32 (narrow
-    storage only); ``stream_id`` is the row stream's counter domain."""
+    storage only); ``stream_id`` is the row stream's counter domain;
+    ``sampling=1`` is the Distributed Approach (worker w samples its own row
+    block) and ``worker_alpha`` a float64 GPU vector of per-worker weights."""
     torch = _torch()
     code, m, n, lda = _matrix(A)
     b = _vec(b, m, "b", False)
     x = out if out is not None else torch.empty(n, dtype=torch.float64, device=A.device)
     _vec(x, n, "out", False)
     info, stats = _Info(), _Stats()
-    opts = _Opts(check_every, grid, 1 if timing else 0, allreduce, accumulate, stream_id, 0)
+    if worker_alpha is not None:
+        _vec(worker_alpha, q, "worker_alpha", False)
+    opts = _Opts(check_every, grid, 1 if timing else 0, allreduce, accumulate, stream_id,
+                 sampling, None if worker_alpha is None else worker_alpha.data_ptr())
     st = lib().rka_solve_ex(_ptr(A), code, m, n, lda, _ptr(b), _ptr(_vec(x0, n, "x0")), _ptr(x),
                             method, q, block_size, alpha, max_iter, tol, seed,
                             _ptr(_vec(x_ref, n, "x_ref")), iter_offset, ctypes.byref(opts),
@@ -339,6 +347,29 @@ def spectral_bounds(A, *, steps=120, seed=1, stream=None):
     _raise_if(lib().rka_spectral_bounds(_ptr(A), code, m, n, lda, steps, seed, _stream(stream),
                                         ctypes.byref(lo), ctypes.byref(hi), ctypes.byref(f)))
     return lo.value, hi.value, f.value
+
+
+def partial_alpha(A, q, *, steps=120, seed=1, stream=None):
+    """Per-worker weights of the partial-matrix variant (rka_partial_alpha):
+    a float64 GPU vector of q entries, for solve_ex(worker_alpha=...)."""
+    torch = _torch()
+    code, m, n, lda = _matrix(A)
+    out = (ctypes.c_double * q)()
+    _raise_if(lib().rka_partial_alpha(_ptr(A), code, m, n, lda, q, steps, seed, _stream(stream),
+                                      out))
+    return torch.tensor(list(out), dtype=torch.float64, device=A.device)
+
+
+def sample_blocks(w, *, seed, iter_offset=0, K, q, bs=1, dom=0, stream=None):
+    """The Distributed Approach row stream (rka_sample_blocks): int32 tensor of
+    K*q*bs indices, worker w drawing from its own row block."""
+    torch = _torch()
+    m = w.shape[0]
+    _vec(w, m, "w", False)
+    idx = torch.empty(K * q * bs, dtype=torch.int32, device=w.device)
+    _raise_if(lib().rka_sample_blocks(_ptr(w), m, seed, iter_offset, K, q, bs, dom, _ptr(idx),
+                                      _stream(stream)))
+    return idx
 
 
 def transpose(A, stream=None):

@@ -247,13 +247,14 @@ constexpr unsigned kSpinLimit = 1u << 22;
 constexpr int kStatusTimeout = -5;  // reported as RKA_EDEVICE
 
 // One sampled row as the iteration kernels consume it: the sampler writes
-// the right-hand side entry and squared norm next to the index, so that a
-// kernel gets all three with one 32-byte read.
+// the right-hand side entry, the squared norm and the relaxation weight of
+// the drawing worker next to the index, so that a kernel gets everything
+// with one 32-byte read.
 struct alignas(16) RowRec {
   double b;
   double wn;
   int64_t row;
-  int64_t pad;
+  double alpha;
 };
 
 // Wait until every memory operation this wave has issued -- in particular

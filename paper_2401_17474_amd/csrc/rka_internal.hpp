@@ -15,12 +15,18 @@ hipError_t launch_row_norms(const void* A, int dtype, int64_t m, int64_t n, int6
                             bool vec_ok, double* w, hipStream_t s);
 hipError_t launch_prefix(const double* w, int64_t m, double* c, int64_t* last_pos, DevStatus* st,
                          hipStream_t s);
+// the running sum restarted at each of nseg row blocks; last_pos: nseg entries
+hipError_t launch_prefix_blocks(const double* w, int64_t m, int32_t nseg, double* c,
+                                int64_t* last_pos, DevStatus* st, hipStream_t s);
 // Row stream of K*q*bs draws: indices into idx and/or records (index, b_i,
-// ||a_i||^2) into rec (either may be NULL; b and wn are needed for rec).
+// ||a_i||^2, worker weight) into rec (either may be NULL; b and wn are needed
+// for rec).  blocks != 0: worker w samples its own row block (c and last_pos
+// from launch_prefix_blocks with nseg = q).  walpha: per-worker weights or NULL.
 hipError_t launch_sample(const double* c, int64_t m, const int64_t* last_pos, uint64_t seed,
                          int64_t k_base, int64_t K, int32_t q, int32_t bs, int32_t dom,
-                         int32_t* idx, RowRec* rec, const double* b, const double* wn,
-                         const DevStatus* st, hipStream_t s);
+                         int32_t blocks, double alpha, const double* walpha, int32_t* idx,
+                         RowRec* rec, const double* b, const double* wn, const DevStatus* st,
+                         hipStream_t s);
 hipError_t launch_check_finite(const double* v, int64_t len, DevStatus* st, hipStream_t s);
 
 // --- iterations (rka_iter.hip) ---------------------------------------------

@@ -81,9 +81,10 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
   const int NE = nsv * V;
   const int NP = NT / NE > 1 ? NT / NE : 1;
 
-  // the scale alpha (b_i - <a_i, x>) / ||a_i||^2 in the accumulation type
-  auto scale_of = [&](double bi, double wi, double D) -> double {
-    return (double)((C)p.alpha * ((C)bi - (C)D) / (C)wi);
+  // the scale alpha_w (b_i - <a_i, x>) / ||a_i||^2 in the accumulation type
+  // (alpha_w: the weight of the drawing worker, carried by the row record)
+  auto scale_of = [&](double ai, double bi, double wi, double D) -> double {
+    return (double)((C)ai * ((C)bi - (C)D) / (C)wi);
   };
 
   C xv[V];
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
   // records needed one iteration ahead: the next rows (for the prefetch) and
   // b_i, ||a_i||^2 of row t (used where a workgroup forms every scale itself:
   // one workgroup, or the all-gather)
-  double mine_b, mine_w;
+  double mine_b, mine_w, mine_a;
   auto load_next = [&](int64_t kn, int64_t kc) {
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
@@ -115,6 +116,7 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
     }
     mine_b = p.rec[kc * q + tq].b;
     mine_w = p.rec[kc * q + tq].wn;
+    mine_a = p.rec[kc * q + tq].alpha;
   };
   load_next(p.K > 1 ? 1 : 0, 0);
 
@@ -210,7 +212,8 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
           if (r < q) {
             const double rb = r == t ? mine_b : p.rec[kl * q + r].b;
             const double rw = r == t ? mine_w : p.rec[kl * q + r].wn;
-            SC[r] = scale_of(rb, rw, D);
+            const double ra = r == t ? mine_a : p.rec[kl * q + r].alpha;
+            SC[r] = scale_of(ra, rb, rw, D);
           } else {
             SC[r] = D;
           }
@@ -248,7 +251,7 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
             v += pv;
           }
           const double D = block_sum(v, RED);
-          if (t == 0) scal.put(r, r < q ? scale_of(rr.b, rr.wn, D) : D, tag);
+          if (t == 0) scal.put(r, r < q ? scale_of(rr.alpha, rr.b, rr.wn, D) : D, tag);
         }
         // phase 2: every workgroup polls the q scales (one slot per thread
         // per round; one round unless q + 1 exceeds the thread count)
@@ -282,7 +285,8 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
       for (int r = t; r < q; r += NT) {
         const double rb = r == t ? mine_b : p.rec[kl * q + r].b;
         const double rw = r == t ? mine_w : p.rec[kl * q + r].wn;
-        SC[r] = scale_of(rb, rw, SC[r]);
+        const double ra = r == t ? mine_a : p.rec[kl * q + r].alpha;
+        SC[r] = scale_of(ra, rb, rw, SC[r]);
       }
     }
     __syncthreads();

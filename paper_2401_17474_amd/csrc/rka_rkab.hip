@@ -61,8 +61,8 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
   const int64_t nvec = p.nvec, n = nvec * V;
   __shared__ double RED[NT / kWave];
   __shared__ C REDC[NT / kWave];
-  __shared__ double Lb[2 * kStage], Lw[2 * kStage];
-  __shared__ int64_t Lr[2 * kStage];
+  __shared__ double Lb[2 * kStage], Lw[2 * kStage], La[2 * kStage];
+  __shared__ int32_t Lr[2 * kStage];
   __shared__ C AV[NT];  // partial sums of the average
   extern __shared__ double vlds_raw[];
   C* vlds = (C*)vlds_raw;
@@ -88,7 +88,8 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
       const RowRec r = wrec[j0 + u];
       Lb[base + u] = r.b;
       Lw[base + u] = r.wn;
-      Lr[base + u] = r.row;
+      La[base + u] = r.alpha;
+      Lr[base + u] = (int32_t)r.row;
     }
   };
   auto slot = [&](int j) { return ((j / kStage) & 1) * kStage + (j % kStage); };
@@ -115,7 +116,7 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
     }
     const C D = block_sum(d, REDC);
     const int sl = slot(j);
-    const C s = (C)p.alpha * ((C)Lb[sl] - D) / (C)Lw[sl];
+    const C s = (C)La[sl] * ((C)Lb[sl] - D) / (C)Lw[sl];
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
       const C si = (t + (int64_t)NT * i < nvec) ? s : (C)0;
@@ -326,7 +327,7 @@ static int vpt_limit_lds(int dtype, int V, int acc) {
   if (acc == 1) return dtype == 2 ? 4 : 8;
   return dtype == 0 ? 10 : (dtype == 1 ? 6 : 3);
 }
-constexpr size_t kMaxLds = 144 * 1024;  // 160 KiB minus the static LDS above
+constexpr size_t kMaxLds = 140 * 1024;  // 160 KiB minus the static LDS above
 
 bool rkab_plan(const SolveShape& sh, RkabGeom* geo) {
   const int esz = sh.dtype == 0 ? 8 : (sh.dtype == 1 ? 4 : 2);

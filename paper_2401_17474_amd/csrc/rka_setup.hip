@@ -72,15 +72,23 @@ __global__ __launch_bounds__(kNormRows) void row_norms_kernel(const T* __restric
 // Running sum c_l = c_{l-1} + w_l.  The rounding of each add depends on the
 // previous partial, so the chain is evaluated by one lane; the other lanes
 // stream the next block of w into LDS while it runs.  Also records the last
-// row with positive weight and validates the total.
+// row with positive weight and validates the total.  With nseg > 1 workgroup
+// g restarts the sum at row floor(g m / nseg) (the block sampled by worker g
+// in the Distributed Approach of Sec. 3.3.2) and records its block's last
+// positive row in last_pos[g].
 // ---------------------------------------------------------------------------
 constexpr int kPrefixThreads = 256;
 constexpr int kPrefixBlock = 1024;
 
-__global__ __launch_bounds__(kPrefixThreads) void prefix_kernel(const double* __restrict__ w,
-                                                                int64_t m, double* __restrict__ c,
+__global__ __launch_bounds__(kPrefixThreads) void prefix_kernel(const double* __restrict__ w_all,
+                                                                int64_t m_all, int32_t nseg,
+                                                                double* __restrict__ c_all,
                                                                 int64_t* __restrict__ last_pos,
                                                                 DevStatus* st) {
+  const int64_t lo = (int64_t)blockIdx.x * m_all / nseg;
+  const int64_t m = ((int64_t)blockIdx.x + 1) * m_all / nseg - lo;
+  const double* __restrict__ w = w_all + lo;
+  double* __restrict__ c = c_all + lo;
   __shared__ double in[2][kPrefixBlock];
   __shared__ double out[kPrefixBlock];
   __shared__ double carry_s;
@@ -128,12 +136,13 @@ __global__ __launch_bounds__(kPrefixThreads) void prefix_kernel(const double* __
     slot ^= 1;
   }
   if (t == 0) {
-    if (last_pos) *last_pos = last_s;
+    const int64_t lastg = last_s >= 0 ? lo + last_s : -1;
+    if (last_pos) last_pos[blockIdx.x] = lastg;
     if (st) {
-      st->last_pos = last_s;
+      if (nseg == 1) st->last_pos = lastg;
       const double W = carry_s;
       if (!(W > 0.0) || !isfinite(W)) {
-        st->status = -2;  // RKA_EZERONORM
+        st->status = -2;  // RKA_EZERONORM (of the matrix, or of one worker's block)
         st->done = 1;
       }
     }
@@ -145,17 +154,23 @@ __global__ __launch_bounds__(kPrefixThreads) void prefix_kernel(const double* __
 // smallest l with c_l > u * c[m-1]; none (only possible for u = 1) falls back
 // to the last row with positive weight.
 // ---------------------------------------------------------------------------
+//
+// blocks != 0: worker w draws from its own rows [floor(w m / q), floor((w+1)
+// m / q)) with the running sum restarted at the block (Distributed Approach,
+// Sec. 3.3.2).  walpha (nullable): the relaxation weight of each worker (the
+// partial-matrix alpha of Sec. 3.3.2), else alpha for all.
 __global__ __launch_bounds__(256) void sample_kernel(const double* __restrict__ c, int64_t m,
                                                      const int64_t* __restrict__ last_pos,
                                                      uint64_t seed, int64_t k_base, int64_t K,
                                                      int32_t q, int32_t bs, uint32_t dom,
+                                                     int32_t blocks, double alpha,
+                                                     const double* __restrict__ walpha,
                                                      int32_t* __restrict__ idx,
                                                      RowRec* __restrict__ rec,
                                                      const double* __restrict__ b,
                                                      const double* __restrict__ wn,
                                                      const DevStatus* st) {
   if (st && st->done) return;
-  const double W = c[m - 1];
   const int64_t total = K * (int64_t)q * bs;
   for (int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; L < total;
        L += (int64_t)gridDim.x * blockDim.x) {
@@ -163,14 +178,20 @@ __global__ __launch_bounds__(256) void sample_kernel(const double* __restrict__ 
     const int64_t wk = (L / bs) % q;
     const int64_t kl = L / ((int64_t)bs * q);
     const double u = draw_uniform(seed, (uint64_t)(k_base + kl), (uint32_t)wk, (uint32_t)j, dom);
-    const int64_t i = pick_row(c, m, W, u, *last_pos);
+    int64_t i;
+    if (blocks) {
+      const int64_t lo = wk * m / q, hi = (wk + 1) * m / q;
+      i = lo + pick_row(c + lo, hi - lo, c[hi - 1], u, last_pos[wk] - lo);
+    } else {
+      i = pick_row(c, m, c[m - 1], u, *last_pos);
+    }
     if (idx) idx[L] = (int32_t)i;
     if (rec) {
       RowRec r;
       r.b = b[i];
       r.wn = wn[i];
       r.row = i;
-      r.pad = 0;
+      r.alpha = walpha ? walpha[wk] : alpha;
       rec[L] = r;
     }
   }
@@ -216,20 +237,28 @@ hipError_t launch_row_norms(const void* A, int dtype, int64_t m, int64_t n, int6
 
 hipError_t launch_prefix(const double* w, int64_t m, double* c, int64_t* last_pos, DevStatus* st,
                          hipStream_t s) {
-  hipLaunchKernelGGL(prefix_kernel, dim3(1), dim3(kPrefixThreads), 0, s, w, m, c, last_pos, st);
+  hipLaunchKernelGGL(prefix_kernel, dim3(1), dim3(kPrefixThreads), 0, s, w, m, 1, c, last_pos, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_prefix_blocks(const double* w, int64_t m, int32_t nseg, double* c,
+                                int64_t* last_pos, DevStatus* st, hipStream_t s) {
+  hipLaunchKernelGGL(prefix_kernel, dim3((unsigned)nseg), dim3(kPrefixThreads), 0, s, w, m, nseg,
+                     c, last_pos, st);
   return hipGetLastError();
 }
 
 hipError_t launch_sample(const double* c, int64_t m, const int64_t* last_pos, uint64_t seed,
                          int64_t k_base, int64_t K, int32_t q, int32_t bs, int32_t dom,
-                         int32_t* idx, RowRec* rec, const double* b, const double* wn,
-                         const DevStatus* st, hipStream_t s) {
+                         int32_t blocks, double alpha, const double* walpha, int32_t* idx,
+                         RowRec* rec, const double* b, const double* wn, const DevStatus* st,
+                         hipStream_t s) {
   const int64_t total = K * (int64_t)q * bs;
   if (total <= 0) return hipSuccess;
-  int64_t blocks = (total + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(sample_kernel, dim3((unsigned)blocks), dim3(256), 0, s, c, m, last_pos, seed,
-                     k_base, K, q, bs, (uint32_t)dom, idx, rec, b, wn, st);
+  int64_t nb = (total + 255) / 256;
+  if (nb > 8192) nb = 8192;
+  hipLaunchKernelGGL(sample_kernel, dim3((unsigned)nb), dim3(256), 0, s, c, m, last_pos, seed,
+                     k_base, K, q, bs, (uint32_t)dom, blocks, alpha, walpha, idx, rec, b, wn, st);
   return hipGetLastError();
 }
 

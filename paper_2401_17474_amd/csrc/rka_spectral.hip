@@ -167,19 +167,15 @@ extern "C" int rka_gemv_t(const void* M, int dtype, int64_t rows, int64_t cols, 
   return RKA_OK;
 }
 
-extern "C" int rka_spectral_bounds(const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
-                                   int32_t steps, uint64_t seed, void* stream, double* lam_min,
-                                   double* lam_max, double* fro2) {
-  if (!A || !lam_min || !lam_max) return rka::api_fail(RKA_EINVAL, "A, lam_min and lam_max must be non-null");
-  if (dtype != RKA_F64 && dtype != RKA_F32 && dtype != RKA_BF16)
-    return rka::api_fail(RKA_EINVAL, "dtype %d is not an rka_dtype", dtype);
-  if (m < 1 || n < 1 || lda < n) return rka::api_fail(RKA_EINVAL, "need m, n >= 1 and lda >= n");
-  if ((m + rka::kTRows - 1) / rka::kTRows > 65535)
-    return rka::api_fail(RKA_EINVAL, "m must be < 65535 * %d", rka::kTRows);
-  if (steps < 1 || steps > 4096) return rka::api_fail(RKA_EINVAL, "steps must be in [1, 4096]");
-  if (rka::api_num_cus() <= 0) return rka::api_fail(RKA_EDEVICE, "no HIP device available");
-  hipStream_t s = (hipStream_t)stream;
-  const int k = (int)(steps < n ? steps : n);
+// Lanczos on the smaller Gram matrix: side 0 is A^T A (vectors of length
+// n), side 1 is A A^T (length m); both have the squared singular values of A
+// as their nonzero eigenvalues.
+static int spectral_core(const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
+                         int32_t steps, uint64_t seed, hipStream_t s, double* lam_min,
+                         double* lam_max, double* fro2) {
+  const int side = m < n ? 1 : 0;
+  const int64_t N = side ? m : n, O = side ? n : m;  // Lanczos length, other length
+  const int k = (int)(steps < N ? steps : N);
   const bool vec_ok = ((uintptr_t)A % 16 == 0) &&
                       ((lda * (dtype == 0 ? 8 : dtype == 1 ? 4 : 2)) % 16 == 0) &&
                       (n % (dtype == 0 ? 2 : dtype == 1 ? 4 : 8) == 0);
@@ -192,7 +188,7 @@ extern "C" int rka_spectral_bounds(const void* A, int dtype, int64_t m, int64_t 
   } bufs{s, {}};
   auto get = [&](double** out, size_t count) {
     void* q = nullptr;
-    hipError_t e = hipMallocAsync(&q, count * sizeof(double), s);
+    hipError_t e = hipMallocAsync(&q, (count > 0 ? count : 1) * sizeof(double), s);
     if (e == hipSuccess) {
       bufs.p.push_back(q);
       *out = (double*)q;
@@ -200,16 +196,15 @@ extern "C" int rka_spectral_bounds(const void* A, int dtype, int64_t m, int64_t 
     return e;
   };
   double *V, *w, *t, *h, *part, *tpart, *scal;
-  SHIP(get(&V, (size_t)(k + 1) * n));
-  SHIP(get(&w, (size_t)n));
-  SHIP(get(&t, (size_t)m));
+  SHIP(get(&V, (size_t)(k + 1) * N));
+  SHIP(get(&w, (size_t)N));
+  SHIP(get(&t, (size_t)O));
   SHIP(get(&h, (size_t)(k + 1)));
   SHIP(get(&part, (size_t)rka::sumsq_part_len()));
   SHIP(get(&tpart, (size_t)std::max<int64_t>(rka::gemvt_part_len(m, n),
-                                             rka::gemvt_part_len(k + 1, n))));
+                                             rka::gemvt_part_len(k + 1, N))));
   SHIP(get(&scal, 2));
-  // ||A||_F^2 from the squared row norms (Eq. (4) denominator)
-  if (fro2) {
+  if (fro2) {  // ||A||_F^2 from the squared row norms (Eq. (4) denominator)
     double* wn;
     SHIP(get(&wn, (size_t)m));
     SHIP(rka::launch_row_norms(A, dtype, m, n, lda, vec_ok, wn, s));
@@ -220,28 +215,29 @@ extern "C" int rka_spectral_bounds(const void* A, int dtype, int64_t m, int64_t 
     for (int64_t i = 0; i < m; ++i) f += hw[i];
     *fro2 = f;
   }
-  // v_0: a Philox start vector, normalised
-  hipLaunchKernelGGL(rka::start_vector_kernel, dim3(64), dim3(256), 0, s, w, n, seed);
+  hipLaunchKernelGGL(rka::start_vector_kernel, dim3(64), dim3(256), 0, s, w, N, seed);
   SHIP(hipGetLastError());
-  SHIP(rka::launch_sumsq(w, nullptr, n, part, scal, s));
-  hipLaunchKernelGGL(rka::scale_kernel, dim3(64), dim3(256), 0, s, V, w, n, scal);
+  SHIP(rka::launch_sumsq(w, nullptr, N, part, scal, s));
+  hipLaunchKernelGGL(rka::scale_kernel, dim3(64), dim3(256), 0, s, V, w, N, scal);
   SHIP(hipGetLastError());
   std::vector<double> al, be;
   for (int j = 0; j < k; ++j) {
-    double* vj = V + (size_t)j * n;
-    // w = A^T (A v_j)
-    SHIP(rka::launch_gemv(A, dtype, m, n, lda, vec_ok, vj, nullptr, 1.0, t, s));
-    SHIP(rka::launch_gemvt(A, dtype, m, n, lda, t, nullptr, 1.0, w, tpart, s));
+    double* vj = V + (size_t)j * N;
+    if (side == 0) {  // w = A^T (A v_j)
+      SHIP(rka::launch_gemv(A, dtype, m, n, lda, vec_ok, vj, nullptr, 1.0, t, s));
+      SHIP(rka::launch_gemvt(A, dtype, m, n, lda, t, nullptr, 1.0, w, tpart, s));
+    } else {  // w = A (A^T v_j)
+      SHIP(rka::launch_gemvt(A, dtype, m, n, lda, vj, nullptr, 1.0, t, tpart, s));
+      SHIP(rka::launch_gemv(A, dtype, m, n, lda, vec_ok, t, nullptr, 1.0, w, s));
+    }
     // full reorthogonalisation against v_0 .. v_j, twice: h = V w, w -= V^T h
     double aj = 0.0;
     for (int pass = 0; pass < 2; ++pass) {
-      SHIP(rka::launch_gemv(V, RKA_F64, j + 1, n, n, n % 2 == 0, w, nullptr, 1.0, h, s));
-      if (pass == 0) {
-        SHIP(hipMemcpyAsync(&aj, h + j, sizeof aj, hipMemcpyDeviceToHost, s));
-      }
-      SHIP(rka::launch_gemvt(V, RKA_F64, j + 1, n, n, h, w, -1.0, w, tpart, s));
+      SHIP(rka::launch_gemv(V, RKA_F64, j + 1, N, N, N % 2 == 0, w, nullptr, 1.0, h, s));
+      if (pass == 0) SHIP(hipMemcpyAsync(&aj, h + j, sizeof aj, hipMemcpyDeviceToHost, s));
+      SHIP(rka::launch_gemvt(V, RKA_F64, j + 1, N, N, h, w, -1.0, w, tpart, s));
     }
-    SHIP(rka::launch_sumsq(w, nullptr, n, part, scal, s));
+    SHIP(rka::launch_sumsq(w, nullptr, N, part, scal, s));
     double b2 = 0.0;
     SHIP(hipMemcpyAsync(&b2, scal, sizeof b2, hipMemcpyDeviceToHost, s));
     SHIP(hipStreamSynchronize(s));
@@ -249,13 +245,12 @@ extern "C" int rka_spectral_bounds(const void* A, int dtype, int64_t m, int64_t 
     const double bj = sqrt(b2);
     if (j + 1 == k || !(bj > 1e-12 * fabs(aj)) || !isfinite(bj)) break;
     be.push_back(bj);
-    hipLaunchKernelGGL(rka::scale_kernel, dim3(64), dim3(256), 0, s, V + (size_t)(j + 1) * n, w, n,
+    hipLaunchKernelGGL(rka::scale_kernel, dim3(64), dim3(256), 0, s, V + (size_t)(j + 1) * N, w, N,
                        scal);
     SHIP(hipGetLastError());
   }
   be.resize(al.size() > 0 ? al.size() - 1 : 0);
-  // Gershgorin interval, then bisection for the extremes
-  double lo = INFINITY, hi = -INFINITY;
+  double lo = INFINITY, hi = -INFINITY;  // Gershgorin interval, then bisection
   for (size_t i = 0; i < al.size(); ++i) {
     const double r = (i > 0 ? fabs(be[i - 1]) : 0.0) + (i < be.size() ? fabs(be[i]) : 0.0);
     lo = std::min(lo, al[i] - r);
@@ -264,5 +259,54 @@ extern "C" int rka_spectral_bounds(const void* A, int dtype, int64_t m, int64_t 
   *lam_min = kth_eigenvalue(al, be, 1, lo, hi);
   *lam_max = kth_eigenvalue(al, be, (int)al.size(), lo, hi);
   SHIP(hipStreamSynchronize(s));
+  return RKA_OK;
+}
+
+static int spectral_args(const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
+                         int32_t steps) {
+  if (!A) return rka::api_fail(RKA_EINVAL, "A must be non-null");
+  if (dtype != RKA_F64 && dtype != RKA_F32 && dtype != RKA_BF16)
+    return rka::api_fail(RKA_EINVAL, "dtype %d is not an rka_dtype", dtype);
+  if (m < 1 || n < 1 || lda < n) return rka::api_fail(RKA_EINVAL, "need m, n >= 1 and lda >= n");
+  if ((m + rka::kTRows - 1) / rka::kTRows > 65535)
+    return rka::api_fail(RKA_EINVAL, "m must be < 65535 * %d", rka::kTRows);
+  if (steps < 1 || steps > 4096) return rka::api_fail(RKA_EINVAL, "steps must be in [1, 4096]");
+  if (rka::api_num_cus() <= 0) return rka::api_fail(RKA_EDEVICE, "no HIP device available");
+  return RKA_OK;
+}
+
+extern "C" int rka_spectral_bounds(const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
+                                   int32_t steps, uint64_t seed, void* stream, double* lam_min,
+                                   double* lam_max, double* fro2) {
+  if (!lam_min || !lam_max) return rka::api_fail(RKA_EINVAL, "lam_min and lam_max must be non-null");
+  const int v = spectral_args(A, dtype, m, n, lda, steps);
+  if (v != RKA_OK) return v;
+  return spectral_core(A, dtype, m, n, lda, steps, seed, (hipStream_t)stream, lam_min, lam_max,
+                       fro2);
+}
+
+// Eq. (6): the uniform weight minimising the worst contraction factor
+static double alpha_star_of(double s_min, double s_max, int q) {
+  if (q == 1 || s_max - s_min <= 1.0 / (q - 1)) return q / (1.0 + (q - 1) * s_min);
+  return 2.0 * q / (1.0 + (q - 1) * (s_min + s_max));
+}
+
+extern "C" int rka_partial_alpha(const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
+                                 int32_t q, int32_t steps, uint64_t seed, void* stream,
+                                 double* alpha_out) {
+  if (!alpha_out) return rka::api_fail(RKA_EINVAL, "alpha_out must be non-null");
+  const int v = spectral_args(A, dtype, m, n, lda, steps);
+  if (v != RKA_OK) return v;
+  if (q < 1 || q > m) return rka::api_fail(RKA_EINVAL, "need 1 <= q <= m");
+  const int es = dtype == RKA_F64 ? 8 : dtype == RKA_F32 ? 4 : 2;
+  for (int w = 0; w < q; ++w) {
+    const int64_t lo = (int64_t)w * m / q, hi = ((int64_t)w + 1) * m / q;
+    double lmin = 0.0, lmax = 0.0, f = 0.0;
+    const int rc = spectral_core((const char*)A + lo * lda * es, dtype, hi - lo, n, lda, steps,
+                                 seed + (uint64_t)w, (hipStream_t)stream, &lmin, &lmax, &f);
+    if (rc != RKA_OK) return rc;
+    if (!(f > 0.0)) return rka::api_fail(RKA_EZERONORM, "worker %d's row block has zero weight", w);
+    alpha_out[w] = alpha_star_of(lmin / f, lmax / f, q);
+  }
   return RKA_OK;
 }
