@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the precision / batching / differentiation measurements")
-    ap.add_argument("--forms", default="precision,batching,differentiation")
+    ap.add_argument("--forms", default="precision,batching,differentiation,distributed_approach")
     ap.add_argument("--batch-systems", type=int, default=512)
     ap.add_argument("--batch-sample", type=int, default=16,
                     help="systems solved one by one in plain FP64 for the batching comparison")
@@ -444,6 +444,37 @@ def pmc_traffic(kernel):
     return d["traffic_bytes_per_launch"]
 
 
+def bench_distributed(rka, workloads):
+    """The four sampling / weight variants of Sec. 3.3.2 (Table 1's layout):
+    outer iterations of RKA to 1e-8 relative error on a planted 10000 x 2500
+    system (Table 1's 4:1 shape), q in {2, 4, 8, 16}; full-matrix alpha* from
+    the device Lanczos, partial-matrix alpha per worker block."""
+    import torch
+    dev = torch.device("cuda:0")
+    m, n = 10000, 2500
+    A, xs, b = workloads.gaussian_system(m, n, seed=workloads.DATA_SEED + 7, rng="torch",
+                                         device=dev)
+    lo, hi, F = rka.spectral_bounds(A, steps=120, seed=5)
+    out = {"shape": f"{m}x{n}", "tol": 1e-8, "rows": []}
+    for q in (2, 4, 8, 16):
+        a_full = rka.alpha_star(lo / F, hi / F, q)
+        wa, pa_ms = _timed(lambda: rka.partial_alpha(A, q, steps=120, seed=9))
+        row = {"q": q, "alpha_full": a_full,
+               "alpha_partial_range": [float(wa.min()), float(wa.max())],
+               "partial_alpha_ms": pa_ms}
+        for name, sampling, walpha in (("full_access_full_alpha", 0, None),
+                                       ("distributed_full_alpha", 1, None),
+                                       ("full_access_partial_alpha", 0, wa),
+                                       ("distributed_partial_alpha", 1, wa)):
+            (x, info, st), ms = _timed(lambda: rka.solve_ex(
+                A, b, method=0, q=q, alpha=a_full, max_iter=2000000, tol=1e-8, x_ref=xs,
+                check_every=10, seed=3, sampling=sampling, worker_alpha=walpha,
+                raise_on_error=False))
+            row[name] = {"iterations": info.iterations, "status": info.status, "ms": ms}
+        out["rows"].append(row)
+    return out
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -592,7 +623,8 @@ def main():
                                                                 (s_min, s_max))),
                          ("batching", lambda: bench_batching(rka, workloads, args.batch_systems,
                                                              args.batch_sample, args.seed)),
-                         ("differentiation", lambda: bench_differentiation(rka))):
+                         ("differentiation", lambda: bench_differentiation(rka)),
+                         ("distributed_approach", lambda: bench_distributed(rka, workloads))):
             if name not in wanted:
                 continue
             log(f"[bench] form: {name}")
