@@ -48,7 +48,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the precision / batching / differentiation measurements")
-    ap.add_argument("--forms", default="precision,batching,differentiation,distributed_approach")
+    ap.add_argument("--forms", default="precision,batching,differentiation,distributed_approach,"
+                    "coherent_rows")
     ap.add_argument("--batch-systems", type=int, default=512)
     ap.add_argument("--batch-sample", type=int, default=16,
                     help="systems solved one by one in plain FP64 for the batching comparison")
@@ -475,6 +476,45 @@ def bench_distributed(rka, workloads):
     return out
 
 
+def bench_coherent(rka, workloads):
+    """Row order on the coherent-row set of Sec. 3.1 (20000 x 1000, every row
+    with its own mean and spread): time and iterations to 1e-6 relative error
+    of Cyclic Kaczmarz (Sec. 2.1) with the rows as drawn and with the same
+    rows sorted so that neighbours are nearly parallel, against RK and RKA
+    sampling by row norm, with alpha = 1 and with alpha* of Eq. (6) (the
+    second case of Eq. (6) at q = 64 on this set)."""
+    import torch
+    dev = torch.device("cuda:0")
+    m, n, tol, cap = 20000, 1000, 1e-6, 1000000
+    out = {"shape": f"{m}x{n}", "tol": tol, "max_iter": cap, "runs": []}
+    for order in ("drawn", "coherent"):
+        Ah, xh, bh = workloads.paper_rows_system(m, n, seed=workloads.DATA_SEED + 11, order=order)
+        A = torch.from_numpy(Ah).to(dev)
+        b = torch.from_numpy(bh).to(dev)
+        xs = torch.from_numpy(xh).to(dev)
+        del Ah
+        lo, hi, F = rka.spectral_bounds(A, steps=150, seed=5)
+        s_min, s_max = lo / F, hi / F
+        out.setdefault("s_min", s_min)
+        out.setdefault("s_max", s_max)
+        a64 = rka.alpha_star(s_min, s_max, 64)
+        out["alpha_star_q64"] = a64
+        out["alpha_star_q64_case"] = 1 if s_max - s_min <= 1.0 / 63 else 2
+        runs = [("cyclic_kaczmarz", 1, 1.0, 2), ("rk", 1, 1.0, 0), ("rka_q64_alpha1", 64, 1.0, 0),
+                ("rka_q64_alpha_star", 64, a64, 0), ("cyclic_q64_alpha_star", 64, a64, 2)]
+        for name, q, alpha, sampling in runs:
+            (x, info, st), ms = _timed(lambda: rka.solve_ex(
+                A, b, method=0, q=q, alpha=alpha, max_iter=cap, tol=tol, x_ref=xs,
+                check_every=50, seed=3, sampling=sampling, raise_on_error=False))
+            out["runs"].append({"order": order, "name": name, "q": q, "alpha": alpha,
+                                "sampling": ["by_norm", "blocks", "cyclic"][sampling],
+                                "iterations": info.iterations, "projections": info.projections,
+                                "rel_err": info.rel_err, "status": info.status, "ms": ms})
+        del A, b, xs
+        torch.cuda.empty_cache()
+    return out
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -490,9 +530,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py runs on one GPU only (asked for {max(args.gpus, world)}): this build "
-              "has no multi-GPU path; how it would shard is described in DESIGN.md.",
-              file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {max(args.gpus, world)}): the solver "
+              "has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -624,7 +663,8 @@ def main():
                          ("batching", lambda: bench_batching(rka, workloads, args.batch_systems,
                                                              args.batch_sample, args.seed)),
                          ("differentiation", lambda: bench_differentiation(rka)),
-                         ("distributed_approach", lambda: bench_distributed(rka, workloads))):
+                         ("distributed_approach", lambda: bench_distributed(rka, workloads)),
+                         ("coherent_rows", lambda: bench_coherent(rka, workloads))):
             if name not in wanted:
                 continue
             log(f"[bench] form: {name}")

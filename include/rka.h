@@ -136,10 +136,21 @@ typedef struct rka_opts {
     int32_t sampling;       /* 0 = every worker samples all rows (default); 1 = the
                                Distributed Approach of Sec. 3.3.2: worker w samples
                                only rows floor(w m / q) .. floor((w+1) m / q) - 1, by
-                               their norms within that block (q <= m)                 */
+                               their norms within that block (q <= m); 2 = cyclic
+                               order (Sec. 2.1): draw (k, w, j) takes row
+                               ((k*q + w)*bs + j) mod m with k counted from
+                               iter_offset, so q = 1 (RKA) is Cyclic Kaczmarz.  In
+                               the cyclic order a row of zero norm is a step that
+                               leaves the iterate unchanged; seed is not used.     */
     const double* worker_alpha; /* NULL (every worker uses alpha) or q doubles on the
                                device: worker w's weight (the partial-matrix alpha of
                                Sec. 3.3.2, rka_partial_alpha)                         */
+    const double* row_weight; /* NULL or m doubles on the device: the row weights w_i
+                               of Eq. (7) (the relaxations alpha_i of Sec. 2.1), used
+                               in place of alpha for every projection onto row i.
+                               Not combined with worker_alpha (RKA_EINVAL if both).
+                               Values are not checked; the convergence results of
+                               the paper assume 0 < w_i < 2.                          */
 } rka_opts;
 
 /* Launch facts and phase times of one rka_solve_ex call. */

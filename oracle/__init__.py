@@ -79,6 +79,11 @@ def lib():
                                               P]
         L.oracle_rkab_walpha_given.argtypes = [P, ctypes.c_int, I64, I64, I64, P, P, I32, I32,
                                                P, I64, P]
+        L.oracle_rka_wrow_given.argtypes = [P, ctypes.c_int, I64, I64, I64, P, P, I32, P, I64, P]
+        L.oracle_rkab_wrow_given.argtypes = [P, ctypes.c_int, I64, I64, I64, P, P, I32, I32, P,
+                                             I64, P]
+        L.oracle_indices_cyclic.argtypes = [I64, I64, I64, I32, I32, P]
+        L.oracle_ck.argtypes = [P, ctypes.c_int, I64, I64, I64, P, P, P, I64]
         _lib = L
     return _lib
 
@@ -319,4 +324,58 @@ def rkab_walpha_given(A, b, x, idx, walpha, *, q, block_size, dtype=None):
                                         _ptr(idx))
     if st != OK:
         raise ValueError(f"oracle_rkab_walpha_given status {st}")
+    return x
+
+
+# -- row weights of Eq. (7) and the cyclic order of Sec. 2.1 ---------------------
+
+def rka_wrow_given(A, b, x, idx, wrow, *, q, dtype=None):
+    """RKA on a given stream with per-row weights w_i (Eq. (7))."""
+    A, code, lda = _matrix(A, dtype)
+    m, n = A.shape
+    x = np.array(x, dtype=np.float64, copy=True)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    wr = _vec(wrow, m)
+    st = lib().oracle_rka_wrow_given(_ptr(A), code, m, n, lda, _ptr(_vec(b, m)), _ptr(x), q,
+                                     _ptr(wr), idx.size // q, _ptr(idx))
+    if st != OK:
+        raise ValueError(f"oracle_rka_wrow_given status {st}")
+    return x
+
+
+def rkab_wrow_given(A, b, x, idx, wrow, *, q, block_size, dtype=None):
+    """RKAB on a given stream with per-row weights w_i."""
+    A, code, lda = _matrix(A, dtype)
+    m, n = A.shape
+    x = np.array(x, dtype=np.float64, copy=True)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    wr = _vec(wrow, m)
+    st = lib().oracle_rkab_wrow_given(_ptr(A), code, m, n, lda, _ptr(_vec(b, m)), _ptr(x), q,
+                                      block_size, _ptr(wr), idx.size // (q * block_size),
+                                      _ptr(idx))
+    if st != OK:
+        raise ValueError(f"oracle_rkab_wrow_given status {st}")
+    return x
+
+
+def indices_cyclic(m, iter_offset, K, q, bs=1):
+    """The cyclic row order: draw (k, w, j) takes row ((k+off)q+w)bs+j mod m."""
+    idx = np.empty(K * q * bs, dtype=np.int32)
+    st = lib().oracle_indices_cyclic(m, iter_offset, K, q, bs, _ptr(idx))
+    if st != OK:
+        raise ValueError(f"oracle_indices_cyclic status {st}")
+    return idx
+
+
+def ck(A, b, *, iters, relax=None, x0=None, dtype=None):
+    """Cyclic Kaczmarz (Sec. 2.1): iters projections onto rows 0, 1, ... in
+    turn, row i relaxed by relax[i] (default 1), from x0 (default zero)."""
+    A, code, lda = _matrix(A, dtype)
+    m, n = A.shape
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    rl = None if relax is None else _vec(relax, m)
+    st = lib().oracle_ck(_ptr(A), code, m, n, lda, _ptr(_vec(b, m)), _ptr(x),
+                         None if rl is None else _ptr(rl), iters)
+    if st != OK:
+        raise ValueError(f"oracle_ck status {st}")
     return x

@@ -331,14 +331,24 @@ int oracle_indices_blocks(const double* w, int64_t m, uint64_t seed, int64_t ite
     return st;
 }
 
-/* RKA, Eq. (7), with a weight per worker (the partial-matrix alpha of
- * Sec. 3.3.2): x^(k+1) = x^(k) + (1/q) sum_w alpha_w (b_i - <A^(i), x^(k)>) /
- * ||A^(i)||^2 A^(i)^T, every dot product against x^(k). */
-int oracle_rka_walpha_given(const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
-                            const double* b, double* x, int32_t q, const double* walpha,
-                            int64_t K, const int32_t* idx)
+/* The weight of a projection onto row i drawn by worker wk: the row's own
+ * weight w_i of Eq. (7) when row weights are given, else the worker's. */
+static double weight_of(const double* walpha, const double* wrow, int32_t wk, int64_t i)
 {
-    if (!A || !b || !x || !walpha || !idx || m < 1 || n < 1 || lda < n || q < 1 || K < 0)
+    return wrow ? wrow[i] : walpha[wk];
+}
+
+/* RKA, Eq. (7), with weights per worker (the partial-matrix alpha of
+ * Sec. 3.3.2) or per row: x^(k+1) = x^(k) + (1/q) sum_w weight (b_i -
+ * <A^(i), x^(k)>) / ||A^(i)||^2 A^(i)^T, every dot product against x^(k).
+ * A row of zero norm contributes nothing (only the cyclic order reaches
+ * one). */
+static int rka_weighted_given(const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
+                              const double* b, double* x, int32_t q, const double* walpha,
+                              const double* wrow, int64_t K, const int32_t* idx)
+{
+    if (!A || !b || !x || (!walpha && !wrow) || !idx || m < 1 || n < 1 || lda < n || q < 1 ||
+        K < 0)
         return ORACLE_EINVAL;
     double* wn = (double*)malloc((size_t)m * sizeof(double));
     double* s = (double*)malloc((size_t)q * sizeof(double));
@@ -354,12 +364,16 @@ int oracle_rka_walpha_given(const void* A, int dtype, int64_t m, int64_t n, int6
         const int32_t* rows = idx + k * q;
         for (int32_t wk = 0; wk < q; ++wk) {
             int64_t i = rows[wk];
+            if (wn[i] == 0.0) {
+                s[wk] = 0.0;
+                continue;
+            }
             double d = 0.0;
             for (int64_t c = 0; c < n; ++c) {
                 double p = elem64(A, dtype, lda, i, c) * x[c];
                 d = d + p;
             }
-            s[wk] = walpha[wk] * ((b[i] - d) / wn[i]);
+            s[wk] = weight_of(walpha, wrow, wk, i) * ((b[i] - d) / wn[i]);
         }
         for (int64_t c = 0; c < n; ++c) {
             double a = 0.0;
@@ -377,13 +391,14 @@ int oracle_rka_walpha_given(const void* A, int dtype, int64_t m, int64_t n, int6
     return ORACLE_OK;
 }
 
-/* RKAB (Sec. 3.4.1) with worker w projecting with its own weight alpha_w. */
-int oracle_rkab_walpha_given(const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
-                             const double* b, double* x, int32_t q, int32_t bs,
-                             const double* walpha, int64_t K, const int32_t* idx)
+/* RKAB (Sec. 3.4.1) with weights per worker or per row; zero rows as above. */
+static int rkab_weighted_given(const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
+                               const double* b, double* x, int32_t q, int32_t bs,
+                               const double* walpha, const double* wrow, int64_t K,
+                               const int32_t* idx)
 {
-    if (!A || !b || !x || !walpha || !idx || m < 1 || n < 1 || lda < n || q < 1 || bs < 1 ||
-        K < 0)
+    if (!A || !b || !x || (!walpha && !wrow) || !idx || m < 1 || n < 1 || lda < n || q < 1 ||
+        bs < 1 || K < 0)
         return ORACLE_EINVAL;
     double* wn = (double*)malloc((size_t)m * sizeof(double));
     double* v = (double*)malloc((size_t)n * sizeof(double));
@@ -401,12 +416,13 @@ int oracle_rkab_walpha_given(const void* A, int dtype, int64_t m, int64_t n, int
             for (int64_t c = 0; c < n; ++c) v[c] = x[c];
             for (int32_t j = 0; j < bs; ++j) {
                 int64_t i = idx[(k * q + wk) * (int64_t)bs + j];
+                if (wn[i] == 0.0) continue;
                 double d = 0.0;
                 for (int64_t c = 0; c < n; ++c) {
                     double p = elem64(A, dtype, lda, i, c) * v[c];
                     d = d + p;
                 }
-                double s = walpha[wk] * ((b[i] - d) / wn[i]);
+                double s = weight_of(walpha, wrow, wk, i) * ((b[i] - d) / wn[i]);
                 for (int64_t c = 0; c < n; ++c) {
                     double t = s * elem64(A, dtype, lda, i, c);
                     v[c] = v[c] + t;
@@ -419,5 +435,82 @@ int oracle_rkab_walpha_given(const void* A, int dtype, int64_t m, int64_t n, int
     free(wn);
     free(v);
     free(sum);
+    return ORACLE_OK;
+}
+
+int oracle_rka_walpha_given(const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
+                            const double* b, double* x, int32_t q, const double* walpha,
+                            int64_t K, const int32_t* idx)
+{
+    if (!walpha) return ORACLE_EINVAL;
+    return rka_weighted_given(A, dtype, m, n, lda, b, x, q, walpha, NULL, K, idx);
+}
+
+int oracle_rkab_walpha_given(const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
+                             const double* b, double* x, int32_t q, int32_t bs,
+                             const double* walpha, int64_t K, const int32_t* idx)
+{
+    if (!walpha) return ORACLE_EINVAL;
+    return rkab_weighted_given(A, dtype, m, n, lda, b, x, q, bs, walpha, NULL, K, idx);
+}
+
+int oracle_rka_wrow_given(const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
+                          const double* b, double* x, int32_t q, const double* wrow, int64_t K,
+                          const int32_t* idx)
+{
+    if (!wrow) return ORACLE_EINVAL;
+    return rka_weighted_given(A, dtype, m, n, lda, b, x, q, NULL, wrow, K, idx);
+}
+
+int oracle_rkab_wrow_given(const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
+                           const double* b, double* x, int32_t q, int32_t bs, const double* wrow,
+                           int64_t K, const int32_t* idx)
+{
+    if (!wrow) return ORACLE_EINVAL;
+    return rkab_weighted_given(A, dtype, m, n, lda, b, x, q, bs, NULL, wrow, K, idx);
+}
+
+/* ------------------------------------------------------------------ */
+/* Cyclic Kaczmarz (Sec. 2.1).                                          */
+/* ------------------------------------------------------------------ */
+
+/* The rows in order: draw (k, w, j) of a stream of q workers with blocks of
+ * bs takes row (((k + iter_offset) q + w) bs + j) mod m, so that one worker
+ * with blocks of one walks the rows 0, 1, ..., m-1, 0, 1, ... */
+int oracle_indices_cyclic(int64_t m, int64_t iter_offset, int64_t K, int32_t q, int32_t bs,
+                          int32_t* idx)
+{
+    if (!idx || m < 1 || m > INT32_MAX || q < 1 || bs < 1 || K < 0 || iter_offset < 0)
+        return ORACLE_EINVAL;
+    for (int64_t k = 0; k < K; ++k)
+        for (int32_t wk = 0; wk < q; ++wk)
+            for (int32_t j = 0; j < bs; ++j) {
+                int64_t pos = ((k + iter_offset) * q + wk) * (int64_t)bs + j;
+                idx[(k * q + wk) * (int64_t)bs + j] = (int32_t)(pos % m);
+            }
+    return ORACLE_OK;
+}
+
+/* Cyclic Kaczmarz as Sec. 2.1 writes it: iteration k projects onto the
+ * hyperplane of row i = k mod m with relaxation alpha_i,
+ *   x <- x + alpha_i (b_i - <A^(i), x>) / ||A^(i)||^2 A^(i)^T,
+ * for k = 0 .. iters-1, starting from the x passed in.  relax: m
+ * relaxations, or NULL for alpha_i = 1.  A zero row leaves x unchanged. */
+int oracle_ck(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const double* b,
+              double* x, const double* relax, int64_t iters)
+{
+    if (!A || !b || !x || m < 1 || n < 1 || lda < n || iters < 0) return ORACLE_EINVAL;
+    for (int64_t k = 0; k < iters; ++k) {
+        int64_t i = k % m;
+        double nrm = 0.0, d = 0.0;
+        for (int64_t c = 0; c < n; ++c) {
+            double a = elem64(A, dtype, lda, i, c);
+            nrm = nrm + a * a;
+            d = d + a * x[c];
+        }
+        if (nrm == 0.0) continue;
+        double s = (relax ? relax[i] : 1.0) * ((b[i] - d) / nrm);
+        for (int64_t c = 0; c < n; ++c) x[c] = x[c] + s * elem64(A, dtype, lda, i, c);
+    }
     return ORACLE_OK;
 }

@@ -143,6 +143,27 @@ int oracle_rkab_walpha_given(const void* A, int dtype, int64_t m, int64_t n, int
                              const double* b, double* x, int32_t q, int32_t bs,
                              const double* walpha, int64_t K, const int32_t* idx);
 
+/* RKA / RKAB on a given stream with the row weights w_i of Eq. (7) in place
+ * of a uniform alpha; wrow: m doubles.  In these and the per-worker forms a
+ * row of zero norm is a step that leaves the iterate unchanged. */
+int oracle_rka_wrow_given(const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
+                          const double* b, double* x, int32_t q, const double* wrow, int64_t K,
+                          const int32_t* idx);
+int oracle_rkab_wrow_given(const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
+                           const double* b, double* x, int32_t q, int32_t bs, const double* wrow,
+                           int64_t K, const int32_t* idx);
+
+/* The cyclic row order of Sec. 2.1 extended to q workers and blocks of bs:
+ * draw (k, w, j) takes row (((k + iter_offset) q + w) bs + j) mod m; layout
+ * as oracle_indices. */
+int oracle_indices_cyclic(int64_t m, int64_t iter_offset, int64_t K, int32_t q, int32_t bs,
+                          int32_t* idx);
+
+/* Cyclic Kaczmarz (Sec. 2.1): iters projections onto rows 0, 1, ..., m-1,
+ * 0, ... in turn, row i relaxed by relax[i] (NULL: 1), x updated in place. */
+int oracle_ck(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const double* b,
+              double* x, const double* relax, int64_t iters);
+
 #ifdef __cplusplus
 }
 #endif

@@ -37,7 +37,8 @@ class _Opts(ctypes.Structure):
     _fields_ = [("check_every", ctypes.c_int64), ("grid", ctypes.c_int32),
                 ("collect_timing", ctypes.c_int32), ("allreduce", ctypes.c_int32),
                 ("accumulate", ctypes.c_int32), ("stream_id", ctypes.c_int32),
-                ("sampling", ctypes.c_int32), ("worker_alpha", ctypes.c_void_p)]
+                ("sampling", ctypes.c_int32), ("worker_alpha", ctypes.c_void_p),
+                ("row_weight", ctypes.c_void_p)]
 
 
 class _Stats(ctypes.Structure):
@@ -251,14 +252,16 @@ def rkab_solve(A, b, *, q, block_size, alpha=1.0, max_iter=1000, tol=0.0, seed=1
 
 def solve_ex(A, b, *, method, q, block_size=1, alpha=1.0, max_iter=1000, tol=0.0, seed=1,
              x0=None, x_ref=None, iter_offset=0, check_every=1, grid=0, allreduce=0,
-             timing=False, accumulate=0, stream_id=0, sampling=0, worker_alpha=None, out=None,
-             stream=None, raise_on_error=True):
+             timing=False, accumulate=0, stream_id=0, sampling=0, worker_alpha=None,
+             row_weight=None, out=None, stream=None, raise_on_error=True):
     """rka_solve_ex: method 0 = RKA, 1 = RKAB.  Returns (x, Info, stats dict);
     with ``timing`` the stats hold per-phase HIP-event times (ms) measured on
     the stream the kernels run on.  ``accumulate=1`` computes in FP32 (narrow
     storage only); ``stream_id`` is the row stream's counter domain;
     ``sampling=1`` is the Distributed Approach (worker w samples its own row
-    block) and ``worker_alpha`` a float64 GPU vector of per-worker weights."""
+    block), ``sampling=2`` the cyclic row order (Cyclic Kaczmarz at q=1);
+    ``worker_alpha`` is a float64 GPU vector of per-worker weights and
+    ``row_weight`` one of per-row weights w_i (Eq. (7))."""
     torch = _torch()
     code, m, n, lda = _matrix(A)
     b = _vec(b, m, "b", False)
@@ -267,8 +270,11 @@ def solve_ex(A, b, *, method, q, block_size=1, alpha=1.0, max_iter=1000, tol=0.0
     info, stats = _Info(), _Stats()
     if worker_alpha is not None:
         _vec(worker_alpha, q, "worker_alpha", False)
+    if row_weight is not None:
+        _vec(row_weight, m, "row_weight", False)
     opts = _Opts(check_every, grid, 1 if timing else 0, allreduce, accumulate, stream_id,
-                 sampling, None if worker_alpha is None else worker_alpha.data_ptr())
+                 sampling, None if worker_alpha is None else worker_alpha.data_ptr(),
+                 None if row_weight is None else row_weight.data_ptr())
     st = lib().rka_solve_ex(_ptr(A), code, m, n, lda, _ptr(b), _ptr(_vec(x0, n, "x0")), _ptr(x),
                             method, q, block_size, alpha, max_iter, tol, seed,
                             _ptr(_vec(x_ref, n, "x_ref")), iter_offset, ctypes.byref(opts),

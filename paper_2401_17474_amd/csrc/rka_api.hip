@@ -159,8 +159,8 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
                const double* b, const double* x0, double* x, int32_t q, int32_t bs, double alpha,
                int64_t max_iter, double tol, uint64_t seed, const double* x_ref,
                int64_t iter_offset, int64_t check_every, int grid, int allreduce, bool timing,
-               int acc, int dom, int sampling, const double* walpha, void* stream, rka_info* info,
-               rka_stats* stats) {
+               int acc, int dom, int sampling, const double* walpha, const double* wrow,
+               void* stream, rka_info* info, rka_stats* stats) {
   g_last_error.clear();
   if (stats) memset(stats, 0, sizeof *stats);
   if (info) {
@@ -179,8 +179,10 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   if (acc == 1 && dtype == RKA_F64)
     return fail(RKA_EINVAL, "FP32 accumulation needs RKA_F32 or RKA_BF16 storage");
   if (dom < 0 || dom > 255) return fail(RKA_EINVAL, "stream_id must be in [0, 255]");
-  if (sampling < 0 || sampling > 1) return fail(RKA_EINVAL, "sampling must be 0 or 1");
-  if (sampling == 1 && q > m)
+  if (sampling < rka::kSampleFull || sampling > rka::kSampleCyclic)
+    return fail(RKA_EINVAL, "sampling must be 0, 1 or 2");
+  if (walpha && wrow) return fail(RKA_EINVAL, "give worker_alpha or row_weight, not both");
+  if (sampling == rka::kSampleBlocks && q > m)
     return fail(RKA_EINVAL, "the Distributed Approach needs q <= m (one row block per worker)");
   const int ncu = num_cus();
   if (ncu <= 0) return fail(RKA_EDEVICE, "no HIP device available");
@@ -236,7 +238,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   HIP_TRY(sc.get(&st, 1));
   HIP_TRY(sc.get(&w, (size_t)m));
   HIP_TRY(sc.get(&c, (size_t)m));
-  HIP_TRY(sc.get(&last_pos, sampling == 1 ? (size_t)q : 1));
+  HIP_TRY(sc.get(&last_pos, sampling == rka::kSampleBlocks ? (size_t)q : 1));
   HIP_TRY(sc.get(&rec, (size_t)(kc_max * per_iter)));
   HIP_TRY(sc.get(&part, part_len));
   HIP_TRY(sc.get(&bar, 1));
@@ -264,7 +266,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   HIP_TRY(rka::launch_row_norms(A, dtype, m, n, lda, sh.vec_ok, w, s));
   tm.end();
   tm.begin(kPrefix);
-  if (sampling == 1)
+  if (sampling == rka::kSampleBlocks)
     HIP_TRY(rka::launch_prefix_blocks(w, m, q, c, last_pos, st, s));
   else
     HIP_TRY(rka::launch_prefix(w, m, c, last_pos, st, s));
@@ -291,7 +293,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
     }
     tm.begin(kSample);
     HIP_TRY(rka::launch_sample(c, m, last_pos, seed, k + iter_offset, kc, q, sh.bs, dom, sampling,
-                               alpha, walpha, nullptr, rec, b, w, st, s));
+                               alpha, walpha, wrow, nullptr, rec, b, w, st, s));
     tm.end();
     tm.begin(kIterate);
     if (use_col)
@@ -374,7 +376,7 @@ int rka_solve(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const
               uint64_t seed, const double* x_ref, int64_t iter_offset, int64_t check_every,
               void* stream, rka_info* info) {
   return solve_impl(false, A, dtype, m, n, lda, b, x0, x, q, 1, alpha, max_iter, tol, seed, x_ref,
-                    iter_offset, check_every, 0, 0, false, 0, 0, 0, nullptr, stream, info, nullptr);
+                    iter_offset, check_every, 0, 0, false, 0, 0, 0, nullptr, nullptr, stream, info, nullptr);
 }
 
 int rka_solve_ex(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const double* b,
@@ -395,9 +397,10 @@ int rka_solve_ex(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, co
   const int dom = opts ? opts->stream_id : 0;
   const int sampling = opts ? opts->sampling : 0;
   const double* walpha = opts ? opts->worker_alpha : nullptr;
+  const double* wrow = opts ? opts->row_weight : nullptr;
   return solve_impl(method == 1, A, dtype, m, n, lda, b, x0, x, q, method == 1 ? block_size : 1,
                     alpha, max_iter, tol, seed, x_ref, iter_offset, ce, grid, allreduce, timing,
-                    acc, dom, sampling, walpha, stream, info, stats);
+                    acc, dom, sampling, walpha, wrow, stream, info, stats);
 }
 
 int rkab_solve(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const double* b,
@@ -405,7 +408,7 @@ int rkab_solve(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, cons
                int64_t max_iter, double tol, uint64_t seed, const double* x_ref,
                int64_t iter_offset, int64_t check_every, void* stream, rka_info* info) {
   return solve_impl(true, A, dtype, m, n, lda, b, x0, x, q, block_size, alpha, max_iter, tol, seed,
-                    x_ref, iter_offset, check_every, 0, 0, false, 0, 0, 0, nullptr, stream, info, nullptr);
+                    x_ref, iter_offset, check_every, 0, 0, false, 0, 0, 0, nullptr, nullptr, stream, info, nullptr);
 }
 
 int rka_row_norms(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, double* w,
@@ -451,8 +454,8 @@ int rka_sample_indices(const double* w, const double* c, int64_t m, uint64_t see
   hipError_t e = hipMallocAsync((void**)&cscratch, (size_t)m * sizeof(double), s);
   if (e == hipSuccess) e = rka::launch_prefix(w, m, cscratch, last_pos, nullptr, s);
   if (e == hipSuccess)
-    e = rka::launch_sample(c, m, last_pos, seed, iter_offset, K, q, bs, dom, 0, 1.0, nullptr, idx,
-                           nullptr, nullptr, nullptr, nullptr, s);
+    e = rka::launch_sample(c, m, last_pos, seed, iter_offset, K, q, bs, dom, rka::kSampleFull, 1.0,
+                           nullptr, nullptr, idx, nullptr, nullptr, nullptr, nullptr, s);
   if (cscratch) (void)hipFreeAsync(cscratch, s);
   (void)hipFreeAsync(last_pos, s);
   if (e != hipSuccess)
@@ -579,7 +582,7 @@ int rka_refine_solve(const void* A, const void* At, int dtype, int64_t m, int64_
       const int st = solve_impl(false, At, dtype, n, m, ldat, g, nullptr, y, o->range_q, 1,
                                 o->range_alpha, o->range_iters, 0.0, seed, nullptr,
                                 (int64_t)sw * o->range_iters, 1, 0, 0, false, o->accumulate, 1, 0,
-                                nullptr, stream, &ii, nullptr);
+                                nullptr, nullptr, stream, &ii, nullptr);
       if (st < 0) return st;
       projections += ii.projections;
       rhs = y;
@@ -600,8 +603,8 @@ int rka_refine_solve(const void* A, const void* At, int dtype, int64_t m, int64_
     const int st = solve_impl(o->method == 1, A, dtype, m, n, lda, rhs, nullptr, d, o->q,
                               o->method == 1 ? o->block_size : 1, o->alpha, o->inner_iters, tol_d,
                               seed, tol_d > 0.0 ? dref : nullptr, (int64_t)sw * o->inner_iters,
-                              kInnerCheck, 0, 0, false, o->accumulate, 0, 0, nullptr, stream, &ii,
-                              nullptr);
+                              kInnerCheck, 0, 0, false, o->accumulate, 0, 0, nullptr, nullptr, stream,
+                              &ii, nullptr);
     if (st < 0) return st;
     projections += ii.projections;
     HIP_TRY(rka::launch_axpy(x, d, n, s));
@@ -659,8 +662,8 @@ int rka_sample_blocks(const double* w, int64_t m, uint64_t seed, int64_t iter_of
   HIP_TRY(sc.get(&st, 1));
   HIP_TRY(rka::launch_status_init(st, 0.0, s));
   HIP_TRY(rka::launch_prefix_blocks(w, m, q, c, last, st, s));
-  HIP_TRY(rka::launch_sample(c, m, last, seed, iter_offset, K, q, bs, dom, 1, 1.0, nullptr, idx,
-                             nullptr, nullptr, nullptr, st, s));
+  HIP_TRY(rka::launch_sample(c, m, last, seed, iter_offset, K, q, bs, dom, rka::kSampleBlocks, 1.0,
+                             nullptr, nullptr, idx, nullptr, nullptr, nullptr, st, s));
   rka::DevStatus hst;
   HIP_TRY(hipMemcpyAsync(&hst, st, sizeof hst, hipMemcpyDeviceToHost, s));
   sc.release();

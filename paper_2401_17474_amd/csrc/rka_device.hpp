@@ -139,6 +139,14 @@ __device__ __forceinline__ U wave_sum(U v) {
   return v;
 }
 
+// Sum over aligned teams of tr lanes (tr a power of two <= 64): every lane of
+// a team receives its team's sum.  All lanes of the wave must take part.
+template <typename U>
+__device__ __forceinline__ U team_sum(U v, int tr) {
+  for (int off = tr / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
 // Sum over the block; every thread receives the same value.  `scratch` holds
 // at least blockDim.x / 64 values of LDS and is free for reuse on return.
 template <typename U>

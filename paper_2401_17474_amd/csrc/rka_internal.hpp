@@ -18,15 +18,21 @@ hipError_t launch_prefix(const double* w, int64_t m, double* c, int64_t* last_po
 // the running sum restarted at each of nseg row blocks; last_pos: nseg entries
 hipError_t launch_prefix_blocks(const double* w, int64_t m, int32_t nseg, double* c,
                                 int64_t* last_pos, DevStatus* st, hipStream_t s);
+// Row orders of the row stream (the `sampling` option of rka_solve_ex).
+constexpr int32_t kSampleFull = 0;    // every worker draws from all rows
+constexpr int32_t kSampleBlocks = 1;  // worker w draws from its own row block
+constexpr int32_t kSampleCyclic = 2;  // rows in order: draw position mod m
+
 // Row stream of K*q*bs draws: indices into idx and/or records (index, b_i,
-// ||a_i||^2, worker weight) into rec (either may be NULL; b and wn are needed
-// for rec).  blocks != 0: worker w samples its own row block (c and last_pos
-// from launch_prefix_blocks with nseg = q).  walpha: per-worker weights or NULL.
+// ||a_i||^2, weight) into rec (either may be NULL; b and wn are needed for
+// rec).  mode kSampleBlocks: c and last_pos from launch_prefix_blocks with
+// nseg = q; kSampleCyclic reads neither.  The record's weight is wrow[i] if
+// wrow is given, else walpha[w] if walpha is given, else alpha.
 hipError_t launch_sample(const double* c, int64_t m, const int64_t* last_pos, uint64_t seed,
                          int64_t k_base, int64_t K, int32_t q, int32_t bs, int32_t dom,
-                         int32_t blocks, double alpha, const double* walpha, int32_t* idx,
-                         RowRec* rec, const double* b, const double* wn, const DevStatus* st,
-                         hipStream_t s);
+                         int32_t mode, double alpha, const double* walpha, const double* wrow,
+                         int32_t* idx, RowRec* rec, const double* b, const double* wn,
+                         const DevStatus* st, hipStream_t s);
 hipError_t launch_check_finite(const double* v, int64_t len, DevStatus* st, hipStream_t s);
 
 // --- iterations (rka_iter.hip) ---------------------------------------------
@@ -39,6 +45,8 @@ struct RkaColGeom {
   int rpt;     // rows per thread (template bucket)
   size_t lds;  // dynamic LDS bytes
   int gather;  // one-barrier all-gather of the partials
+  int tr;      // lanes per row for the slice sums (power of two <= 64)
+  int tr_g;    // lanes per row for the gathered sums (1 without all-gather)
 };
 
 struct SolveShape {

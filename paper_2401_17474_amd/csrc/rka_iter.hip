@@ -39,6 +39,8 @@ struct RkaColArgs {
   double alpha, inv_q;
   int32_t q, nsv, rg, G;
   int32_t gather;     // 1: one-barrier all-gather of the partials; 0: two barriers
+  int32_t tr;         // lanes that sum one row's nsv slice partials (power of two <= 64)
+  int32_t tr_g;       // lanes that sum one row's G gathered partials (all-gather only)
   int64_t k0, K, check_every;
   uint64_t* part;  // tagged slots: gather 2 x G x (q+1) (by iteration parity); else G x (q+1)
   uint64_t* scal;  // tagged slots: q+1 scales (two-phase exchange)
@@ -95,7 +97,9 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
   // entries are masked in the arithmetic): a load under a branch would make
   // the compiler drain every in-flight load where the branches join.
   const int64_t cvl = cv < p.nvec ? cv : p.nvec - 1;
-  const int tq = t < q ? t : q - 1;
+  // the row whose scale this thread forms (first round of its team)
+  const int tr_s = G == 1 ? p.tr : (gather ? p.tr_g : 1);
+  const int tq = t / tr_s < q ? t / tr_s : q - 1;
   raw_t a[RPT], an[RPT];
   int rows[RPT], rows_n[RPT];
 #pragma unroll
@@ -152,21 +156,37 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
       E[j] = s;
     }
     __syncthreads();
-    for (int r = t; r < q; r += NT) {
-      C d = 0;
-      for (int jj = 0; jj < nsv; ++jj) d += P[r * nsv + jj];
-      if (G > 1)
-        part.put((int64_t)g * (q + 1) + r, (double)d, tag);
-      else
-        SC[r] = (double)d;
+    // row r's nsv partials: a team of tr lanes, lane u adding entries u,
+    // u + tr, ... in order, then an xor fold over the team (fixed order).
+    // The loop bound is uniform, so every lane takes part in the folds.
+    {
+      const int TR = p.tr, team = t / TR, u = t & (TR - 1), nteams = NT / TR;
+      for (int r0 = 0; r0 < q; r0 += nteams) {
+        const int r = r0 + team;
+        C d = 0;
+        if (r < q)
+          for (int jj = u; jj < nsv; jj += TR) d += P[r * nsv + jj];
+        d = team_sum(d, TR);
+        if (u == 0 && r < q) {
+          if (G > 1)
+            part.put((int64_t)g * (q + 1) + r, (double)d, tag);
+          else
+            SC[r] = (r0 == 0) ? scale_of(mine_a, mine_b, mine_w, (double)d)
+                              : scale_of(p.rec[kl * q + r].alpha, p.rec[kl * q + r].b,
+                                         p.rec[kl * q + r].wn, (double)d);
+        }
+      }
     }
-    if (check && t == 0) {
+    if (check && t < kWave) {  // the whole first wave
       double s = 0.0;
-      for (int jj = 0; jj < nsv; ++jj) s += E[jj];
-      if (G > 1)
-        part.put((int64_t)g * (q + 1) + q, s, tag);
-      else
-        SC[q] = s;
+      for (int jj = t; jj < nsv; jj += kWave) s += E[jj];
+      s = wave_sum(s);
+      if (t == 0) {
+        if (G > 1)
+          part.put((int64_t)g * (q + 1) + q, s, tag);
+        else
+          SC[q] = s;
+      }
     }
     // the next iteration's rows (independent of x) are requested now, so that
     // they stream in while the exchange below is in progress
@@ -206,16 +226,26 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
           }
           __builtin_amdgcn_s_sleep(1);
         }
-        for (int r = t; r < nr; r += NT) {
-          double D = 0.0;
-          for (int gg = 0; gg < G; ++gg) D += PG[gg * (q + 1) + r];
-          if (r < q) {
-            const double rb = r == t ? mine_b : p.rec[kl * q + r].b;
-            const double rw = r == t ? mine_w : p.rec[kl * q + r].wn;
-            const double ra = r == t ? mine_a : p.rec[kl * q + r].alpha;
-            SC[r] = scale_of(ra, rb, rw, D);
-          } else {
-            SC[r] = D;
+        // row r's G partials: a team of tr_g lanes, as for the slice sums
+        {
+          const int TR = p.tr_g, team = t / TR, u = t & (TR - 1), nteams = NT / TR;
+          for (int r0 = 0; r0 < nr; r0 += nteams) {
+            const int r = r0 + team;
+            double D = 0.0;
+            if (r < nr)
+              for (int gg = u; gg < G; gg += TR) D += PG[gg * (q + 1) + r];
+            D = team_sum(D, TR);
+            if (u == 0 && r < nr) {
+              if (r < q) {
+                const bool mine = r0 == 0;
+                const double rb = mine ? mine_b : p.rec[kl * q + r].b;
+                const double rw = mine ? mine_w : p.rec[kl * q + r].wn;
+                const double ra = mine ? mine_a : p.rec[kl * q + r].alpha;
+                SC[r] = scale_of(ra, rb, rw, D);
+              } else {
+                SC[r] = D;
+              }
+            }
           }
         }
       } else if constexpr (!GATHER) {
@@ -279,14 +309,6 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
         if (t == 0) note_timeout(p.st);
         stopped = true;
         break;
-      }
-    } else {
-      __syncthreads();
-      for (int r = t; r < q; r += NT) {
-        const double rb = r == t ? mine_b : p.rec[kl * q + r].b;
-        const double rw = r == t ? mine_w : p.rec[kl * q + r].wn;
-        const double ra = r == t ? mine_a : p.rec[kl * q + r].alpha;
-        SC[r] = scale_of(ra, rb, rw, SC[r]);
       }
     }
     __syncthreads();
@@ -429,6 +451,14 @@ bool rka_col_plan(const SolveShape& sh, RkaColGeom* geo) {
                      csz * ((size_t)sh.q * nsv + (size_t)nt * V + (size_t)nsv * V +
                             (size_t)std::max(nt, nsv * V));
   if (lds > 64 * 1024) return false;
+  // reduction teams: as many lanes per row as keep every row in one round
+  auto pow2_team = [](int64_t cap) {
+    int tr = 1;
+    while (tr * 2 <= cap && tr * 2 <= kWave) tr *= 2;
+    return tr;
+  };
+  geo->tr = pow2_team(std::min<int64_t>(nt / sh.q, nsv));
+  geo->tr_g = gather ? pow2_team(std::min<int64_t>(nt / (sh.q + 1), G)) : 1;
   geo->G = G;
   geo->nsv = nsv;
   geo->rg = rg;
@@ -477,6 +507,8 @@ hipError_t launch_rka_chunk(const SolveShape& sh, const RkaColGeom& geo, const R
   a.rg = geo.rg;
   a.G = geo.G;
   a.gather = geo.gather;
+  a.tr = geo.tr;
+  a.tr_g = geo.tr_g;
   a.k0 = k0;
   a.K = K;
   a.check_every = check_every;

@@ -163,8 +163,9 @@ __global__ __launch_bounds__(256) void sample_kernel(const double* __restrict__ 
                                                      const int64_t* __restrict__ last_pos,
                                                      uint64_t seed, int64_t k_base, int64_t K,
                                                      int32_t q, int32_t bs, uint32_t dom,
-                                                     int32_t blocks, double alpha,
+                                                     int32_t mode, double alpha,
                                                      const double* __restrict__ walpha,
+                                                     const double* __restrict__ wrow,
                                                      int32_t* __restrict__ idx,
                                                      RowRec* __restrict__ rec,
                                                      const double* __restrict__ b,
@@ -177,13 +178,21 @@ __global__ __launch_bounds__(256) void sample_kernel(const double* __restrict__ 
     const int64_t j = L % bs;
     const int64_t wk = (L / bs) % q;
     const int64_t kl = L / ((int64_t)bs * q);
-    const double u = draw_uniform(seed, (uint64_t)(k_base + kl), (uint32_t)wk, (uint32_t)j, dom);
     int64_t i;
-    if (blocks) {
-      const int64_t lo = wk * m / q, hi = (wk + 1) * m / q;
-      i = lo + pick_row(c + lo, hi - lo, c[hi - 1], u, last_pos[wk] - lo);
+    if (mode == kSampleCyclic) {
+      // position of the draw in the whole stream, rows taken in order
+      const uint64_t pos = ((uint64_t)(k_base + kl) * (uint64_t)q + (uint64_t)wk) * (uint64_t)bs +
+                           (uint64_t)j;
+      i = (int64_t)(pos % (uint64_t)m);
     } else {
-      i = pick_row(c, m, c[m - 1], u, *last_pos);
+      const double u =
+          draw_uniform(seed, (uint64_t)(k_base + kl), (uint32_t)wk, (uint32_t)j, dom);
+      if (mode == kSampleBlocks) {
+        const int64_t lo = wk * m / q, hi = (wk + 1) * m / q;
+        i = lo + pick_row(c + lo, hi - lo, c[hi - 1], u, last_pos[wk] - lo);
+      } else {
+        i = pick_row(c, m, c[m - 1], u, *last_pos);
+      }
     }
     if (idx) idx[L] = (int32_t)i;
     if (rec) {
@@ -191,7 +200,13 @@ __global__ __launch_bounds__(256) void sample_kernel(const double* __restrict__ 
       r.b = b[i];
       r.wn = wn[i];
       r.row = i;
-      r.alpha = walpha ? walpha[wk] : alpha;
+      r.alpha = wrow ? wrow[i] : (walpha ? walpha[wk] : alpha);
+      // Only the cyclic order reaches a zero row: its step leaves x as it is
+      // (weight 0 over a unit norm keeps the scale finite and zero).
+      if (r.wn == 0.0) {
+        r.alpha = 0.0;
+        r.wn = 1.0;
+      }
       rec[L] = r;
     }
   }
@@ -250,15 +265,15 @@ hipError_t launch_prefix_blocks(const double* w, int64_t m, int32_t nseg, double
 
 hipError_t launch_sample(const double* c, int64_t m, const int64_t* last_pos, uint64_t seed,
                          int64_t k_base, int64_t K, int32_t q, int32_t bs, int32_t dom,
-                         int32_t blocks, double alpha, const double* walpha, int32_t* idx,
-                         RowRec* rec, const double* b, const double* wn, const DevStatus* st,
-                         hipStream_t s) {
+                         int32_t mode, double alpha, const double* walpha, const double* wrow,
+                         int32_t* idx, RowRec* rec, const double* b, const double* wn,
+                         const DevStatus* st, hipStream_t s) {
   const int64_t total = K * (int64_t)q * bs;
   if (total <= 0) return hipSuccess;
   int64_t nb = (total + 255) / 256;
   if (nb > 8192) nb = 8192;
   hipLaunchKernelGGL(sample_kernel, dim3((unsigned)nb), dim3(256), 0, s, c, m, last_pos, seed,
-                     k_base, K, q, bs, (uint32_t)dom, blocks, alpha, walpha, idx, rec, b, wn, st);
+                     k_base, K, q, bs, (uint32_t)dom, mode, alpha, walpha, wrow, idx, rec, b, wn, st);
   return hipGetLastError();
 }
 

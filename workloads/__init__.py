@@ -61,14 +61,23 @@ def gaussian_system(m, n, *, seed=DATA_SEED, noise_var=0.0, dtype="f64", rng="nu
     return A, x, b
 
 
-def paper_rows_system(m, n, *, seed=DATA_SEED, dtype="f64"):
-    """Consistent system following the recipe of Sec. 3.1 (host only)."""
+def paper_rows_system(m, n, *, seed=DATA_SEED, dtype="f64", order="drawn"):
+    """Consistent system following the recipe of Sec. 3.1 (host only).
+
+    ``order="coherent"`` stores the same rows sorted by mu_i / sigma_i, so
+    that neighbouring rows are nearly parallel (the situation in which
+    Sec. 2.1 finds the cyclic order slow); the system and its solution are
+    unchanged, only the row order differs."""
     g = _np_rng(seed)
     mu = g.uniform(-5.0, 5.0, size=m)
     sd = g.uniform(1.0, 20.0, size=m)
     A = mu[:, None] + sd[:, None] * g.standard_normal((m, n))
     r = int(g.integers(0, m))
     x = mu[r] + sd[r] * g.standard_normal(n)
+    if order == "coherent":
+        A = A[np.argsort(mu / sd, kind="stable")]
+    elif order != "drawn":
+        raise ValueError(f"unknown row order {order!r}")
     A = _round_np(A, dtype)
     b = _widen_np(A, dtype) @ x
     return A, x, b
