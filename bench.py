@@ -86,11 +86,14 @@ def make_cells(spec, astar):
 
 def kernel_name(stats, storage="double", vec=2):
     """Template instance as named in the library: <storage, accumulation,
-    elements per 16-byte vec, register bucket, all-gather / iterate in LDS>."""
+    elements per 16-byte vec, register bucket, all-gather / iterate in LDS>
+    (the block kernel: <storage, elements per vec, rows per thread>)."""
     acc = "float" if stats.get("accumulate") == 1 else "double"
     flag = "true" if stats.get("variant") == 1 else "false"
     if stats["kernel"] == 1:
         return f"rka_col_kernel<{storage}, {acc}, {vec}, {stats['bucket']}, {flag}>"
+    if stats["kernel"] == 3:
+        return f"rka_sstep_kernel<{storage}, {vec}, {stats['bucket']}>"
     return f"rkab_kernel<{storage}, {acc}, {vec}, {stats['bucket']}, {flag}>"
 
 

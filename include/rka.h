@@ -151,6 +151,16 @@ typedef struct rka_opts {
                                Not combined with worker_alpha (RKA_EINVAL if both).
                                Values are not checked; the convergence results of
                                the paper assume 0 < w_i < 2.                          */
+    int32_t steps_per_exchange; /* RKA only: iterations per exchange between
+                               workgroups.  0 = chosen by the library; 1 = one (the
+                               column-split kernel); p >= 2 = blocks of up to p
+                               iterations whose scales come from one exchange of the
+                               dot products with x^(k) and the inner products between
+                               the block's rows (the same iteration in exact
+                               arithmetic; rounding differs).  Needs FP64 arithmetic,
+                               allreduce = 0 and q p <= 64; otherwise, or if the shape
+                               does not fit, the column-split kernel runs.  Blocks end
+                               at stopping tests, so check_every = 1 gives p = 1.     */
 } rka_opts;
 
 /* Launch facts and phase times of one rka_solve_ex call. */
@@ -161,13 +171,15 @@ typedef struct rka_stats {
     double iterate_ms;        /* persistent iteration kernel, summed over chunks       */
     double measure_ms;        /* stopping measures                                     */
     int64_t iterate_launches; /* chunks (launches of the iteration kernel)             */
-    int32_t kernel;           /* 1 = column-split RKA kernel, 2 = worker-split kernel  */
+    int32_t kernel;           /* 1 = column-split RKA kernel, 2 = worker-split kernel,
+                                 3 = RKA with several iterations per exchange           */
     int32_t grid;             /* workgroups of the iteration kernel                    */
     int32_t threads;          /* threads per workgroup of the iteration kernel         */
     int32_t bucket;           /* register-tile bucket of the kernel instance: rows per
                                  thread (kernel 1) or 16-byte vecs per thread (kernel 2) */
     int32_t variant;          /* kernel 1: 1 = one-barrier all-gather of the partials;
-                                 kernel 2: 1 = worker iterate kept in LDS               */
+                                 kernel 2: 1 = worker iterate kept in LDS;
+                                 kernel 3: iterations per exchange (p)                  */
     int32_t accumulate;       /* accumulation type used: 0 = FP64, 1 = FP32             */
 } rka_stats;
 

@@ -23,6 +23,7 @@ ARCH = os.environ.get("RKA_OFFLOAD_ARCH", "gfx950")
 SOURCES = {
     "rka_setup.hip": ["-ffp-contract=off"],
     "rka_iter.hip": [],
+    "rka_sstep.hip": [],
     "rka_rkab.hip": [],
     "rka_dense.hip": [],
     "rka_batch.hip": [],

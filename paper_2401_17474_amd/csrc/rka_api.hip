@@ -154,13 +154,19 @@ int validate(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const 
 
 // Row records per chunk: at most 4 Mi entries (128 MiB).
 constexpr int64_t kRecBudget = 4ll << 20;
+// Largest q for which the library runs several RKA iterations per exchange
+// by itself (steps_per_exchange = 0): measured at 80000 x 10000 FP64, blocks
+// of 64 / q iterations take 4.5 us per iteration at q = 16 (one-iteration
+// kernel: 5.5 us at its best grid) and 2.7 us at q = 8 (5.2 us); at q = 32
+// the block's exchange outweighs the saved round trips.
+constexpr int kAutoSstepMaxQ = 16;
 
 int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
                const double* b, const double* x0, double* x, int32_t q, int32_t bs, double alpha,
                int64_t max_iter, double tol, uint64_t seed, const double* x_ref,
                int64_t iter_offset, int64_t check_every, int grid, int allreduce, bool timing,
                int acc, int dom, int sampling, const double* walpha, const double* wrow,
-               void* stream, rka_info* info, rka_stats* stats) {
+               int sstep, void* stream, rka_info* info, rka_stats* stats) {
   g_last_error.clear();
   if (stats) memset(stats, 0, sizeof *stats);
   if (info) {
@@ -182,6 +188,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   if (sampling < rka::kSampleFull || sampling > rka::kSampleCyclic)
     return fail(RKA_EINVAL, "sampling must be 0, 1 or 2");
   if (walpha && wrow) return fail(RKA_EINVAL, "give worker_alpha or row_weight, not both");
+  if (sstep < 0 || sstep > 64) return fail(RKA_EINVAL, "steps_per_exchange must be in [0, 64]");
   if (sampling == rka::kSampleBlocks && q > m)
     return fail(RKA_EINVAL, "the Distributed Approach needs q <= m (one row block per worker)");
   const int ncu = num_cus();
@@ -208,8 +215,22 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
 
   rka::RkaColGeom cgeo{};
   rka::RkabGeom bgeo{};
-  bool use_col = !block && rka::rka_col_plan(sh, &cgeo);
-  if (!use_col) {
+  rka::RkaSstepGeom sgeo{};
+  const int64_t in_kernel_check = (tol > 0.0 && sh.x_ref) ? check_every : 0;
+  // several iterations per exchange: asked for (sstep >= 2), or chosen for
+  // small q when blocks can be longer than one iteration between tests
+  bool use_sstep = false;
+  if (!block && acc == 0 && allreduce == 0) {
+    if (sstep >= 2) {
+      use_sstep = rka::rka_sstep_plan(sh, sstep, &sgeo);
+    } else if (sstep == 0 && q <= kAutoSstepMaxQ && in_kernel_check != 1) {
+      // not where one workgroup holds the whole problem (no exchange at all)
+      rka::RkaColGeom one{};
+      if (rka::rka_col_plan(sh, &one) && one.G > 1) use_sstep = rka::rka_sstep_plan(sh, 0, &sgeo);
+    }
+  }
+  bool use_col = !block && !use_sstep && rka::rka_col_plan(sh, &cgeo);
+  if (!use_col && !use_sstep) {
     // RKA whose q rows do not fit the column kernel's tile runs as RKAB with
     // one projection per worker, which is the same iteration (Sec. 3.4.2).
     if (!rka::rkab_plan(sh, &bgeo))
@@ -229,7 +250,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   int64_t kc_max = kRecBudget / per_iter;
   if (kc_max < 1) kc_max = 1;
   if (kc_max > max_iter) kc_max = max_iter > 0 ? max_iter : 1;
-  const int G = use_col ? cgeo.G : bgeo.G;
+  const int G = use_sstep ? sgeo.G : (use_col ? cgeo.G : bgeo.G);
   size_t part_len = (size_t)G;
   if (!sh.x_ref && tol > 0.0) {
     const size_t rb = (size_t)rka::resid_blocks(m);
@@ -243,7 +264,12 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   HIP_TRY(sc.get(&part, part_len));
   HIP_TRY(sc.get(&bar, 1));
   size_t nslots = 0, nsslots = 0;
-  if (use_col) {
+  if (use_sstep) {
+    nslots = (size_t)sgeo.G * sgeo.nv;
+    nsslots = (size_t)sgeo.nv;
+    HIP_TRY(sc.get(&slots, 2 * nslots));
+    HIP_TRY(sc.get(&sslots, 2 * nsslots));
+  } else if (use_col) {
     // 16-byte slots: 2 words each
     nslots = (size_t)(cgeo.gather ? 2 : 1) * G * (q + 1);
     nsslots = (size_t)q + 1;
@@ -256,7 +282,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   sh.wn = w;
 
   PhaseTimer tm(s, timing && stats);
-  if (use_col) {  // tag 0 never matches: slots start empty for the whole solve
+  if (use_col || use_sstep) {  // tag 0 never matches: slots start empty for the whole solve
     HIP_TRY(hipMemsetAsync(slots, 0, 16 * nslots, s));
     HIP_TRY(hipMemsetAsync(sslots, 0, 16 * nsslots, s));
   }
@@ -284,7 +310,6 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
     tm.end();
   }
   int64_t launches = 0;
-  const int64_t in_kernel_check = (tol > 0.0 && sh.x_ref) ? check_every : 0;
   for (int64_t k = 0; k < max_iter;) {
     int64_t kc = max_iter - k < kc_max ? max_iter - k : kc_max;
     if (resid_mode) {
@@ -296,7 +321,9 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
                                alpha, walpha, wrow, nullptr, rec, b, w, st, s));
     tm.end();
     tm.begin(kIterate);
-    if (use_col)
+    if (use_sstep)
+      HIP_TRY(rka::launch_sstep_chunk(sh, sgeo, rec, k, kc, in_kernel_check, slots, sslots, st, s));
+    else if (use_col)
       HIP_TRY(rka::launch_rka_chunk(sh, cgeo, rec, k, kc, in_kernel_check, slots, sslots, st, s));
     else
       HIP_TRY(rka::launch_rkab_chunk(sh, bgeo, rec, k, kc, in_kernel_check, vbuf, part, bar, st, s));
@@ -329,11 +356,19 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
     stats->iterate_ms = ph[kIterate];
     stats->measure_ms = ph[kMeasure];
     stats->iterate_launches = launches;
-    stats->kernel = use_col ? 1 : 2;
-    stats->grid = use_col ? cgeo.G : bgeo.G;
-    stats->threads = use_col ? cgeo.nt : bgeo.nt;
-    stats->bucket = use_col ? cgeo.rpt : bgeo.vpt;
-    stats->variant = use_col ? cgeo.gather : (bgeo.vlds ? 1 : 0);
+    if (use_sstep) {
+      stats->kernel = 3;
+      stats->grid = sgeo.G;
+      stats->threads = sgeo.nt;
+      stats->bucket = sgeo.rpt;
+      stats->variant = sgeo.p;
+    } else {
+      stats->kernel = use_col ? 1 : 2;
+      stats->grid = use_col ? cgeo.G : bgeo.G;
+      stats->threads = use_col ? cgeo.nt : bgeo.nt;
+      stats->bucket = use_col ? cgeo.rpt : bgeo.vpt;
+      stats->variant = use_col ? cgeo.gather : (bgeo.vlds ? 1 : 0);
+    }
     stats->accumulate = acc;
   }
   int status = hst.status;
@@ -376,7 +411,8 @@ int rka_solve(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const
               uint64_t seed, const double* x_ref, int64_t iter_offset, int64_t check_every,
               void* stream, rka_info* info) {
   return solve_impl(false, A, dtype, m, n, lda, b, x0, x, q, 1, alpha, max_iter, tol, seed, x_ref,
-                    iter_offset, check_every, 0, 0, false, 0, 0, 0, nullptr, nullptr, stream, info, nullptr);
+                    iter_offset, check_every, 0, 0, false, 0, 0, 0, nullptr, nullptr, 0, stream,
+                    info, nullptr);
 }
 
 int rka_solve_ex(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const double* b,
@@ -398,9 +434,10 @@ int rka_solve_ex(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, co
   const int sampling = opts ? opts->sampling : 0;
   const double* walpha = opts ? opts->worker_alpha : nullptr;
   const double* wrow = opts ? opts->row_weight : nullptr;
+  const int sstep = opts ? opts->steps_per_exchange : 0;
   return solve_impl(method == 1, A, dtype, m, n, lda, b, x0, x, q, method == 1 ? block_size : 1,
                     alpha, max_iter, tol, seed, x_ref, iter_offset, ce, grid, allreduce, timing,
-                    acc, dom, sampling, walpha, wrow, stream, info, stats);
+                    acc, dom, sampling, walpha, wrow, sstep, stream, info, stats);
 }
 
 int rkab_solve(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const double* b,
@@ -408,7 +445,8 @@ int rkab_solve(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, cons
                int64_t max_iter, double tol, uint64_t seed, const double* x_ref,
                int64_t iter_offset, int64_t check_every, void* stream, rka_info* info) {
   return solve_impl(true, A, dtype, m, n, lda, b, x0, x, q, block_size, alpha, max_iter, tol, seed,
-                    x_ref, iter_offset, check_every, 0, 0, false, 0, 0, 0, nullptr, nullptr, stream, info, nullptr);
+                    x_ref, iter_offset, check_every, 0, 0, false, 0, 0, 0, nullptr, nullptr, 0,
+                    stream, info, nullptr);
 }
 
 int rka_row_norms(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, double* w,
@@ -582,7 +620,7 @@ int rka_refine_solve(const void* A, const void* At, int dtype, int64_t m, int64_
       const int st = solve_impl(false, At, dtype, n, m, ldat, g, nullptr, y, o->range_q, 1,
                                 o->range_alpha, o->range_iters, 0.0, seed, nullptr,
                                 (int64_t)sw * o->range_iters, 1, 0, 0, false, o->accumulate, 1, 0,
-                                nullptr, nullptr, stream, &ii, nullptr);
+                                nullptr, nullptr, 0, stream, &ii, nullptr);
       if (st < 0) return st;
       projections += ii.projections;
       rhs = y;
@@ -603,8 +641,8 @@ int rka_refine_solve(const void* A, const void* At, int dtype, int64_t m, int64_
     const int st = solve_impl(o->method == 1, A, dtype, m, n, lda, rhs, nullptr, d, o->q,
                               o->method == 1 ? o->block_size : 1, o->alpha, o->inner_iters, tol_d,
                               seed, tol_d > 0.0 ? dref : nullptr, (int64_t)sw * o->inner_iters,
-                              kInnerCheck, 0, 0, false, o->accumulate, 0, 0, nullptr, nullptr, stream,
-                              &ii, nullptr);
+                              kInnerCheck, 0, 0, false, o->accumulate, 0, 0, nullptr, nullptr, 0,
+                              stream, &ii, nullptr);
     if (st < 0) return st;
     projections += ii.projections;
     HIP_TRY(rka::launch_axpy(x, d, n, s));

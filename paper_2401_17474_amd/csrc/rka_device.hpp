@@ -139,12 +139,85 @@ __device__ __forceinline__ U wave_sum(U v) {
   return v;
 }
 
-// Sum over aligned teams of tr lanes (tr a power of two <= 64): every lane of
-// a team receives its team's sum.  All lanes of the wave must take part.
+// Lane exchanges for team reductions.  Within a row of 16 lanes the data
+// moves through DPP (a VALU operand modifier, no LDS round trip): quad
+// permutes [1,0,3,2] and [2,3,0,1], then the half-row and row mirrors
+// (lane i <-> 7 - i within 8, i <-> 15 - i within 16).  Across rows:
+// ds_swizzle (xor 16 within 32 lanes) and a full-wave permute (xor 32).
+constexpr int kDppQuadXor1 = 0xB1;
+constexpr int kDppQuadXor2 = 0x4E;
+constexpr int kDppRowHalfMirror = 0x141;
+constexpr int kDppRowMirror = 0x140;
+constexpr int kSwizzleXor16 = 0x1F | (0x10 << 10);
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint64_t lo = dpp_u32<CTRL>((uint32_t)b), hi = dpp_u32<CTRL>((uint32_t)(b >> 32));
+  return __builtin_bit_cast(double, (hi << 32) | lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __builtin_bit_cast(float, dpp_u32<CTRL>(__builtin_bit_cast(uint32_t, v)));
+}
+__device__ __forceinline__ double swizzle_xor16(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint64_t lo = (uint32_t)__builtin_amdgcn_ds_swizzle((int)(uint32_t)b, kSwizzleXor16);
+  const uint64_t hi = (uint32_t)__builtin_amdgcn_ds_swizzle((int)(uint32_t)(b >> 32), kSwizzleXor16);
+  return __builtin_bit_cast(double, (hi << 32) | lo);
+}
+__device__ __forceinline__ float swizzle_xor16(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), kSwizzleXor16));
+}
+
+// Sum over aligned teams of tr lanes (tr a power of two <= 64, uniform over
+// the wave): every lane of a team receives its team's sum, and the order of
+// the additions is fixed (a + b == b + a exactly, so partners agree).  All
+// lanes of the wave must take part.
 template <typename U>
 __device__ __forceinline__ U team_sum(U v, int tr) {
-  for (int off = tr / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  if (tr >= 2) v += dpp_move<kDppQuadXor1>(v);
+  if (tr >= 4) v += dpp_move<kDppQuadXor2>(v);
+  if (tr >= 8) v += dpp_move<kDppRowHalfMirror>(v);
+  if (tr >= 16) v += dpp_move<kDppRowMirror>(v);
+  if (tr >= 32) v += swizzle_xor16(v);
+  if (tr >= 64) v += __shfl_xor(v, 32, kWave);
   return v;
+}
+
+// team_sum of N independent values, step by step (the N exchanges of a step
+// are in flight together).
+template <typename U, int N>
+__device__ __forceinline__ void team_sum_n(U (&v)[N], int tr) {
+  if (tr >= 2) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += dpp_move<kDppQuadXor1>(v[i]);
+  }
+  if (tr >= 4) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += dpp_move<kDppQuadXor2>(v[i]);
+  }
+  if (tr >= 8) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += dpp_move<kDppRowHalfMirror>(v[i]);
+  }
+  if (tr >= 16) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += dpp_move<kDppRowMirror>(v[i]);
+  }
+  if (tr >= 32) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += swizzle_xor16(v[i]);
+  }
+  if (tr >= 64) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], 32, kWave);
+  }
 }
 
 // Sum over the block; every thread receives the same value.  `scratch` holds
@@ -180,6 +253,7 @@ __device__ __forceinline__ void store_agent(U* p, U v) {
 // Unlike atomic loads they are ordinary loads to the compiler, so many can be
 // in flight at once.  Out-of-range offsets read 0 / drop the write.
 typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 constexpr int kCoherentSC1 = 1 << 4;       // buffer cache policy: device scope
 constexpr int kRawBufferWord3 = 0x00020000;  // gfx9 raw-buffer descriptor word 3
 
@@ -240,6 +314,19 @@ struct TagSlots {
                                                                           kCoherentSC1));
     hi = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(r, (int)(i * 16 + 8), 0,
                                                                           kCoherentSC1));
+  }
+  // The same slot written or read with one 16-byte access.  Each word still
+  // carries its own tag, so an access that lands in two halves is harmless:
+  // the reader simply sees one half early and polls again.
+  __device__ __forceinline__ void put16(int64_t i, double v, uint32_t tag) const {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const u32x4_t w = {(uint32_t)(b & 0xffffffffull), tag, (uint32_t)(b >> 32), tag};
+    __builtin_amdgcn_raw_buffer_store_b128(w, r, (int)(i * 16), 0, kCoherentSC1);
+  }
+  __device__ __forceinline__ void fetch16(int64_t i, uint64_t& lo, uint64_t& hi) const {
+    const u32x4_t w = __builtin_amdgcn_raw_buffer_load_b128(r, (int)(i * 16), 0, kCoherentSC1);
+    lo = ((uint64_t)w[1] << 32) | w[0];
+    hi = ((uint64_t)w[3] << 32) | w[2];
   }
   static __device__ __forceinline__ bool decode(uint64_t lo, uint64_t hi, uint32_t tag, double& v) {
     if ((uint32_t)(lo >> 32) != tag || (uint32_t)(hi >> 32) != tag) return false;

@@ -77,6 +77,24 @@ hipError_t launch_rka_chunk(const SolveShape& sh, const RkaColGeom& geo, const R
                             int64_t k0, int64_t K, int64_t check_every, uint64_t* part,
                             uint64_t* scal, DevStatus* st, hipStream_t s);
 
+// Geometry of the RKA kernel with several iterations per exchange
+// (rka_sstep.hip): column slices as in the column-split kernel.
+struct RkaSstepGeom {
+  int G, nsv, rg, nt, rpt;
+  int p;       // iterations per exchange (at most)
+  int nv;      // exchange values of a full block
+  int tr, trp, trs, cg;  // reduction teams (see the kernel's arguments)
+  int pg_in_s;           // reduce-scatter gathers into the row-slice buffer
+  size_t lds;
+};
+// p_req = 0: the largest p the tile allows.  False when the shape does not
+// fit (the caller then runs the one-iteration kernel).  FP64 arithmetic only.
+bool rka_sstep_plan(const SolveShape& sh, int p_req, RkaSstepGeom* geo);
+// part: G x nv tagged slots, red: nv tagged slots, both zeroed once per solve.
+hipError_t launch_sstep_chunk(const SolveShape& sh, const RkaSstepGeom& geo, const RowRec* rec,
+                              int64_t k0, int64_t K, int64_t check_every, uint64_t* part,
+                              uint64_t* red, DevStatus* st, hipStream_t s);
+
 struct RkabGeom {
   int G;       // workgroups (each runs workers g, g + G, ...)
   int nt;      // threads per workgroup

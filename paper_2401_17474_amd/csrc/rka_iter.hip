@@ -393,13 +393,17 @@ static int rpt_bucket(int need) {
   return 0;
 }
 
-// Column slices: one workgroup per CU by default.  Measured on MI355X at
-// 80000 x 10000 and x 20000, FP64, FP32 and BF16 storage, the widest grid is
-// fastest or within a few percent for every q (16, 64, 256), even where a
-// BF16 slice is only 80 bytes of a row: the per-iteration critical path is
-// the in-workgroup reductions (which shrink with the slice) and the exchange
-// latency, not the HBM fetch granularity or the number of participants.  Tiny problems (<= 64 KB of rows per iteration, one slice
-// that fits a workgroup) run in one workgroup with no exchange at all.
+// Column slices: one workgroup per CU by default, except for small q.
+// Measured on MI355X at 80000 x 10000 FP64 (team reductions in place): q = 64
+// and 256 are fastest on the widest grid (the exchange latency and the
+// in-workgroup work per iteration, not the HBM fetch granularity, set the
+// time); at q = 16 and below 48 workgroups take 5.5 us per iteration against
+// 7.0 us on 250, since the rows of one iteration are few and the exchange
+// with fewer participants is shorter.  Tiny problems (<= 64 KB of rows per
+// iteration, one slice that fits a workgroup) run in one workgroup with no
+// exchange at all.
+constexpr int kSmallQ = 16;
+constexpr int kSmallQGrid = 48;
 constexpr int64_t kOneGroupBytes = 64 << 10;
 // one-barrier all-gather while every workgroup reads at most this many partials
 constexpr int kGatherMax = 2048;
@@ -411,6 +415,7 @@ bool rka_col_plan(const SolveShape& sh, RkaColGeom* geo) {
   const int64_t bytes_per_iter = (int64_t)sh.q * sh.n * esz;
   int G, nsv;
   int target = sh.grid > 0 ? sh.grid : sh.num_cu;
+  if (sh.grid == 0 && sh.q <= kSmallQ) target = std::min(sh.num_cu, kSmallQGrid);
   if (sh.grid == 0 && bytes_per_iter <= kOneGroupBytes) target = 1;
   if (target == 1 && nvec <= kMaxColThreads) {
     G = 1;

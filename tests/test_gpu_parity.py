@@ -171,7 +171,7 @@ def test_rka_allreduce_modes_and_grids(q, grid, allreduce):
     say(f"rka modes q={q} grid={grid} allreduce={allreduce}")
     A, _, b = _system(2500, 1200, seed=q + grid)
     x, info, st = rka.solve_ex(to_dev(A), vec(b), method=0, q=q, max_iter=30, seed=9,
-                               grid=grid, allreduce=allreduce)
+                               grid=grid, allreduce=allreduce, steps_per_exchange=1)
     xo, _ = oracle.rka(A, b, q=q, max_iter=30, seed=9)
     assert info.status == rka.OK and st["kernel"] == 1
     if grid:
