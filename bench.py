@@ -431,21 +431,25 @@ def bench_differentiation(rka):
 def pmc_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE
     counter runs (profiles/pmc_traffic.json, scaled by a copy of known size),
-    or None when they were taken on another kernel or on other kernel sources."""
+    or None when the counters were not taken on this kernel or were taken on
+    other kernel sources."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     try:
         with open(path) as f:
             d = json.load(f)
-        h = hashlib.sha256()
-        for p in d["sources"]:
-            with open(os.path.join(ROOT, p), "rb") as f:
-                h.update(f.read())
-    except (OSError, KeyError, ValueError):
+        for e in d["entries"]:
+            if e.get("kernel") != kernel:
+                continue
+            h = hashlib.sha256()
+            for p in e["sources"]:
+                with open(os.path.join(ROOT, p), "rb") as f:
+                    h.update(f.read())
+            if h.hexdigest() == e.get("sources_sha256"):
+                return e["traffic_bytes_per_launch"]
+    except (OSError, KeyError, ValueError, TypeError):
         return None
-    if d.get("kernel") != kernel or h.hexdigest() != d.get("sources_sha256"):
-        return None
-    return d["traffic_bytes_per_launch"]
+    return None
 
 
 def bench_distributed(rka, workloads):
