@@ -38,7 +38,8 @@ class _Opts(ctypes.Structure):
                 ("collect_timing", ctypes.c_int32), ("allreduce", ctypes.c_int32),
                 ("accumulate", ctypes.c_int32), ("stream_id", ctypes.c_int32),
                 ("sampling", ctypes.c_int32), ("worker_alpha", ctypes.c_void_p),
-                ("row_weight", ctypes.c_void_p), ("steps_per_exchange", ctypes.c_int32)]
+                ("row_weight", ctypes.c_void_p), ("steps_per_exchange", ctypes.c_int32),
+                ("rkab_split", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -253,7 +254,7 @@ def rkab_solve(A, b, *, q, block_size, alpha=1.0, max_iter=1000, tol=0.0, seed=1
 def solve_ex(A, b, *, method, q, block_size=1, alpha=1.0, max_iter=1000, tol=0.0, seed=1,
              x0=None, x_ref=None, iter_offset=0, check_every=1, grid=0, allreduce=0,
              timing=False, accumulate=0, stream_id=0, sampling=0, worker_alpha=None,
-             row_weight=None, steps_per_exchange=0, out=None, stream=None,
+             row_weight=None, steps_per_exchange=0, rkab_split=0, out=None, stream=None,
              raise_on_error=True):
     """rka_solve_ex: method 0 = RKA, 1 = RKAB.  Returns (x, Info, stats dict);
     with ``timing`` the stats hold per-phase HIP-event times (ms) measured on
@@ -264,7 +265,8 @@ def solve_ex(A, b, *, method, q, block_size=1, alpha=1.0, max_iter=1000, tol=0.0
     ``worker_alpha`` is a float64 GPU vector of per-worker weights and
     ``row_weight`` one of per-row weights w_i (Eq. (7)); ``steps_per_exchange``
     (RKA) runs blocks of up to that many iterations per exchange between
-    workgroups (0: the library's choice, 1: one)."""
+    workgroups (0: the library's choice, 1: one); ``rkab_split`` (RKAB) picks
+    the worker-split (1) or column-split (2) kernel (0: the library's choice)."""
     torch = _torch()
     code, m, n, lda = _matrix(A)
     b = _vec(b, m, "b", False)
@@ -277,7 +279,8 @@ def solve_ex(A, b, *, method, q, block_size=1, alpha=1.0, max_iter=1000, tol=0.0
         _vec(row_weight, m, "row_weight", False)
     opts = _Opts(check_every, grid, 1 if timing else 0, allreduce, accumulate, stream_id,
                  sampling, None if worker_alpha is None else worker_alpha.data_ptr(),
-                 None if row_weight is None else row_weight.data_ptr(), steps_per_exchange)
+                 None if row_weight is None else row_weight.data_ptr(), steps_per_exchange,
+                 rkab_split)
     st = lib().rka_solve_ex(_ptr(A), code, m, n, lda, _ptr(b), _ptr(_vec(x0, n, "x0")), _ptr(x),
                             method, q, block_size, alpha, max_iter, tol, seed,
                             _ptr(_vec(x_ref, n, "x_ref")), iter_offset, ctypes.byref(opts),

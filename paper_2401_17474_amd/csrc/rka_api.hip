@@ -160,13 +160,20 @@ constexpr int64_t kRecBudget = 4ll << 20;
 // kernel: 5.5 us at its best grid) and 2.7 us at q = 8 (5.2 us); at q = 32
 // the block's exchange outweighs the saved round trips.
 constexpr int kAutoSstepMaxQ = 16;
+// RKAB with at most a quarter as many workers as CUs runs column-split
+// (every workgroup holds a slice of every worker's rows) when the q bs rows
+// of an outer iteration fit the block kernel's tile.  Measured at
+// 80000 x 10000 FP64, us per outer iteration, worker-split -> column-split:
+// q = 16, bs = 10: 54 -> 22; q = 8, bs = 10: 37 -> 18; q = 32, bs = 4:
+// 24 -> 16; q = 64, bs = 2: 29 -> 15; q = 4, bs = 32: 94 -> 35.
+constexpr int64_t kAutoSplitMaxRows = 256;
 
 int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
                const double* b, const double* x0, double* x, int32_t q, int32_t bs, double alpha,
                int64_t max_iter, double tol, uint64_t seed, const double* x_ref,
                int64_t iter_offset, int64_t check_every, int grid, int allreduce, bool timing,
                int acc, int dom, int sampling, const double* walpha, const double* wrow,
-               int sstep, void* stream, rka_info* info, rka_stats* stats) {
+               int sstep, int split, void* stream, rka_info* info, rka_stats* stats) {
   g_last_error.clear();
   if (stats) memset(stats, 0, sizeof *stats);
   if (info) {
@@ -189,6 +196,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
     return fail(RKA_EINVAL, "sampling must be 0, 1 or 2");
   if (walpha && wrow) return fail(RKA_EINVAL, "give worker_alpha or row_weight, not both");
   if (sstep < 0 || sstep > 64) return fail(RKA_EINVAL, "steps_per_exchange must be in [0, 64]");
+  if (split < 0 || split > 2) return fail(RKA_EINVAL, "rkab_split must be 0, 1 or 2");
   if (sampling == rka::kSampleBlocks && q > m)
     return fail(RKA_EINVAL, "the Distributed Approach needs q <= m (one row block per worker)");
   const int ncu = num_cus();
@@ -220,7 +228,12 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   // several iterations per exchange: asked for (sstep >= 2), or chosen for
   // small q when blocks can be longer than one iteration between tests
   bool use_sstep = false;
-  if (!block && acc == 0 && allreduce == 0) {
+  if (block && acc == 0 && split != 1) {
+    // RKAB with every workgroup holding a slice of every worker's rows: asked
+    // for, or chosen when the workers alone would leave most CUs idle
+    if (split == 2 || (q * 4 <= ncu && (int64_t)q * bs <= kAutoSplitMaxRows))
+      use_sstep = rka::rka_sstep_plan(sh, 1, &sgeo);
+  } else if (!block && acc == 0 && allreduce == 0) {
     if (sstep >= 2) {
       use_sstep = rka::rka_sstep_plan(sh, sstep, &sgeo);
     } else if (sstep == 0 && q <= kAutoSstepMaxQ && in_kernel_check != 1) {
@@ -411,7 +424,7 @@ int rka_solve(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const
               uint64_t seed, const double* x_ref, int64_t iter_offset, int64_t check_every,
               void* stream, rka_info* info) {
   return solve_impl(false, A, dtype, m, n, lda, b, x0, x, q, 1, alpha, max_iter, tol, seed, x_ref,
-                    iter_offset, check_every, 0, 0, false, 0, 0, 0, nullptr, nullptr, 0, stream,
+                    iter_offset, check_every, 0, 0, false, 0, 0, 0, nullptr, nullptr, 0, 0, stream,
                     info, nullptr);
 }
 
@@ -435,9 +448,10 @@ int rka_solve_ex(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, co
   const double* walpha = opts ? opts->worker_alpha : nullptr;
   const double* wrow = opts ? opts->row_weight : nullptr;
   const int sstep = opts ? opts->steps_per_exchange : 0;
+  const int split = opts ? opts->rkab_split : 0;
   return solve_impl(method == 1, A, dtype, m, n, lda, b, x0, x, q, method == 1 ? block_size : 1,
                     alpha, max_iter, tol, seed, x_ref, iter_offset, ce, grid, allreduce, timing,
-                    acc, dom, sampling, walpha, wrow, sstep, stream, info, stats);
+                    acc, dom, sampling, walpha, wrow, sstep, split, stream, info, stats);
 }
 
 int rkab_solve(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const double* b,
@@ -445,7 +459,7 @@ int rkab_solve(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, cons
                int64_t max_iter, double tol, uint64_t seed, const double* x_ref,
                int64_t iter_offset, int64_t check_every, void* stream, rka_info* info) {
   return solve_impl(true, A, dtype, m, n, lda, b, x0, x, q, block_size, alpha, max_iter, tol, seed,
-                    x_ref, iter_offset, check_every, 0, 0, false, 0, 0, 0, nullptr, nullptr, 0,
+                    x_ref, iter_offset, check_every, 0, 0, false, 0, 0, 0, nullptr, nullptr, 0, 0,
                     stream, info, nullptr);
 }
 
@@ -620,7 +634,7 @@ int rka_refine_solve(const void* A, const void* At, int dtype, int64_t m, int64_
       const int st = solve_impl(false, At, dtype, n, m, ldat, g, nullptr, y, o->range_q, 1,
                                 o->range_alpha, o->range_iters, 0.0, seed, nullptr,
                                 (int64_t)sw * o->range_iters, 1, 0, 0, false, o->accumulate, 1, 0,
-                                nullptr, nullptr, 0, stream, &ii, nullptr);
+                                nullptr, nullptr, 0, 0, stream, &ii, nullptr);
       if (st < 0) return st;
       projections += ii.projections;
       rhs = y;
@@ -642,7 +656,7 @@ int rka_refine_solve(const void* A, const void* At, int dtype, int64_t m, int64_
                               o->method == 1 ? o->block_size : 1, o->alpha, o->inner_iters, tol_d,
                               seed, tol_d > 0.0 ? dref : nullptr, (int64_t)sw * o->inner_iters,
                               kInnerCheck, 0, 0, false, o->accumulate, 0, 0, nullptr, nullptr, 0,
-                              stream, &ii, nullptr);
+                              0, stream, &ii, nullptr);
     if (st < 0) return st;
     projections += ii.projections;
     HIP_TRY(rka::launch_axpy(x, d, n, s));

@@ -81,14 +81,17 @@ hipError_t launch_rka_chunk(const SolveShape& sh, const RkaColGeom& geo, const R
 // (rka_sstep.hip): column slices as in the column-split kernel.
 struct RkaSstepGeom {
   int G, nsv, rg, nt, rpt;
-  int p;       // iterations per exchange (at most)
+  int p;       // iterations per exchange (at most; 1 for RKAB)
+  int bs;      // projections per worker per iteration (1: RKA)
   int nv;      // exchange values of a full block
   int tr, trp, trs, cg;  // reduction teams (see the kernel's arguments)
   int pg_in_s;           // reduce-scatter gathers into the row-slice buffer
   size_t lds;
 };
-// p_req = 0: the largest p the tile allows.  False when the shape does not
-// fit (the caller then runs the one-iteration kernel).  FP64 arithmetic only.
+// RKA (sh.bs = 1): p_req = 0 gives the largest p the tile allows.  RKAB
+// (sh.bs > 1): one outer iteration per exchange (p_req 0 or 1).  False when
+// the shape does not fit (the caller then runs the column-split or the
+// worker-split kernel).  FP64 arithmetic only.
 bool rka_sstep_plan(const SolveShape& sh, int p_req, RkaSstepGeom* geo);
 // part: G x nv tagged slots, red: nv tagged slots, both zeroed once per solve.
 hipError_t launch_sstep_chunk(const SolveShape& sh, const RkaSstepGeom& geo, const RowRec* rec,

@@ -61,6 +61,7 @@ struct SstepArgs {
   const double* x_ref;
   double inv_q;
   int32_t q, p;       // workers, iterations per exchange (at most)
+  int32_t bs;         // projections per worker per iteration (1: RKA; > 1: RKAB, p = 1)
   int32_t nsv, rg, G;
   int32_t nv_max;     // exchange values of a full block
   int32_t tr;         // lanes per row for the slice sums of the dot products
@@ -74,13 +75,14 @@ struct SstepArgs {
   DevStatus* st;
 };
 
-constexpr int kSMaxRows = 64;      // q * p
+constexpr int kSMaxRows = 64;      // q * p (RKA)
+constexpr int kSMaxRowsB = 256;    // q * bs (RKAB)
 constexpr int kSMaxP = 8;
 constexpr int kSPoll = 8;          // slots one lane polls in either phase
 constexpr int kSThreads = 512;
 constexpr size_t kSMaxLds = 150 * 1024;  // of the 160 KiB of a CU
 
-// Exchange values of a block of L iterations: [0, L q) the dot products
+// Exchange values of an RKA block of L iterations: [0, L q) the dot products
 // <a_{j,r}, x^(k)> at j q + r; then for every pair l < j (pair index
 // j (j-1) / 2 + l) a q x q tile of <a_{j,r}, a_{l,s}> at r q + s; last, the
 // squared error of x^(k) against x_ref (0 when the block has no test).
@@ -90,6 +92,15 @@ __device__ __forceinline__ int sv_count(int L, int q) {
 __device__ __forceinline__ int sv_gram(int L, int q, int j, int l) {
   return L * q + (j * (j - 1) / 2 + l) * q * q;
 }
+// RKAB (one outer iteration per exchange, Sec. 3.4.1): worker w projects its
+// rows w bs .. w bs + bs - 1 in order on its own copy of x, so row jb of a
+// worker needs <a_{w,jb}, a_{w,jb'}> for jb' < jb only.  Values: [0, q bs)
+// the dot products with x^(k); then worker w's pairs at
+// q bs + w bs (bs-1) / 2 + jb (jb-1) / 2 + jb'; last, the squared error.
+__device__ __forceinline__ int svb_count(int q, int bs) { return q * bs + q * (bs * (bs - 1) / 2) + 1; }
+__device__ __forceinline__ int svb_pair(int q, int bs, int w, int jb, int jb2) {
+  return q * bs + w * (bs * (bs - 1) / 2) + jb * (jb - 1) / 2 + jb2;
+}
 
 template <typename T, int V, int RPT>
 __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
@@ -98,8 +109,9 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
   const T* __restrict__ A = (const T*)p.A;
   const int t = threadIdx.x, g = blockIdx.x, NT = blockDim.x;
   const int q = p.q, nsv = p.nsv, rg = p.rg, G = p.G;
+  const int bs = p.bs, Q = q * bs;  // rows of one (outer) iteration
   const int W = nsv * V;          // slice width in elements
-  const int Rmax = p.p * q;
+  const int Rmax = p.p * Q;
   const bool active = t < nsv * rg;
   const int j = active ? t % nsv : 0;
   const int rgi = active ? t / nsv : rg;
@@ -148,11 +160,11 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
   };
   // row indices of the block at kl (rows clamped to the block: masked later)
   auto load_rows = [&](int64_t kl, int L, int* rows) {
-    const int R = L * q;
+    const int R = L * Q;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int br = rgi + rg * i;
-      rows[i] = (int)p.rec[kl * q + (br < R ? br : R - 1)].row;
+      rows[i] = (int)p.rec[kl * Q + (br < R ? br : R - 1)].row;
     }
   };
 
@@ -166,7 +178,7 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
     load_rows(0, L, rows0);
 #pragma unroll
     for (int i = 0; i < RPT; ++i) a[i] = load_raw<T, V>(A + (int64_t)rows0[i] * p.lda + cvl * V);
-    if (t < L * q) {
+    if (t < L * Q) {
       const RowRec r = p.rec[t];
       mb = r.b;
       mw = r.wn;
@@ -181,8 +193,8 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
   SPROF_DECL
   while (kl < p.K) {
     const int64_t k = p.k0 + kl;
-    const int R = L * q;
-    const int nv = sv_count(L, q);
+    const int R = L * Q;
+    const int nv = bs > 1 ? svb_count(q, bs) : sv_count(L, q);
     const bool check = p.check_every > 0 && k > 0 && (k % p.check_every) == 0;
     const uint32_t tag = (uint32_t)(k + 1);
     const TagSlots part(p.part, (int64_t)G * p.nv_max);
@@ -233,7 +245,7 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
     }
     // (2) inner products between rows of different iterations: 4 x 4 tiles,
     // cg lanes per tile over consecutive column ranges, folded in lane order
-    {
+    if (bs == 1) {
       const int q4 = (q + 3) / 4;
       const int ntile = (L * (L - 1) / 2) * q4 * q4;
       const int CG = p.cg, per = NT / CG;
@@ -295,6 +307,66 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
               if (rb + u1 < q && sb + u2 < q) HV[base + (rb + u1) * q + sb + u2] = acc[4 * u1 + u2];
         }
       }
+    } else {
+      // RKAB: the pairs within each worker's rows, 4 x 4 tiles (ta, tb), tb <= ta
+      const int b4 = (bs + 3) / 4, tpw = b4 * (b4 + 1) / 2;
+      const int ntile = q * tpw;
+      const int CG = p.cg, per = NT / CG;
+      const int cu = t & (CG - 1);
+      const int c0 = cu * W / CG, c1 = (cu + 1) * W / CG;
+      for (int tb0 = 0; tb0 < ntile; tb0 += per) {
+        const int tile = tb0 + t / CG;
+        const bool tin = tile < ntile;
+        int w = 0, ta = 0, tb = 0;
+        if (tin) {
+          w = tile / tpw;
+          int rem = tile - w * tpw;
+          while (rem >= ta + 1) {
+            rem -= ta + 1;
+            ++ta;
+          }
+          tb = rem;
+        }
+        double acc[16];  // acc[4 u1 + u2] = <row 4 ta + u1, row 4 tb + u2> of worker w
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+        if (tin) {
+          const double* Sa = S + w * bs + 4 * ta;
+          const double* Sb = S + w * bs + 4 * tb;
+#pragma unroll 2
+          for (int c = c0; c < c1; ++c) {
+            double va[4], vb[4];
+            if (bs % 2 == 0) {  // 16-byte aligned pairs
+              const double2 a01 = *(const double2*)(Sa + (size_t)c * RS);
+              const double2 a23 = *(const double2*)(Sa + (size_t)c * RS + 2);
+              const double2 b01 = *(const double2*)(Sb + (size_t)c * RS);
+              const double2 b23 = *(const double2*)(Sb + (size_t)c * RS + 2);
+              va[0] = a01.x, va[1] = a01.y, va[2] = a23.x, va[3] = a23.y;
+              vb[0] = b01.x, vb[1] = b01.y, vb[2] = b23.x, vb[3] = b23.y;
+            } else {
+#pragma unroll
+              for (int u1 = 0; u1 < 4; ++u1) {
+                va[u1] = Sa[(size_t)c * RS + u1];
+                vb[u1] = Sb[(size_t)c * RS + u1];
+              }
+            }
+#pragma unroll
+            for (int u1 = 0; u1 < 4; ++u1)
+#pragma unroll
+              for (int u2 = 0; u2 < 4; ++u2) acc[4 * u1 + u2] = fma(va[u1], vb[u2], acc[4 * u1 + u2]);
+          }
+        }
+        team_sum_n(acc, CG);
+        if (tin && cu == 0) {
+#pragma unroll
+          for (int u1 = 0; u1 < 4; ++u1)
+#pragma unroll
+            for (int u2 = 0; u2 < 4; ++u2) {
+              const int jb = 4 * ta + u1, jb2 = 4 * tb + u2;
+              if (jb < bs && jb2 < jb) HV[svb_pair(q, bs, w, jb, jb2)] = acc[4 * u1 + u2];
+            }
+        }
+      }
     }
     // (3) the error partial of this slice (0 without a test)
     if (t < kWave) {
@@ -312,8 +384,8 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
     const int Ln = kn < p.K ? block_len(kn) : L;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) an[i] = load_raw<T, V>(A + (int64_t)rows_n[i] * p.lda + cvl * V);
-    if (kn < p.K && t < Ln * q) {
-      const RowRec r = p.rec[kn * q + t];
+    if (kn < p.K && t < Ln * Q) {
+      const RowRec r = p.rec[kn * Q + t];
       mb = r.b;
       mw = r.wn;
       ma = r.alpha;
@@ -428,7 +500,9 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
     }
     // the scales, one iteration of the block after the other:
     // D_{j,r} = <a_{j,r}, x^(k)> + (1/q) sum_{l<j} sum_s s_{l,s} <a_{j,r}, a_{l,s}>
-    {
+    // (RKAB: one worker's projections after the other, weight 1:
+    //  D_{w,jb} = <a_{w,jb}, x^(k)> + sum_{jb'<jb} s_{w,jb'} <a_{w,jb}, a_{w,jb'}>)
+    if (bs == 1) {
       const int TR = p.trs, team = t / TR, u = t & (TR - 1), nteams = NT / TR;
       for (int jj = 0; jj < L; ++jj) {
         for (int r0 = 0; r0 < q; r0 += nteams) {
@@ -445,6 +519,24 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
           if (u == 0 && r < q) {
             const int br = jj * q + r;
             const double D = HV[br] + p.inv_q * acc;
+            SC[br] = RA[br] * (RB[br] - D) / RW[br];
+          }
+        }
+        __syncthreads();
+      }
+    } else {
+      const int TR = p.trs, team = t / TR, u = t & (TR - 1), nteams = NT / TR;
+      for (int jb = 0; jb < bs; ++jb) {
+        for (int w0 = 0; w0 < q; w0 += nteams) {
+          const int w = w0 + team;
+          double acc = 0.0;
+          if (w < q)
+            for (int f = u; f < jb; f += TR)
+              acc = fma(SC[w * bs + f], HV[svb_pair(q, bs, w, jb, f)], acc);
+          acc = team_sum(acc, TR);
+          if (u == 0 && w < q) {
+            const int br = w * bs + jb;
+            const double D = HV[br] + acc;
             SC[br] = RA[br] * (RB[br] - D) / RW[br];
           }
         }
@@ -544,10 +636,17 @@ static bool sstep_plan_at(const SolveShape& sh, int p_req, RkaSstepGeom* geo) {
   const int esz = sh.dtype == 0 ? 8 : (sh.dtype == 1 ? 4 : 2);
   const int V = sh.vec_ok ? 16 / esz : 1;
   const int64_t nvec = sh.n / V;
-  int pmax = kSMaxRows / sh.q;
-  if (pmax > kSMaxP) pmax = kSMaxP;
-  const int pp = p_req > 0 ? p_req : pmax;
-  if (pp < 2 || pp > pmax) return false;
+  const int bs = sh.bs;
+  int pp;
+  if (bs > 1) {  // RKAB: one outer iteration (q bs rows) per exchange
+    if (p_req > 1 || (int64_t)sh.q * bs > kSMaxRowsB) return false;
+    pp = 1;
+  } else {
+    int pmax = kSMaxRows / sh.q;
+    if (pmax > kSMaxP) pmax = kSMaxP;
+    pp = p_req > 0 ? p_req : pmax;
+    if (pp < 2 || pp > pmax) return false;
+  }
   // half the CUs by default: a block's exchange is large enough that fewer,
   // wider slices win (measured at 80000 x 10000 FP64, q = 16 and 8)
   const int target = sh.grid > 0 ? sh.grid : std::max(2, sh.num_cu / 2);
@@ -555,7 +654,7 @@ static bool sstep_plan_at(const SolveShape& sh, int p_req, RkaSstepGeom* geo) {
   const int nsv = (int)((nvec + g0 - 1) / g0);
   const int G = (int)((nvec + nsv - 1) / nsv);
   if (nsv > kSThreads || G < 2) return false;
-  const int R = pp * sh.q;
+  const int R = pp * sh.q * bs;
   int rg = kSThreads / nsv;
   if (rg > R) rg = R;
   const int rpt = sstep_bucket((R + rg - 1) / rg);
@@ -563,7 +662,8 @@ static bool sstep_plan_at(const SolveShape& sh, int p_req, RkaSstepGeom* geo) {
   const int rpt_max = sh.dtype == 0 ? 8 : (sh.dtype == 1 ? 4 : 2);
   if (rpt == 0 || rpt > rpt_max) return false;
   const int W = nsv * V;
-  const int nv = pp * sh.q + sh.q * sh.q * (pp * (pp - 1) / 2) + 1;
+  const int nv = bs > 1 ? sh.q * bs + sh.q * (bs * (bs - 1) / 2) + 1
+                       : pp * sh.q + sh.q * sh.q * (pp * (pp - 1) / 2) + 1;
   // threads: the row tile, at least 256, more if the exchange needs them:
   // the reduce-scatter gathers G x C partials (C = ceil(nv / G) values per
   // workgroup) with at most kSPoll slots per lane, the all-gather nv sums
@@ -583,14 +683,16 @@ static bool sstep_plan_at(const SolveShape& sh, int p_req, RkaSstepGeom* geo) {
                                        (size_t)nt * V + W + std::max(nt, W) + nsv +
                                        (pg_in_s ? 0 : (size_t)gathered));
   if (lds > kSMaxLds) return false;
-  const int q4 = (sh.q + 3) / 4;
-  const int64_t ntile = (int64_t)(pp * (pp - 1) / 2) * q4 * q4;
+  const int q4 = (sh.q + 3) / 4, b4 = (bs + 3) / 4;
+  const int64_t ntile = bs > 1 ? (int64_t)sh.q * (b4 * (b4 + 1) / 2)
+                               : (int64_t)(pp * (pp - 1) / 2) * q4 * q4;
   geo->G = G;
   geo->nsv = nsv;
   geo->rg = rg;
   geo->nt = nt;
   geo->rpt = rpt;
   geo->p = pp;
+  geo->bs = bs;
   geo->nv = nv;
   geo->lds = lds;
   geo->tr = pow2_floor_cap(std::min<int64_t>(nt / R, nsv), kWave);
@@ -636,6 +738,7 @@ hipError_t launch_sstep_chunk(const SolveShape& sh, const RkaSstepGeom& geo, con
   a.inv_q = 1.0 / (double)sh.q;
   a.q = sh.q;
   a.p = geo.p;
+  a.bs = geo.bs;
   a.nsv = geo.nsv;
   a.rg = geo.rg;
   a.G = geo.G;

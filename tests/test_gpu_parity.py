@@ -162,6 +162,20 @@ def test_rkab_parity(m, n, dtype, q, bs, K, alpha):
     assert_x_close(host(x), xo, what=f"rkab {m}x{n} q={q} bs={bs}")
 
 
+@pytest.mark.parametrize("m,n,dtype,q,bs,K,alpha", RKAB_CASES)
+def test_rkab_worker_kernel_parity(m, n, dtype, q, bs, K, alpha):
+    """The worker-split kernel on the same cases (the library may pick the
+    column-split kernel for them by default)."""
+    say(f"rkab worker-split {dtype} {m}x{n} q={q} bs={bs} K={K}")
+    A, _, b = _system(m, n, dtype, seed=m + 2 * n)
+    x, info, st = rka.solve_ex(to_dev(A, dtype), vec(b), method=1, q=q, block_size=bs,
+                               alpha=alpha, max_iter=K, seed=5, rkab_split=1)
+    assert info.status == rka.OK and st["kernel"] == 2
+    xo, _ = oracle.rkab(A, b, q=q, block_size=bs, alpha=alpha, max_iter=K, seed=5,
+                        dtype="bf16" if dtype == "bf16" else None)
+    assert_x_close(host(x), xo, what=f"rkab worker-split {m}x{n} q={q} bs={bs}")
+
+
 @pytest.mark.parametrize("q,grid,allreduce", [
     (16, 8, 1), (16, 0, 2), (16, 7, 1), (16, 64, 2), (64, 24, 1), (64, 0, 2), (100, 16, 1),
     (200, 25, 2), (5, 2, 0),

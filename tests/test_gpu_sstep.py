@@ -100,3 +100,70 @@ def test_sstep_falls_back_when_the_block_does_not_fit():
     with pytest.raises(rka.RKAError) as e:
         rka.solve_ex(to_dev(A), vec(b), method=0, q=4, max_iter=3, steps_per_exchange=-1)
     assert e.value.status == rka.EINVAL
+
+
+# -- RKAB split over columns (one outer iteration per exchange) -----------------
+
+RKAB_CASES = [  # m, n, q, bs, K, dtype
+    (3000, 2000, 16, 10, 12, "f64"),
+    (2000, 1500, 8, 5, 20, "f64"),       # odd bs: unaligned tile reads
+    (1500, 777, 6, 7, 15, "f64"),        # scalar path (odd n)
+    (5000, 10000, 16, 10, 6, "f64"),     # 160 rows of 40-column slices: the 8-row tile
+    (2000, 3000, 12, 4, 10, "f32"),      # narrow storage, FP64 arithmetic
+    (2000, 3000, 12, 4, 10, "bf16"),
+]
+
+
+@pytest.mark.parametrize("m,n,q,bs,K,dtype", RKAB_CASES)
+def test_rkab_column_split_vs_oracle(m, n, q, bs, K, dtype):
+    say(f"rkab split {dtype} m={m} n={n} q={q} bs={bs} K={K}")
+    A, _, b = workloads.gaussian_system(m, n, seed=36, noise_var=1e-2, dtype=dtype)
+    A = np.array(A)
+    x, info, st = rka.solve_ex(to_dev(A, dtype), vec(b), method=1, q=q, block_size=bs,
+                               alpha=0.9, max_iter=K, seed=7, rkab_split=2)
+    assert info.status == rka.OK and info.iterations == K and info.projections == K * q * bs
+    assert st["kernel"] == 3 and st["variant"] == 1
+    odt = "bf16" if dtype == "bf16" else None
+    idx = oracle.indices(oracle.row_norms(A, dtype=odt), 7, 0, K, q, bs)
+    xo = oracle.rkab_given(A, b, np.zeros(n), idx, q=q, block_size=bs, alpha=0.9, dtype=odt)
+    assert_x_close(host(x), xo, 1e-12, "rkab split")
+
+
+def test_rkab_column_split_stops_where_the_worker_kernel_stops():
+    A, xs, b = workloads.gaussian_system(4000, 300, seed=37)
+    A = np.array(A)
+    kw = dict(method=1, q=8, block_size=6, max_iter=20000, tol=1e-8, x_ref=vec(xs),
+              check_every=5, seed=3)
+    x1, i1, s1 = rka.solve_ex(to_dev(A), vec(b), rkab_split=1, **kw)
+    x2, i2, s2 = rka.solve_ex(to_dev(A), vec(b), rkab_split=2, **kw)
+    assert s1["kernel"] == 2 and s2["kernel"] == 3
+    assert i1.status == rka.OK and i2.status == rka.OK
+    assert i2.iterations == i1.iterations and i2.iterations % 5 == 0
+    assert_x_close(host(x2), host(x1), 1e-12, "rkab split stop")
+
+
+def test_rkab_column_split_cyclic_and_row_weights():
+    A, _, b = workloads.paper_rows_system(1500, 900, seed=38)
+    wrow = np.random.default_rng(38).uniform(0.5, 1.5, size=1500)
+    K, q, bs = 12, 10, 6
+    x, info, st = rka.solve_ex(to_dev(A), vec(b), method=1, q=q, block_size=bs, max_iter=K,
+                               sampling=2, row_weight=vec(wrow), rkab_split=2)
+    assert st["kernel"] == 3
+    xo = oracle.rkab_wrow_given(A, b, np.zeros(900), oracle.indices_cyclic(1500, 0, K, q, bs),
+                                wrow, q=q, block_size=bs)
+    assert_x_close(host(x), xo, 1e-12, "rkab split cyclic")
+
+
+def test_rkab_column_split_falls_back_and_checks_arguments():
+    A, _, b = workloads.gaussian_system(2000, 500, seed=39)
+    A = np.array(A)
+    # q bs = 320 rows exceed the block tile: the worker-split kernel runs
+    x, info, st = rka.solve_ex(to_dev(A), vec(b), method=1, q=32, block_size=10, max_iter=4,
+                               seed=2, rkab_split=2)
+    assert st["kernel"] == 2
+    idx = oracle.indices(oracle.row_norms(A), 2, 0, 4, 32, 10)
+    assert_x_close(host(x), oracle.rkab_given(A, b, np.zeros(500), idx, q=32, block_size=10),
+                   1e-12, "rkab fallback")
+    with pytest.raises(rka.RKAError) as e:
+        rka.solve_ex(to_dev(A), vec(b), method=1, q=4, block_size=3, max_iter=3, rkab_split=3)
+    assert e.value.status == rka.EINVAL
