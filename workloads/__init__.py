@@ -61,13 +61,30 @@ def gaussian_system(m, n, *, seed=DATA_SEED, noise_var=0.0, dtype="f64", rng="nu
     return A, x, b
 
 
-def paper_rows_system(m, n, *, seed=DATA_SEED, dtype="f64", order="drawn"):
-    """Consistent system following the recipe of Sec. 3.1 (host only).
+def paper_rows_system(m, n, *, seed=DATA_SEED, dtype="f64", order="drawn", rng="numpy",
+                      device="cpu"):
+    """Consistent system following the recipe of Sec. 3.1.
 
     ``order="coherent"`` stores the same rows sorted by mu_i / sigma_i, so
     that neighbouring rows are nearly parallel (the situation in which
     Sec. 2.1 finds the cyclic order slow); the system and its solution are
-    unchanged, only the row order differs."""
+    unchanged, only the row order differs.  ``rng="torch"`` draws on
+    ``device`` (drawn order, FP64 only) for the multi-GB shapes."""
+    if rng == "torch":
+        import torch
+        if order != "drawn" or dtype != "f64":
+            raise ValueError("the torch generator supports the drawn order in FP64 only")
+        gen = torch.Generator(device=device)
+        gen.manual_seed(seed)
+        f64 = dict(device=device, dtype=torch.float64)
+        mu = torch.rand(m, generator=gen, **f64) * 10.0 - 5.0
+        sd = torch.rand(m, generator=gen, **f64) * 19.0 + 1.0
+        A = torch.randn((m, n), generator=gen, **f64)
+        A.mul_(sd[:, None]).add_(mu[:, None])
+        r = int(torch.randint(0, m, (1,), generator=gen, device=device).item())
+        x = mu[r] + sd[r] * torch.randn(n, generator=gen, **f64)
+        b = A @ x
+        return A, x, b
     g = _np_rng(seed)
     mu = g.uniform(-5.0, 5.0, size=m)
     sd = g.uniform(1.0, 20.0, size=m)
