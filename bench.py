@@ -84,16 +84,16 @@ def make_cells(spec, astar):
     return out
 
 
-def kernel_name(stats, storage="double", vec=2):
+def kernel_name(stats, storage="double", vec=2, rkab=False):
     """Template instance as named in the library: <storage, accumulation,
     elements per 16-byte vec, register bucket, all-gather / iterate in LDS>
-    (the block kernel: <storage, elements per vec, rows per thread>)."""
+    (the block kernel: <storage, elements per vec, rows per thread, RKAB>)."""
     acc = "float" if stats.get("accumulate") == 1 else "double"
     flag = "true" if stats.get("variant") == 1 else "false"
     if stats["kernel"] == 1:
         return f"rka_col_kernel<{storage}, {acc}, {vec}, {stats['bucket']}, {flag}>"
     if stats["kernel"] == 3:
-        return f"rka_sstep_kernel<{storage}, {vec}, {stats['bucket']}>"
+        return f"rka_sstep_kernel<{storage}, {vec}, {stats['bucket']}, {'true' if rkab else 'false'}>"
     return f"rkab_kernel<{storage}, {acc}, {vec}, {stats['bucket']}, {flag}>"
 
 
@@ -671,7 +671,7 @@ def main():
             pc["sample_ms"] += st["sample_ms"]
             pc["stats"] = st
             total_proj += info.projections
-            name = kernel_name(st)
+            name = kernel_name(st, rkab=c[0] == "rkab")
             kk = kern.setdefault(name, {"ms": 0.0, "launches": 0, "bytes": 0.0})
             kk["ms"] += st["iterate_ms"]
             kk["launches"] += st["iterate_launches"]
@@ -696,7 +696,7 @@ def main():
             "iterate_ms_per_solve": pc["iter_ms"] / args.steps,
             "setup_ms_per_solve": pc["setup_ms"] / args.steps,
             "sample_ms_per_solve": pc["sample_ms"] / args.steps,
-            "kernel": kernel_name(pc["stats"]), "grid": pc["stats"]["grid"],
+            "kernel": kernel_name(pc["stats"], rkab=meth == "rkab"), "grid": pc["stats"]["grid"],
             "threads": pc["stats"]["threads"],
             "rel_err_vs_x_ls": errs.get(i),
         })

@@ -163,13 +163,15 @@ typedef struct rka_opts {
                                at stopping tests, so check_every = 1 gives p = 1.     */
     int32_t rkab_split;     /* RKAB only: 0 = chosen by the library; 1 = worker-split
                                (one workgroup per worker, kernel 2); 2 = column-split
-                               (every workgroup holds a slice of every worker's rows;
-                               one exchange per outer iteration carries the q bs dot
-                               products with x^(k) and each worker's inner products
-                               between its rows, from which every workgroup forms the
-                               bs projections of each worker in order: the same
+                               (every workgroup holds a slice of every worker's rows
+                               and of every worker's iterate; an outer iteration runs
+                               as sub-blocks of c <= bs projections per worker, q c <=
+                               256, one exchange each carrying the rows' dot products
+                               with their worker's iterate and each worker's inner
+                               products between its rows, from which every workgroup
+                               forms each worker's projections in order: the same
                                iteration in exact arithmetic, kernel 3).  2 needs FP64
-                               arithmetic and q bs <= 256, else kernel 2 runs.        */
+                               arithmetic and q <= 256, else kernel 2 runs.          */
 } rka_opts;
 
 /* Launch facts and phase times of one rka_solve_ex call. */
@@ -188,7 +190,8 @@ typedef struct rka_stats {
                                  thread (kernel 1) or 16-byte vecs per thread (kernel 2) */
     int32_t variant;          /* kernel 1: 1 = one-barrier all-gather of the partials;
                                  kernel 2: 1 = worker iterate kept in LDS;
-                                 kernel 3: iterations per exchange (p; 1 for RKAB)      */
+                                 kernel 3: RKA iterations per exchange (p), or RKAB
+                                 projections per worker per exchange (c)          */
     int32_t accumulate;       /* accumulation type used: 0 = FP64, 1 = FP32             */
 } rka_stats;
 

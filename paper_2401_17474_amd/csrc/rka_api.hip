@@ -162,11 +162,12 @@ constexpr int64_t kRecBudget = 4ll << 20;
 constexpr int kAutoSstepMaxQ = 16;
 // RKAB with at most a quarter as many workers as CUs runs column-split
 // (every workgroup holds a slice of every worker's rows) when the q bs rows
-// of an outer iteration fit the block kernel's tile.  Measured at
-// 80000 x 10000 FP64, us per outer iteration, worker-split -> column-split:
-// q = 16, bs = 10: 54 -> 22; q = 8, bs = 10: 37 -> 18; q = 32, bs = 4:
-// 24 -> 16; q = 64, bs = 2: 29 -> 15; q = 4, bs = 32: 94 -> 35.
-constexpr int64_t kAutoSplitMaxRows = 256;
+// of an outer iteration fit one exchange of the block kernel, or in
+// sub-blocks when q is at most kAutoSubBlockMaxQ.  Measured at 80000 x 10000
+// FP64, us per outer iteration, worker-split -> column-split: q = 16,
+// bs = 10: 54 -> 22; q = 8, bs = 10: 37 -> 18; q = 32, bs = 4: 24 -> 16;
+// q = 64, bs = 2: 29 -> 15; q = 4, bs = 32: 94 -> 35.
+constexpr int kAutoSubBlockMaxQ = 16;
 
 int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
                const double* b, const double* x0, double* x, int32_t q, int32_t bs, double alpha,
@@ -228,11 +229,16 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   // several iterations per exchange: asked for (sstep >= 2), or chosen for
   // small q when blocks can be longer than one iteration between tests
   bool use_sstep = false;
-  if (block && acc == 0 && split != 1) {
+  if (block && acc == 0 && split != 1 && (split == 2 || q * 4 <= ncu)) {
     // RKAB with every workgroup holding a slice of every worker's rows: asked
-    // for, or chosen when the workers alone would leave most CUs idle
-    if (split == 2 || (q * 4 <= ncu && (int64_t)q * bs <= kAutoSplitMaxRows))
-      use_sstep = rka::rka_sstep_plan(sh, 1, &sgeo);
+    // for, or chosen when the workers alone would leave most CUs idle and
+    // the outer iteration fits one exchange or q is small
+    rka::RkaSstepGeom cand{};
+    if (rka::rka_sstep_plan(sh, 1, &cand) &&
+        (split == 2 || cand.c == bs || q <= kAutoSubBlockMaxQ)) {
+      sgeo = cand;
+      use_sstep = true;
+    }
   } else if (!block && acc == 0 && allreduce == 0) {
     if (sstep >= 2) {
       use_sstep = rka::rka_sstep_plan(sh, sstep, &sgeo);
@@ -374,7 +380,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
       stats->grid = sgeo.G;
       stats->threads = sgeo.nt;
       stats->bucket = sgeo.rpt;
-      stats->variant = sgeo.p;
+      stats->variant = block ? sgeo.c : sgeo.p;
     } else {
       stats->kernel = use_col ? 1 : 2;
       stats->grid = use_col ? cgeo.G : bgeo.G;

@@ -83,15 +83,18 @@ struct RkaSstepGeom {
   int G, nsv, rg, nt, rpt;
   int p;       // iterations per exchange (at most; 1 for RKAB)
   int bs;      // projections per worker per iteration (1: RKA)
+  int c;       // RKAB: projections per worker per exchange (sub-block)
   int nv;      // exchange values of a full block
   int tr, trp, trs, cg;  // reduction teams (see the kernel's arguments)
   int pg_in_s;           // reduce-scatter gathers into the row-slice buffer
+  int pg_len;            // length of its own buffer otherwise
   size_t lds;
 };
 // RKA (sh.bs = 1): p_req = 0 gives the largest p the tile allows.  RKAB
-// (sh.bs > 1): one outer iteration per exchange (p_req 0 or 1).  False when
-// the shape does not fit (the caller then runs the column-split or the
-// worker-split kernel).  FP64 arithmetic only.
+// (sh.bs > 1, p_req 0 or 1): sub-blocks of the largest c <= bs projections
+// per worker that fit (geo->c; c = bs is one exchange per outer iteration).
+// False when the shape does not fit (the caller then runs the column-split or
+// the worker-split kernel).  FP64 arithmetic only.
 bool rka_sstep_plan(const SolveShape& sh, int p_req, RkaSstepGeom* geo);
 // part: G x nv tagged slots, red: nv tagged slots, both zeroed once per solve.
 hipError_t launch_sstep_chunk(const SolveShape& sh, const RkaSstepGeom& geo, const RowRec* rec,

@@ -62,6 +62,7 @@ struct SstepArgs {
   double inv_q;
   int32_t q, p;       // workers, iterations per exchange (at most)
   int32_t bs;         // projections per worker per iteration (1: RKA; > 1: RKAB, p = 1)
+  int32_t c;          // RKAB: projections per worker per exchange (sub-block, <= bs)
   int32_t nsv, rg, G;
   int32_t nv_max;     // exchange values of a full block
   int32_t tr;         // lanes per row for the slice sums of the dot products
@@ -69,6 +70,7 @@ struct SstepArgs {
   int32_t trs;        // lanes per row for the scale sums
   int32_t cg;         // lanes (column groups) per 4 x 4 tile of inner products
   int32_t pg_in_s;    // the reduce-scatter gathers into the row-slice buffer
+  int32_t pg_len;     // its own buffer's length otherwise
   int64_t k0, K, check_every;
   uint64_t* part;     // G x nv_max tagged slots: per-workgroup partial sums
   uint64_t* red;      // nv_max tagged slots: the summed values
@@ -92,26 +94,30 @@ __device__ __forceinline__ int sv_count(int L, int q) {
 __device__ __forceinline__ int sv_gram(int L, int q, int j, int l) {
   return L * q + (j * (j - 1) / 2 + l) * q * q;
 }
-// RKAB (one outer iteration per exchange, Sec. 3.4.1): worker w projects its
-// rows w bs .. w bs + bs - 1 in order on its own copy of x, so row jb of a
-// worker needs <a_{w,jb}, a_{w,jb'}> for jb' < jb only.  Values: [0, q bs)
-// the dot products with x^(k); then worker w's pairs at
-// q bs + w bs (bs-1) / 2 + jb (jb-1) / 2 + jb'; last, the squared error.
+// RKAB (Sec. 3.4.1): worker w projects its bs rows in order on its own
+// iterate v_w, which every workgroup keeps for its slice.  An outer iteration
+// runs as sub-blocks of c rows per worker; in a sub-block row jb of a worker
+// needs its dot product with v_w and <a_{w,jb}, a_{w,jb'}> for jb' < jb only.
+// Values of a sub-block of cs rows per worker: [0, q cs) the dot products;
+// then worker w's pairs at q cs + w cs (cs-1) / 2 + jb (jb-1) / 2 + jb';
+// last, the squared error of x^(k) (first sub-block of a tested iteration).
 __device__ __forceinline__ int svb_count(int q, int bs) { return q * bs + q * (bs * (bs - 1) / 2) + 1; }
 __device__ __forceinline__ int svb_pair(int q, int bs, int w, int jb, int jb2) {
   return q * bs + w * (bs * (bs - 1) / 2) + jb * (jb - 1) / 2 + jb2;
 }
 
-template <typename T, int V, int RPT>
+// B: the RKAB instance (separate, so that the RKA instance carries none of
+// the workers' state in its registers)
+template <typename T, int V, int RPT, bool B>
 __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
   using raw_t = typename Vec<T, V>::raw_t;
   if (p.st->done) return;
   const T* __restrict__ A = (const T*)p.A;
   const int t = threadIdx.x, g = blockIdx.x, NT = blockDim.x;
   const int q = p.q, nsv = p.nsv, rg = p.rg, G = p.G;
-  const int bs = p.bs, Q = q * bs;  // rows of one (outer) iteration
+  const int bs = B ? p.bs : 1;     // 1: RKA; > 1: RKAB with sub-blocks of p.c rows per worker
   const int W = nsv * V;          // slice width in elements
-  const int Rmax = p.p * Q;
+  const int Rmax = bs > 1 ? q * p.c : p.p * q;  // rows of the largest block
   const bool active = t < nsv * rg;
   const int j = active ? t % nsv : 0;
   const int rgi = active ? t / nsv : rg;
@@ -139,6 +145,9 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
   // G * ceil(nv / G) gathered partials of the reduce-scatter: in the row
   // slices (free by then) when they are large enough, else after E
   double* PG = p.pg_in_s ? S : E + nsv;
+  // RKAB: the workers' iterates for this slice, q x W (after PG); unused
+  // (pointed at XS) for RKA
+  double* VW = bs > 1 ? E + nsv + (p.pg_in_s ? 0 : p.pg_len) : XS;
   const int NE = W;
   const int NP = NT / NE > 1 ? NT / NE : 1;
 
@@ -158,13 +167,37 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
     }
     return (int)L;
   };
-  // row indices of the block at kl (rows clamped to the block: masked later)
-  auto load_rows = [&](int64_t kl, int L, int* rows) {
-    const int R = L * Q;
+  // RKAB sub-blocks: sub-block sb of an outer iteration holds rows
+  // sb c .. sb c + cs - 1 of every worker (block row br = w cs + jj)
+  const int cblk = bs > 1 ? p.c : 1;
+  const int nsub = (bs + cblk - 1) / cblk;
+  auto sub_len = [&](int sb) { return bs - sb * cblk < cblk ? bs - sb * cblk : cblk; };
+  auto block_rows = [&](int sb, int L) { return bs > 1 ? q * sub_len(sb) : L * q; };
+  auto rec_index = [&](int64_t kl, int sb, int br) -> int64_t {
+    if (bs == 1) return kl * q + br;
+    const int cs = sub_len(sb), w = br / cs;
+    return (kl * q + w) * (int64_t)bs + sb * cblk + (br - w * cs);
+  };
+  // the block after (kl, sb, L): the next sub-block, or the next iteration
+  auto advance = [&](int64_t& kl2, int& sb2, int& L2) {
+    if (bs > 1) {
+      if (++sb2 == nsub) {
+        sb2 = 0;
+        ++kl2;
+      }
+      L2 = 1;
+    } else {
+      kl2 += L2;
+      L2 = kl2 < p.K ? block_len(kl2) : L2;
+    }
+  };
+  // row indices of a block (rows clamped to the block: masked later)
+  auto load_rows = [&](int64_t kl2, int sb2, int L2, int* rows) {
+    const int R2 = block_rows(sb2, L2);
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int br = rgi + rg * i;
-      rows[i] = (int)p.rec[kl * Q + (br < R ? br : R - 1)].row;
+      rows[i] = (int)p.rec[rec_index(kl2, sb2, br < R2 ? br : R2 - 1)].row;
     }
   };
 
@@ -172,31 +205,47 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
   int rows_n[RPT];
   double mb = 0.0, mw = 1.0, ma = 0.0;  // record of block row t (t < R)
   int64_t kl = 0;
-  int L = block_len(0);
+  int sb = 0;
+  int L = bs > 1 ? 1 : block_len(0);
   {
     int rows0[RPT];
-    load_rows(0, L, rows0);
+    load_rows(0, 0, L, rows0);
 #pragma unroll
     for (int i = 0; i < RPT; ++i) a[i] = load_raw<T, V>(A + (int64_t)rows0[i] * p.lda + cvl * V);
-    if (t < L * Q) {
-      const RowRec r = p.rec[t];
+    if (t < block_rows(0, L)) {
+      const RowRec r = p.rec[rec_index(0, 0, t)];
       mb = r.b;
       mw = r.wn;
       ma = r.alpha;
     }
 #pragma unroll
     for (int i = 0; i < RPT; ++i) rows_n[i] = rows0[i];
-    if (L < p.K) load_rows(L, block_len(L), rows_n);
+    int64_t k1 = 0;
+    int s1 = 0, L1 = L;
+    advance(k1, s1, L1);
+    if (k1 < p.K) load_rows(k1, s1, L1, rows_n);
+  }
+  // RKAB: every worker's iterate starts each outer iteration at x
+  if (bs > 1) {
+    if (active && rgi == 0) {
+#pragma unroll
+      for (int e = 0; e < V; ++e) XS[j * V + e] = xv[e];
+    }
+    __syncthreads();
+    for (int Lx = t; Lx < q * W; Lx += NT) VW[Lx] = XS[Lx % W];
+    __syncthreads();
   }
 
   bool stopped = false;
   SPROF_DECL
   while (kl < p.K) {
     const int64_t k = p.k0 + kl;
-    const int R = L * Q;
-    const int nv = bs > 1 ? svb_count(q, bs) : sv_count(L, q);
-    const bool check = p.check_every > 0 && k > 0 && (k % p.check_every) == 0;
-    const uint32_t tag = (uint32_t)(k + 1);
+    const int cs = bs > 1 ? sub_len(sb) : 1;  // rows per worker in this sub-block
+    const int R = block_rows(sb, L);
+    const int nv = bs > 1 ? svb_count(q, cs) : sv_count(L, q);
+    const bool check = sb == 0 && p.check_every > 0 && k > 0 && (k % p.check_every) == 0;
+    // one tag per exchange of the solve: iteration, then sub-block
+    const uint32_t tag = (uint32_t)(k * nsub + sb + 1);
     const TagSlots part(p.part, (int64_t)G * p.nv_max);
     const TagSlots red(p.red, p.nv_max);
 
@@ -206,14 +255,16 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
       RA[t] = ma;
     }
     // stage the slices of the block's rows and form their dot products with x
+    // (RKAB: with the iterate of the row's worker)
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int br = rgi + rg * i;
+      const double* vw = VW + (size_t)((bs > 1 && br < R) ? br / cs : 0) * W + j * V;
       double s = 0.0;
 #pragma unroll
       for (int e = 0; e < V; ++e) {
         const double v = colv ? raw_elem<T, V>(a[i], e) : 0.0;
-        s = fma(v, xv[e], s);
+        s = fma(v, bs > 1 ? vw[e] : xv[e], s);
         if (active && br < R) S[(size_t)(j * V + e) * RS + br] = v;
       }
       if (active && br < R) P[br * nsv + j] = s;
@@ -309,7 +360,7 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
       }
     } else {
       // RKAB: the pairs within each worker's rows, 4 x 4 tiles (ta, tb), tb <= ta
-      const int b4 = (bs + 3) / 4, tpw = b4 * (b4 + 1) / 2;
+      const int b4 = (cs + 3) / 4, tpw = b4 * (b4 + 1) / 2;
       const int ntile = q * tpw;
       const int CG = p.cg, per = NT / CG;
       const int cu = t & (CG - 1);
@@ -331,12 +382,12 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
 #pragma unroll
         for (int u = 0; u < 16; ++u) acc[u] = 0.0;
         if (tin) {
-          const double* Sa = S + w * bs + 4 * ta;
-          const double* Sb = S + w * bs + 4 * tb;
+          const double* Sa = S + w * cs + 4 * ta;
+          const double* Sb = S + w * cs + 4 * tb;
 #pragma unroll 2
           for (int c = c0; c < c1; ++c) {
             double va[4], vb[4];
-            if (bs % 2 == 0) {  // 16-byte aligned pairs
+            if (cs % 2 == 0) {  // 16-byte aligned pairs
               const double2 a01 = *(const double2*)(Sa + (size_t)c * RS);
               const double2 a23 = *(const double2*)(Sa + (size_t)c * RS + 2);
               const double2 b01 = *(const double2*)(Sb + (size_t)c * RS);
@@ -363,7 +414,7 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
 #pragma unroll
             for (int u2 = 0; u2 < 4; ++u2) {
               const int jb = 4 * ta + u1, jb2 = 4 * tb + u2;
-              if (jb < bs && jb2 < jb) HV[svb_pair(q, bs, w, jb, jb2)] = acc[4 * u1 + u2];
+              if (jb < cs && jb2 < jb) HV[svb_pair(q, cs, w, jb, jb2)] = acc[4 * u1 + u2];
             }
         }
       }
@@ -380,19 +431,22 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
 
     // the next block's rows and records (independent of x) are requested now,
     // so that they stream in while the exchange is in progress
-    const int64_t kn = kl + L;
-    const int Ln = kn < p.K ? block_len(kn) : L;
+    int64_t kn = kl;
+    int sbn = sb, Ln = L;
+    advance(kn, sbn, Ln);
 #pragma unroll
     for (int i = 0; i < RPT; ++i) an[i] = load_raw<T, V>(A + (int64_t)rows_n[i] * p.lda + cvl * V);
-    if (kn < p.K && t < Ln * Q) {
-      const RowRec r = p.rec[kn * Q + t];
+    if (kn < p.K && t < block_rows(sbn, Ln)) {
+      const RowRec r = p.rec[rec_index(kn, sbn, t)];
       mb = r.b;
       mw = r.wn;
       ma = r.alpha;
     }
     if (kn < p.K) {
-      const int64_t knn = kn + Ln;
-      if (knn < p.K) load_rows(knn, block_len(knn), rows_n);
+      int64_t knn = kn;
+      int sbnn = sbn, Lnn = Ln;
+      advance(knn, sbnn, Lnn);
+      if (knn < p.K) load_rows(knn, sbnn, Lnn, rows_n);
     }
 
     // the workgroup's nv partial sums leave in one coalesced pass (a fixed
@@ -501,7 +555,7 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
     // the scales, one iteration of the block after the other:
     // D_{j,r} = <a_{j,r}, x^(k)> + (1/q) sum_{l<j} sum_s s_{l,s} <a_{j,r}, a_{l,s}>
     // (RKAB: one worker's projections after the other, weight 1:
-    //  D_{w,jb} = <a_{w,jb}, x^(k)> + sum_{jb'<jb} s_{w,jb'} <a_{w,jb}, a_{w,jb'}>)
+    //  D_{w,jb} = <a_{w,jb}, v_w> + sum_{jb'<jb} s_{w,jb'} <a_{w,jb}, a_{w,jb'}>)
     if (bs == 1) {
       const int TR = p.trs, team = t / TR, u = t & (TR - 1), nteams = NT / TR;
       for (int jj = 0; jj < L; ++jj) {
@@ -526,16 +580,16 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
       }
     } else {
       const int TR = p.trs, team = t / TR, u = t & (TR - 1), nteams = NT / TR;
-      for (int jb = 0; jb < bs; ++jb) {
+      for (int jb = 0; jb < cs; ++jb) {
         for (int w0 = 0; w0 < q; w0 += nteams) {
           const int w = w0 + team;
           double acc = 0.0;
           if (w < q)
             for (int f = u; f < jb; f += TR)
-              acc = fma(SC[w * bs + f], HV[svb_pair(q, bs, w, jb, f)], acc);
+              acc = fma(SC[w * cs + f], HV[svb_pair(q, cs, w, jb, f)], acc);
           acc = team_sum(acc, TR);
           if (u == 0 && w < q) {
-            const int br = w * bs + jb;
+            const int br = w * cs + jb;
             const double D = HV[br] + acc;
             SC[br] = RA[br] * (RB[br] - D) / RW[br];
           }
@@ -544,48 +598,75 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
       }
     }
     SPROF(5);
-    // x_slice += (1/q) sum over the block's rows of s * A[i, slice]
-    double uu[V];
-#pragma unroll
-    for (int e = 0; e < V; ++e) uu[e] = 0.0;
-#pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-      const int br = rgi + rg * i;
-      const double s = (colv && br < R) ? SC[br < R ? br : 0] : 0.0;
-#pragma unroll
-      for (int e = 0; e < V; ++e) uu[e] = fma(s, raw_elem<T, V>(a[i], e), uu[e]);
-    }
-    if (active) {
-#pragma unroll
-      for (int e = 0; e < V; ++e) U[t * V + e] = uu[e];
-    }
-    __syncthreads();
-    for (int Lx = t; Lx < NE * NP; Lx += NT) {
-      const int je = Lx % NE, pp = Lx / NE;
-      const int jj = je / V, e = je % V;
-      const int g0 = pp * rg / NP, g1 = (pp + 1) * rg / NP;
-      double acc = 0.0;
-      for (int gg = g0; gg < g1; ++gg) acc += U[(gg * nsv + jj) * V + e];
-      UP[Lx] = acc;
-    }
-    __syncthreads();
-    if (colv && rgi == 0) {
-#pragma unroll
-      for (int e = 0; e < V; ++e) {
+    if (bs > 1) {
+      // each worker's slice: v_w += sum_jj s_{w,jj} A[i_{w,jj}, slice], rows in order
+      for (int Lx = t; Lx < q * W; Lx += NT) {
+        const int w = Lx / W, c = Lx - w * W;
         double acc = 0.0;
-        for (int pp = 0; pp < NP; ++pp) acc += UP[pp * NE + j * V + e];
-        xv[e] = fma(acc, p.inv_q, xv[e]);
-        XS[j * V + e] = xv[e];
+        for (int jj = 0; jj < cs; ++jj) acc = fma(SC[w * cs + jj], S[(size_t)c * RS + w * cs + jj], acc);
+        VW[Lx] += acc;
       }
-    }
-    __syncthreads();
-    if (colv) {
+      __syncthreads();
+      if (sb == nsub - 1) {
+        // end of the outer iteration: x = (1/q) sum_w v_w, and every v_w restarts at x
+        for (int c = t; c < W; c += NT) {
+          double acc = 0.0;
+          for (int w = 0; w < q; ++w) acc += VW[w * W + c];
+          XS[c] = acc / (double)q;
+        }
+        __syncthreads();
+        for (int Lx = t; Lx < q * W; Lx += NT) VW[Lx] = XS[Lx % W];
+        if (colv) {
 #pragma unroll
-      for (int e = 0; e < V; ++e) xv[e] = XS[j * V + e];
+          for (int e = 0; e < V; ++e) xv[e] = XS[j * V + e];
+        }
+        __syncthreads();
+      }
+    } else {
+      // x_slice += (1/q) sum over the block's rows of s * A[i, slice]
+      double uu[V];
+#pragma unroll
+      for (int e = 0; e < V; ++e) uu[e] = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int br = rgi + rg * i;
+        const double s = (colv && br < R) ? SC[br < R ? br : 0] : 0.0;
+#pragma unroll
+        for (int e = 0; e < V; ++e) uu[e] = fma(s, raw_elem<T, V>(a[i], e), uu[e]);
+      }
+      if (active) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) U[t * V + e] = uu[e];
+      }
+      __syncthreads();
+      for (int Lx = t; Lx < NE * NP; Lx += NT) {
+        const int je = Lx % NE, pp = Lx / NE;
+        const int jj = je / V, e = je % V;
+        const int g0 = pp * rg / NP, g1 = (pp + 1) * rg / NP;
+        double acc = 0.0;
+        for (int gg = g0; gg < g1; ++gg) acc += U[(gg * nsv + jj) * V + e];
+        UP[Lx] = acc;
+      }
+      __syncthreads();
+      if (colv && rgi == 0) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          double acc = 0.0;
+          for (int pp = 0; pp < NP; ++pp) acc += UP[pp * NE + j * V + e];
+          xv[e] = fma(acc, p.inv_q, xv[e]);
+          XS[j * V + e] = xv[e];
+        }
+      }
+      __syncthreads();
+      if (colv) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) xv[e] = XS[j * V + e];
+      }
     }
 #pragma unroll
     for (int i = 0; i < RPT; ++i) a[i] = an[i];
     kl = kn;
+    sb = sbn;
     L = Ln;
     SPROF(6);
 #ifdef RKA_SSTEP_PROF
@@ -621,25 +702,34 @@ static int pow2_floor_cap(int64_t cap, int limit) {
   return v;
 }
 
-static bool sstep_plan_at(const SolveShape& sh, int p_req, RkaSstepGeom* geo);
+static bool sstep_plan_at(const SolveShape& sh, int p_req, int c, RkaSstepGeom* geo);
 
-bool rka_sstep_plan(const SolveShape& sh, int p_req, RkaSstepGeom* geo) {
-  if (sstep_plan_at(sh, p_req, geo)) return true;
+static bool sstep_plan_c(const SolveShape& sh, int p_req, int c, RkaSstepGeom* geo) {
+  if (sstep_plan_at(sh, p_req, c, geo)) return true;
   if (sh.grid > 0) return false;
   SolveShape wide = sh;  // slices too wide for the tile at half the CUs
   wide.grid = sh.num_cu;
-  return sstep_plan_at(wide, p_req, geo);
+  return sstep_plan_at(wide, p_req, c, geo);
 }
 
-static bool sstep_plan_at(const SolveShape& sh, int p_req, RkaSstepGeom* geo) {
+bool rka_sstep_plan(const SolveShape& sh, int p_req, RkaSstepGeom* geo) {
+  if (sh.bs <= 1) return sstep_plan_c(sh, p_req, 1, geo);
+  // RKAB: the longest sub-block that fits (the whole outer iteration if it can)
+  int c = (int)std::min<int64_t>(sh.bs, kSMaxRowsB / sh.q);
+  for (; c >= 1; --c)
+    if (sstep_plan_c(sh, p_req, c, geo)) return true;
+  return false;
+}
+
+static bool sstep_plan_at(const SolveShape& sh, int p_req, int c, RkaSstepGeom* geo) {
   if (sh.acc != 0 || sh.q < 1) return false;
   const int esz = sh.dtype == 0 ? 8 : (sh.dtype == 1 ? 4 : 2);
   const int V = sh.vec_ok ? 16 / esz : 1;
   const int64_t nvec = sh.n / V;
   const int bs = sh.bs;
   int pp;
-  if (bs > 1) {  // RKAB: one outer iteration (q bs rows) per exchange
-    if (p_req > 1 || (int64_t)sh.q * bs > kSMaxRowsB) return false;
+  if (bs > 1) {  // RKAB: sub-blocks of c projections per worker
+    if (p_req > 1 || c < 1 || c > bs || (int64_t)sh.q * c > kSMaxRowsB) return false;
     pp = 1;
   } else {
     int pmax = kSMaxRows / sh.q;
@@ -654,7 +744,7 @@ static bool sstep_plan_at(const SolveShape& sh, int p_req, RkaSstepGeom* geo) {
   const int nsv = (int)((nvec + g0 - 1) / g0);
   const int G = (int)((nvec + nsv - 1) / nsv);
   if (nsv > kSThreads || G < 2) return false;
-  const int R = pp * sh.q * bs;
+  const int R = bs > 1 ? sh.q * c : pp * sh.q;
   int rg = kSThreads / nsv;
   if (rg > R) rg = R;
   const int rpt = sstep_bucket((R + rg - 1) / rg);
@@ -662,7 +752,7 @@ static bool sstep_plan_at(const SolveShape& sh, int p_req, RkaSstepGeom* geo) {
   const int rpt_max = sh.dtype == 0 ? 8 : (sh.dtype == 1 ? 4 : 2);
   if (rpt == 0 || rpt > rpt_max) return false;
   const int W = nsv * V;
-  const int nv = bs > 1 ? sh.q * bs + sh.q * (bs * (bs - 1) / 2) + 1
+  const int nv = bs > 1 ? sh.q * c + sh.q * (c * (c - 1) / 2) + 1
                        : pp * sh.q + sh.q * sh.q * (pp * (pp - 1) / 2) + 1;
   // threads: the row tile, at least 256, more if the exchange needs them:
   // the reduce-scatter gathers G x C partials (C = ceil(nv / G) values per
@@ -677,13 +767,16 @@ static bool sstep_plan_at(const SolveShape& sh, int p_req, RkaSstepGeom* geo) {
   if (!fits(nt)) nt = kSThreads;
   if (!fits(nt)) return false;
   const int trp = pow2_floor_cap(nt / cmax, kWave);
-  const bool pg_in_s = (int64_t)(R + 4) * W >= gathered;
+  // RKAB reads the row slices after the exchange (the workers' updates), so
+  // its reduce-scatter gathers into a buffer of its own
+  const bool pg_in_s = bs == 1 && (int64_t)(R + 4) * W >= gathered;
   const size_t lds = sizeof(double) * (16 + 4 * (size_t)R + ((nv + 1) & ~1) + (size_t)(R + 4) * W +
                                        (size_t)R * nsv +
                                        (size_t)nt * V + W + std::max(nt, W) + nsv +
-                                       (pg_in_s ? 0 : (size_t)gathered));
+                                       (pg_in_s ? 0 : (size_t)gathered) +
+                                       (bs > 1 ? (size_t)sh.q * W : 0));
   if (lds > kSMaxLds) return false;
-  const int q4 = (sh.q + 3) / 4, b4 = (bs + 3) / 4;
+  const int q4 = (sh.q + 3) / 4, b4 = (c + 3) / 4;
   const int64_t ntile = bs > 1 ? (int64_t)sh.q * (b4 * (b4 + 1) / 2)
                                : (int64_t)(pp * (pp - 1) / 2) * q4 * q4;
   geo->G = G;
@@ -693,28 +786,36 @@ static bool sstep_plan_at(const SolveShape& sh, int p_req, RkaSstepGeom* geo) {
   geo->rpt = rpt;
   geo->p = pp;
   geo->bs = bs;
+  geo->c = bs > 1 ? c : 1;
   geo->nv = nv;
   geo->lds = lds;
   geo->tr = pow2_floor_cap(std::min<int64_t>(nt / R, nsv), kWave);
   geo->trp = trp;
   geo->pg_in_s = pg_in_s ? 1 : 0;
+  geo->pg_len = pg_in_s ? 0 : (int)gathered;
   geo->trs = pow2_floor_cap(nt / sh.q, kWave);
   geo->cg = pow2_floor_cap(std::min<int64_t>(ntile > 0 ? nt / ntile : nt, W), 16);
   return true;
 }
 
+template <typename T, int V, bool B>
+static const void* sstep_fn(int rpt) {
+  // tiles instantiated only where they do not spill (rka_sstep_plan keeps to them)
+  const void* fn = rpt == 1 ? (const void*)rka_sstep_kernel<T, V, 1, B>
+                            : (const void*)rka_sstep_kernel<T, V, 2, B>;
+  if constexpr (sizeof(T) >= 4) {
+    if (rpt == 4) fn = (const void*)rka_sstep_kernel<T, V, 4, B>;
+  }
+  if constexpr (sizeof(T) == 8) {
+    if (rpt == 8) fn = (const void*)rka_sstep_kernel<T, V, 8, B>;
+  }
+  return fn;
+}
+
 template <typename T, int V>
 static hipError_t launch_sstep_t(const RkaSstepGeom& geo, SstepArgs& a, hipStream_t s) {
   void* args[] = {&a};
-  // tiles instantiated only where they do not spill (rka_sstep_plan keeps to them)
-  const void* fn = geo.rpt == 1 ? (const void*)rka_sstep_kernel<T, V, 1>
-                                : (const void*)rka_sstep_kernel<T, V, 2>;
-  if constexpr (sizeof(T) >= 4) {
-    if (geo.rpt == 4) fn = (const void*)rka_sstep_kernel<T, V, 4>;
-  }
-  if constexpr (sizeof(T) == 8) {
-    if (geo.rpt == 8) fn = (const void*)rka_sstep_kernel<T, V, 8>;
-  }
+  const void* fn = geo.bs > 1 ? sstep_fn<T, V, true>(geo.rpt) : sstep_fn<T, V, false>(geo.rpt);
   size_t lds = geo.lds;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -739,6 +840,7 @@ hipError_t launch_sstep_chunk(const SolveShape& sh, const RkaSstepGeom& geo, con
   a.q = sh.q;
   a.p = geo.p;
   a.bs = geo.bs;
+  a.c = geo.c;
   a.nsv = geo.nsv;
   a.rg = geo.rg;
   a.G = geo.G;
@@ -746,6 +848,7 @@ hipError_t launch_sstep_chunk(const SolveShape& sh, const RkaSstepGeom& geo, con
   a.tr = geo.tr;
   a.trp = geo.trp;
   a.pg_in_s = geo.pg_in_s;
+  a.pg_len = geo.pg_len;
   a.trs = geo.trs;
   a.cg = geo.cg;
   a.k0 = k0;

@@ -104,25 +104,32 @@ def test_sstep_falls_back_when_the_block_does_not_fit():
 
 # -- RKAB split over columns (one outer iteration per exchange) -----------------
 
-RKAB_CASES = [  # m, n, q, bs, K, dtype
-    (3000, 2000, 16, 10, 12, "f64"),
-    (2000, 1500, 8, 5, 20, "f64"),       # odd bs: unaligned tile reads
-    (1500, 777, 6, 7, 15, "f64"),        # scalar path (odd n)
-    (5000, 10000, 16, 10, 6, "f64"),     # 160 rows of 40-column slices: the 8-row tile
-    (2000, 3000, 12, 4, 10, "f32"),      # narrow storage, FP64 arithmetic
-    (2000, 3000, 12, 4, 10, "bf16"),
+RKAB_CASES = [  # m, n, q, bs, K, dtype, sub-block length the library picks
+    (3000, 2000, 16, 10, 12, "f64", 10),
+    (2000, 1500, 8, 5, 20, "f64", 5),        # odd bs: unaligned tile reads
+    (1500, 777, 6, 7, 15, "f64", 7),         # scalar path (odd n)
+    (5000, 10000, 16, 10, 6, "f64", 10),     # 160 rows of 40-column slices: the 8-row tile
+    (2000, 3000, 12, 4, 10, "f32", 4),       # narrow storage, FP64 arithmetic
+    (2000, 3000, 12, 4, 10, "bf16", 4),
+    (3000, 2000, 16, 40, 5, "f64", 16),      # sub-blocks 16, 16, 8
+    (2000, 1200, 4, 150, 3, "f64", None),    # long blocks: ragged last sub-block
+    (1500, 777, 6, 50, 4, "f64", None),      # sub-blocks on the scalar path
 ]
 
 
-@pytest.mark.parametrize("m,n,q,bs,K,dtype", RKAB_CASES)
-def test_rkab_column_split_vs_oracle(m, n, q, bs, K, dtype):
+@pytest.mark.parametrize("m,n,q,bs,K,dtype,c", RKAB_CASES)
+def test_rkab_column_split_vs_oracle(m, n, q, bs, K, dtype, c):
     say(f"rkab split {dtype} m={m} n={n} q={q} bs={bs} K={K}")
     A, _, b = workloads.gaussian_system(m, n, seed=36, noise_var=1e-2, dtype=dtype)
     A = np.array(A)
     x, info, st = rka.solve_ex(to_dev(A, dtype), vec(b), method=1, q=q, block_size=bs,
                                alpha=0.9, max_iter=K, seed=7, rkab_split=2)
     assert info.status == rka.OK and info.iterations == K and info.projections == K * q * bs
-    assert st["kernel"] == 3 and st["variant"] == 1
+    assert st["kernel"] == 3 and 1 <= st["variant"] <= bs
+    if c is not None:
+        assert st["variant"] == c
+    else:
+        assert st["variant"] < bs  # sub-blocks
     odt = "bf16" if dtype == "bf16" else None
     idx = oracle.indices(oracle.row_norms(A, dtype=odt), 7, 0, K, q, bs)
     xo = oracle.rkab_given(A, b, np.zeros(n), idx, q=q, block_size=bs, alpha=0.9, dtype=odt)
@@ -142,10 +149,23 @@ def test_rkab_column_split_stops_where_the_worker_kernel_stops():
     assert_x_close(host(x2), host(x1), 1e-12, "rkab split stop")
 
 
+def test_rkab_sub_blocks_stop_where_the_worker_kernel_stops():
+    A, xs, b = workloads.gaussian_system(3000, 400, seed=40)
+    A = np.array(A)
+    kw = dict(method=1, q=4, block_size=90, max_iter=5000, tol=1e-9, x_ref=vec(xs),
+              check_every=2, seed=5)
+    x1, i1, s1 = rka.solve_ex(to_dev(A), vec(b), rkab_split=1, **kw)
+    x2, i2, s2 = rka.solve_ex(to_dev(A), vec(b), rkab_split=2, **kw)
+    assert s1["kernel"] == 2 and s2["kernel"] == 3 and s2["variant"] < 90
+    assert i1.status == rka.OK and i2.status == rka.OK
+    assert i2.iterations == i1.iterations
+    assert_x_close(host(x2), host(x1), 1e-12, "rkab sub-block stop")
+
+
 def test_rkab_column_split_cyclic_and_row_weights():
     A, _, b = workloads.paper_rows_system(1500, 900, seed=38)
     wrow = np.random.default_rng(38).uniform(0.5, 1.5, size=1500)
-    K, q, bs = 12, 10, 6
+    K, q, bs = 12, 10, 30  # sub-blocks of 25 and 5
     x, info, st = rka.solve_ex(to_dev(A), vec(b), method=1, q=q, block_size=bs, max_iter=K,
                                sampling=2, row_weight=vec(wrow), rkab_split=2)
     assert st["kernel"] == 3
@@ -157,12 +177,12 @@ def test_rkab_column_split_cyclic_and_row_weights():
 def test_rkab_column_split_falls_back_and_checks_arguments():
     A, _, b = workloads.gaussian_system(2000, 500, seed=39)
     A = np.array(A)
-    # q bs = 320 rows exceed the block tile: the worker-split kernel runs
-    x, info, st = rka.solve_ex(to_dev(A), vec(b), method=1, q=32, block_size=10, max_iter=4,
+    # more than 256 workers: not even one row per worker fits the block tile
+    x, info, st = rka.solve_ex(to_dev(A), vec(b), method=1, q=300, block_size=2, max_iter=3,
                                seed=2, rkab_split=2)
     assert st["kernel"] == 2
-    idx = oracle.indices(oracle.row_norms(A), 2, 0, 4, 32, 10)
-    assert_x_close(host(x), oracle.rkab_given(A, b, np.zeros(500), idx, q=32, block_size=10),
+    idx = oracle.indices(oracle.row_norms(A), 2, 0, 3, 300, 2)
+    assert_x_close(host(x), oracle.rkab_given(A, b, np.zeros(500), idx, q=300, block_size=2),
                    1e-12, "rkab fallback")
     with pytest.raises(rka.RKAError) as e:
         rka.solve_ex(to_dev(A), vec(b), method=1, q=4, block_size=3, max_iter=3, rkab_split=3)
