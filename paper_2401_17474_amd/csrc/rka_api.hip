@@ -253,7 +253,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
     // RKA whose q rows do not fit the column kernel's tile runs as RKAB with
     // one projection per worker, which is the same iteration (Sec. 3.4.2).
     if (!rka::rkab_plan(sh, &bgeo))
-      return fail(RKA_EINVAL, "n = %lld is too large for this build's worker kernel",
+      return fail(RKA_EINVAL, "n = %lld is too large for the worker kernel's register and LDS tiles",
                   (long long)n);
   }
 

@@ -1,6 +1,6 @@
 """GPU parity: the HIP path, called through the C ABI, against the oracle.
 
-Bars (arXiv 2401.17474 method; tolerances as stated for this build):
+Bars (arXiv 2401.17474 method; tolerances as stated below):
   * row norms, running sum and the sampled row stream: bit-exact;
   * x in FP64: norm-wise relative difference <= 1e-12 and every element within
     1e-12 of the oracle's largest entry, for the same index stream.
