@@ -71,16 +71,29 @@ struct SstepArgs {
   int32_t cg;         // lanes (column groups) per 4 x 4 tile of inner products
   int32_t pg_in_s;    // the reduce-scatter gathers into the row-slice buffer
   int32_t pg_len;     // its own buffer's length otherwise
+  int32_t nt;         // threads of a workgroup (blockDim.x: a 32-bit argument
+                      // keeps its reads off the vector memory counter)
   int64_t k0, K, check_every;
   uint64_t* part;     // G x nv_max tagged slots: per-workgroup partial sums
   uint64_t* red;      // nv_max tagged slots: the summed values
   DevStatus* st;
 };
 
+// Column stride of the row-slice tile for blocks of at most rmax rows: at
+// least rmax + 4 (slack for the 4 x 4 inner-product tiles), even (pairs of
+// rows stay 16-byte aligned) and not a multiple of 4, so that the lanes of a
+// wave, which stage consecutive columns, spread over 8 of the 16 double-word
+// LDS banks instead of 2 or 4.
+__host__ __device__ constexpr int sstep_rs(int rmax) {
+  const int even = (rmax + 5) & ~1;  // rmax + 4 rounded up to even
+  return even % 4 == 0 ? even + 2 : even;
+}
+
 constexpr int kSMaxRows = 64;      // q * p (RKA)
 constexpr int kSMaxRowsB = 256;    // q * bs (RKAB)
 constexpr int kSMaxP = 8;
 constexpr int kSPoll = 8;          // slots one lane polls in either phase
+constexpr int kSBatch = 4;         // poll loads in flight per lane
 constexpr int kSThreads = 512;
 constexpr size_t kSMaxLds = 150 * 1024;  // of the 160 KiB of a CU
 
@@ -113,11 +126,13 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
   using raw_t = typename Vec<T, V>::raw_t;
   if (p.st->done) return;
   const T* __restrict__ A = (const T*)p.A;
-  const int t = threadIdx.x, g = blockIdx.x, NT = blockDim.x;
+  const int t = threadIdx.x, g = blockIdx.x, NT = p.nt;
   const int q = p.q, nsv = p.nsv, rg = p.rg, G = p.G;
-  const int bs = B ? p.bs : 1;     // 1: RKA; > 1: RKAB with sub-blocks of p.c rows per worker
+  // B: RKAB, bs > 1 projections per worker with sub-blocks of p.c rows per
+  // worker (the host launches bs = 1 as RKA, B false)
+  const int bs = B ? p.bs : 1;
   const int W = nsv * V;          // slice width in elements
-  const int Rmax = bs > 1 ? q * p.c : p.p * q;  // rows of the largest block
+  const int Rmax = B ? q * p.c : p.p * q;  // rows of the largest block
   const bool active = t < nsv * rg;
   const int j = active ? t % nsv : 0;
   const int rgi = active ? t / nsv : rg;
@@ -132,10 +147,11 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
   double* RW = RB + Rmax;                 // Rmax        ||a_i||^2
   double* RA = RW + Rmax;                 // Rmax        weights
   double* HV = RA + Rmax;                 // nv_max      summed exchange values
-  // row slices of the block, column-major: S[c RS + row], RS = Rmax + 4
-  // (even, so pairs of rows are 16-byte aligned; 4 rows of slack past the
-  // block for the inner-product tiles)
-  const int RS = Rmax + 4;
+  // row slices of the block, column-major: S[s RS + row], RS = sstep_rs(Rmax);
+  // element e of column vector jv of the slice (column jv V + e) sits in slot
+  // s = e nsv + jv, so that the lanes of a wave (consecutive jv) stage
+  // consecutive slots
+  const int RS = sstep_rs(Rmax);
   double* S = HV + ((p.nv_max + 1) & ~1);  // W * RS (16-byte aligned)
   double* P = S + (size_t)W * RS;         // Rmax * nsv  dot partials per vec
   double* U = P + (size_t)Rmax * nsv;     // NT * V      update partials per thread
@@ -147,7 +163,7 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
   double* PG = p.pg_in_s ? S : E + nsv;
   // RKAB: the workers' iterates for this slice, q x W (after PG); unused
   // (pointed at XS) for RKA
-  double* VW = bs > 1 ? E + nsv + (p.pg_in_s ? 0 : p.pg_len) : XS;
+  double* VW = B ? E + nsv + (p.pg_in_s ? 0 : p.pg_len) : XS;
   const int NE = W;
   const int NP = NT / NE > 1 ? NT / NE : 1;
 
@@ -169,18 +185,18 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
   };
   // RKAB sub-blocks: sub-block sb of an outer iteration holds rows
   // sb c .. sb c + cs - 1 of every worker (block row br = w cs + jj)
-  const int cblk = bs > 1 ? p.c : 1;
+  const int cblk = B ? p.c : 1;
   const int nsub = (bs + cblk - 1) / cblk;
   auto sub_len = [&](int sb) { return bs - sb * cblk < cblk ? bs - sb * cblk : cblk; };
-  auto block_rows = [&](int sb, int L) { return bs > 1 ? q * sub_len(sb) : L * q; };
+  auto block_rows = [&](int sb, int L) { return B ? q * sub_len(sb) : L * q; };
   auto rec_index = [&](int64_t kl, int sb, int br) -> int64_t {
-    if (bs == 1) return kl * q + br;
+    if (!B) return kl * q + br;
     const int cs = sub_len(sb), w = br / cs;
     return (kl * q + w) * (int64_t)bs + sb * cblk + (br - w * cs);
   };
   // the block after (kl, sb, L): the next sub-block, or the next iteration
   auto advance = [&](int64_t& kl2, int& sb2, int& L2) {
-    if (bs > 1) {
+    if (B) {
       if (++sb2 == nsub) {
         sb2 = 0;
         ++kl2;
@@ -206,7 +222,7 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
   double mb = 0.0, mw = 1.0, ma = 0.0;  // record of block row t (t < R)
   int64_t kl = 0;
   int sb = 0;
-  int L = bs > 1 ? 1 : block_len(0);
+  int L = B ? 1 : block_len(0);
   {
     int rows0[RPT];
     load_rows(0, 0, L, rows0);
@@ -226,7 +242,7 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
     if (k1 < p.K) load_rows(k1, s1, L1, rows_n);
   }
   // RKAB: every worker's iterate starts each outer iteration at x
-  if (bs > 1) {
+  if (B) {
     if (active && rgi == 0) {
 #pragma unroll
       for (int e = 0; e < V; ++e) XS[j * V + e] = xv[e];
@@ -236,13 +252,57 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
     __syncthreads();
   }
 
+  // Poll `total` tagged slots, slot idx(L) for L = t + NT s (at most kSPoll
+  // per lane), until every tag matches, and store the values to dst[L].  A
+  // sweep issues a lane's loads kSBatch at a time before it waits for them;
+  // slots already read, and lanes past the end, load at `oob`, out of the
+  // buffer's range (zero, no memory access).  False if the wait gave up (in
+  // every thread).
+  auto gather = [&](const TagSlots& sl, int oob, int total, uint32_t tg, auto idx,
+                    double* dst) -> bool {
+    const int ns = (total + NT - 1) / NT;  // loads per lane and sweep, uniform
+    uint32_t need = 0;                     // bit s: slot t + NT s still to read
+#pragma unroll
+    for (int s = 0; s < kSPoll; ++s)
+      if (t + NT * s < total) need |= 1u << s;
+    for (unsigned spins = 0;; ++spins) {
+#pragma unroll
+      for (int s0 = 0; s0 < kSPoll; s0 += kSBatch) {
+        if (s0 < ns) {
+          uint64_t lo[kSBatch], hi[kSBatch];
+#pragma unroll
+          for (int s = 0; s < kSBatch; ++s) {
+            lo[s] = hi[s] = 0;
+            if (s0 + s < ns) {
+              // recomputed every sweep rather than held in registers
+              int Lx = t + NT * (s0 + s);
+              __asm__ volatile("" : "+v"(Lx));
+              sl.fetch16((need >> (s0 + s)) & 1u ? (int)idx(Lx) : oob, lo[s], hi[s]);
+            }
+          }
+#pragma unroll
+          for (int s = 0; s < kSBatch; ++s) {
+            double v;
+            if (s0 + s < ns && ((need >> (s0 + s)) & 1u) && TagSlots::decode(lo[s], hi[s], tg, v)) {
+              dst[t + NT * (s0 + s)] = v;
+              need &= ~(1u << (s0 + s));
+            }
+          }
+        }
+      }
+      if (__syncthreads_and(need == 0)) return true;
+      if (spins >= kSpinLimit) return false;
+      __builtin_amdgcn_s_sleep(1);
+    }
+  };
+
   bool stopped = false;
   SPROF_DECL
   while (kl < p.K) {
     const int64_t k = p.k0 + kl;
-    const int cs = bs > 1 ? sub_len(sb) : 1;  // rows per worker in this sub-block
+    const int cs = B ? sub_len(sb) : 1;  // rows per worker in this sub-block
     const int R = block_rows(sb, L);
-    const int nv = bs > 1 ? svb_count(q, cs) : sv_count(L, q);
+    const int nv = B ? svb_count(q, cs) : sv_count(L, q);
     const bool check = sb == 0 && p.check_every > 0 && k > 0 && (k % p.check_every) == 0;
     // one tag per exchange of the solve: iteration, then sub-block
     const uint32_t tag = (uint32_t)(k * nsub + sb + 1);
@@ -259,13 +319,13 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int br = rgi + rg * i;
-      const double* vw = VW + (size_t)((bs > 1 && br < R) ? br / cs : 0) * W + j * V;
+      const double* vw = VW + (size_t)((B && br < R) ? br / cs : 0) * W + j * V;
       double s = 0.0;
 #pragma unroll
       for (int e = 0; e < V; ++e) {
         const double v = colv ? raw_elem<T, V>(a[i], e) : 0.0;
-        s = fma(v, bs > 1 ? vw[e] : xv[e], s);
-        if (active && br < R) S[(size_t)(j * V + e) * RS + br] = v;
+        s = fma(v, B ? vw[e] : xv[e], s);
+        if (active && br < R) S[(size_t)(e * nsv + j) * RS + br] = v;
       }
       if (active && br < R) P[br * nsv + j] = s;
     }
@@ -296,7 +356,7 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
     }
     // (2) inner products between rows of different iterations: 4 x 4 tiles,
     // cg lanes per tile over consecutive column ranges, folded in lane order
-    if (bs == 1) {
+    if (!B) {
       const int q4 = (q + 3) / 4;
       const int ntile = (L * (L - 1) / 2) * q4 * q4;
       const int CG = p.cg, per = NT / CG;
@@ -429,8 +489,10 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
     }
     SPROF(1);
 
-    // the next block's rows and records (independent of x) are requested now,
-    // so that they stream in while the exchange is in progress
+    // the next block's rows and records (independent of x) are requested now.
+    // The exchange's first poll waits for them (the vector memory counter
+    // drains in order), but they overlap the other workgroups' arrival;
+    // issuing them after the exchange instead is slower (80000 x 10000, q 16).
     int64_t kn = kl;
     int sbn = sb, Ln = L;
     advance(kn, sbn, Ln);
@@ -466,33 +528,12 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
       const int C = (nv + G - 1) / G;
       const int v0 = g * C;
       const int cnt = nv - v0 < C ? (nv - v0 > 0 ? nv - v0 : 0) : C;
-      const int total = G * cnt;
-      bool have[kSPoll];
-#pragma unroll
-      for (int s = 0; s < kSPoll; ++s) have[s] = t + NT * s >= total;
-      for (unsigned spins = 0;; ++spins) {
-        bool all = true;
-#pragma unroll
-        for (int s = 0; s < kSPoll; ++s) {
-          if (!have[s]) {
-            const int Lx = t + NT * s, gg = Lx / cnt, c = Lx - gg * cnt;
-            uint64_t lo, hi;
-            part.fetch16((int64_t)gg * p.nv_max + v0 + c, lo, hi);
-            double pv;
-            if (TagSlots::decode(lo, hi, tag, pv)) {
-              PG[Lx] = pv;
-              have[s] = true;
-            }
-          }
-          all = all && have[s];
-        }
-        if (__syncthreads_and(all)) break;
-        if (spins >= kSpinLimit) {
-          ok = false;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
+      ok = gather(part, G * p.nv_max, G * cnt, tag,
+                  [&](int Lx) {
+                    const int gg = Lx / cnt, c = Lx - gg * cnt;
+                    return gg * p.nv_max + v0 + c;
+                  },
+                  PG);
       // value c: a team of trp lanes, lane u adding workgroups u, u + trp, ...
       // in order, then the team fold (one round: cnt <= NT / trp)
       const int TR = p.trp, team = t / TR, u = t & (TR - 1);
@@ -504,33 +545,8 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
     }
     SPROF(3);
     // phase 2: every workgroup reads all nv sums
-    if (__syncthreads_and(ok)) {
-      bool have[kSPoll];
-#pragma unroll
-      for (int s = 0; s < kSPoll; ++s) have[s] = t + NT * s >= nv;
-      for (unsigned spins = 0;; ++spins) {
-        bool all = true;
-#pragma unroll
-        for (int s = 0; s < kSPoll; ++s) {
-          if (!have[s]) {
-            uint64_t lo, hi;
-            red.fetch16(t + NT * s, lo, hi);
-            double v;
-            if (TagSlots::decode(lo, hi, tag, v)) {
-              HV[t + NT * s] = v;
-              have[s] = true;
-            }
-          }
-          all = all && have[s];
-        }
-        if (__syncthreads_and(all)) break;
-        if (spins >= kSpinLimit) {
-          ok = false;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-    }
+    if (__syncthreads_and(ok))
+      ok = gather(red, p.nv_max, nv, tag, [&](int Lx) { return Lx; }, HV);
     if (!__syncthreads_and(ok)) {
       if (t == 0) note_timeout(p.st);
       stopped = true;
@@ -556,7 +572,7 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
     // D_{j,r} = <a_{j,r}, x^(k)> + (1/q) sum_{l<j} sum_s s_{l,s} <a_{j,r}, a_{l,s}>
     // (RKAB: one worker's projections after the other, weight 1:
     //  D_{w,jb} = <a_{w,jb}, v_w> + sum_{jb'<jb} s_{w,jb'} <a_{w,jb}, a_{w,jb'}>)
-    if (bs == 1) {
+    if (!B) {
       const int TR = p.trs, team = t / TR, u = t & (TR - 1), nteams = NT / TR;
       for (int jj = 0; jj < L; ++jj) {
         for (int r0 = 0; r0 < q; r0 += nteams) {
@@ -598,12 +614,13 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
       }
     }
     SPROF(5);
-    if (bs > 1) {
+    if (B) {
       // each worker's slice: v_w += sum_jj s_{w,jj} A[i_{w,jj}, slice], rows in order
       for (int Lx = t; Lx < q * W; Lx += NT) {
         const int w = Lx / W, c = Lx - w * W;
         double acc = 0.0;
-        for (int jj = 0; jj < cs; ++jj) acc = fma(SC[w * cs + jj], S[(size_t)c * RS + w * cs + jj], acc);
+        const double* Sc = S + (size_t)((c % V) * nsv + c / V) * RS + w * cs;
+        for (int jj = 0; jj < cs; ++jj) acc = fma(SC[w * cs + jj], Sc[jj], acc);
         VW[Lx] += acc;
       }
       __syncthreads();
@@ -769,8 +786,8 @@ static bool sstep_plan_at(const SolveShape& sh, int p_req, int c, RkaSstepGeom* 
   const int trp = pow2_floor_cap(nt / cmax, kWave);
   // RKAB reads the row slices after the exchange (the workers' updates), so
   // its reduce-scatter gathers into a buffer of its own
-  const bool pg_in_s = bs == 1 && (int64_t)(R + 4) * W >= gathered;
-  const size_t lds = sizeof(double) * (16 + 4 * (size_t)R + ((nv + 1) & ~1) + (size_t)(R + 4) * W +
+  const bool pg_in_s = bs == 1 && (int64_t)sstep_rs(R) * W >= gathered;
+  const size_t lds = sizeof(double) * (16 + 4 * (size_t)R + ((nv + 1) & ~1) + (size_t)sstep_rs(R) * W +
                                        (size_t)R * nsv +
                                        (size_t)nt * V + W + std::max(nt, W) + nsv +
                                        (pg_in_s ? 0 : (size_t)gathered) +
@@ -851,6 +868,7 @@ hipError_t launch_sstep_chunk(const SolveShape& sh, const RkaSstepGeom& geo, con
   a.pg_len = geo.pg_len;
   a.trs = geo.trs;
   a.cg = geo.cg;
+  a.nt = geo.nt;
   a.k0 = k0;
   a.K = K;
   a.check_every = check_every;
