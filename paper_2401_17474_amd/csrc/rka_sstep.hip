@@ -67,7 +67,7 @@ struct SstepArgs {
   int32_t nv_max;     // exchange values of a full block
   int32_t tr;         // lanes per row for the slice sums of the dot products
   int32_t trp;        // lanes per value in the reduce-scatter
-  int32_t trs;        // lanes per row for the scale sums
+  int32_t trs;        // lanes per row for the scale sums (one wave: trs q <= 64)
   int32_t cg;         // lanes (column groups) per 4 x 4 tile of inner products
   int32_t pg_in_s;    // the reduce-scatter gathers into the row-slice buffer
   int32_t pg_len;     // its own buffer's length otherwise
@@ -117,6 +117,15 @@ __device__ __forceinline__ int sv_gram(int L, int q, int j, int l) {
 __device__ __forceinline__ int svb_count(int q, int bs) { return q * bs + q * (bs * (bs - 1) / 2) + 1; }
 __device__ __forceinline__ int svb_pair(int q, int bs, int w, int jb, int jb2) {
   return q * bs + w * (bs * (bs - 1) / 2) + jb * (jb - 1) / 2 + jb2;
+}
+
+// Orders a wave's LDS writes before its later LDS reads by other lanes of
+// the same wave: the LDS serves one wave's accesses in order, the fences keep
+// the compiler from moving them.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // B: the RKAB instance (separate, so that the RKA instance carries none of
@@ -571,48 +580,52 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
     // the scales, one iteration of the block after the other:
     // D_{j,r} = <a_{j,r}, x^(k)> + (1/q) sum_{l<j} sum_s s_{l,s} <a_{j,r}, a_{l,s}>
     // (RKAB: one worker's projections after the other, weight 1:
-    //  D_{w,jb} = <a_{w,jb}, v_w> + sum_{jb'<jb} s_{w,jb'} <a_{w,jb}, a_{w,jb'}>)
-    if (!B) {
-      const int TR = p.trs, team = t / TR, u = t & (TR - 1), nteams = NT / TR;
-      for (int jj = 0; jj < L; ++jj) {
-        for (int r0 = 0; r0 < q; r0 += nteams) {
-          const int r = r0 + team;
-          double acc = 0.0;
-          if (r < q) {
-            const int nterm = jj * q;
-            for (int f = u; f < nterm; f += TR) {
-              const int l = f / q, s = f - l * q;
-              acc = fma(SC[l * q + s], HV[sv_gram(L, q, jj, l) + r * q + s], acc);
+    //  D_{w,jb} = <a_{w,jb}, v_w> + sum_{jb'<jb} s_{w,jb'} <a_{w,jb}, a_{w,jb'}>).
+    // The rounds are short and dependent, so one wave runs them (teams of trs
+    // lanes per row, trs q <= 64) with no workgroup barrier between rounds;
+    // one barrier hands the scales to the other waves.
+    if (t < kWave) {
+      const int TR = p.trs, team = t / TR, u = t & (TR - 1), nteams = kWave / TR;
+      if (!B) {
+        for (int jj = 0; jj < L; ++jj) {
+          for (int r0 = 0; r0 < q; r0 += nteams) {
+            const int r = r0 + team;
+            double acc = 0.0;
+            if (r < q)
+              for (int l = 0; l < jj; ++l) {
+                const double* Gr = HV + sv_gram(L, q, jj, l) + r * q;
+                const double* Sl = SC + l * q;
+                for (int s = u; s < q; s += TR) acc = fma(Sl[s], Gr[s], acc);
+              }
+            acc = team_sum(acc, TR);
+            if (u == 0 && r < q) {
+              const int br = jj * q + r;
+              const double D = HV[br] + p.inv_q * acc;
+              SC[br] = RA[br] * (RB[br] - D) / RW[br];
             }
           }
-          acc = team_sum(acc, TR);
-          if (u == 0 && r < q) {
-            const int br = jj * q + r;
-            const double D = HV[br] + p.inv_q * acc;
-            SC[br] = RA[br] * (RB[br] - D) / RW[br];
-          }
+          wave_lds_sync();
         }
-        __syncthreads();
-      }
-    } else {
-      const int TR = p.trs, team = t / TR, u = t & (TR - 1), nteams = NT / TR;
-      for (int jb = 0; jb < cs; ++jb) {
-        for (int w0 = 0; w0 < q; w0 += nteams) {
-          const int w = w0 + team;
-          double acc = 0.0;
-          if (w < q)
-            for (int f = u; f < jb; f += TR)
-              acc = fma(SC[w * cs + f], HV[svb_pair(q, cs, w, jb, f)], acc);
-          acc = team_sum(acc, TR);
-          if (u == 0 && w < q) {
-            const int br = w * cs + jb;
-            const double D = HV[br] + acc;
-            SC[br] = RA[br] * (RB[br] - D) / RW[br];
+      } else {
+        for (int jb = 0; jb < cs; ++jb) {
+          for (int w0 = 0; w0 < q; w0 += nteams) {
+            const int w = w0 + team;
+            double acc = 0.0;
+            if (w < q)
+              for (int f = u; f < jb; f += TR)
+                acc = fma(SC[w * cs + f], HV[svb_pair(q, cs, w, jb, f)], acc);
+            acc = team_sum(acc, TR);
+            if (u == 0 && w < q) {
+              const int br = w * cs + jb;
+              const double D = HV[br] + acc;
+              SC[br] = RA[br] * (RB[br] - D) / RW[br];
+            }
           }
+          wave_lds_sync();
         }
-        __syncthreads();
       }
     }
+    __syncthreads();
     SPROF(5);
     if (B) {
       // each worker's slice: v_w += sum_jj s_{w,jj} A[i_{w,jj}, slice], rows in order
@@ -810,7 +823,7 @@ static bool sstep_plan_at(const SolveShape& sh, int p_req, int c, RkaSstepGeom* 
   geo->trp = trp;
   geo->pg_in_s = pg_in_s ? 1 : 0;
   geo->pg_len = pg_in_s ? 0 : (int)gathered;
-  geo->trs = pow2_floor_cap(nt / sh.q, kWave);
+  geo->trs = pow2_floor_cap(kWave / sh.q, kWave);
   geo->cg = pow2_floor_cap(std::min<int64_t>(ntile > 0 ? nt / ntile : nt, W), 16);
   return true;
 }
