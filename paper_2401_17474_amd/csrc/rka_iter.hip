@@ -393,30 +393,40 @@ static int rpt_bucket(int need) {
   return 0;
 }
 
-// Column slices: one workgroup per CU by default, except for small q.
-// Measured on MI355X at 80000 x 10000 FP64 (team reductions in place): q = 64
-// and 256 are fastest on the widest grid (the exchange latency and the
-// in-workgroup work per iteration, not the HBM fetch granularity, set the
-// time); at q = 16 and below 48 workgroups take 5.5 us per iteration against
-// 7.0 us on 250, since the rows of one iteration are few and the exchange
-// with fewer participants is shorter.  Tiny problems (<= 64 KB of rows per
-// iteration, one slice that fits a workgroup) run in one workgroup with no
-// exchange at all.
+// Column slices.  Measured on MI355X with FP64 storage: at q = 16 and below
+// 48 workgroups take 5.5 us per iteration against 7.0 us on 250 (80000 x
+// 10000), since the rows of one iteration are few and the exchange with fewer
+// participants is shorter; for q = 32 .. 128 about 5/8 of the CUs is fastest
+// (q = 64: 8.3 us on 157 workgroups against 8.7 on 250 at 80000 x 10000, 9.5
+// against 9.8 on 179 at 200000 x 20000), and where the q rows do not fit
+// the tiles of that grid the full grid takes them (q = 256 at 80000 x
+// 10000).  Other storage types keep one workgroup per CU.  Tiny problems
+// (<= 64 KB of rows per iteration, one slice that fits a workgroup) run in
+// one workgroup with no exchange at all.
 constexpr int kSmallQ = 16;
 constexpr int kSmallQGrid = 48;
+constexpr int kWideGridNum = 5, kWideGridDen = 8;
 constexpr int64_t kOneGroupBytes = 64 << 10;
 // one-barrier all-gather while every workgroup reads at most this many partials
 constexpr int kGatherMax = 2048;
 
+static bool col_plan_at(const SolveShape& sh, int target, RkaColGeom* geo);
+
 bool rka_col_plan(const SolveShape& sh, RkaColGeom* geo) {
+  const int esz = sh.dtype == 0 ? 8 : (sh.dtype == 1 ? 4 : 2);
+  const int64_t bytes_per_iter = (int64_t)sh.q * sh.n * esz;
+  if (sh.grid > 0) return col_plan_at(sh, sh.grid, geo);
+  if (bytes_per_iter <= kOneGroupBytes) return col_plan_at(sh, 1, geo);
+  if (sh.q <= kSmallQ) return col_plan_at(sh, std::min(sh.num_cu, kSmallQGrid), geo);
+  if (sh.dtype == 0 && col_plan_at(sh, sh.num_cu * kWideGridNum / kWideGridDen, geo)) return true;
+  return col_plan_at(sh, sh.num_cu, geo);
+}
+
+static bool col_plan_at(const SolveShape& sh, int target, RkaColGeom* geo) {
   const int esz = sh.dtype == 0 ? 8 : (sh.dtype == 1 ? 4 : 2);
   const int V = sh.vec_ok ? 16 / esz : 1;
   const int64_t nvec = sh.n / V;
-  const int64_t bytes_per_iter = (int64_t)sh.q * sh.n * esz;
   int G, nsv;
-  int target = sh.grid > 0 ? sh.grid : sh.num_cu;
-  if (sh.grid == 0 && sh.q <= kSmallQ) target = std::min(sh.num_cu, kSmallQGrid);
-  if (sh.grid == 0 && bytes_per_iter <= kOneGroupBytes) target = 1;
   if (target == 1 && nvec <= kMaxColThreads) {
     G = 1;
     nsv = (int)nvec;
