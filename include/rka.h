@@ -436,6 +436,18 @@ int rka_batch_solve(const rka_batch_system* systems, int32_t count, int dtype, u
                     void* stream, rka_batch_result* results, rka_batch_stats* stats);
 
 /*
+ * rka_batch_sample_indices -- parity hook of the batching form: runs the set-up
+ * and the row-stream launches of rka_batch_solve (same chunks of chunk_iters
+ * iterations, 0 = the library's chunk length) without iterating, and copies
+ * the draws: system i's max_iter * q * block_size row indices, layout
+ * [(k * q + w) * block_size + j] as rka_sample_indices, at idx + sum over
+ * j < i of max_iter_j * q_j * block_size_j (device int32).  Every system must
+ * give q >= 1 and block_size >= 1; x is not touched.  Waits for the stream.
+ */
+int rka_batch_sample_indices(const rka_batch_system* systems, int32_t count, int dtype,
+                             uint64_t seed, int64_t chunk_iters, int32_t* idx, void* stream);
+
+/*
  * rka_batch_refine_solve -- the batch with FP64 iterative refinement (the
  * precision form of rka_refine_solve, for consistent systems): per sweep s,
  * r = b - A x in FP64 for every system and right-hand side, then one batch
@@ -482,6 +494,81 @@ int rka_batch_tune(rka_batch_system* systems, int32_t count, int dtype, uint64_t
  */
 int rka_sample_blocks(const double* w, int64_t m, uint64_t seed, int64_t iter_offset, int64_t K,
                       int32_t q, int32_t bs, int32_t dom, int32_t* idx, void* stream);
+
+/*
+ * Plans: the sampling distribution of Eq. (4) as a per-matrix object.  A plan
+ * holds, on the device it was made on, the squared row norms w_l of A
+ * (rka_row_norms' order), their running sum c (rka_prefix's order), W =
+ * ||A||_F^2 and the last row of positive weight, computed once; every solve,
+ * refinement and row stream over the same A then skips that set-up (a pass
+ * over A and a sequential sum over its m rows).  The plan refers to A by
+ * pointer: A must stay allocated and unchanged while the plan is used.
+ */
+typedef struct rka_plan rka_plan;
+
+/*
+ * rka_plan_create -- make a plan for A (layout and dtype as in rka_solve):
+ * allocates 16 m + 264 bytes of device memory (hipMalloc), enqueues the row
+ * norms and the running sum on `stream` and waits for it to read W back.
+ * *plan receives the handle (NULL on failure).  RKA_EZERONORM if W is zero
+ * or not finite (nothing is kept), RKA_ENOMEM if the allocation fails.
+ */
+int rka_plan_create(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, void* stream,
+                    rka_plan** plan);
+
+/* rka_plan_destroy -- free a plan's device memory (hipFree, which waits for
+ * the device); NULL is accepted.  No call may still use the plan. */
+int rka_plan_destroy(rka_plan* plan);
+
+/* rka_plan_query -- m, n, ||A||_F^2 and the last row of positive weight of a
+ * plan (each output nullable; last_pos is read from the device, waiting for
+ * the null stream). */
+int rka_plan_query(const rka_plan* plan, int64_t* m, int64_t* n, double* fro2, int64_t* last_pos);
+
+/* rka_plan_row_norms -- copy the plan's m squared row norms (Eq. (4)
+ * numerators, as rka_row_norms computes them) to w (m doubles, device).
+ * Enqueue only. */
+int rka_plan_row_norms(const rka_plan* plan, double* w, void* stream);
+
+/* rka_plan_sample_indices -- the row stream of rka_sample_indices (same
+ * counters, same layout idx[(k*q + w)*bs + j]) from the plan's running sum.
+ * Enqueue only. */
+int rka_plan_sample_indices(const rka_plan* plan, uint64_t seed, int64_t iter_offset, int64_t K,
+                            int32_t q, int32_t bs, int32_t dom, int32_t* idx, void* stream);
+
+/*
+ * rka_plan_solve -- rka_solve_ex on the plan's matrix: the same iteration,
+ * options and results (bitwise: the plan's norms and running sum are the
+ * ones the solve would compute), without the per-call set-up.  With
+ * opts->sampling = 1 (Distributed Approach) the running sum is still
+ * restarted per worker block, from the plan's norms.
+ */
+int rka_plan_solve(const rka_plan* plan, const double* b, const double* x0, double* x,
+                   int32_t method, int32_t q, int32_t block_size, double alpha, int64_t max_iter,
+                   double tol, uint64_t seed, const double* x_ref, int64_t iter_offset,
+                   const rka_opts* opts, void* stream, rka_info* info, rka_stats* stats);
+
+/*
+ * rka_plan_refine_solve -- rka_refine_solve on the plans of A and of its
+ * transpose At (pAt nullable when opts->range_iters == 0; else a plan of the
+ * n x m transpose, same dtype).  rka_refine_solve itself builds both plans
+ * once per call, in stream-ordered scratch.
+ */
+int rka_plan_refine_solve(const rka_plan* pA, const rka_plan* pAt, const double* b,
+                          const double* x0, double* x, const rka_refine_opts* opts, uint64_t seed,
+                          const double* x_ref, double* sweep_measure, void* stream,
+                          rka_refine_info* info);
+
+/*
+ * rka_alpha_star -- the optimal uniform weight of Eq. (6) (Sec. 2.3.1) for q
+ * workers, from s_min = sigma_min^2 / ||A||_F^2 and s_max = sigma_max^2 /
+ * ||A||_F^2 (rka_spectral_bounds):
+ *     alpha* = q / (1 + (q-1) s_min)                if s_max - s_min <= 1/(q-1),
+ *     alpha* = 2q / (1 + (q-1) (s_min + s_max))     otherwise
+ * (q = 1 takes the first case).  *alpha (host) receives it; RKA_EINVAL
+ * unless q >= 1 and 0 <= s_min <= s_max <= 1.
+ */
+int rka_alpha_star(double s_min, double s_max, int32_t q, double* alpha);
 
 /* Name of a status code (static string). */
 const char* rka_status_string(int status);

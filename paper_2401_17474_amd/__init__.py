@@ -130,6 +130,8 @@ def lib():
                                              U64, D, I64, I32, I32, P,
                                              ctypes.POINTER(_BatchResult),
                                              ctypes.POINTER(_BatchStats)]
+        L.rka_batch_sample_indices.argtypes = [ctypes.POINTER(_BatchSystem), I32, ctypes.c_int,
+                                               U64, I64, P, P]
         L.rka_batch_tune.argtypes = [ctypes.POINTER(_BatchSystem), I32, ctypes.c_int, U64, P,
                                      ctypes.POINTER(I32)]
         L.rka_gemv_t.argtypes = [P, ctypes.c_int, I64, I64, I64, P, P, D, P, P]
@@ -138,6 +140,19 @@ def lib():
                                           ctypes.POINTER(D)]
         L.rka_partial_alpha.argtypes = [P, ctypes.c_int, I64, I64, I64, I32, I32, U64, P, P]
         L.rka_sample_blocks.argtypes = [P, I64, U64, I64, I64, I32, I32, I32, P, P]
+        PP = ctypes.POINTER(ctypes.c_void_p)
+        L.rka_plan_create.argtypes = [P, ctypes.c_int, I64, I64, I64, P, PP]
+        L.rka_plan_destroy.argtypes = [P]
+        L.rka_plan_query.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64),
+                                     ctypes.POINTER(D), ctypes.POINTER(I64)]
+        L.rka_plan_row_norms.argtypes = [P, P, P]
+        L.rka_plan_sample_indices.argtypes = [P, U64, I64, I64, I32, I32, I32, P, P]
+        L.rka_plan_solve.argtypes = [P, P, P, P, I32, I32, I32, D, I64, D, U64, P, I64,
+                                     ctypes.POINTER(_Opts), P, ctypes.POINTER(_Info),
+                                     ctypes.POINTER(_Stats)]
+        L.rka_plan_refine_solve.argtypes = [P, P, P, P, P, ctypes.POINTER(_RefineOpts), U64, P,
+                                            P, P, ctypes.POINTER(_RefineInfo)]
+        L.rka_alpha_star.argtypes = [D, D, I32, ctypes.POINTER(D)]
         L.rka_status_string.argtypes = [ctypes.c_int]
         L.rka_status_string.restype = ctypes.c_char_p
         L.rka_last_error.argtypes = []
@@ -147,7 +162,10 @@ def lib():
                   "rka_sample_indices", "rka_gemv", "rka_transpose", "rka_lsq_grad_A",
                   "rka_refine_solve", "rka_batch_solve", "rka_batch_tune",
                   "rka_batch_refine_solve", "rka_gemv_t", "rka_spectral_bounds",
-                  "rka_partial_alpha", "rka_sample_blocks"):
+                  "rka_partial_alpha", "rka_sample_blocks", "rka_plan_create",
+                  "rka_plan_destroy", "rka_plan_query", "rka_plan_row_norms",
+                  "rka_plan_sample_indices", "rka_plan_solve", "rka_plan_refine_solve",
+                  "rka_alpha_star", "rka_batch_sample_indices"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -267,10 +285,21 @@ def solve_ex(A, b, *, method, q, block_size=1, alpha=1.0, max_iter=1000, tol=0.0
     (RKA) runs blocks of up to that many iterations per exchange between
     workgroups (0: the library's choice, 1: one); ``rkab_split`` (RKAB) picks
     the worker-split (1) or column-split (2) kernel (0: the library's choice)."""
-    torch = _torch()
     code, m, n, lda = _matrix(A)
+    return _solve_ex_call(lambda b_, x0_, x_, opts, info, stats: lib().rka_solve_ex(
+        _ptr(A), code, m, n, lda, b_, x0_, x_, method, q, block_size, alpha, max_iter, tol, seed,
+        _ptr(_vec(x_ref, n, "x_ref")), iter_offset, ctypes.byref(opts), _stream(stream),
+        ctypes.byref(info), ctypes.byref(stats)), A.device, m, n, b, x0, out, q, check_every,
+        grid, timing, allreduce, accumulate, stream_id, sampling, worker_alpha, row_weight,
+        steps_per_exchange, rkab_split, raise_on_error)
+
+
+def _solve_ex_call(call, device, m, n, b, x0, out, q, check_every, grid, timing, allreduce,
+                   accumulate, stream_id, sampling, worker_alpha, row_weight,
+                   steps_per_exchange, rkab_split, raise_on_error):
+    torch = _torch()
     b = _vec(b, m, "b", False)
-    x = out if out is not None else torch.empty(n, dtype=torch.float64, device=A.device)
+    x = out if out is not None else torch.empty(n, dtype=torch.float64, device=device)
     _vec(x, n, "out", False)
     info, stats = _Info(), _Stats()
     if worker_alpha is not None:
@@ -281,14 +310,79 @@ def solve_ex(A, b, *, method, q, block_size=1, alpha=1.0, max_iter=1000, tol=0.0
                  sampling, None if worker_alpha is None else worker_alpha.data_ptr(),
                  None if row_weight is None else row_weight.data_ptr(), steps_per_exchange,
                  rkab_split)
-    st = lib().rka_solve_ex(_ptr(A), code, m, n, lda, _ptr(b), _ptr(_vec(x0, n, "x0")), _ptr(x),
-                            method, q, block_size, alpha, max_iter, tol, seed,
-                            _ptr(_vec(x_ref, n, "x_ref")), iter_offset, ctypes.byref(opts),
-                            _stream(stream), ctypes.byref(info), ctypes.byref(stats))
+    st = call(_ptr(b), _ptr(_vec(x0, n, "x0")), _ptr(x), opts, info, stats)
     if raise_on_error:
         _raise_if(st)
     sd = {f: getattr(stats, f) for f, _ in _Stats._fields_}
     return x, Info(info.iterations, info.projections, info.rel_err, st), sd
+
+
+class Plan:
+    """rka_plan_create: the squared row norms, running sum, ||A||_F^2 and last
+    positive row of A (Eq. (4)), computed once on the device and reused by
+    every solve, refinement and row stream over A.  Keeps a reference to A
+    (the plan points into its storage).  Freed by close() or when collected."""
+
+    def __init__(self, A, stream=None):
+        code, m, n, lda = _matrix(A)
+        h = ctypes.c_void_p()
+        _raise_if(lib().rka_plan_create(_ptr(A), code, m, n, lda, _stream(stream),
+                                        ctypes.byref(h)))
+        self._h, self.A, self.m, self.n = h, A, m, n
+        f = ctypes.c_double()
+        _raise_if(lib().rka_plan_query(h, None, None, ctypes.byref(f), None))
+        self.fro2 = f.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _raise_if(lib().rka_plan_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        if self._h is None or not self._h.value:
+            raise ValueError("the plan has been closed")
+        return self._h
+
+    def last_pos(self):
+        v = ctypes.c_int64()
+        _raise_if(lib().rka_plan_query(self.handle, None, None, None, ctypes.byref(v)))
+        return v.value
+
+    def row_norms(self, stream=None):
+        """The plan's squared row norms as a float64 GPU tensor (a copy)."""
+        torch = _torch()
+        w = torch.empty(self.m, dtype=torch.float64, device=self.A.device)
+        _raise_if(lib().rka_plan_row_norms(self.handle, _ptr(w), _stream(stream)))
+        return w
+
+    def sample_indices(self, *, seed, iter_offset=0, K, q, bs=1, dom=0, stream=None):
+        """The row stream from the plan's running sum (rka_plan_sample_indices)."""
+        torch = _torch()
+        idx = torch.empty(K * q * bs, dtype=torch.int32, device=self.A.device)
+        _raise_if(lib().rka_plan_sample_indices(self.handle, seed, iter_offset, K, q, bs, dom,
+                                                _ptr(idx), _stream(stream)))
+        return idx
+
+    def solve(self, b, *, method, q, block_size=1, alpha=1.0, max_iter=1000, tol=0.0, seed=1,
+              x0=None, x_ref=None, iter_offset=0, check_every=1, grid=0, allreduce=0,
+              timing=False, accumulate=0, stream_id=0, sampling=0, worker_alpha=None,
+              row_weight=None, steps_per_exchange=0, rkab_split=0, out=None, stream=None,
+              raise_on_error=True):
+        """rka_plan_solve: solve_ex on the plan's matrix without the per-call set-up."""
+        h = self.handle
+        return _solve_ex_call(lambda b_, x0_, x_, opts, info, stats: lib().rka_plan_solve(
+            h, b_, x0_, x_, method, q, block_size, alpha, max_iter, tol, seed,
+            _ptr(_vec(x_ref, self.n, "x_ref")), iter_offset, ctypes.byref(opts), _stream(stream),
+            ctypes.byref(info), ctypes.byref(stats)), self.A.device, self.m, self.n, b, x0, out,
+            q, check_every, grid, timing, allreduce, accumulate, stream_id, sampling,
+            worker_alpha, row_weight, steps_per_exchange, rkab_split, raise_on_error)
 
 
 def row_norms(A, stream=None):
@@ -420,11 +514,19 @@ class RefineInfo:
 def refine_solve(A, b, *, At=None, method=0, q, block_size=1, accumulate=1, alpha=1.0,
                  inner_iters, range_iters=0, range_q=1, range_alpha=1.0, max_sweeps=4,
                  tol=0.0, seed=1, x0=None, x_ref=None, out=None, stream=None,
-                 raise_on_error=True):
+                 raise_on_error=True, plan=None, plan_t=None):
     """rka_refine_solve: FP64 refinement sweeps around inner RKA/RKAB solves
     (optionally FP32), with the residual projected onto range(A) by a column
-    solve on ``At`` when ``range_iters`` > 0.  Returns (x, RefineInfo)."""
+    solve on ``At`` when ``range_iters`` > 0.  With ``plan`` (a Plan of A) and
+    ``plan_t`` (a Plan of At) the norms and running sums come from the plans
+    (rka_plan_refine_solve).  Returns (x, RefineInfo)."""
     torch = _torch()
+    if plan is not None:
+        A = plan.A
+        if range_iters > 0 and plan_t is None:
+            raise ValueError("with plan and range_iters > 0, give plan_t (a Plan of At)")
+        if plan_t is not None:
+            At = plan_t.A
     code, m, n, lda = _matrix(A)
     ldat = 0
     if At is not None:
@@ -438,10 +540,16 @@ def refine_solve(A, b, *, At=None, method=0, q, block_size=1, accumulate=1, alph
                     max_sweeps, range_alpha, tol)
     meas = (ctypes.c_double * max_sweeps)()
     info = _RefineInfo()
-    st = lib().rka_refine_solve(_ptr(A), _ptr(At), code, m, n, lda, ldat, _ptr(b),
-                                _ptr(_vec(x0, n, "x0")), _ptr(x), ctypes.byref(o), seed,
-                                _ptr(_vec(x_ref, n, "x_ref")), meas, _stream(stream),
-                                ctypes.byref(info))
+    if plan is not None:
+        st = lib().rka_plan_refine_solve(plan.handle, None if plan_t is None else plan_t.handle,
+                                         _ptr(b), _ptr(_vec(x0, n, "x0")), _ptr(x),
+                                         ctypes.byref(o), seed, _ptr(_vec(x_ref, n, "x_ref")),
+                                         meas, _stream(stream), ctypes.byref(info))
+    else:
+        st = lib().rka_refine_solve(_ptr(A), _ptr(At), code, m, n, lda, ldat, _ptr(b),
+                                    _ptr(_vec(x0, n, "x0")), _ptr(x), ctypes.byref(o), seed,
+                                    _ptr(_vec(x_ref, n, "x_ref")), meas, _stream(stream),
+                                    ctypes.byref(info))
     if raise_on_error:
         _raise_if(st)
     return x, RefineInfo(info.sweeps, st, info.rel, info.projections,
@@ -510,6 +618,23 @@ def batch_tune(systems, *, seed=1, stream=None):
     return trials.value
 
 
+def batch_sample_indices(systems, *, seed=1, chunk_iters=0, stream=None):
+    """rka_batch_sample_indices: the row streams a batch solve would draw
+    (every system must give q and block_size), as one int32 GPU tensor per
+    system of max_iter * q * block_size indices."""
+    torch = _torch()
+    arr, code = _batch_array(systems)
+    sizes = [S.max_iter * S.q * S.block_size for S in systems]
+    idx = torch.empty(max(1, sum(sizes)), dtype=torch.int32, device=systems[0].A.device)
+    _raise_if(lib().rka_batch_sample_indices(arr, len(systems), code, seed, chunk_iters,
+                                             _ptr(idx), _stream(stream)))
+    out, off = [], 0
+    for z in sizes:
+        out.append(idx[off:off + z])
+        off += z
+    return out
+
+
 def batch_solve(systems, *, seed=1, tol=0.0, check_every=1, chunk_iters=0, graph=True,
                 refine_sweeps=0, stream=None, raise_on_error=True):
     """rka_batch_solve (or, with refine_sweeps > 0, rka_batch_refine_solve)
@@ -547,8 +672,9 @@ def batch_solve(systems, *, seed=1, tol=0.0, check_every=1, chunk_iters=0, graph
 # -- host helpers --------------------------------------------------------------
 
 def alpha_star(s_min: float, s_max: float, q: int) -> float:
-    """Optimal uniform weight for consistent systems, Eq. (6) (Sec. 2.3.1):
-    s = sigma^2(A) / ||A||_F^2 at the extreme singular values."""
-    if q == 1 or s_max - s_min <= 1.0 / (q - 1):  # q = 1: the first case always holds
-        return q / (1.0 + (q - 1) * s_min)
-    return 2.0 * q / (1.0 + (q - 1) * (s_min + s_max))
+    """Optimal uniform weight for consistent systems, Eq. (6) (Sec. 2.3.1),
+    from s = sigma^2(A) / ||A||_F^2 at the extreme singular values
+    (rka_alpha_star)."""
+    a = ctypes.c_double()
+    _raise_if(lib().rka_alpha_star(float(s_min), float(s_max), int(q), ctypes.byref(a)))
+    return a.value

@@ -17,13 +17,15 @@ g = dL/dx,
 
 Every step runs in the library's kernels through the C ABI; this module only
 sequences the calls.  The forward and the two backward solves draw their
-rows from independent streams (seeds seed, seed + 1, seed + 2).
+rows from independent streams (seeds seed, seed + 1, seed + 2).  The forward
+makes one plan of A and one of A^T (row norms and running sums, Eq. (4)),
+which the backward's solves reuse.
 """
 from __future__ import annotations
 
 from dataclasses import dataclass
 
-from . import gemv, lsq_grad_A, refine_solve, transpose
+from . import Plan, gemv, lsq_grad_A, refine_solve, transpose
 
 
 @dataclass
@@ -43,14 +45,17 @@ def _torch():
     return torch
 
 
-def _solve(M, rhs, o: SolveOpts, seed, Mt=None, range_iters=0, acc=None):
+def _solve(P, rhs, o: SolveOpts, seed, Pt=None, range_iters=0, acc=None):
+    """Refined solve on the plan P's matrix (Pt: plan of its transpose, for
+    the range projection)."""
     if acc is None:
         acc = o.accumulate
-    if M.dtype == _torch().float64:
+    if P.A.dtype == _torch().float64:
         acc = 0
-    x, info = refine_solve(M, rhs, At=Mt, method=0, q=o.q, accumulate=acc, alpha=o.alpha,
-                           inner_iters=o.inner_iters, range_iters=range_iters, range_q=o.q,
-                           range_alpha=o.alpha, max_sweeps=o.sweeps, tol=o.tol, seed=seed)
+    x, info = refine_solve(None, rhs, plan=P, plan_t=Pt, method=0, q=o.q, accumulate=acc,
+                           alpha=o.alpha, inner_iters=o.inner_iters, range_iters=range_iters,
+                           range_q=o.q, range_alpha=o.alpha, max_sweeps=o.sweeps, tol=o.tol,
+                           seed=seed)
     return x, info
 
 
@@ -62,8 +67,10 @@ class RKASolve(_torch().autograd.Function):
     def forward(ctx, A, b, opts=None):
         o = opts or SolveOpts()
         At = transpose(A)
-        x, info = _solve(A, b, o, o.seed, Mt=At, range_iters=o.range_iters)
+        PA, PT = Plan(A), Plan(At)
+        x, info = _solve(PA, b, o, o.seed, Pt=PT, range_iters=o.range_iters)
         ctx.save_for_backward(A, At, b, x)
+        ctx.plans = (PA, PT)
         ctx.opts = o
         ctx.forward_info = info
         return x
@@ -72,13 +79,14 @@ class RKASolve(_torch().autograd.Function):
     def backward(ctx, gx):
         torch = _torch()
         A, At, b, x = ctx.saved_tensors
+        PA, PT = ctx.plans
         o = ctx.opts
         g = gx.to(torch.float64).contiguous()
         # min-norm A^T z = g.  Always FP64 arithmetic: rounding errors of the
         # updates land mostly in null(A^T), which the residual g - A^T z
         # cannot see, so refinement would never remove binary32 ones.
-        z, _ = _solve(At, g, o, o.seed + 1, acc=0)
-        lam, _ = _solve(A, z, o, o.seed + 2)           # A lambda = z
+        z, _ = _solve(PT, g, o, o.seed + 1, acc=0)
+        lam, _ = _solve(PA, z, o, o.seed + 2)          # A lambda = z
         r = gemv(A, x, c=b, gamma=-1.0)                # r = b - A x
         dA = lsq_grad_A(r, lam, z, x, dtype=A.dtype if A.dtype == torch.float64
                         else torch.float32)

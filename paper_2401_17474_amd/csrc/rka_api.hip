@@ -14,11 +14,28 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <new>
 #include <string>
 
 #include "rka.h"
 #include "rka_device.hpp"
 #include "rka_internal.hpp"
+
+// A plan (rka_plan_create): the squared row norms of one matrix, their
+// running sum and its last row of positive weight (Eq. (4)), computed once
+// and kept on the device for every solve and row stream over that matrix.
+struct rka_plan {
+  const void* A;
+  int dtype;
+  int64_t m, n, lda;
+  bool vec_ok;
+  int device;
+  double* w;          // m squared row norms
+  double* c;          // m running sums; c[m-1] = ||A||_F^2
+  int64_t* last_pos;  // the largest row with w > 0
+  double fro2;        // ||A||_F^2, read back at creation
+  void* mem;          // one allocation holding w, c and last_pos (public plans)
+};
 
 namespace {
 
@@ -51,16 +68,28 @@ int num_cus() {
   return cus;
 }
 
-// Stream-ordered scratch for one call; freed (on the stream) by release().
+// Scratch for one call: stream-ordered allocations freed (on the stream) by
+// release(), or -- arena mode -- pieces of caller-provided device memory
+// (256-byte aligned) that nothing frees.
 struct Scratch {
   hipStream_t s;
+  char* arena = nullptr;
+  size_t cap = 0, used = 0;
   void* ptrs[16];
   int n = 0;
   explicit Scratch(hipStream_t st) : s(st) {}
+  Scratch(hipStream_t st, void* base, size_t bytes) : s(st), arena((char*)base), cap(bytes) {}
+  static size_t round(size_t b) { return (b + 255) & ~(size_t)255; }
   template <typename U>
   hipError_t get(U** out, size_t count) {
-    void* p = nullptr;
     const size_t bytes = count * sizeof(U) > 0 ? count * sizeof(U) : 16;
+    if (arena) {
+      if (used + round(bytes) > cap) return hipErrorOutOfMemory;
+      *out = (U*)(arena + used);
+      used += round(bytes);
+      return hipSuccess;
+    }
+    void* p = nullptr;
     hipError_t e = hipMallocAsync(&p, bytes, s);
     if (e != hipSuccess) return e;
     ptrs[n++] = p;
@@ -174,7 +203,8 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
                int64_t max_iter, double tol, uint64_t seed, const double* x_ref,
                int64_t iter_offset, int64_t check_every, int grid, int allreduce, bool timing,
                int acc, int dom, int sampling, const double* walpha, const double* wrow,
-               int sstep, int split, void* stream, rka_info* info, rka_stats* stats) {
+               int sstep, int split, void* stream, rka_info* info, rka_stats* stats,
+               const rka_plan* plan = nullptr, void* arena = nullptr, size_t arena_bytes = 0) {
   g_last_error.clear();
   if (stats) memset(stats, 0, sizeof *stats);
   if (info) {
@@ -257,7 +287,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
                   (long long)n);
   }
 
-  Scratch sc(s);
+  Scratch sc = arena ? Scratch(s, arena, arena_bytes) : Scratch(s);
   rka::DevStatus* st;
   double *w, *c, *part;
   void* vbuf = nullptr;
@@ -275,51 +305,87 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
     const size_t rb = (size_t)rka::resid_blocks(m);
     if (rb > part_len) part_len = rb;
   }
-  HIP_TRY(sc.get(&st, 1));
-  HIP_TRY(sc.get(&w, (size_t)m));
-  HIP_TRY(sc.get(&c, (size_t)m));
-  HIP_TRY(sc.get(&last_pos, sampling == rka::kSampleBlocks ? (size_t)q : 1));
-  HIP_TRY(sc.get(&rec, (size_t)(kc_max * per_iter)));
-  HIP_TRY(sc.get(&part, part_len));
-  HIP_TRY(sc.get(&bar, 1));
-  size_t nslots = 0, nsslots = 0;
+  // a plan brings the norms and the running sum; the Distributed Approach
+  // still restarts the running sum at every worker's block
+  const bool own_norms = plan == nullptr;
+  const bool own_prefix = plan == nullptr || sampling == rka::kSampleBlocks;
+  const size_t n_last = sampling == rka::kSampleBlocks ? (size_t)q : 1;
+  size_t nslots = 0, nsslots = 0, vb = 0;
   if (use_sstep) {
     nslots = (size_t)sgeo.G * sgeo.nv;
     nsslots = (size_t)sgeo.nv;
-    HIP_TRY(sc.get(&slots, 2 * nslots));
-    HIP_TRY(sc.get(&sslots, 2 * nsslots));
   } else if (use_col) {
     // 16-byte slots: 2 words each
     nslots = (size_t)(cgeo.gather ? 2 : 1) * G * (q + 1);
     nsslots = (size_t)q + 1;
+  } else {
+    vb = (size_t)q * (size_t)n * (acc == 1 ? sizeof(float) : sizeof(double));
+  }
+  if (arena) {
+    // the fixed buffers first, then as many iterations of row records per
+    // chunk as the rest holds (at most the stream-ordered path's chunk)
+    auto R = [](size_t b) { return Scratch::round(b > 0 ? b : 16); };
+    size_t fixed = R(sizeof(rka::DevStatus)) + R(part_len * 8) + R(8);
+    if (own_norms) fixed += R((size_t)m * 8);
+    if (own_prefix) fixed += R((size_t)m * 8) + R(n_last * 8);
+    if (nslots) fixed += R(32 * nslots) + R(32 * nsslots);
+    if (vb) fixed += R(vb);
+    const size_t per_rec_iter = sizeof(rka::RowRec) * (size_t)per_iter;
+    const int64_t fit =
+        arena_bytes > fixed + 256 ? (int64_t)((arena_bytes - fixed - 256) / per_rec_iter) : 0;
+    if (fit < 1)
+      return fail(RKA_EINVAL,
+                  "the problem needs %zu bytes of scratch for its fixed buffers plus %zu per "
+                  "iteration of row records; the allocation-free scratch holds %zu",
+                  fixed, per_rec_iter, arena_bytes);
+    if (kc_max > fit) kc_max = fit;
+  }
+  HIP_TRY(sc.get(&st, 1));
+  if (own_norms)
+    HIP_TRY(sc.get(&w, (size_t)m));
+  else
+    w = plan->w;
+  if (own_prefix) {
+    HIP_TRY(sc.get(&c, (size_t)m));
+    HIP_TRY(sc.get(&last_pos, n_last));
+  } else {
+    c = plan->c;
+    last_pos = plan->last_pos;
+  }
+  HIP_TRY(sc.get(&rec, (size_t)(kc_max * per_iter)));
+  HIP_TRY(sc.get(&part, part_len));
+  HIP_TRY(sc.get(&bar, 2));
+  if (nslots) {
     HIP_TRY(sc.get(&slots, 2 * nslots));
     HIP_TRY(sc.get(&sslots, 2 * nsslots));
-  } else {
-    const size_t vb = (size_t)q * (size_t)n * (acc == 1 ? sizeof(float) : sizeof(double));
-    HIP_TRY(sc.get((char**)&vbuf, vb));
   }
+  if (vb) HIP_TRY(sc.get((char**)&vbuf, vb));
   sh.wn = w;
 
   PhaseTimer tm(s, timing && stats);
-  if (use_col || use_sstep) {  // tag 0 never matches: slots start empty for the whole solve
-    HIP_TRY(hipMemsetAsync(slots, 0, 16 * nslots, s));
-    HIP_TRY(hipMemsetAsync(sslots, 0, 16 * nsslots, s));
+  if (nslots) {  // tag 0 never matches: slots start empty for the whole solve
+    HIP_TRY(rka::launch_zero(slots, 16 * nslots, s));
+    HIP_TRY(rka::launch_zero(sslots, 16 * nsslots, s));
   }
   HIP_TRY(rka::launch_status_init(st, tol, s));
   HIP_TRY(rka::launch_check_finite(b, m, st, s));
-  tm.begin(kNorms);
-  HIP_TRY(rka::launch_row_norms(A, dtype, m, n, lda, sh.vec_ok, w, s));
-  tm.end();
-  tm.begin(kPrefix);
-  if (sampling == rka::kSampleBlocks)
-    HIP_TRY(rka::launch_prefix_blocks(w, m, q, c, last_pos, st, s));
-  else
-    HIP_TRY(rka::launch_prefix(w, m, c, last_pos, st, s));
-  tm.end();
+  if (own_norms) {
+    tm.begin(kNorms);
+    HIP_TRY(rka::launch_row_norms(A, dtype, m, n, lda, sh.vec_ok, w, s));
+    tm.end();
+  }
+  if (own_prefix) {
+    tm.begin(kPrefix);
+    if (sampling == rka::kSampleBlocks)
+      HIP_TRY(rka::launch_prefix_blocks(w, m, q, c, last_pos, st, s));
+    else
+      HIP_TRY(rka::launch_prefix(w, m, c, last_pos, st, s));
+    tm.end();
+  }
   if (x0) {
     if (x0 != x) HIP_TRY(hipMemcpyAsync(x, x0, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
   } else {
-    HIP_TRY(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), s));
+    HIP_TRY(rka::launch_zero(x, (size_t)n * sizeof(double), s));
   }
   const bool resid_mode = tol > 0.0 && !sh.x_ref;
   if (tol > 0.0) {
@@ -434,11 +500,15 @@ int rka_solve(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const
                     info, nullptr);
 }
 
-int rka_solve_ex(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const double* b,
-                 const double* x0, double* x, int32_t method, int32_t q, int32_t block_size,
-                 double alpha, int64_t max_iter, double tol, uint64_t seed, const double* x_ref,
-                 int64_t iter_offset, const rka_opts* opts, void* stream, rka_info* info,
-                 rka_stats* stats) {
+// rka_solve_ex and its variants: unpack the options and solve, with the
+// norms and running sum of `plan` when given, and scratch carved from
+// `arena` when given.
+static int solve_ex_impl(const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
+                         const double* b, const double* x0, double* x, int32_t method, int32_t q,
+                         int32_t block_size, double alpha, int64_t max_iter, double tol,
+                         uint64_t seed, const double* x_ref, int64_t iter_offset,
+                         const rka_opts* opts, void* stream, rka_info* info, rka_stats* stats,
+                         const rka_plan* plan, void* arena, size_t arena_bytes) {
   if (method != 0 && method != 1) {
     g_last_error.clear();
     if (info) info->status = RKA_EINVAL;
@@ -457,7 +527,149 @@ int rka_solve_ex(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, co
   const int split = opts ? opts->rkab_split : 0;
   return solve_impl(method == 1, A, dtype, m, n, lda, b, x0, x, q, method == 1 ? block_size : 1,
                     alpha, max_iter, tol, seed, x_ref, iter_offset, ce, grid, allreduce, timing,
-                    acc, dom, sampling, walpha, wrow, sstep, split, stream, info, stats);
+                    acc, dom, sampling, walpha, wrow, sstep, split, stream, info, stats, plan,
+                    arena, arena_bytes);
+}
+
+int rka_solve_ex(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const double* b,
+                 const double* x0, double* x, int32_t method, int32_t q, int32_t block_size,
+                 double alpha, int64_t max_iter, double tol, uint64_t seed, const double* x_ref,
+                 int64_t iter_offset, const rka_opts* opts, void* stream, rka_info* info,
+                 rka_stats* stats) {
+  return solve_ex_impl(A, dtype, m, n, lda, b, x0, x, method, q, block_size, alpha, max_iter, tol,
+                       seed, x_ref, iter_offset, opts, stream, info, stats, nullptr, nullptr, 0);
+}
+
+// A plan is usable on the device it was made on only.
+static int check_plan(const rka_plan* plan) {
+  if (!plan) return fail(RKA_EINVAL, "plan must be non-null");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(RKA_EDEVICE, "no HIP device available");
+  if (dev != plan->device)
+    return fail(RKA_EINVAL, "the plan was made on device %d, the current device is %d",
+                plan->device, dev);
+  return RKA_OK;
+}
+
+int rka_plan_create(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, void* stream,
+                    rka_plan** out) {
+  g_last_error.clear();
+  if (!out) return fail(RKA_EINVAL, "out must be non-null");
+  *out = nullptr;
+  if (!A) return fail(RKA_EINVAL, "A must be non-null");
+  if (bad_dtype(dtype)) return fail(RKA_EINVAL, "dtype %d is not an rka_dtype", dtype);
+  if (m < 1 || n < 1 || lda < n) return fail(RKA_EINVAL, "need m, n >= 1 and lda >= n");
+  if (m > INT32_MAX) return fail(RKA_EINVAL, "m must be < 2^31");
+  if (num_cus() <= 0) return fail(RKA_EDEVICE, "no HIP device available");
+  hipStream_t s = (hipStream_t)stream;
+  rka_plan* p = new (std::nothrow) rka_plan{};
+  if (!p) return fail(RKA_ENOMEM, "host allocation of the plan failed");
+  p->A = A;
+  p->dtype = dtype;
+  p->m = m;
+  p->n = n;
+  p->lda = lda;
+  p->vec_ok = vector_path_ok(A, dtype, n, lda);
+  (void)hipGetDevice(&p->device);
+  const size_t wbytes = Scratch::round((size_t)m * 8);
+  hipError_t e = hipMalloc(&p->mem, 2 * wbytes + 256);
+  if (e != hipSuccess) {
+    delete p;
+    return fail(e == hipErrorOutOfMemory ? RKA_ENOMEM : RKA_EDEVICE, "hipMalloc: %s",
+                hipGetErrorString(e));
+  }
+  p->w = (double*)p->mem;
+  p->c = (double*)((char*)p->mem + wbytes);
+  p->last_pos = (int64_t*)((char*)p->mem + 2 * wbytes);
+  e = rka::launch_row_norms(A, dtype, m, n, lda, p->vec_ok, p->w, s);
+  if (e == hipSuccess) e = rka::launch_prefix(p->w, m, p->c, p->last_pos, nullptr, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&p->fro2, p->c + (m - 1), sizeof(double),
+                                          hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    (void)hipFree(p->mem);
+    delete p;
+    return fail(RKA_EDEVICE, "plan set-up: %s", hipGetErrorString(e));
+  }
+  if (!(p->fro2 > 0.0) || !isfinite(p->fro2)) {
+    (void)hipFree(p->mem);
+    delete p;
+    return fail(RKA_EZERONORM, "||A||_F^2 is zero or not finite");
+  }
+  *out = p;
+  return RKA_OK;
+}
+
+int rka_plan_destroy(rka_plan* plan) {
+  g_last_error.clear();
+  if (!plan) return RKA_OK;
+  hipError_t e = plan->mem ? hipFree(plan->mem) : hipSuccess;
+  delete plan;
+  if (e != hipSuccess) return fail(RKA_EDEVICE, "hipFree: %s", hipGetErrorString(e));
+  return RKA_OK;
+}
+
+int rka_plan_query(const rka_plan* plan, int64_t* m, int64_t* n, double* fro2,
+                   int64_t* last_pos) {
+  g_last_error.clear();
+  if (!plan) return fail(RKA_EINVAL, "plan must be non-null");
+  if (m) *m = plan->m;
+  if (n) *n = plan->n;
+  if (fro2) *fro2 = plan->fro2;
+  if (last_pos) {
+    if (hipMemcpy(last_pos, plan->last_pos, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(RKA_EDEVICE, "reading the plan's last positive row failed");
+  }
+  return RKA_OK;
+}
+
+int rka_plan_row_norms(const rka_plan* plan, double* w, void* stream) {
+  g_last_error.clear();
+  int v = check_plan(plan);
+  if (v != RKA_OK) return v;
+  if (!w) return fail(RKA_EINVAL, "w must be non-null");
+  HIP_TRY(hipMemcpyAsync(w, plan->w, (size_t)plan->m * sizeof(double), hipMemcpyDeviceToDevice,
+                         (hipStream_t)stream));
+  return RKA_OK;
+}
+
+int rka_plan_sample_indices(const rka_plan* plan, uint64_t seed, int64_t iter_offset, int64_t K,
+                            int32_t q, int32_t bs, int32_t dom, int32_t* idx, void* stream) {
+  g_last_error.clear();
+  int v = check_plan(plan);
+  if (v != RKA_OK) return v;
+  if (!idx) return fail(RKA_EINVAL, "idx must be non-null");
+  if (K < 0 || q < 1 || bs < 1 || bs >= (1 << 24) || iter_offset < 0 || dom < 0 || dom > 255)
+    return fail(RKA_EINVAL, "need K >= 0, q >= 1, 1 <= bs < 2^24, iter_offset >= 0, 0 <= dom < 256");
+  HIP_TRY(rka::launch_sample(plan->c, plan->m, plan->last_pos, seed, iter_offset, K, q, bs, dom,
+                             rka::kSampleFull, 1.0, nullptr, nullptr, idx, nullptr, nullptr,
+                             nullptr, nullptr, (hipStream_t)stream));
+  return RKA_OK;
+}
+
+int rka_plan_solve(const rka_plan* plan, const double* b, const double* x0, double* x,
+                   int32_t method, int32_t q, int32_t block_size, double alpha, int64_t max_iter,
+                   double tol, uint64_t seed, const double* x_ref, int64_t iter_offset,
+                   const rka_opts* opts, void* stream, rka_info* info, rka_stats* stats) {
+  g_last_error.clear();
+  if (info) info->status = RKA_EINVAL;
+  int v = check_plan(plan);
+  if (v != RKA_OK) return v;
+  return solve_ex_impl(plan->A, plan->dtype, plan->m, plan->n, plan->lda, b, x0, x, method, q,
+                       block_size, alpha, max_iter, tol, seed, x_ref, iter_offset, opts, stream,
+                       info, stats, plan, nullptr, 0);
+}
+
+int rka_alpha_star(double s_min, double s_max, int32_t q, double* alpha) {
+  g_last_error.clear();
+  if (!alpha) return fail(RKA_EINVAL, "alpha must be non-null");
+  *alpha = NAN;
+  if (q < 1) return fail(RKA_EINVAL, "q must be >= 1");
+  if (!(s_min >= 0.0) || !(s_max >= s_min) || !(s_max <= 1.0))
+    return fail(RKA_EINVAL, "need 0 <= s_min <= s_max <= 1 (squared singular values over "
+                            "||A||_F^2)");
+  *alpha = rka::alpha_star_eq6(s_min, s_max, q);
+  return RKA_OK;
 }
 
 int rkab_solve(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const double* b,
@@ -563,11 +775,35 @@ int rka_lsq_grad_A(int64_t m, int64_t n, const double* r, const double* lam, con
 // stopping-test interval of the inner solves when a reference is given
 constexpr int64_t kInnerCheck = 25;
 
-int rka_refine_solve(const void* A, const void* At, int dtype, int64_t m, int64_t n, int64_t lda,
-                     int64_t ldat, const double* b, const double* x0, double* x,
-                     const rka_refine_opts* o, uint64_t seed, const double* x_ref,
-                     double* sweep_measure, void* stream, rka_refine_info* info) {
-  g_last_error.clear();
+// The norms, running sum and last positive row of a matrix in stream-ordered
+// scratch (an internal plan for the length of one call).
+static int scratch_plan(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, Scratch& sc,
+                        hipStream_t s, rka_plan* p) {
+  *p = rka_plan{};
+  p->A = A;
+  p->dtype = dtype;
+  p->m = m;
+  p->n = n;
+  p->lda = lda;
+  p->vec_ok = vector_path_ok(A, dtype, n, lda);
+  (void)hipGetDevice(&p->device);
+  HIP_TRY(sc.get(&p->w, (size_t)m));
+  HIP_TRY(sc.get(&p->c, (size_t)m));
+  HIP_TRY(sc.get(&p->last_pos, 1));
+  HIP_TRY(rka::launch_row_norms(A, dtype, m, n, lda, p->vec_ok, p->w, s));
+  HIP_TRY(rka::launch_prefix(p->w, m, p->c, p->last_pos, nullptr, s));
+  HIP_TRY(hipMemcpyAsync(&p->fro2, p->c + (m - 1), sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (!(p->fro2 > 0.0) || !isfinite(p->fro2))
+    return fail(RKA_EZERONORM, "||A||_F^2 is zero or not finite");
+  return RKA_OK;
+}
+
+static int refine_impl(const void* A, const void* At, int dtype, int64_t m, int64_t n,
+                       int64_t lda, int64_t ldat, const rka_plan* pA, const rka_plan* pAt,
+                       const double* b, const double* x0, double* x, const rka_refine_opts* o,
+                       uint64_t seed, const double* x_ref, double* sweep_measure, void* stream,
+                       rka_refine_info* info) {
   if (info) {
     info->sweeps = 0;
     info->status = RKA_EINVAL;
@@ -612,10 +848,22 @@ int rka_refine_solve(const void* A, const void* At, int dtype, int64_t m, int64_
     HIP_TRY(sc.get(&y, (size_t)m));
     HIP_TRY(sc.get(&g, (size_t)n));
   }
+  // norms and running sums once per call, not once per sweep
+  rka_plan own_a, own_t;
+  if (!pA) {
+    const int v = scratch_plan(A, dtype, m, n, lda, sc, s, &own_a);
+    if (v != RKA_OK) return v;
+    pA = &own_a;
+  }
+  if (range && !pAt) {
+    const int v = scratch_plan(At, dtype, n, m, ldat, sc, s, &own_t);
+    if (v != RKA_OK) return v;
+    pAt = &own_t;
+  }
   if (x0) {
     if (x0 != x) HIP_TRY(hipMemcpyAsync(x, x0, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
   } else {
-    HIP_TRY(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), s));
+    HIP_TRY(rka::launch_zero(x, (size_t)n * sizeof(double), s));
   }
   // denominator of the sweep measure
   HIP_TRY(rka::launch_sumsq(x_ref ? x_ref : b, nullptr, x_ref ? n : m, part, acc2 + 1, s));
@@ -640,7 +888,7 @@ int rka_refine_solve(const void* A, const void* At, int dtype, int64_t m, int64_
       const int st = solve_impl(false, At, dtype, n, m, ldat, g, nullptr, y, o->range_q, 1,
                                 o->range_alpha, o->range_iters, 0.0, seed, nullptr,
                                 (int64_t)sw * o->range_iters, 1, 0, 0, false, o->accumulate, 1, 0,
-                                nullptr, nullptr, 0, 0, stream, &ii, nullptr);
+                                nullptr, nullptr, 0, 0, stream, &ii, nullptr, pAt);
       if (st < 0) return st;
       projections += ii.projections;
       rhs = y;
@@ -662,7 +910,7 @@ int rka_refine_solve(const void* A, const void* At, int dtype, int64_t m, int64_
                               o->method == 1 ? o->block_size : 1, o->alpha, o->inner_iters, tol_d,
                               seed, tol_d > 0.0 ? dref : nullptr, (int64_t)sw * o->inner_iters,
                               kInnerCheck, 0, 0, false, o->accumulate, 0, 0, nullptr, nullptr, 0,
-                              0, stream, &ii, nullptr);
+                              0, stream, &ii, nullptr, pA);
     if (st < 0) return st;
     projections += ii.projections;
     HIP_TRY(rka::launch_axpy(x, d, n, s));
@@ -698,6 +946,34 @@ int rka_refine_solve(const void* A, const void* At, int dtype, int64_t m, int64_
     info->projections = projections;
   }
   return status;
+}
+
+int rka_refine_solve(const void* A, const void* At, int dtype, int64_t m, int64_t n, int64_t lda,
+                     int64_t ldat, const double* b, const double* x0, double* x,
+                     const rka_refine_opts* o, uint64_t seed, const double* x_ref,
+                     double* sweep_measure, void* stream, rka_refine_info* info) {
+  g_last_error.clear();
+  return refine_impl(A, At, dtype, m, n, lda, ldat, nullptr, nullptr, b, x0, x, o, seed, x_ref,
+                     sweep_measure, stream, info);
+}
+
+int rka_plan_refine_solve(const rka_plan* pA, const rka_plan* pAt, const double* b,
+                          const double* x0, double* x, const rka_refine_opts* o, uint64_t seed,
+                          const double* x_ref, double* sweep_measure, void* stream,
+                          rka_refine_info* info) {
+  g_last_error.clear();
+  if (info) info->status = RKA_EINVAL;
+  int v = check_plan(pA);
+  if (v != RKA_OK) return v;
+  if (pAt) {
+    v = check_plan(pAt);
+    if (v != RKA_OK) return v;
+    if (pAt->m != pA->n || pAt->n != pA->m || pAt->dtype != pA->dtype)
+      return fail(RKA_EINVAL, "pAt must be a plan of the n x m transpose of A, same dtype");
+  }
+  return refine_impl(pA->A, pAt ? pAt->A : nullptr, pA->dtype, pA->m, pA->n, pA->lda,
+                     pAt ? pAt->lda : 0, pA, pAt, b, x0, x, o, seed, x_ref, sweep_measure, stream,
+                     info);
 }
 
 int rka_sample_blocks(const double* w, int64_t m, uint64_t seed, int64_t iter_offset, int64_t K,

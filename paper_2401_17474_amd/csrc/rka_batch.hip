@@ -401,11 +401,15 @@ int validate_sys(const rka_batch_system& S, int i, int dtype) {
 // The batch solve; ref2_rhs (nullable): per system and right-hand side (in
 // system order), the squared norm that stands for ||x_ref||^2 in the
 // stopping test (the refinement measures corrections against x_ref - x).
+// dump (nullable): run the set-up and the row streams only, copying every
+// chunk's draws of system i to dump + sum_{j<i} max_iter_j q_j bs_j (the
+// parity hook rka_batch_sample_indices); no iteration runs.
 static int batch_core(const rka_batch_system* systems, int32_t count, int dtype, uint64_t seed,
                       double tol, int64_t check_every, int64_t chunk_iters, int32_t use_graph,
                       void* stream, rka_batch_result* results, rka_batch_stats* stats,
-                      const double* ref2_rhs) {
+                      const double* ref2_rhs, int32_t* dump = nullptr) {
   if (stats) memset(stats, 0, sizeof *stats);
+  if (dump) use_graph = 0;
   if (!systems || count < 1 || count > 65535)
     return rka::api_fail(RKA_EINVAL, "need 1 to 65535 systems");
   if (dtype != RKA_F32 && dtype != RKA_BF16)
@@ -628,6 +632,19 @@ static int batch_core(const rka_batch_system* systems, int32_t count, int dtype,
     if (nb > 1024) nb = 1024;
     for (int64_t c = 0; c < nchunks; ++c) {
       hipLaunchKernelGGL(rka::batch_sample_kernel, dim3(nb, count), dim3(256), 0, s, dsys, c);
+      if (dump) {
+        int64_t doff = 0;
+        for (int i = 0; i < count; ++i) {
+          const int64_t per = (int64_t)q[i] * bs[i], k0 = c * kc[i], mi = systems[i].max_iter;
+          if (k0 < mi) {
+            const int64_t K = mi - k0 < kc[i] ? mi - k0 : kc[i];
+            (void)hipMemcpyAsync(dump + doff + k0 * per, hsys[i].idx, (size_t)(K * per) * 4,
+                                 hipMemcpyDeviceToDevice, s);
+          }
+          doff += mi * per;
+        }
+        continue;
+      }
       hipLaunchKernelGGL(rka::batch_iter_kernel, dim3(ntask), dim3(rka::kBT), (unsigned)lds, s,
                          dtask, c, tol > 0.0 ? check_every : 0, tol * tol);
       hipLaunchKernelGGL(rka::batch_alive_kernel, dim3((count + 255) / 256), dim3(256), 0, s,
@@ -706,6 +723,22 @@ extern "C" int rka_batch_solve(const rka_batch_system* systems, int32_t count, i
                                rka_batch_stats* stats) {
   return batch_core(systems, count, dtype, seed, tol, check_every, chunk_iters, use_graph, stream,
                     results, stats, nullptr);
+}
+
+extern "C" int rka_batch_sample_indices(const rka_batch_system* systems, int32_t count,
+                                        int dtype, uint64_t seed, int64_t chunk_iters,
+                                        int32_t* idx, void* stream) {
+  if (!idx) return rka::api_fail(RKA_EINVAL, "idx must be non-null");
+  if (systems)
+    for (int i = 0; i < count; ++i)
+      if (systems[i].q < 1 || systems[i].block_size < 1)
+        return rka::api_fail(RKA_EINVAL, "system %d: give q and block_size (>= 1)", i);
+  const int rc = batch_core(systems, count, dtype, seed, 0.0, 1, chunk_iters, 0, stream, nullptr,
+                            nullptr, nullptr, idx);
+  if (rc < 0) return rc;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+    return rka::api_fail(RKA_EDEVICE, "batch row stream copy failed");
+  return RKA_OK;
 }
 
 // Refinement of a batch: every sweep solves, for all systems at once and in

@@ -138,6 +138,23 @@ hipError_t launch_axpy(double* x, const double* d, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Zero `words` 8-byte words (a kernel rather than a memset node, so that the
+// solve's launch sequence holds kernels and copies only).
+__global__ __launch_bounds__(256) void zero_kernel(uint64_t* __restrict__ p, int64_t words) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+  const int64_t words = (int64_t)(bytes / 8);
+  if (words == 0) return hipSuccess;
+  int64_t nb = (words + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(zero_kernel, dim3((unsigned)nb), dim3(256), 0, s, (uint64_t*)p, words);
+  return hipGetLastError();
+}
+
 // out = a - b
 __global__ __launch_bounds__(256) void sub_kernel(double* __restrict__ out,
                                                   const double* __restrict__ a,

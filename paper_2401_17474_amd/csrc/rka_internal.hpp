@@ -101,6 +101,29 @@ hipError_t launch_sstep_chunk(const SolveShape& sh, const RkaSstepGeom& geo, con
                               int64_t k0, int64_t K, int64_t check_every, uint64_t* part,
                               uint64_t* red, DevStatus* st, hipStream_t s);
 
+// Geometry of RKA in blocks of p iterations with precomputed coefficients
+// (rka_blk.hip): column slices as in the column-split kernel; the
+// coefficient pass runs 8 x 8 inner-product tiles of f lanes each.
+struct RkaBlkGeom {
+  int G, nsv, rg, nt, rpt;
+  int p;                 // iterations per exchange (at most)
+  int nv;                // exchange values of a full block: p q + 1
+  int ncoef;             // coefficients of a full block: q^2 p (p-1) / 2
+  int tr, trp, trm;      // reduction teams (see the kernel's arguments)
+  size_t lds;
+  int ctiles, cf, crs;   // coefficient pass: tiles, lanes per tile, LDS stride
+  size_t clds;
+};
+// p_req = 0: the largest p that fits (q p <= 128).  FP64 arithmetic, RKA only.
+bool rka_blk_plan(const SolveShape& sh, int p_req, RkaBlkGeom* geo);
+// blocks of a chunk [k0, k0 + K) with stopping tests every check_every (0: none)
+int64_t rka_blk_nblk(const RkaBlkGeom& geo, int64_t k0, int64_t K, int64_t check_every);
+// coef: rka_blk_nblk(...) x ncoef doubles; part: G x nv, red: nv tagged slots
+// (zeroed once per solve).  Runs the coefficient pass, then the iterations.
+hipError_t launch_blk_chunk(const SolveShape& sh, const RkaBlkGeom& geo, const RowRec* rec,
+                            int64_t k0, int64_t K, int64_t check_every, double* coef,
+                            uint64_t* part, uint64_t* red, DevStatus* st, hipStream_t s);
+
 struct RkabGeom {
   int G;       // workgroups (each runs workers g, g + G, ...)
   int nt;      // threads per workgroup
@@ -136,6 +159,8 @@ hipError_t launch_transpose(const void* A, int dtype, int64_t m, int64_t n, int6
                             int64_t ldat, hipStream_t s);
 hipError_t launch_axpy(double* x, const double* d, int64_t n, hipStream_t s);
 hipError_t launch_sub(double* out, const double* a, const double* b, int64_t n, hipStream_t s);
+// zero `bytes` (a multiple of 8) at p with a kernel
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // out_c = (cin ? cin_c : 0) + gamma * sum_i M[i, c] t_i (FP64, fixed order); part holds
 // gemvt_part_len(rows, cols) doubles (rka_spectral.hip)
 int64_t gemvt_part_len(int64_t rows, int64_t cols);
@@ -146,6 +171,9 @@ hipError_t launch_gemvt(const void* M, int dtype, int64_t rows, int64_t cols, in
 int sumsq_part_len();
 hipError_t launch_sumsq(const double* a, const double* b, int64_t len, double* part, double* out,
                         hipStream_t s);
+// alpha* of Eq. (6) for q workers from s = sigma^2 / ||A||_F^2 at the extreme
+// singular values (rka_spectral.hip)
+double alpha_star_eq6(double s_min, double s_max, int q);
 // out[i, j] = r_i lam_j - z_i x_j; out_dtype 0 = FP64, 1 = FP32
 hipError_t launch_rank2(int64_t m, int64_t n, const double* r, const double* lam, const double* z,
                         const double* x, void* out, int out_dtype, int64_t ldo, hipStream_t s);

@@ -406,7 +406,7 @@ hipError_t launch_rkab_chunk(const SolveShape& sh, const RkabGeom& geo, const Ro
   a.bar = bar;
   a.st = st;
   if (geo.G > 1) {
-    hipError_t e = hipMemsetAsync(bar, 0, sizeof(unsigned), s);
+    hipError_t e = launch_zero(bar, 8, s);  // bar has room for two counters
     if (e != hipSuccess) return e;
   }
   if (sh.acc == 1) {

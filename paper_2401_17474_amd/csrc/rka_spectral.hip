@@ -285,11 +285,14 @@ extern "C" int rka_spectral_bounds(const void* A, int dtype, int64_t m, int64_t 
                        fro2);
 }
 
-// Eq. (6): the uniform weight minimising the worst contraction factor
-static double alpha_star_of(double s_min, double s_max, int q) {
+namespace rka {
+// Eq. (6): the uniform weight minimising the worst contraction factor over
+// s = sigma^2 / ||A||_F^2 in [s_min, s_max]; q = 1 always takes the first case
+double alpha_star_eq6(double s_min, double s_max, int q) {
   if (q == 1 || s_max - s_min <= 1.0 / (q - 1)) return q / (1.0 + (q - 1) * s_min);
   return 2.0 * q / (1.0 + (q - 1) * (s_min + s_max));
 }
+}  // namespace rka
 
 extern "C" int rka_partial_alpha(const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
                                  int32_t q, int32_t steps, uint64_t seed, void* stream,
@@ -306,7 +309,7 @@ extern "C" int rka_partial_alpha(const void* A, int dtype, int64_t m, int64_t n,
                                  seed + (uint64_t)w, (hipStream_t)stream, &lmin, &lmax, &f);
     if (rc != RKA_OK) return rc;
     if (!(f > 0.0)) return rka::api_fail(RKA_EZERONORM, "worker %d's row block has zero weight", w);
-    alpha_out[w] = alpha_star_of(lmin / f, lmax / f, q);
+    alpha_out[w] = rka::alpha_star_eq6(lmin / f, lmax / f, q);
   }
   return RKA_OK;
 }

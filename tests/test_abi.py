@@ -131,3 +131,37 @@ def test_alpha_star_is_the_minimizer_of_the_contraction_factor():
         rho = np.maximum(phi(smin), phi(smax))
         best = grid[np.argmin(rho)]
         assert abs(a - best) <= 2 * (grid[1] - grid[0]) + 1e-9 * a, (q, a, best)
+
+
+def test_plan_entry_points_reject_invalid_arguments(L):
+    import paper_2401_17474_amd as pkg
+    h = ctypes.c_void_p(123)
+    assert L.rka_plan_create(None, 0, 5, 5, 5, None, ctypes.byref(h)) == pkg.EINVAL
+    assert h.value is None  # cleared on failure
+    assert L.rka_plan_create(FAKE, 9, 5, 5, 5, None, ctypes.byref(h)) == pkg.EINVAL
+    assert L.rka_plan_create(FAKE, 0, 5, 5, 4, None, ctypes.byref(h)) == pkg.EINVAL
+    assert L.rka_plan_create(FAKE, 0, 5, 5, 5, None, None) == pkg.EINVAL
+    assert L.rka_plan_destroy(None) == pkg.OK
+    info = _info()
+    st = L.rka_plan_solve(None, FAKE, None, FAKE, 0, 2, 1, 1.0, 5, 0.0, 1, None, 0, None, None,
+                          ctypes.byref(info), None)
+    assert st == pkg.EINVAL and info.status == pkg.EINVAL
+    assert "plan" in L.rka_last_error().decode()
+    assert L.rka_plan_sample_indices(None, 1, 0, 3, 2, 1, 0, FAKE, None) == pkg.EINVAL
+    assert L.rka_plan_row_norms(None, FAKE, None) == pkg.EINVAL
+    assert L.rka_plan_query(None, None, None, None, None) == pkg.EINVAL
+    o = pkg._RefineOpts(0, 2, 1, 0, 1.0, 10, 0, 1, 1, 1.0, 0.0)
+    ri = pkg._RefineInfo()
+    assert L.rka_plan_refine_solve(None, None, FAKE, None, FAKE, ctypes.byref(o), 1, None, None,
+                                   None, ctypes.byref(ri)) == pkg.EINVAL
+
+
+def test_alpha_star_entry_point_rejects_invalid_arguments(L):
+    import paper_2401_17474_amd as pkg
+    a = ctypes.c_double(1.0)
+    for smin, smax, q in ((0.1, 0.05, 4), (-1e-3, 0.1, 4), (0.1, 1.5, 4), (0.1, 0.2, 0),
+                          (float("nan"), 0.2, 4)):
+        assert L.rka_alpha_star(smin, smax, q, ctypes.byref(a)) == pkg.EINVAL
+    assert L.rka_alpha_star(0.1, 0.2, 4, None) == pkg.EINVAL
+    # q = 1 is RK: alpha* = 1 whatever the spectrum (first case of Eq. (6))
+    assert L.rka_alpha_star(0.01, 0.9, 1, ctypes.byref(a)) == pkg.OK and a.value == 1.0

@@ -3,15 +3,18 @@
 Every system of a batch is the plain RKAB iteration of Sec. 3.4.1 (block
 size 1: RKA, Eq. (7)) in binary32, on its own row stream (key seed + index);
 each system's x is compared with the oracle's binary32 iteration on the
-oracle's own index stream.  Bar: norm-wise within 4 K bs n u32 (the bound of
-the single-system FP32 parity tests; alpha <= 1).  Right-hand sides of a
+oracle's own index stream, which the batch's own stream equals bit for bit.
+Bar: norm-wise within the binary32 bar of tests/bars.py (16 times the
+oracle's binary32-vs-binary64 gap on that stream).  Right-hand sides of a
 shared matrix share one stream and are compared one by one.  The captured
 graph and the plain launch sequence give bitwise-identical results."""
 import numpy as np
 import pytest
 
 import oracle
+import parity_cases as pc
 import workloads
+from bars import binary32_bar, oracle_pair, rel
 from gpu_util import DEV, host, say, to_dev, vec
 
 pytestmark = pytest.mark.gpu
@@ -33,38 +36,52 @@ def _odt(dtype):
     return "bf16" if dtype == "bf16" else None
 
 
-def _mk(shapes, dtype, params, seed0=100):
+def _mk(shapes, dtype, params, seed0=pc.BATCH_SEED0, alphas=None):
     host_sys, systems = [], []
     for s, ((m, n), (q, bs, tpr, K)) in enumerate(zip(shapes, params)):
         A, xs, b = workloads.scaled_rows_system(m, n, seed=seed0 + s, dtype=dtype)
         A = np.array(A)
-        host_sys.append((A, xs, b, q, bs, K))
+        alpha = alphas[s] if alphas else 1.0
+        host_sys.append((A, xs, b, q, bs, K, alpha))
         X = torch.zeros(n, dtype=torch.float64, device=DEV)
         systems.append(rka.BatchSystem(A=to_dev(A, dtype), B=vec(b), X=X, q=q, block_size=bs,
-                                       tpr=tpr, alpha=1.0, max_iter=K))
+                                       tpr=tpr, alpha=alpha, max_iter=K))
     return host_sys, systems
 
 
-SHAPES = [(300, 50), (1200, 97), (800, 200), (2000, 500), (5000, 1024), (700, 64), (900, 130),
-          (3000, 2000), (640, 160), (1500, 256)]
-PARAMS = [(16, 4, 16, 6), (8, 8, 32, 5), (4, 16, 64, 4), (2, 20, 128, 3), (1, 30, 256, 3),
-          (20, 2, 16, 5), (5, 3, 32, 7), (3, 10, 256, 2), (1, 1, 64, 40), (6, 6, 128, 4)]
+SHAPES, PARAMS = pc.BATCH_SHAPES, pc.BATCH_PARAMS
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_batch_matches_oracle_per_system(dtype):
     say(f"batch {dtype}: {len(SHAPES)} systems")
-    hs, systems = _mk(SHAPES, dtype, PARAMS)
-    res, st = rka.batch_solve(systems, seed=7, graph=False)
+    hs, systems = _mk(SHAPES, dtype, PARAMS, alphas=pc.BATCH_ALPHA)
+    res, st = rka.batch_solve(systems, seed=pc.BATCH_KEY, graph=False)
     assert st["tasks"] == len(SHAPES)
-    for s, ((A, xs, b, q, bs, K), S, r) in enumerate(zip(hs, systems, res)):
+    for s, ((A, xs, b, q, bs, K, alpha), S, r) in enumerate(zip(hs, systems, res)):
         assert r["iterations"] == K and (r["q"], r["block_size"]) == (q, bs)
         w = oracle.row_norms(A, dtype=_odt(dtype))
-        idx = oracle.indices(w, 7 + s, 0, K, q, bs)
-        xo = oracle.rkab_f32_given(A, b, np.zeros(A.shape[1]), idx, q=q, block_size=bs,
-                                   dtype=_odt(dtype))
-        gap = np.linalg.norm(host(S.X) - xo) / np.linalg.norm(xo)
-        assert gap <= 4 * K * bs * A.shape[1] * U32, (s, gap)
+        idx = oracle.indices(w, pc.BATCH_KEY + s, 0, K, q, bs)
+        xo, x64 = oracle_pair(oracle, A, b, np.zeros(A.shape[1]), idx, q=q, block_size=bs,
+                              alpha=alpha, dtype=_odt(dtype), rkab=True)
+        gap, bar = rel(host(S.X), xo), binary32_bar(xo, x64)
+        assert gap <= bar, (s, gap, bar)
+
+
+@pytest.mark.parametrize("chunk", [0, 3])
+def test_batch_row_streams_bitwise(chunk):
+    """Each system's row stream (key seed + i, counters (k, w, j, 0)) equals the
+    oracle's bit for bit, in one chunk or in chunks of 3 iterations; and the
+    keys of refinement sweep s (seed + s * 65536 + i)."""
+    say(f"batch streams chunk={chunk}")
+    hs, systems = _mk(SHAPES, "f32", PARAMS)
+    for key in (pc.BATCH_KEY, pc.BATCH_KEY + 2 * 65536):
+        got = rka.batch_sample_indices(systems, seed=key, chunk_iters=chunk)
+        for s, ((A, xs, b, q, bs, K, _), idx) in enumerate(zip(hs, got)):
+            want = oracle.indices(oracle.row_norms(A), key + s, 0, K, q, bs)
+            assert np.array_equal(host(idx), want), s
+    for S in systems:  # the hook does not iterate
+        assert not torch.any(S.X)
 
 
 def test_graph_is_bitwise_the_plain_sequence():
@@ -85,21 +102,21 @@ def test_graph_is_bitwise_the_plain_sequence():
 
 @pytest.mark.parametrize("R", [0, 1, 3])
 def test_shared_matrix_many_rhs(R):
-    m, n, nrhs, q, bs, K = 2000, 160, 7, 4, 8, 5
+    m, n, nrhs, q, bs, K, dseed, key = pc.MULTI_RHS
     say(f"multi-rhs R={R}")
-    A, Xs, B = workloads.multi_rhs_system(m, n, nrhs, seed=31)
+    A, Xs, B = workloads.multi_rhs_system(m, n, nrhs, seed=dseed)
     X = torch.zeros((nrhs, n), dtype=torch.float64, device=DEV)
     S = rka.BatchSystem(A=to_dev(A, "f32"), B=vec(B.ravel()).view(nrhs, m), X=X, q=q,
                         block_size=bs, tpr=64, rhs_per_task=R, max_iter=K)
-    res, st = rka.batch_solve([S], seed=11, graph=False)
+    res, st = rka.batch_solve([S], seed=key, graph=False)
     Rused = res[0]["rhs_per_task"]
     assert st["tasks"] == -(-nrhs // Rused)
     w = oracle.row_norms(A)
-    idx = oracle.indices(w, 11, 0, K, q, bs)
+    idx = oracle.indices(w, key, 0, K, q, bs)
     Xg = host(X)
     for r in range(nrhs):
-        xo = oracle.rkab_f32_given(A, B[r], np.zeros(n), idx, q=q, block_size=bs)
-        assert np.linalg.norm(Xg[r] - xo) <= 4 * K * bs * n * U32 * np.linalg.norm(xo), r
+        xo, x64 = oracle_pair(oracle, A, B[r], np.zeros(n), idx, q=q, block_size=bs, rkab=True)
+        assert rel(Xg[r], xo) <= binary32_bar(xo, x64), r
 
 
 def test_batch_stops_at_tolerance():

@@ -8,6 +8,7 @@ import pytest
 
 import oracle
 import workloads
+from bars import binary32_bar, oracle_pair, rel
 from gpu_util import assert_x_close, host, say, to_dev, vec
 
 pytestmark = pytest.mark.gpu
@@ -110,10 +111,10 @@ def test_cyclic_fp32_accumulation_vs_oracle(dtype):
                                accumulate=1, sampling=2)
     assert info.status == rka.OK and st["accumulate"] == 1
     odt = "bf16" if dtype == "bf16" else None
-    xo = oracle.rka_f32_given(A, b, np.zeros(n), oracle.indices_cyclic(m, 0, K, q, 1), q=q,
-                              dtype=odt)
-    gap = np.linalg.norm(host(x) - xo) / np.linalg.norm(xo)
-    assert gap <= 4 * K * n * U32, gap
+    xo, x64 = oracle_pair(oracle, A, b, np.zeros(n), oracle.indices_cyclic(m, 0, K, q, 1), q=q,
+                          dtype=odt)
+    gap, bar = rel(host(x), xo), binary32_bar(xo, x64)
+    assert gap <= bar, (gap, bar)
 
 
 @pytest.mark.parametrize("m,n,q", [(4000, 200, 16), (2000, 3000, 64)])

@@ -175,3 +175,71 @@ def test_refine_residual_measure_and_fp64_inner():
     assert np.linalg.norm(x - xls) <= 1e-12 * np.linalg.norm(xls)
     with pytest.raises(ValueError):  # FP32 accumulation needs narrow storage
         oracle.refine(A, b, q=8, acc32=1, inner_iters=10, sweeps=1)
+
+
+# -- binary32 operation order, pinned by hand-worked examples -------------------
+# Every expected value below is worked out by hand from IEEE binary32
+# round-to-nearest-even; each example is built so that another order or
+# another precision of the same step gives a different, stated result.
+T = 2.0 ** -24  # half an ulp of 1 in binary32: 1 + T rounds to 1 (ties to even)
+
+
+def test_rka_f32_dot_is_left_to_right_binary32():
+    """One RK step (q = 1, alpha = 1) on the row a = (1, 1, 1), b = 3, from
+    x = (1, T, T).  Left to right in binary32 the dot is 1 (1 + T rounds down
+    to even, twice); the scale is (3 - 1) / 3 = 2/3 rounded, 11184811 * 2^-24;
+    then x_0 = 1 + that rounds up to even, 13981014 * 2^-23, and x_1 = x_2 =
+    T + s = 11184812 * 2^-24 exactly.  With the dot kept in binary64 (1 + 2T)
+    the scale would be 11184810 * 2^-24 and x = (1.6666666269302368,
+    0.6666666865348816, 0.6666666865348816)."""
+    A = np.ones((1, 3), dtype=np.float32)
+    b = np.array([3.0])
+    x0 = np.array([1.0, T, T])
+    x = oracle.rka_f32_given(A, b, x0, np.zeros(1, dtype=np.int32), q=1)
+    assert x[0] == 13981014 * 2.0 ** -23 == 1.6666667461395264
+    assert x[1] == x[2] == 11184812 * 2.0 ** -24 == 0.6666667461395264
+
+
+def test_rka_f32_average_sums_workers_in_order_then_scales():
+    """Three workers on three one-column rows (1), b = (1, T, T), from x = 0:
+    the scales are b itself; their sum in worker order is 1 + T + T = 1 in
+    binary32 (T + T + 1 would be 1 + 2T), times (1/3) rounded to binary32
+    (11184811 * 2^-25) gives x = 0.3333333432674408 exactly."""
+    A = np.ones((3, 1), dtype=np.float32)
+    b = np.array([1.0, T, T])
+    x = oracle.rka_f32_given(A, b, np.zeros(1), np.array([0, 1, 2], dtype=np.int32), q=3)
+    assert x[0] == 11184811 * 2.0 ** -25 == 0.3333333432674408
+
+
+def test_rkab_f32_average_divides_the_ordered_sum():
+    """The same three rows as RKAB with one projection per worker: the worker
+    iterates are (1), (T), (T); their binary32 sum in worker order is 1, and
+    1 / 3 rounds to 11184811 * 2^-25."""
+    A = np.ones((3, 1), dtype=np.float32)
+    b = np.array([1.0, T, T])
+    x = oracle.rkab_f32_given(A, b, np.zeros(1), np.array([0, 1, 2], dtype=np.int32), q=3,
+                              block_size=1)
+    assert x[0] == 11184811 * 2.0 ** -25
+    # order matters: the same draws listed with the large one last give
+    # T + T + 1 = 1 + 2T, and (1 + 2T) / 3 rounds to 11184812 * 2^-25
+    b2 = np.array([T, T, 1.0])
+    x2 = oracle.rkab_f32_given(A, b2, np.zeros(1), np.array([0, 1, 2], dtype=np.int32), q=3,
+                               block_size=1)
+    assert x2[0] == 11184812 * 2.0 ** -25
+
+
+def test_rka_f32_scale_multiplies_alpha_first():
+    """alpha (b - d) / w, evaluated left to right.  alpha = 3, b = 1 and the
+    row (1, 1, 1) (w = 3) from x = 0: 3 * 1 / 3 = 1 exactly, so x = (1, 1, 1).
+    With b = 0.1 (binary32 13421773 * 2^-27): 3 * b rounds to 10066330 * 2^-25
+    and that over 3 rounds back to 13421773 * 2^-27, while alpha times (b / 3)
+    would round to 13421774 * 2^-27."""
+    A = np.ones((1, 3), dtype=np.float32)
+    x = oracle.rka_f32_given(A, np.array([1.0]), np.zeros(3), np.zeros(1, dtype=np.int32), q=1,
+                             alpha=3.0)
+    assert np.array_equal(x, np.ones(3))
+    x = oracle.rka_f32_given(A, np.array([0.1]), np.zeros(3), np.zeros(1, dtype=np.int32), q=1,
+                             alpha=3.0)
+    b32 = float(np.float32(0.1))
+    assert b32 == 13421773 * 2.0 ** -27
+    assert np.all(x == 13421773 * 2.0 ** -27)

@@ -131,3 +131,23 @@ def test_indices_layout_and_offset(orc):
         assert full[(k * 4 + wk) * 3 + j] == orc.pick_row(c, w, u)
     dom1 = orc.indices(w, seed=3, iter_offset=0, K=6, q=4, bs=3, dom=1)
     assert not np.array_equal(full, dom1)
+
+
+@pytest.mark.parametrize("ctr,key,out", _kat())
+def test_uniform_is_the_published_output_mapped(orc, ctr, key, out):
+    """The uniform of draw (k, w, j, dom) under key `seed` is the published
+    Philox4x32-10 output for counter (k_lo, k_hi, w, j | dom << 24) and key
+    (seed_lo, seed_hi), mapped to [0, 1) from its first two words as
+    ((out0 << 32 | out1) >> 11) * 2^-53.  This pins the counter layout and the
+    53-bit mapping to the known-answer vectors, not to the oracle itself."""
+    seed = key[0] | (key[1] << 32)
+    k = ctr[0] | (ctr[1] << 32)
+    w, j, dom = ctr[2], ctr[3] & 0xFFFFFF, ctr[3] >> 24
+    want = (((out[0] << 32) | out[1]) >> 11) * 2.0 ** -53
+    assert orc.uniform(seed, k, w, j, dom) == want
+
+
+def test_uniform_of_the_zero_counter(orc):
+    # the all-zero vector: out0 = 0x6627e8d5, out1 = 0xe169c58d, so
+    # u = 0x6627e8d5e169c58d >> 11 over 2^53
+    assert orc.uniform(0, 0, 0, 0, 0) == 0.3990464708489645
