@@ -208,6 +208,32 @@ int rka_solve_ex(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, co
                  rka_stats* stats);
 
 /*
+ * rka_solve_ex_noalloc -- rka_solve_ex for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same arguments, iteration and results, with
+ * every scratch buffer carved from a fixed 64 MiB device array of the library
+ * instead of stream-ordered allocations.  The call makes no hipMalloc /
+ * hipFree or other allocating call; the caller still passes A, b, x0, x and
+ * x_ref.  The array holds the squared row norms and running sum (16 m
+ * bytes), the exchange slots or worker iterates of the chosen kernel, and
+ * the row records of one chunk (32 bytes per projection; chunks are
+ * shortened to fit, which for RKA with several iterations per exchange moves
+ * block ends and so changes results at rounding level).  A problem whose
+ * fixed buffers plus one iteration of records exceed 64 MiB is rejected with
+ * RKA_EINVAL before anything is enqueued.  opts->collect_timing is ignored
+ * (no events are created).  Every call on one device shares that device's
+ * array: calls that overlap on a device (on different streams or threads)
+ * race and give undefined results; calls ordered on one stream are safe
+ * (each clears what it needs zeroed).  Each device that runs it holds its
+ * own copy of the array; its address is looked up once per device.
+ */
+int rka_solve_ex_noalloc(const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
+                         const double* b, const double* x0, double* x, int32_t method, int32_t q,
+                         int32_t block_size, double alpha, int64_t max_iter, double tol,
+                         uint64_t seed, const double* x_ref, int64_t iter_offset,
+                         const rka_opts* opts, void* stream, rka_info* info, rka_stats* stats);
+
+/*
  * rka_row_norms -- w_l = sum_c A[l,c]^2 for every row (the numerators of
  * Eq. (4)), each summed left to right in FP64 with a rounded square and a
  * rounded add per term (narrow types widen exactly first).  w: m doubles.

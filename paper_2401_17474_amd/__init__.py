@@ -114,6 +114,7 @@ def lib():
         L.rka_solve_ex.argtypes = [P, ctypes.c_int, I64, I64, I64, P, P, P, I32, I32, I32, D,
                                    I64, D, U64, P, I64, ctypes.POINTER(_Opts), P,
                                    ctypes.POINTER(_Info), ctypes.POINTER(_Stats)]
+        L.rka_solve_ex_noalloc.argtypes = L.rka_solve_ex.argtypes
         L.rka_row_norms.argtypes = [P, ctypes.c_int, I64, I64, I64, P, P]
         L.rka_prefix.argtypes = [P, I64, P, P, P]
         L.rka_sample_indices.argtypes = [P, P, I64, U64, I64, I64, I32, I32, I32, P, P]
@@ -165,7 +166,7 @@ def lib():
                   "rka_partial_alpha", "rka_sample_blocks", "rka_plan_create",
                   "rka_plan_destroy", "rka_plan_query", "rka_plan_row_norms",
                   "rka_plan_sample_indices", "rka_plan_solve", "rka_plan_refine_solve",
-                  "rka_alpha_star", "rka_batch_sample_indices"):
+                  "rka_alpha_star", "rka_solve_ex_noalloc", "rka_batch_sample_indices"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -273,7 +274,7 @@ def solve_ex(A, b, *, method, q, block_size=1, alpha=1.0, max_iter=1000, tol=0.0
              x0=None, x_ref=None, iter_offset=0, check_every=1, grid=0, allreduce=0,
              timing=False, accumulate=0, stream_id=0, sampling=0, worker_alpha=None,
              row_weight=None, steps_per_exchange=0, rkab_split=0, out=None, stream=None,
-             raise_on_error=True):
+             raise_on_error=True, no_alloc=False):
     """rka_solve_ex: method 0 = RKA, 1 = RKAB.  Returns (x, Info, stats dict);
     with ``timing`` the stats hold per-phase HIP-event times (ms) measured on
     the stream the kernels run on.  ``accumulate=1`` computes in FP32 (narrow
@@ -284,9 +285,12 @@ def solve_ex(A, b, *, method, q, block_size=1, alpha=1.0, max_iter=1000, tol=0.0
     ``row_weight`` one of per-row weights w_i (Eq. (7)); ``steps_per_exchange``
     (RKA) runs blocks of up to that many iterations per exchange between
     workgroups (0: the library's choice, 1: one); ``rkab_split`` (RKAB) picks
-    the worker-split (1) or column-split (2) kernel (0: the library's choice)."""
+    the worker-split (1) or column-split (2) kernel (0: the library's choice).
+    ``no_alloc`` calls rka_solve_ex_noalloc (scratch from the library's fixed
+    device array instead of stream-ordered allocations)."""
     code, m, n, lda = _matrix(A)
-    return _solve_ex_call(lambda b_, x0_, x_, opts, info, stats: lib().rka_solve_ex(
+    fn = lib().rka_solve_ex_noalloc if no_alloc else lib().rka_solve_ex
+    return _solve_ex_call(lambda b_, x0_, x_, opts, info, stats: fn(
         _ptr(A), code, m, n, lda, b_, x0_, x_, method, q, block_size, alpha, max_iter, tol, seed,
         _ptr(_vec(x_ref, n, "x_ref")), iter_offset, ctypes.byref(opts), _stream(stream),
         ctypes.byref(info), ctypes.byref(stats)), A.device, m, n, b, x0, out, q, check_every,

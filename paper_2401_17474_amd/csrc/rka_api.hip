@@ -14,6 +14,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -489,6 +490,39 @@ int api_num_cus() {
 }
 }  // namespace rka
 
+// Scratch of the allocation-free entry point: a fixed array that every
+// device loading the library holds until the process ends.  Host code never
+// uses the array's name as an address (on the host it is a stand-in symbol):
+// each device's address comes from hipGetSymbolAddress, taken once per device
+// with that device current.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+// The current device's address of `scratch`, or an rka_status on failure.
+int noalloc_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0)
+    return fail(RKA_EDEVICE, "no HIP device available");
+  if (dev >= kMaxDevices) return fail(RKA_EDEVICE, "device %d beyond the %d supported", dev,
+                                      kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(RKA_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return RKA_OK;
+}
+}  // namespace
+
 extern "C" {
 
 int rka_solve(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const double* b,
@@ -538,6 +572,27 @@ int rka_solve_ex(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, co
                  rka_stats* stats) {
   return solve_ex_impl(A, dtype, m, n, lda, b, x0, x, method, q, block_size, alpha, max_iter, tol,
                        seed, x_ref, iter_offset, opts, stream, info, stats, nullptr, nullptr, 0);
+}
+
+int rka_solve_ex_noalloc(const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
+                         const double* b, const double* x0, double* x, int32_t method, int32_t q,
+                         int32_t block_size, double alpha, int64_t max_iter, double tol,
+                         uint64_t seed, const double* x_ref, int64_t iter_offset,
+                         const rka_opts* opts, void* stream, rka_info* info, rka_stats* stats) {
+  g_last_error.clear();
+  if (info) info->status = RKA_EINVAL;
+  void* arena = nullptr;
+  const int v = noalloc_scratch(&arena);
+  if (v != RKA_OK) {
+    if (info) info->status = v;
+    return v;
+  }
+  rka_opts o{};
+  if (opts) o = *opts;
+  o.collect_timing = 0;  // timing would create HIP events
+  return solve_ex_impl(A, dtype, m, n, lda, b, x0, x, method, q, block_size, alpha, max_iter, tol,
+                       seed, x_ref, iter_offset, &o, stream, info, stats, nullptr, arena,
+                       kNoAllocScratchBytes);
 }
 
 // A plan is usable on the device it was made on only.
