@@ -25,9 +25,17 @@
  *     once, at the end, to read it back; the others only enqueue work.
  *   - Scratch memory is allocated and freed on `stream` (stream-ordered
  *     allocation); no scratch outlives a call.
- *   - Results depend only on the inputs and the method parameters for a
- *     given device and library build; two identical calls give bitwise
- *     identical outputs.
+ *   - Two identical calls give bitwise identical outputs.  The iteration
+ *     (the rows drawn, the projections, the average) depends only on the
+ *     inputs and the method parameters (q, block_size, alpha, seed,
+ *     iter_offset, max_iter, tol).  Its floating-point rounding also depends
+ *     on the launch: the number of workgroups (by default one per compute
+ *     unit of the device, or the grid option) fixes the order in which
+ *     partial sums meet, and the kernels that run several RKA iterations per
+ *     exchange end a block wherever a stopping test falls (every
+ *     check_every iterations), so check_every moves block ends.  Results of
+ *     different launches agree to rounding (for FP64 arithmetic within
+ *     1e-12 relative of the plain iteration in every case tested).
  *   - Return value: an rka_status.  Arguments are validated before any
  *     work is enqueued; a violation returns RKA_EINVAL and touches nothing.
  *     No entry point throws, aborts or exits.  rka_status_string() names a
@@ -153,14 +161,15 @@ typedef struct rka_opts {
                                the paper assume 0 < w_i < 2.                          */
     int32_t steps_per_exchange; /* RKA only: iterations per exchange between
                                workgroups.  0 = chosen by the library; 1 = one (the
-                               column-split kernel); p >= 2 = blocks of up to p
-                               iterations whose scales come from one exchange of the
-                               dot products with x^(k) and the inner products between
-                               the block's rows (the same iteration in exact
-                               arithmetic; rounding differs).  Needs FP64 arithmetic,
-                               allreduce = 0 and q p <= 64; otherwise, or if the shape
-                               does not fit, the column-split kernel runs.  Blocks end
-                               at stopping tests, so check_every = 1 gives p = 1.     */
+                               column-split kernel, or kernel 4 with p = 1 when
+                               rka_block = 2); p >= 2 = blocks of up to p iterations
+                               whose scales come from one exchange (rka_block says
+                               how; the same iteration in exact arithmetic, rounding
+                               differs).  Needs FP64 arithmetic and allreduce = 0;
+                               if the block does not fit (q p <= 64 for kernel 3,
+                               <= 128 for kernel 4), the column-split kernel runs.
+                               Blocks end at stopping tests, so check_every = 1
+                               gives p = 1.                                           */
     int32_t rkab_split;     /* RKAB only: 0 = chosen by the library; 1 = worker-split
                                (one workgroup per worker, kernel 2); 2 = column-split
                                (every workgroup holds a slice of every worker's rows
@@ -172,6 +181,19 @@ typedef struct rka_opts {
                                forms each worker's projections in order: the same
                                iteration in exact arithmetic, kernel 3).  2 needs FP64
                                arithmetic and q <= 256, else kernel 2 runs.          */
+    int32_t rka_block;      /* RKA only, with several iterations per exchange: 0 = chosen
+                               by the library (kernel 4 when it fits and q <= 64,
+                               else kernel 3); 1 = the inner products between the
+                               block's rows travel in the exchange (kernel 3); 2 = a
+                               streaming pass over the chunk's rows forms, per block,
+                               M = (I + N)^-1 with N_{r,c} = alpha_r <a_r, a_c> /
+                               (q ||a_r||^2) for rows c of earlier iterations of the
+                               block, and the exchange carries only the q p dot
+                               products with x^(k): the scales are s = M c with c_r =
+                               alpha_r (b_r - <a_r, x^(k)>) / ||a_r||^2 (the same
+                               iteration in exact arithmetic, kernel 4; q p <= 128,
+                               or p = 1 and q <= 256, else the column-split kernel
+                               runs).                                                 */
 } rka_opts;
 
 /* Launch facts and phase times of one rka_solve_ex call. */
@@ -183,7 +205,8 @@ typedef struct rka_stats {
     double measure_ms;        /* stopping measures                                     */
     int64_t iterate_launches; /* chunks (launches of the iteration kernel)             */
     int32_t kernel;           /* 1 = column-split RKA kernel, 2 = worker-split kernel,
-                                 3 = RKA with several iterations per exchange           */
+                                 3 = RKA with several iterations per exchange, 4 = the
+                                 same with coefficients from a streaming pass           */
     int32_t grid;             /* workgroups of the iteration kernel                    */
     int32_t threads;          /* threads per workgroup of the iteration kernel         */
     int32_t bucket;           /* register-tile bucket of the kernel instance: rows per
@@ -193,6 +216,8 @@ typedef struct rka_stats {
                                  kernel 3: RKA iterations per exchange (p), or RKAB
                                  projections per worker per exchange (c)          */
     int32_t accumulate;       /* accumulation type used: 0 = FP64, 1 = FP32             */
+    double coef_ms;           /* kernel 4: the coefficient passes, summed over chunks
+                                 (not in iterate_ms); 0 for the other kernels           */
 } rka_stats;
 
 /*

@@ -39,7 +39,7 @@ class _Opts(ctypes.Structure):
                 ("accumulate", ctypes.c_int32), ("stream_id", ctypes.c_int32),
                 ("sampling", ctypes.c_int32), ("worker_alpha", ctypes.c_void_p),
                 ("row_weight", ctypes.c_void_p), ("steps_per_exchange", ctypes.c_int32),
-                ("rkab_split", ctypes.c_int32)]
+                ("rkab_split", ctypes.c_int32), ("rka_block", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -48,7 +48,8 @@ class _Stats(ctypes.Structure):
                 ("measure_ms", ctypes.c_double), ("iterate_launches", ctypes.c_int64),
                 ("kernel", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("threads", ctypes.c_int32), ("bucket", ctypes.c_int32),
-                ("variant", ctypes.c_int32), ("accumulate", ctypes.c_int32)]
+                ("variant", ctypes.c_int32), ("accumulate", ctypes.c_int32),
+                ("coef_ms", ctypes.c_double)]
 
 
 class _RefineOpts(ctypes.Structure):
@@ -273,8 +274,8 @@ def rkab_solve(A, b, *, q, block_size, alpha=1.0, max_iter=1000, tol=0.0, seed=1
 def solve_ex(A, b, *, method, q, block_size=1, alpha=1.0, max_iter=1000, tol=0.0, seed=1,
              x0=None, x_ref=None, iter_offset=0, check_every=1, grid=0, allreduce=0,
              timing=False, accumulate=0, stream_id=0, sampling=0, worker_alpha=None,
-             row_weight=None, steps_per_exchange=0, rkab_split=0, out=None, stream=None,
-             raise_on_error=True, no_alloc=False):
+             row_weight=None, steps_per_exchange=0, rkab_split=0, rka_block=0, out=None,
+             stream=None, raise_on_error=True, no_alloc=False):
     """rka_solve_ex: method 0 = RKA, 1 = RKAB.  Returns (x, Info, stats dict);
     with ``timing`` the stats hold per-phase HIP-event times (ms) measured on
     the stream the kernels run on.  ``accumulate=1`` computes in FP32 (narrow
@@ -295,12 +296,12 @@ def solve_ex(A, b, *, method, q, block_size=1, alpha=1.0, max_iter=1000, tol=0.0
         _ptr(_vec(x_ref, n, "x_ref")), iter_offset, ctypes.byref(opts), _stream(stream),
         ctypes.byref(info), ctypes.byref(stats)), A.device, m, n, b, x0, out, q, check_every,
         grid, timing, allreduce, accumulate, stream_id, sampling, worker_alpha, row_weight,
-        steps_per_exchange, rkab_split, raise_on_error)
+        steps_per_exchange, rkab_split, rka_block, raise_on_error)
 
 
 def _solve_ex_call(call, device, m, n, b, x0, out, q, check_every, grid, timing, allreduce,
                    accumulate, stream_id, sampling, worker_alpha, row_weight,
-                   steps_per_exchange, rkab_split, raise_on_error):
+                   steps_per_exchange, rkab_split, rka_block, raise_on_error):
     torch = _torch()
     b = _vec(b, m, "b", False)
     x = out if out is not None else torch.empty(n, dtype=torch.float64, device=device)
@@ -313,7 +314,7 @@ def _solve_ex_call(call, device, m, n, b, x0, out, q, check_every, grid, timing,
     opts = _Opts(check_every, grid, 1 if timing else 0, allreduce, accumulate, stream_id,
                  sampling, None if worker_alpha is None else worker_alpha.data_ptr(),
                  None if row_weight is None else row_weight.data_ptr(), steps_per_exchange,
-                 rkab_split)
+                 rkab_split, rka_block)
     st = call(_ptr(b), _ptr(_vec(x0, n, "x0")), _ptr(x), opts, info, stats)
     if raise_on_error:
         _raise_if(st)
@@ -377,8 +378,8 @@ class Plan:
     def solve(self, b, *, method, q, block_size=1, alpha=1.0, max_iter=1000, tol=0.0, seed=1,
               x0=None, x_ref=None, iter_offset=0, check_every=1, grid=0, allreduce=0,
               timing=False, accumulate=0, stream_id=0, sampling=0, worker_alpha=None,
-              row_weight=None, steps_per_exchange=0, rkab_split=0, out=None, stream=None,
-              raise_on_error=True):
+              row_weight=None, steps_per_exchange=0, rkab_split=0, rka_block=0, out=None,
+              stream=None, raise_on_error=True):
         """rka_plan_solve: solve_ex on the plan's matrix without the per-call set-up."""
         h = self.handle
         return _solve_ex_call(lambda b_, x0_, x_, opts, info, stats: lib().rka_plan_solve(
@@ -386,7 +387,7 @@ class Plan:
             _ptr(_vec(x_ref, self.n, "x_ref")), iter_offset, ctypes.byref(opts), _stream(stream),
             ctypes.byref(info), ctypes.byref(stats)), self.A.device, self.m, self.n, b, x0, out,
             q, check_every, grid, timing, allreduce, accumulate, stream_id, sampling,
-            worker_alpha, row_weight, steps_per_exchange, rkab_split, raise_on_error)
+            worker_alpha, row_weight, steps_per_exchange, rkab_split, rka_block, raise_on_error)
 
 
 def row_norms(A, stream=None):

@@ -24,6 +24,7 @@ SOURCES = {
     "rka_setup.hip": ["-ffp-contract=off"],
     "rka_iter.hip": [],
     "rka_sstep.hip": [],
+    "rka_blk.hip": [],
     "rka_rkab.hip": [],
     "rka_dense.hip": [],
     "rka_batch.hip": [],

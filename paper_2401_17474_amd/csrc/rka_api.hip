@@ -12,6 +12,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <mutex>
@@ -105,7 +106,7 @@ struct Scratch {
 };
 
 // Phase timing with HIP events recorded on the solve's stream.
-enum Phase { kNorms = 0, kPrefix, kSample, kIterate, kMeasure, kPhases };
+enum Phase { kNorms = 0, kPrefix, kSample, kIterate, kMeasure, kCoef, kPhases };
 struct PhaseTimer {
   hipStream_t s;
   bool on;
@@ -198,6 +199,14 @@ constexpr int kAutoSstepMaxQ = 16;
 // bs = 10: 54 -> 22; q = 8, bs = 10: 37 -> 18; q = 32, bs = 4: 24 -> 16;
 // q = 64, bs = 2: 29 -> 15; q = 4, bs = 32: 94 -> 35.
 constexpr int kAutoSubBlockMaxQ = 16;
+// RKA blocks with coefficients from a streaming pass (kernel 4) are the
+// library's choice for several iterations per exchange up to q = 64.
+// Measured at 80000 x 10000 FP64, us per iteration with the coefficient
+// pass included, kernel 4 against the best other kernel: q = 8: 1.17 (2.56,
+// kernel 3); q = 16: 2.13 (5.0, kernel 3); q = 32: 4.1 (8.0, one-iteration
+// kernel); q = 64: 7.6 (8.7, one-iteration kernel).
+constexpr bool kAutoBlk = true;
+constexpr int kAutoBlkMaxQ = 64;
 
 int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
                const double* b, const double* x0, double* x, int32_t q, int32_t bs, double alpha,
@@ -205,7 +214,8 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
                int64_t iter_offset, int64_t check_every, int grid, int allreduce, bool timing,
                int acc, int dom, int sampling, const double* walpha, const double* wrow,
                int sstep, int split, void* stream, rka_info* info, rka_stats* stats,
-               const rka_plan* plan = nullptr, void* arena = nullptr, size_t arena_bytes = 0) {
+               const rka_plan* plan = nullptr, void* arena = nullptr, size_t arena_bytes = 0,
+               int rblk = 0) {
   g_last_error.clear();
   if (stats) memset(stats, 0, sizeof *stats);
   if (info) {
@@ -229,6 +239,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   if (walpha && wrow) return fail(RKA_EINVAL, "give worker_alpha or row_weight, not both");
   if (sstep < 0 || sstep > 64) return fail(RKA_EINVAL, "steps_per_exchange must be in [0, 64]");
   if (split < 0 || split > 2) return fail(RKA_EINVAL, "rkab_split must be 0, 1 or 2");
+  if (rblk < 0 || rblk > 2) return fail(RKA_EINVAL, "rka_block must be 0, 1 or 2");
   if (sampling == rka::kSampleBlocks && q > m)
     return fail(RKA_EINVAL, "the Distributed Approach needs q <= m (one row block per worker)");
   const int ncu = num_cus();
@@ -256,6 +267,8 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   rka::RkaColGeom cgeo{};
   rka::RkabGeom bgeo{};
   rka::RkaSstepGeom sgeo{};
+  rka::RkaBlkGeom kgeo{};
+  bool use_blk = false;
   const int64_t in_kernel_check = (tol > 0.0 && sh.x_ref) ? check_every : 0;
   // several iterations per exchange: asked for (sstep >= 2), or chosen for
   // small q when blocks can be longer than one iteration between tests
@@ -271,16 +284,22 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
       use_sstep = true;
     }
   } else if (!block && acc == 0 && allreduce == 0) {
-    if (sstep >= 2) {
-      use_sstep = rka::rka_sstep_plan(sh, sstep, &sgeo);
-    } else if (sstep == 0 && q <= kAutoSstepMaxQ && in_kernel_check != 1) {
+    // blocks of iterations: coefficients from a streaming pass (rka_block 2),
+    // or the inner products in the exchange (1)
+    const bool want_blk = rblk == 2 || (rblk == 0 && kAutoBlk);
+    bool multi = sstep >= 2 || (rblk == 2 && sstep == 1);  // kernel 4 also runs p = 1
+    if (sstep == 0 && q <= (want_blk ? kAutoBlkMaxQ : kAutoSstepMaxQ) && in_kernel_check != 1) {
       // not where one workgroup holds the whole problem (no exchange at all)
       rka::RkaColGeom one{};
-      if (rka::rka_col_plan(sh, &one) && one.G > 1) use_sstep = rka::rka_sstep_plan(sh, 0, &sgeo);
+      multi = rka::rka_col_plan(sh, &one) && one.G > 1;
+    }
+    if (multi) {
+      if (want_blk) use_blk = rka::rka_blk_plan(sh, sstep >= 1 ? sstep : 0, &kgeo);
+      if (!use_blk && rblk != 2) use_sstep = rka::rka_sstep_plan(sh, sstep >= 2 ? sstep : 0, &sgeo);
     }
   }
-  bool use_col = !block && !use_sstep && rka::rka_col_plan(sh, &cgeo);
-  if (!use_col && !use_sstep) {
+  bool use_col = !block && !use_sstep && !use_blk && rka::rka_col_plan(sh, &cgeo);
+  if (!use_col && !use_sstep && !use_blk) {
     // RKA whose q rows do not fit the column kernel's tile runs as RKAB with
     // one projection per worker, which is the same iteration (Sec. 3.4.2).
     if (!rka::rkab_plan(sh, &bgeo))
@@ -300,7 +319,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   int64_t kc_max = kRecBudget / per_iter;
   if (kc_max < 1) kc_max = 1;
   if (kc_max > max_iter) kc_max = max_iter > 0 ? max_iter : 1;
-  const int G = use_sstep ? sgeo.G : (use_col ? cgeo.G : bgeo.G);
+  const int G = use_blk ? kgeo.G : (use_sstep ? sgeo.G : (use_col ? cgeo.G : bgeo.G));
   size_t part_len = (size_t)G;
   if (!sh.x_ref && tol > 0.0) {
     const size_t rb = (size_t)rka::resid_blocks(m);
@@ -312,7 +331,17 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   const bool own_prefix = plan == nullptr || sampling == rka::kSampleBlocks;
   const size_t n_last = sampling == rka::kSampleBlocks ? (size_t)q : 1;
   size_t nslots = 0, nsslots = 0, vb = 0;
-  if (use_sstep) {
+  // coefficient blocks of a chunk of kc iterations (blk kernel): a segment
+  // between stopping tests adds at most one partial block
+  auto coef_blocks = [&](int64_t kc) -> int64_t {
+    int64_t nb = kc / kgeo.p + 2;
+    if (in_kernel_check > 0) nb += kc / in_kernel_check + 1;
+    return nb;
+  };
+  if (use_blk) {
+    nslots = (size_t)kgeo.G * kgeo.nv;
+    nsslots = (size_t)kgeo.nv;
+  } else if (use_sstep) {
     nslots = (size_t)sgeo.G * sgeo.nv;
     nsslots = (size_t)sgeo.nv;
   } else if (use_col) {
@@ -331,7 +360,14 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
     if (own_prefix) fixed += R((size_t)m * 8) + R(n_last * 8);
     if (nslots) fixed += R(32 * nslots) + R(32 * nsslots);
     if (vb) fixed += R(vb);
-    const size_t per_rec_iter = sizeof(rka::RowRec) * (size_t)per_iter;
+    size_t per_rec_iter = sizeof(rka::RowRec) * (size_t)per_iter;
+    if (use_blk) {
+      // coefficients: (kc / p + 2 [+ kc / C + 1]) blocks of cstride doubles
+      const size_t cb = (size_t)kgeo.cstride * 8;
+      fixed += 256 + cb * (in_kernel_check > 0 ? 3 : 2);
+      per_rec_iter += (cb + kgeo.p - 1) / kgeo.p;
+      if (in_kernel_check > 0) per_rec_iter += (cb + in_kernel_check - 1) / in_kernel_check;
+    }
     const int64_t fit =
         arena_bytes > fixed + 256 ? (int64_t)((arena_bytes - fixed - 256) / per_rec_iter) : 0;
     if (fit < 1)
@@ -361,6 +397,8 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
     HIP_TRY(sc.get(&sslots, 2 * nsslots));
   }
   if (vb) HIP_TRY(sc.get((char**)&vbuf, vb));
+  double* coef = nullptr;
+  if (use_blk) HIP_TRY(sc.get(&coef, (size_t)coef_blocks(kc_max) * kgeo.cstride));
   sh.wn = w;
 
   PhaseTimer tm(s, timing && stats);
@@ -406,8 +444,16 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
     HIP_TRY(rka::launch_sample(c, m, last_pos, seed, k + iter_offset, kc, q, sh.bs, dom, sampling,
                                alpha, walpha, wrow, nullptr, rec, b, w, st, s));
     tm.end();
+    if (use_blk) {
+      tm.begin(kCoef);
+      HIP_TRY(rka::launch_blk_coef(sh, kgeo, rec, k, kc, in_kernel_check, coef, s));
+      tm.end();
+    }
     tm.begin(kIterate);
-    if (use_sstep)
+    if (use_blk)
+      HIP_TRY(rka::launch_blk_iter(sh, kgeo, rec, k, kc, in_kernel_check, coef, slots, sslots, st,
+                                   s));
+    else if (use_sstep)
       HIP_TRY(rka::launch_sstep_chunk(sh, sgeo, rec, k, kc, in_kernel_check, slots, sslots, st, s));
     else if (use_col)
       HIP_TRY(rka::launch_rka_chunk(sh, cgeo, rec, k, kc, in_kernel_check, slots, sslots, st, s));
@@ -441,8 +487,15 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
     stats->sample_ms = ph[kSample];
     stats->iterate_ms = ph[kIterate];
     stats->measure_ms = ph[kMeasure];
+    stats->coef_ms = ph[kCoef];
     stats->iterate_launches = launches;
-    if (use_sstep) {
+    if (use_blk) {
+      stats->kernel = 4;
+      stats->grid = kgeo.G;
+      stats->threads = kgeo.nt;
+      stats->bucket = kgeo.rpt;
+      stats->variant = kgeo.p;
+    } else if (use_sstep) {
       stats->kernel = 3;
       stats->grid = sgeo.G;
       stats->threads = sgeo.nt;
@@ -472,6 +525,18 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
 }
 
 }  // namespace
+
+namespace rka {
+hipError_t launch_persistent(const void* fn, dim3 grid, dim3 block, void** args, unsigned lds,
+                             hipStream_t s) {
+  static const bool cooperative = [] {
+    const char* v = getenv("RKA_COOPERATIVE");
+    return !(v && v[0] == '0');
+  }();
+  if (cooperative) return hipLaunchCooperativeKernel(fn, grid, block, args, lds, s);
+  return hipLaunchKernel(fn, grid, block, args, lds, s);
+}
+}  // namespace rka
 
 namespace rka {
 // error reporting and device query for the other translation units' entry points
@@ -559,10 +624,11 @@ static int solve_ex_impl(const void* A, int dtype, int64_t m, int64_t n, int64_t
   const double* wrow = opts ? opts->row_weight : nullptr;
   const int sstep = opts ? opts->steps_per_exchange : 0;
   const int split = opts ? opts->rkab_split : 0;
+  const int rblk = opts ? opts->rka_block : 0;
   return solve_impl(method == 1, A, dtype, m, n, lda, b, x0, x, q, method == 1 ? block_size : 1,
                     alpha, max_iter, tol, seed, x_ref, iter_offset, ce, grid, allreduce, timing,
                     acc, dom, sampling, walpha, wrow, sstep, split, stream, info, stats, plan,
-                    arena, arena_bytes);
+                    arena, arena_bytes, rblk);
 }
 
 int rka_solve_ex(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const double* b,

@@ -1,0 +1,926 @@
+// rka_blk.hip -- RKA (Eq. (7), arXiv 2401.17474 Sec. 3.3.1) in blocks of p
+// iterations per cross-workgroup exchange, with the block's x-independent
+// coefficients computed by a separate streaming pass.
+//
+// Within a block of iterations k .. k+p-1 the rows are drawn in advance, and
+// x^(k+j) - x^(k) = (1/q) sum_{l<j} sum_r s_{l,r} a_{l,r}.  The scale of row
+// r (iteration j) is s_r = alpha_r (b_r - <a_r, x^(k+j)>) / w_r, so with
+// c_r = alpha_r (b_r - <a_r, x^(k)>) / w_r and
+//     N_{r,c} = alpha_r / (q w_r) <a_r, a_c>   (c drawn in an earlier
+//                                              iteration of the block, else 0)
+// the block's scales solve (I + N) s = c, i.e. s = M c with M = (I + N)^-1,
+// unit lower triangular in q x q blocks.  M depends on the rows only, not on
+// x: blk_coef_kernel forms it for every block of a chunk ahead of the
+// iterations (inner products over the full rows, then block forward
+// substitution), streaming the rows once more.  The iteration kernel then
+// exchanges only the p q dot products with x^(k) (and the error of a
+// stopping test) per block: one reduce-scatter + broadcast of p q + 1
+// values, after which every workgroup forms s = M c and updates its slice of
+// x from the rows it holds in registers.  Same iteration in exact
+// arithmetic; the floating-point scales differ from one-iteration RKA's by
+// rounding.
+//
+// Blocks never run across a stopping test (they end where a test falls) or a
+// chunk end; both kernels locate blocks the same way (BlkLayout).  All sums
+// have a fixed order: results are bitwise reproducible for a given launch
+// geometry.
+#include <math.h>
+
+#include <algorithm>
+
+#include "rka_device.hpp"
+#include "rka_internal.hpp"
+
+namespace rka {
+
+// Phase timing of workgroups 0 and G/2 of the iteration kernel (printed at
+// the end of a launch), for builds with RKA_BLK_PROF defined only.
+#ifdef RKA_BLK_PROF
+#define BPROF_DECL                             \
+  uint64_t bp_t[8] = {0, 0, 0, 0, 0, 0, 0, 0}; \
+  uint64_t bp_last = __builtin_readcyclecounter();
+#define BPROF(i)                                          \
+  do {                                                    \
+    const uint64_t bp_now = __builtin_readcyclecounter(); \
+    bp_t[i] += bp_now - bp_last;                          \
+    bp_last = bp_now;                                     \
+  } while (0)
+#else
+#define BPROF_DECL
+#define BPROF(i) \
+  do {           \
+  } while (0)
+#endif
+
+// Blocks of a chunk [k0, k0 + K): segments end at multiples of C (the
+// stopping-test interval, 0 = none) and at K; a segment of S iterations holds
+// ceil(S / p) blocks of p iterations (the last one shorter).  The host fills
+// the segment counts once (make); locate() then needs one 32-bit division,
+// and only with stopping tests.
+struct BlkLayout {
+  int64_t k0;         // first iteration of the chunk
+  int64_t C;          // stopping-test interval (0: none)
+  int32_t K, p;       // iterations of the chunk, iterations per block
+  int32_t f;          // iterations of the first segment
+  int32_t nbf, nbc;   // blocks of the first segment, of a full segment
+  int32_t nblk;       // blocks of the chunk
+  int32_t first_test; // the chunk starts at a stopping test
+  static BlkLayout make(int64_t k0, int64_t K, int64_t C, int p) {
+    BlkLayout l{};
+    l.k0 = k0;
+    l.C = C > 0 ? C : 0;
+    l.K = (int32_t)K;
+    l.p = p;
+    int64_t f = K;
+    if (l.C > 0) {
+      f = l.C - k0 % l.C;
+      if (f > K) f = K;
+    }
+    l.f = (int32_t)f;
+    l.nbf = (int32_t)((f + p - 1) / p);
+    l.nblk = l.nbf;
+    l.nbc = 0;
+    if (l.C > 0 && f < K) {
+      // here C < K + C - f, and whole segments exist only if C <= K < 2^31
+      const int64_t rest = K - f, full = rest / l.C, tail = rest % l.C;
+      const int64_t nbc = (l.C + p - 1) / p;
+      l.nbc = (int32_t)(nbc < INT32_MAX ? nbc : INT32_MAX);
+      l.nblk += (int32_t)(full * nbc + (tail + p - 1) / p);
+    }
+    l.first_test = l.C > 0 && k0 > 0 && k0 % l.C == 0;
+    return l;
+  }
+  // block b: first chunk-local iteration, length, and whether a stopping
+  // test falls at its start
+  __device__ __forceinline__ void locate(int b, int* kl, int* L, bool* test) const {
+    int64_t s0, slen;
+    int i;
+    if (b < nbf) {
+      s0 = 0;
+      slen = f;
+      i = b;
+      *test = first_test && b == 0;
+    } else {
+      const int bb = b - nbf, seg = bb / nbc;
+      i = bb - seg * nbc;
+      s0 = f + (int64_t)seg * C;
+      slen = (int64_t)K - s0 < C ? (int64_t)K - s0 : C;
+      *test = i == 0;
+    }
+    const int64_t k = s0 + (int64_t)i * p;
+    const int64_t left = s0 + slen - k;
+    *kl = (int)k;
+    *L = (int)(left < p ? left : p);
+  }
+};
+
+// strictly lower q x q blocks (j, l), l < j, of M, in pair order
+__host__ __device__ constexpr int blk_pair(int j, int l) { return j * (j - 1) / 2 + l; }
+__host__ __device__ constexpr int blk_ncoef(int q, int p) { return q * q * (p * (p - 1) / 2); }
+
+constexpr int kBMaxRows = 128;   // q p
+constexpr int kBThreads = 512;   // iteration kernel
+constexpr int kBPoll = 2;        // slots one lane polls in either phase
+constexpr int kBBatch = 4;       // poll loads in flight per lane
+constexpr int kCThreads = 256;   // coefficient kernel (4 waves)
+constexpr int kCElems = 4096;    // elements of a staged chunk (rows x columns)
+constexpr int kCPre = kCElems / kCThreads;  // staged elements per lane
+constexpr int kCMaxSlots = 9;    // 16 x 16 Gram tiles per wave (36 = 8 * 9 / 2 over 4 waves)
+
+// ===========================================================================
+// The coefficient pass: M of every block of a chunk.
+// ===========================================================================
+struct CoefArgs {
+  const void* A;
+  int64_t lda, n;
+  const RowRec* rec;  // K x q records of the chunk
+  BlkLayout lay;
+  int32_t q;
+  int32_t RS;         // column stride of the staged chunk (doubles, >= rows rounded to 16)
+  int32_t lcw;        // log2 of the columns of a staged chunk
+  double inv_q;
+  double* coef;       // nblk x cstride
+  int32_t ncoef;      // coefficients of a full block
+  int32_t cstride;    // doubles between blocks in coef (a multiple of 128)
+};
+
+template <typename T>
+__device__ __forceinline__ double elem_at(const T* A, int64_t off) {
+  return widen(A[off]);
+}
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// Offset of row r = jr q + rho in the row-major packing of M's strictly lower
+// part: row r holds its jr q coefficients (iterations 0 .. jr-1) contiguously.
+__host__ __device__ __forceinline__ int blk_rowoff(int q, int jr, int rho) {
+  return q * q * (jr * (jr - 1) / 2) + rho * jr * q;
+}
+
+// Wave W's part of a block's Gram tiles: stage the rows chunk by chunk
+// (every wave takes part and meets every barrier), accumulate the wave's
+// tiles, then write its entries of N into NB (over S, once every wave is
+// done with S).
+//
+// Tiles: the lower 16 x 16 tiles (I, J), J <= I, that hold a pair of rows
+// from different iterations, in the order I = 0, 1, ...; J = 0 .. I; wave W
+// takes every fourth from the W-th into its NS slots (slots past its share
+// repeat tile (0, 0); their sums are never used).  Per 4 columns a lane loads
+// both fragments of every slot (lane l: column c + l / 16, row 16 I + l % 16),
+// the next 4 columns' while the current ones feed v_mfma_f64_16x16x4f64.
+//
+// Chunks of CW columns (RP x CW <= 4096 elements) are staged in LDS, the next
+// chunk's elements in flight in registers while the current one is used.
+// Element e: row e >> lcw, column e & (CW - 1) -- consecutive lanes read
+// consecutive columns of a row.  Loads are unconditional (clamped rows and
+// columns); elements past the block's rows or past n are zero.
+template <typename T, int NS>
+__device__ __forceinline__ void coef_gram(const CoefArgs& p, const T* __restrict__ A, double* S,
+                                          double* NB, const double* FAC, const int64_t* ROW, int R,
+                                          int RG) {
+  const int t = threadIdx.x, q = p.q, lane = t & (kWave - 1), wv = t / kWave;
+  const int CW = 1 << p.lcw, RP = 16 * RG;
+  int tI[NS], tJ[NS];
+  int nt = 0;
+#pragma unroll
+  for (int u = 0; u < NS; ++u) tI[u] = tJ[u] = 0;
+  {
+    int idx = 0;
+    for (int I = 0; I < RG; ++I)
+      for (int J = 0; J <= I; ++J) {
+        const int rlast = (16 * I + 15 < R ? 16 * I + 15 : R - 1);
+        if (rlast / q > (16 * J) / q) {  // some row of I is of a later iteration
+          if (idx % 4 == wv && nt < NS) {
+#pragma unroll
+            for (int u = 0; u < NS; ++u)
+              if (u == nt) {
+                tI[u] = I;
+                tJ[u] = J;
+              }
+            ++nt;
+          }
+          ++idx;
+        }
+      }
+  }
+  f64x4 acc[NS];
+#pragma unroll
+  for (int u = 0; u < NS; ++u) acc[u] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  // (the loads only: zeroing happens at the LDS store, so that no load waits
+  // for the one before it)
+  double nxt[kCPre];
+  const T* rowp[kCPre];
+#pragma unroll
+  for (int i = 0; i < kCPre; ++i) {
+    const int r = (t + kCThreads * i) >> p.lcw;
+    rowp[i] = A + ROW[r < R ? r : R - 1] * p.lda;
+  }
+  auto fetch = [&](int64_t c0) {
+#pragma unroll
+    for (int i = 0; i < kCPre; ++i) {
+      const int c = (t + kCThreads * i) & (CW - 1);
+      nxt[i] = elem_at<T>(rowp[i], c0 + c < p.n ? c0 + c : p.n - 1);
+    }
+  };
+  const double* base = S + (size_t)(lane >> 4) * p.RS + (lane & 15);
+  double fa[2 * NS], fb[2 * NS];
+  auto load = [&](double(&f)[2 * NS], int c) {
+    const double* Sc = base + (size_t)c * p.RS;
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      f[2 * u] = Sc[16 * tI[u]];
+      f[2 * u + 1] = Sc[16 * tJ[u]];
+    }
+  };
+  auto step = [&](const double(&f)[2 * NS]) {
+#pragma unroll
+    for (int u = 0; u < NS; ++u)
+      acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[2 * u], f[2 * u + 1], acc[u], 0, 0, 0);
+  };
+  fetch(0);
+  for (int64_t c0 = 0; c0 < p.n; c0 += CW) {
+    __syncthreads();  // the previous chunk has been used
+#pragma unroll
+    for (int i = 0; i < kCPre; ++i) {
+      const int e = t + kCThreads * i;
+      const int r = e >> p.lcw, c = e & (CW - 1);
+      if (r < RP) S[(size_t)c * p.RS + r] = (r < R && c0 + c < p.n) ? nxt[i] : 0.0;
+    }
+    __syncthreads();
+    if (c0 + CW < p.n) fetch(c0 + CW);
+    load(fa, 0);
+    for (int c = 0; c < CW; c += 8) {  // CW is a multiple of 8
+      load(fb, c + 4);
+      step(fa);
+      if (c + 8 < CW) load(fa, c + 8);
+      step(fb);
+    }
+  }
+  __syncthreads();  // every wave is done with S: NB takes its place
+  // N = alpha_r / (q w_r) <a_r, a_c> for rows r, c of iterations j > l
+#pragma unroll
+  for (int u = 0; u < NS; ++u) {
+    if (u < nt) {
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int r = 16 * tI[u] + lane / 16 + 4 * rr, c = 16 * tJ[u] + (lane & 15);
+        if (r < R && c < R) {
+          const int jr = r / q, lc = c / q;
+          if (jr > lc)
+            NB[blk_pair(jr, lc) * q * q + (r - jr * q) * q + (c - lc * q)] = FAC[r] * acc[u][rr];
+        }
+      }
+    }
+  }
+}
+
+// The inner products of a block's rows are the needed lower 16 x 16 tiles of
+// its R x R Gram matrix, each accumulated over the columns with
+// v_mfma_f64_16x16x4f64: lane l supplies row 16 I + l % 16 and row
+// 16 J + l % 16 at column c + l / 16, and holds D[l / 16 + 4 r][l % 16] in
+// register r (D[i][j] = the inner product of rows 16 I + i and 16 J + j).
+// The staged chunk and N (then M) share LDS: N is written once the last
+// chunk has been used.
+template <typename T, int NS>
+__global__ __launch_bounds__(kCThreads) void blk_coef_kernel(CoefArgs p) {
+  const T* __restrict__ A = (const T*)p.A;
+  const int t = threadIdx.x, q = p.q;
+  extern __shared__ double lds[];
+  // S: the staged chunk, column-major S[c RS + r]; NB: N (then M) in q x q
+  // blocks by pair, over S once the Gram tiles are complete
+  const int CW = 1 << p.lcw;
+  double* S = lds;                                                      // CW * RS
+  double* NB = lds;                                                     // ncoef
+  const int nS = CW * p.RS > p.ncoef ? CW * p.RS : p.ncoef;
+  double* FAC = lds + nS;                        // kBMaxRows  alpha_r / (q w_r)
+  int64_t* ROW = (int64_t*)(FAC + kBMaxRows);    // kBMaxRows
+  for (int b = blockIdx.x; b < p.lay.nblk; b += gridDim.x) {
+    int kl, L;
+    bool test;
+    p.lay.locate(b, &kl, &L, &test);
+    const int R = L * q, RG = (R + 15) / 16;
+    __syncthreads();  // the previous block's LDS reads are done
+    for (int r = t; r < R; r += kCThreads) {
+      const RowRec rc = p.rec[(int64_t)kl * q + r];
+      ROW[r] = rc.row;
+      FAC[r] = rc.alpha * p.inv_q / rc.wn;
+    }
+    __syncthreads();  // ROW and FAC are complete
+    coef_gram<T, NS>(p, A, S, NB, FAC, ROW, R, RG);  // the Gram tiles, then N into NB
+    __syncthreads();
+    // block forward substitution, in place (N_{j,l} becomes M_{j,l}):
+    //   M_{j,l} = -N_{j,l} - sum_{t=l+1}^{j-1} N_{j,t} M_{t,l}
+    // for j ascending and, within j, l ascending: N_{j,t} (t > l) is not yet
+    // overwritten when used, M_{t,l} (t < j) is final, and every element of
+    // the (j, l) block reads only its own old value of that block.
+    for (int jj = 1; jj < L; ++jj) {
+      for (int ll = 0; ll < jj; ++ll) {
+        double* Mjl = NB + blk_pair(jj, ll) * q * q;
+        for (int e = t; e < q * q; e += kCThreads) {
+          const int rr = e / q, cc = e - rr * q;
+          double sacc = Mjl[e];
+          for (int tt = ll + 1; tt < jj; ++tt) {
+            const double* Njt = NB + blk_pair(jj, tt) * q * q + rr * q;
+            const double* Mtl = NB + blk_pair(tt, ll) * q * q + cc;
+            for (int k2 = 0; k2 < q; ++k2) sacc = fma(Njt[k2], Mtl[k2 * q], sacc);
+          }
+          Mjl[e] = -sacc;
+        }
+        __syncthreads();
+      }
+    }
+    // out: row r = jr q + rho holds M_{r, c} for c < jr q contiguously
+    double* out = p.coef + (size_t)b * p.cstride;
+    for (int e = t; e < q * q * (L * (L - 1) / 2); e += kCThreads) {
+      // e walks the pair blocks: block (jr, lc), entry (rho, sg)
+      const int pb = e / (q * q), rem = e - pb * q * q;
+      int jr = 1, lc = pb;
+      while (lc >= jr) {
+        lc -= jr;
+        ++jr;
+      }
+      const int rho = rem / q, sg = rem - rho * q;
+      out[blk_rowoff(q, jr, rho) + lc * q + sg] = NB[e];
+    }
+  }
+}
+
+// ===========================================================================
+// The iteration kernel.
+// ===========================================================================
+struct BlkArgs {
+  const void* A;
+  int64_t lda, nvec;
+  const RowRec* rec;  // K x q records of the chunk
+  const double* coef; // nblk x cstride (blk_coef_kernel): M's rows packed
+  double* x;
+  const double* x_ref;
+  double inv_q;
+  BlkLayout lay;
+  int32_t q, nsv, rg, G, nt;
+  int32_t nsvp;       // lanes per row group: nsv rounded up to a power of two <= 64
+  int32_t nv_max;     // exchange values of a full block: p q + 1
+  int32_t cstride;    // doubles between blocks in coef (a multiple of 128)
+  int32_t tr;         // lanes per row for the slice sums of the dot products
+  int32_t trp;        // lanes per value in the reduce-scatter
+  int32_t trm;        // lanes per row of s = M c
+  uint64_t* part;     // G x nv_max tagged slots
+  uint64_t* red;      // nv_max tagged slots
+  DevStatus* st;
+};
+
+// Poll `total` tagged slots, slot idx(L) for L = t + NT s (at most kBPoll per
+// lane), until every tag matches, storing the values to dst[L].  A sweep
+// issues kBBatch loads per lane before waiting for any; slots already read,
+// and lanes past the end, load at `oob`, out of the buffer's range (zero, no
+// memory access).  False (in every thread) if the wait gave up.
+template <typename IdxFn>
+__device__ __forceinline__ bool blk_gather(const TagSlots& sl, int oob, int total, uint32_t tg,
+                                           IdxFn idx, double* dst, int t, int NT) {
+  const int ns = (total + NT - 1) / NT;
+  uint32_t need = 0;
+#pragma unroll
+  for (int s = 0; s < kBPoll; ++s)
+    if (t + NT * s < total) need |= 1u << s;
+  for (unsigned spins = 0;; ++spins) {
+#pragma unroll
+    for (int s0 = 0; s0 < kBPoll; s0 += kBBatch) {
+      if (s0 < ns) {
+        uint64_t lo[kBBatch], hi[kBBatch];
+#pragma unroll
+        for (int s = 0; s < kBBatch; ++s) {
+          lo[s] = hi[s] = 0;
+          if (s0 + s < ns) {
+            int Lx = t + NT * (s0 + s);
+            __asm__ volatile("" : "+v"(Lx));
+            sl.fetch16((need >> (s0 + s)) & 1u ? (int)idx(Lx) : oob, lo[s], hi[s]);
+          }
+        }
+#pragma unroll
+        for (int s = 0; s < kBBatch; ++s) {
+          double v;
+          if (s0 + s < ns && ((need >> (s0 + s)) & 1u) && TagSlots::decode(lo[s], hi[s], tg, v)) {
+            dst[t + NT * (s0 + s)] = v;
+            need &= ~(1u << (s0 + s));
+          }
+        }
+      }
+    }
+    if (__syncthreads_and(need == 0)) return true;
+    if (spins >= kSpinLimit) return false;
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+template <typename T, int V, int RPT>
+__global__ __launch_bounds__(kBThreads) void rka_blk_kernel(BlkArgs p) {
+  using raw_t = typename Vec<T, V>::raw_t;
+  if (p.st->done) return;
+  const T* __restrict__ A = (const T*)p.A;
+  const int t = threadIdx.x, g = blockIdx.x, NT = p.nt;
+  const int q = p.q, nsv = p.nsv, rg = p.rg, G = p.G, NSVP = p.nsvp;
+  // lane j of row group rgi holds vec j of the slice (lanes j >= nsv idle):
+  // a row group is an aligned team of NSVP lanes inside one wave
+  const int j = t & (NSVP - 1);
+  const int rgi = t / NSVP;
+  const bool active = j < nsv;
+  const int64_t cv = (int64_t)g * nsv + j;
+  const bool colv = active && cv < p.nvec;
+  const int64_t cvl = cv < p.nvec ? cv : p.nvec - 1;
+  const int Rmax = p.nv_max - 1;
+
+  extern __shared__ double lds[];
+  double* MC = lds;                       // cstride  M of the block (16-byte aligned)
+  double* HV = MC + p.cstride;            // nv_max   this slice's partials, then the sums
+  double* CC = HV + p.nv_max;             // Rmax     c_r, then the scales s_r
+  double* RB = CC + Rmax;                 // Rmax     b_r
+  double* RW = RB + Rmax;                 // Rmax     ||a_r||^2
+  double* RA = RW + Rmax;                 // Rmax     weights
+  double* U = RA + Rmax;                  // (NT / 64) * NSVP * V  update sums per wave
+  double* XS = U + (size_t)(NT / kWave) * NSVP * V;  // NSVP * V  new slice of x
+  double* PG = XS + (size_t)NSVP * V;     // G * ceil(nv_max / G)  gathered partials
+  const int nwaves = NT / kWave;
+
+  double xv[V];
+#pragma unroll
+  for (int e = 0; e < V; ++e) xv[e] = colv ? p.x[cv * V + e] : 0.0;
+  if (t < NSVP) {  // the slice's x, kept in LDS: the update adds to it
+#pragma unroll
+    for (int e = 0; e < V; ++e) XS[t * V + e] = xv[e];
+  }
+
+  const TagSlots part(p.part, (int64_t)G * p.nv_max);
+  const TagSlots red(p.red, p.nv_max);
+
+  auto load_rows = [&](int kl2, int L2, int* rows) {
+    const int R2 = L2 * q;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int br = rgi + rg * i;
+      rows[i] = (int)p.rec[(int64_t)kl2 * q + (br < R2 ? br : R2 - 1)].row;
+    }
+  };
+  raw_t a[RPT], an[RPT];
+  int rows_n[RPT];
+  double mb = 0.0, mw = 1.0, ma = 0.0;  // record of block row t
+  int b = 0, kl = 0, L = 1;
+  bool check = false;
+  p.lay.locate(0, &kl, &L, &check);
+  const int nblk = p.lay.nblk;
+  {
+    int rows0[RPT];
+    load_rows(kl, L, rows0);
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) a[i] = load_raw<T, V>(A + (int64_t)rows0[i] * p.lda + cvl * V);
+    if (t < L * q) {
+      const RowRec r = p.rec[(int64_t)kl * q + t];
+      mb = r.b;
+      mw = r.wn;
+      ma = r.alpha;
+    }
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) rows_n[i] = rows0[i];
+    if (nblk > 1) {
+      int kl1, L1;
+      bool t1;
+      p.lay.locate(1, &kl1, &L1, &t1);
+      load_rows(kl1, L1, rows_n);
+    }
+  }
+
+  bool stopped = false;
+  BPROF_DECL
+  while (b < nblk) {
+    const int64_t k = p.lay.k0 + kl;
+    const int R = L * q, nv = R + 1;
+    const uint32_t tag = (uint32_t)(k + 1);
+    if (t < R) {
+      RB[t] = mb;
+      RW[t] = mw;
+      RA[t] = ma;
+    }
+    // (1) the dot products of the block's rows with this slice of x^(k): a
+    // lane's products, then the row group's fixed DPP / swizzle fold
+    {
+      double sd[RPT];
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int e = 0; e < V; ++e) s = fma(colv ? raw_elem<T, V>(a[i], e) : 0.0, xv[e], s);
+        sd[i] = s;
+      }
+      team_sum_n(sd, NSVP);
+      if (j == 0) {
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+          const int br = rgi + rg * i;
+          if (br < R) HV[br] = sd[i];
+        }
+      }
+    }
+    if (t < kWave) {  // row group 0's lanes: the error of this slice (0 without a test)
+      double s = 0.0;
+      if (check && t < NSVP && colv) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          const double d = xv[e] - p.x_ref[cv * V + e];
+          s = fma(d, d, s);
+        }
+      }
+      s = team_sum(s, NSVP);
+      if (t == 0) HV[R] = s;
+    }
+    BPROF(0);
+    __syncthreads();
+    // (2) the nv partials leave in one coalesced pass
+    for (int v = t; v < nv; v += NT) part.put16((int64_t)g * p.nv_max + v, HV[v], tag);
+    // (3) the block's coefficients M (L2-resident) straight into LDS, 16 bytes
+    // a lane and 1 KB a wave per load, in flight across the exchange (issued
+    // after the barrier above, which would otherwise wait for them)
+    {
+      const double* Mg = p.coef + (size_t)b * p.cstride;
+      const int npieces = (q * q * (L * (L - 1) / 2) + 127) / 128;  // within cstride
+      const int wv = t / kWave, lane = t & (kWave - 1);
+      for (int i = wv; i < npieces; i += NT / kWave)
+        __builtin_amdgcn_global_load_lds((const void*)(Mg + 128 * i + 2 * lane),
+                                         (__attribute__((address_space(3))) void*)(MC + 128 * i),
+                                         16, 0, 0);
+    }
+    BPROF(1);
+    // phase 1: workgroup g sums the values [g C, g C + C) over all workgroups
+    bool ok = true;
+    {
+      const int C = (nv + G - 1) / G;
+      const int v0 = g * C;
+      const int cnt = nv - v0 < C ? (nv - v0 > 0 ? nv - v0 : 0) : C;
+      ok = blk_gather(part, G * p.nv_max, G * cnt, tag,
+                      [&](int Lx) {
+                        const int gg = Lx / cnt, c = Lx - gg * cnt;
+                        return gg * p.nv_max + v0 + c;
+                      },
+                      PG, t, NT);
+      const int TR = p.trp, team = t / TR, u = t & (TR - 1);
+      double sum = 0.0;
+      if (team < cnt)
+        for (int gg = u; gg < G; gg += TR) sum += PG[gg * cnt + team];
+      sum = team_sum(sum, TR);
+      if (ok && u == 0 && team < cnt) red.put16(v0 + team, sum, tag);
+    }
+    BPROF(2);
+    // phase 2: every workgroup reads all nv sums
+    if (__syncthreads_and(ok))
+      ok = blk_gather(red, p.nv_max, nv, tag, [&](int Lx) { return Lx; }, HV, t, NT);
+    BPROF(3);
+    if (!__syncthreads_and(ok)) {
+      if (t == 0) note_timeout(p.st);
+      stopped = true;
+      break;
+    }
+    if (check) {
+      const double e2 = HV[R];
+      const bool conv = e2 <= p.st->thresh2;
+      const bool div = !isfinite(e2);
+      if (conv || div) {
+        if (g == 0 && t == 0) {
+          p.st->iterations = k;
+          p.st->rel2 = e2 / p.st->ref2;
+          p.st->status = conv ? 0 : -3;
+          p.st->done = 1;
+        }
+        stopped = true;
+        break;
+      }
+    }
+    // This wave's loads of M have landed in LDS (nothing else of its memory
+    // traffic is outstanding after the polls, so the wait is free).  Then the
+    // next block's rows and records, in flight across the rest of this block:
+    // their addresses use the row indices loaded one block earlier.
+    __builtin_amdgcn_s_waitcnt(0);
+    int kn = kl, Ln = L;
+    bool checkn = false;
+    if (b + 1 < nblk) p.lay.locate(b + 1, &kn, &Ln, &checkn);
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) an[i] = load_raw<T, V>(A + (int64_t)rows_n[i] * p.lda + cvl * V);
+    if (b + 1 < nblk && t < Ln * q) {
+      const RowRec r = p.rec[(int64_t)kn * q + t];
+      mb = r.b;
+      mw = r.wn;
+      ma = r.alpha;
+    }
+    if (b + 2 < nblk) {
+      int kn2, Ln2;
+      bool t2;
+      p.lay.locate(b + 2, &kn2, &Ln2, &t2);
+      load_rows(kn2, Ln2, rows_n);
+    }
+    // (4) c_r = alpha_r (b_r - <a_r, x^(k)>) / w_r, then s = M c: row r of
+    // iteration jr adds M_{r,c} c_c over the jr q rows c of earlier
+    // iterations (contiguous in M's row packing); a team of trm lanes per
+    // row, lane u taking every trm-th term into four running sums
+    if (t < R) CC[t] = RA[t] * (RB[t] - HV[t]) / RW[t];
+    __syncthreads();
+    double sr = 0.0;
+    {
+      const int TR = p.trm, r = t / TR, u = t & (TR - 1);
+      const int jr = r < R ? r / q : 0, rho = r - jr * q;
+      const double* mr = MC + blk_rowoff(q, jr, rho);
+      const int nterm = jr * q;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int c = u;
+      for (; c + 3 * TR < nterm; c += 4 * TR) {
+        a0 = fma(mr[c], CC[c], a0);
+        a1 = fma(mr[c + TR], CC[c + TR], a1);
+        a2 = fma(mr[c + 2 * TR], CC[c + 2 * TR], a2);
+        a3 = fma(mr[c + 3 * TR], CC[c + 3 * TR], a3);
+      }
+      for (; c < nterm; c += TR) a0 = fma(mr[c], CC[c], a0);
+      double acc = (a0 + a1) + (a2 + a3);
+      acc = team_sum(acc, TR);
+      if (r < R) sr = CC[r] + acc;
+    }
+    __syncthreads();
+    if ((t & (p.trm - 1)) == 0 && t / p.trm < R) CC[t / p.trm] = sr;
+    __syncthreads();
+    BPROF(4);
+    // (5) x_slice += (1/q) sum over the block's rows of s_r A[i_r, slice]: a
+    // lane's rows, then the row groups of a wave (xor folds), then the waves
+    // in order
+    double uu[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) uu[e] = 0.0;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int br = rgi + rg * i;
+      const double s = (colv && br < R) ? CC[br < R ? br : 0] : 0.0;
+#pragma unroll
+      for (int e = 0; e < V; ++e) uu[e] = fma(s, raw_elem<T, V>(a[i], e), uu[e]);
+    }
+    for (int off = NSVP; off < kWave; off *= 2) {
+#pragma unroll
+      for (int e = 0; e < V; ++e) uu[e] += __shfl_xor(uu[e], off, kWave);
+    }
+    if ((t & (kWave - 1)) < NSVP) {
+#pragma unroll
+      for (int e = 0; e < V; ++e) U[((t / kWave) * NSVP + j) * V + e] = uu[e];
+    }
+    __syncthreads();
+    if (t < NSVP * V) {
+      const int jj = t / V, e = t - jj * V;
+      double acc = 0.0;
+      for (int w = 0; w < nwaves; ++w) acc += U[(w * NSVP + jj) * V + e];
+      XS[t] = fma(acc, p.inv_q, XS[t]);
+    }
+    __syncthreads();
+    if (colv) {
+#pragma unroll
+      for (int e = 0; e < V; ++e) xv[e] = XS[j * V + e];
+    }
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) a[i] = an[i];
+    ++b;
+    kl = kn;
+    L = Ln;
+    check = checkn;
+    BPROF(5);
+  }
+#ifdef RKA_BLK_PROF
+  if (t == 0 && (g == 0 || g == G / 2))
+    printf("blk-prof g=%d blocks=%lld dots=%llu put=%llu phase1=%llu phase2=%llu scales=%llu "
+           "update=%llu\n",
+           g, (long long)b, (unsigned long long)bp_t[0], (unsigned long long)bp_t[1],
+           (unsigned long long)bp_t[2], (unsigned long long)bp_t[3], (unsigned long long)bp_t[4],
+           (unsigned long long)bp_t[5]);
+#endif
+  if (colv && rgi == 0) {
+#pragma unroll
+    for (int e = 0; e < V; ++e) p.x[cv * V + e] = xv[e];
+  }
+  if (!stopped && g == 0 && t == 0) p.st->iterations = p.lay.k0 + p.lay.K;
+}
+
+// ===========================================================================
+// Host side: geometry and launches.
+// ===========================================================================
+static int pow2_at_most(int v) {
+  int r = 1;
+  while (r * 2 <= v) r *= 2;
+  return r;
+}
+
+static size_t blk_lds_bytes(int q, int p, int nsvp, int V, int NT, int G) {
+  const int Rmax = q * p, nv = Rmax + 1;
+  const int cstride = (blk_ncoef(q, p) + 127) & ~127;
+  size_t d = (size_t)cstride + nv + 4 * Rmax + (size_t)(NT / kWave) * nsvp * V + (size_t)nsvp * V +
+             (size_t)G * ((nv + G - 1) / G);
+  return d * sizeof(double);
+}
+
+constexpr size_t kBMaxLds = 150 * 1024;
+constexpr int kBMaxRPT = 16;
+
+bool rka_blk_plan(const SolveShape& sh, int p_req, RkaBlkGeom* geo) {
+  const int esz = sh.dtype == 0 ? 8 : (sh.dtype == 1 ? 4 : 2);
+  const int V = sh.vec_ok ? 16 / esz : 1;
+  if (sh.acc != 0 || sh.bs != 1) return false;
+  const int64_t nvec = sh.vec_ok ? sh.n / V : sh.n;
+  const int q = sh.q;
+  // rows per block: at most 128 (256 with one iteration per block, which
+  // needs no coefficients); default blocks of 64 rows (128 for q > 32)
+  const int rmax = kBMaxRows;
+  int p = p_req > 0 ? p_req : std::max(1, (q <= 32 ? 64 : rmax) / q);
+  if (p > 1 && p > rmax / q) p = rmax / q;
+  if (p < 1 || (p == 1 && q > 2 * rmax)) return false;
+  const int target = sh.grid > 0 ? sh.grid : sh.num_cu;
+  int64_t nsv = (nvec + target - 1) / target;
+  if (nsv < 1) nsv = 1;
+  if (nsv > kWave) return false;  // a row group is one team of lanes inside a wave
+  const int G = (int)((nvec + nsv - 1) / nsv);
+  if (G < 2) return false;  // one slice: no exchange to save
+  const int NT = kBThreads;
+  int nsvp = 1;
+  while (nsvp < nsv) nsvp *= 2;
+  const int rg = NT / nsvp;
+  // the largest p whose rows fit the register tile and LDS
+  for (; p >= 1; --p) {
+    const int R = q * p;
+    const int rpt = (R + rg - 1) / rg;
+    if (rpt > kBMaxRPT) continue;
+    if (blk_lds_bytes(q, p, nsvp, V, NT, G) > kBMaxLds) continue;
+    if (R + 1 > kBPoll * NT || (int64_t)G * ((R + 1 + G - 1) / G) > (int64_t)kBPoll * NT) continue;
+    break;
+  }
+  if (p < 1) return false;
+  const int R = q * p;
+  int rpt = (R + rg - 1) / rg;
+  const int buckets[] = {1, 2, 3, 4, 6, 8, 11, 16};
+  for (int bk : buckets)
+    if (rpt <= bk) {
+      rpt = bk;
+      break;
+    }
+  geo->G = G;
+  geo->nsv = (int)nsv;
+  geo->nsvp = nsvp;
+  geo->rg = rg;
+  geo->nt = NT;
+  geo->rpt = rpt;
+  geo->p = p;
+  geo->nv = R + 1;
+  geo->ncoef = blk_ncoef(q, p);
+  geo->tr = 1;
+  {
+    const int C = (R + 1 + G - 1) / G;
+    geo->trp = pow2_at_most(std::max(1, std::min(64, NT / C)));
+  }
+  geo->trm = pow2_at_most(std::max(1, std::min(64, NT / R)));
+  geo->lds = blk_lds_bytes(q, p, nsvp, V, NT, G);
+  geo->cstride = (geo->ncoef + 127) & ~127;
+  // coefficient pass: rows padded to 16, an odd column stride (staging
+  // writes of consecutive columns spread over the banks), chunks of
+  // 4096 / (rows rounded up to a power of two) columns
+  const int RP = 16 * ((R + 15) / 16);
+  geo->crs = RP + 1;
+  {
+    int rp = 1, l = 12;
+    while (rp < RP) {
+      rp *= 2;
+      --l;
+    }
+    geo->clcw = l;
+  }
+  // Gram tiles of a full block (those of a shorter block are among them),
+  // spread over the 4 waves
+  {
+    int nt = 0;
+    for (int I = 0; I < RP / 16; ++I)
+      for (int J = 0; J <= I; ++J)
+        if (std::min(16 * I + 15, R - 1) / q > (16 * J) / q) ++nt;
+    const int per = (nt + 3) / 4;
+    geo->cslots = per <= 2 ? 2 : per <= 4 ? 4 : per <= 6 ? 6 : per <= 7 ? 7 : kCMaxSlots;
+  }
+  // the staged chunk and N share LDS
+  geo->clds = (std::max((size_t)(1 << geo->clcw) * geo->crs, (size_t)blk_ncoef(q, p)) + kBMaxRows) *
+                  sizeof(double) + kBMaxRows * sizeof(int64_t);
+  if (geo->clds > kBMaxLds) return false;
+  return true;
+}
+
+int64_t rka_blk_nblk(const RkaBlkGeom& geo, int64_t k0, int64_t K, int64_t check_every) {
+  return BlkLayout::make(k0, K, check_every, geo.p).nblk;
+}
+
+template <typename T, int NS>
+static hipError_t launch_coef_ns(const RkaBlkGeom& geo, CoefArgs& a, int grid, hipStream_t s) {
+  const void* fn = (const void*)blk_coef_kernel<T, NS>;
+  if (geo.clds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)geo.clds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((blk_coef_kernel<T, NS>), dim3(grid), dim3(kCThreads), geo.clds, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_coef_t(const RkaBlkGeom& geo, CoefArgs& a, int grid, hipStream_t s) {
+  switch (geo.cslots) {
+    case 2: return launch_coef_ns<T, 2>(geo, a, grid, s);
+    case 4: return launch_coef_ns<T, 4>(geo, a, grid, s);
+    case 6: return launch_coef_ns<T, 6>(geo, a, grid, s);
+    case 7: return launch_coef_ns<T, 7>(geo, a, grid, s);
+    default: return launch_coef_ns<T, kCMaxSlots>(geo, a, grid, s);
+  }
+}
+
+template <typename T, int V, int RPT>
+static hipError_t launch_blk_t(const RkaBlkGeom& geo, BlkArgs& a, hipStream_t s) {
+  const void* fn = (const void*)rka_blk_kernel<T, V, RPT>;
+  if (geo.lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)geo.lds);
+    if (e != hipSuccess) return e;
+  }
+  void* args[] = {&a};
+  return launch_persistent(fn, dim3(geo.G), dim3(geo.nt), args, (unsigned)geo.lds, s);
+}
+
+template <typename T, int V>
+static hipError_t launch_blk_rpt(const RkaBlkGeom& geo, BlkArgs& a, hipStream_t s) {
+  switch (geo.rpt) {
+    case 1: return launch_blk_t<T, V, 1>(geo, a, s);
+    case 2: return launch_blk_t<T, V, 2>(geo, a, s);
+    case 3: return launch_blk_t<T, V, 3>(geo, a, s);
+    case 4: return launch_blk_t<T, V, 4>(geo, a, s);
+    case 6: return launch_blk_t<T, V, 6>(geo, a, s);
+    case 8: return launch_blk_t<T, V, 8>(geo, a, s);
+    case 11: return launch_blk_t<T, V, 11>(geo, a, s);
+    default: return launch_blk_t<T, V, 16>(geo, a, s);
+  }
+}
+
+hipError_t launch_blk_coef(const SolveShape& sh, const RkaBlkGeom& geo, const RowRec* rec,
+                           int64_t k0, int64_t K, int64_t check_every, double* coef,
+                           hipStream_t s) {
+  if (geo.p <= 1) return hipSuccess;  // one iteration per block: no coefficients
+  const BlkLayout lay = BlkLayout::make(k0, K, check_every, geo.p);
+  const int64_t nblk = lay.nblk;
+  CoefArgs c{};
+  c.A = sh.A;
+  c.lda = sh.lda;
+  c.n = sh.n;
+  c.rec = rec;
+  c.lay = lay;
+  c.q = sh.q;
+  c.RS = geo.crs;
+  c.lcw = geo.clcw;
+  c.cstride = geo.cstride;
+  c.inv_q = 1.0 / (double)sh.q;
+  c.coef = coef;
+  c.ncoef = geo.ncoef;
+  const int grid = (int)std::min<int64_t>(nblk, (int64_t)sh.num_cu * 4);
+  switch (sh.dtype) {
+    case 0: return launch_coef_t<double>(geo, c, grid, s);
+    case 1: return launch_coef_t<float>(geo, c, grid, s);
+    default: return launch_coef_t<bf16_t>(geo, c, grid, s);
+  }
+}
+
+hipError_t launch_blk_iter(const SolveShape& sh, const RkaBlkGeom& geo, const RowRec* rec,
+                           int64_t k0, int64_t K, int64_t check_every, const double* coef,
+                           uint64_t* part, uint64_t* red, DevStatus* st, hipStream_t s) {
+  const BlkLayout lay = BlkLayout::make(k0, K, check_every, geo.p);
+  const int esz = sh.dtype == 0 ? 8 : (sh.dtype == 1 ? 4 : 2);
+  BlkArgs a{};
+  a.A = sh.A;
+  a.lda = sh.lda;
+  a.nvec = sh.vec_ok ? sh.n / (16 / esz) : sh.n;
+  a.rec = rec;
+  a.coef = coef;
+  a.x = sh.x;
+  a.x_ref = sh.x_ref;
+  a.inv_q = 1.0 / (double)sh.q;
+  a.lay = lay;
+  a.q = sh.q;
+  a.nsv = geo.nsv;
+  a.nsvp = geo.nsvp;
+  a.rg = geo.rg;
+  a.G = geo.G;
+  a.nt = geo.nt;
+  a.nv_max = geo.nv;
+  a.cstride = geo.cstride;
+  a.tr = geo.tr;
+  a.trp = geo.trp;
+  a.trm = geo.trm;
+  a.part = part;
+  a.red = red;
+  a.st = st;
+  switch (sh.dtype) {
+    case 0:
+      return sh.vec_ok ? launch_blk_rpt<double, 2>(geo, a, s) : launch_blk_rpt<double, 1>(geo, a, s);
+    case 1:
+      return sh.vec_ok ? launch_blk_rpt<float, 4>(geo, a, s) : launch_blk_rpt<float, 1>(geo, a, s);
+    default:
+      return sh.vec_ok ? launch_blk_rpt<bf16_t, 8>(geo, a, s) : launch_blk_rpt<bf16_t, 1>(geo, a, s);
+  }
+}
+
+}  // namespace rka

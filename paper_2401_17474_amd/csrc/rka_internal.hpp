@@ -10,6 +10,16 @@ namespace rka {
 struct DevStatus;
 struct RowRec;
 
+// Launch of a persistent kernel whose workgroups wait for one another: a
+// cooperative launch, for which the runtime checks that the whole grid is
+// co-resident; or, with RKA_COOPERATIVE=0 in the environment, a plain launch
+// (for tools that do not handle cooperative launches -- rocprofv3 ends with a
+// segmentation fault in its exit handlers after a program that made one).
+// Every wait inside the kernels is bounded, so a grid that is not
+// co-resident ends with RKA_EDEVICE rather than hanging.  (rka_api.hip)
+hipError_t launch_persistent(const void* fn, dim3 grid, dim3 block, void** args, unsigned lds,
+                             hipStream_t s);
+
 // --- sampler side (rka_setup.hip) ------------------------------------------
 hipError_t launch_row_norms(const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
                             bool vec_ok, double* w, hipStream_t s);
@@ -106,23 +116,32 @@ hipError_t launch_sstep_chunk(const SolveShape& sh, const RkaSstepGeom& geo, con
 // coefficient pass runs 8 x 8 inner-product tiles of f lanes each.
 struct RkaBlkGeom {
   int G, nsv, rg, nt, rpt;
+  int nsvp;              // lanes per row group (nsv rounded up to a power of two)
   int p;                 // iterations per exchange (at most)
   int nv;                // exchange values of a full block: p q + 1
   int ncoef;             // coefficients of a full block: q^2 p (p-1) / 2
   int tr, trp, trm;      // reduction teams (see the kernel's arguments)
   size_t lds;
-  int ctiles, cf, crs;   // coefficient pass: tiles, lanes per tile, LDS stride
+  int cstride;           // doubles between blocks in the coefficient buffer
+  int crs;               // coefficient pass: column stride of its staged chunk
+  int clcw;              // log2 of its staged chunk's columns
+  int cslots;            // its Gram tiles per wave
   size_t clds;
 };
 // p_req = 0: the largest p that fits (q p <= 128).  FP64 arithmetic, RKA only.
 bool rka_blk_plan(const SolveShape& sh, int p_req, RkaBlkGeom* geo);
 // blocks of a chunk [k0, k0 + K) with stopping tests every check_every (0: none)
 int64_t rka_blk_nblk(const RkaBlkGeom& geo, int64_t k0, int64_t K, int64_t check_every);
-// coef: rka_blk_nblk(...) x ncoef doubles; part: G x nv, red: nv tagged slots
-// (zeroed once per solve).  Runs the coefficient pass, then the iterations.
-hipError_t launch_blk_chunk(const SolveShape& sh, const RkaBlkGeom& geo, const RowRec* rec,
-                            int64_t k0, int64_t K, int64_t check_every, double* coef,
-                            uint64_t* part, uint64_t* red, DevStatus* st, hipStream_t s);
+// The coefficient pass of a chunk (nothing for p = 1) into coef:
+// rka_blk_nblk(...) x cstride doubles.
+hipError_t launch_blk_coef(const SolveShape& sh, const RkaBlkGeom& geo, const RowRec* rec,
+                           int64_t k0, int64_t K, int64_t check_every, double* coef,
+                           hipStream_t s);
+// The chunk's iterations from those coefficients; part: G x nv, red: nv
+// tagged slots (zeroed once per solve).
+hipError_t launch_blk_iter(const SolveShape& sh, const RkaBlkGeom& geo, const RowRec* rec,
+                           int64_t k0, int64_t K, int64_t check_every, const double* coef,
+                           uint64_t* part, uint64_t* red, DevStatus* st, hipStream_t s);
 
 struct RkabGeom {
   int G;       // workgroups (each runs workers g, g + G, ...)

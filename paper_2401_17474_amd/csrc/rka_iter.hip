@@ -271,15 +271,26 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
             }
             __builtin_amdgcn_s_sleep(1);
           }
-          for (int gg = t + NT; gg < G; gg += NT) {  // only when G > NT
+          // slots beyond the thread count (G > NT), under the same bounded
+          // wait: a slot that never arrives makes the whole solve report
+          // RKA_EDEVICE instead of adding zero
+          bool got_all = true;
+          for (int gg = t + NT; gg < G; gg += NT) {
             uint64_t lo, hi;
             double pv = 0.0;
+            bool got = false;
             for (unsigned spins = 0; spins < kSpinLimit; ++spins) {
               part.fetch((int64_t)gg * (q + 1) + r, lo, hi);
-              if (TagSlots::decode(lo, hi, tag, pv)) break;
+              if (TagSlots::decode(lo, hi, tag, pv)) {
+                got = true;
+                break;
+              }
+              __builtin_amdgcn_s_sleep(1);
             }
+            got_all = got_all && got;
             v += pv;
           }
+          if (!__syncthreads_and(got_all)) ok = false;
           const double D = block_sum(v, RED);
           if (t == 0) scal.put(r, r < q ? scale_of(rr.alpha, rr.b, rr.wn, D) : D, tag);
         }
@@ -500,7 +511,7 @@ static hipError_t launch_col_t(const RkaColGeom& geo, RkaColArgs& a, hipStream_t
   const void* fn = geo.rpt == 11 ? (const void*)rka_col_kernel<T, C, V, 11, false>
                    : geo.gather  ? col_fn<T, C, V, true>(geo.rpt)
                                  : col_fn<T, C, V, false>(geo.rpt);
-  return hipLaunchCooperativeKernel(fn, dim3(geo.G), dim3(geo.nt), args, (unsigned)geo.lds, s);
+  return launch_persistent(fn, dim3(geo.G), dim3(geo.nt), args, (unsigned)geo.lds, s);
 }
 
 hipError_t launch_rka_chunk(const SolveShape& sh, const RkaColGeom& geo, const RowRec* rec,

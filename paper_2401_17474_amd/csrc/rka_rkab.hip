@@ -378,7 +378,7 @@ static hipError_t launch_rkab_t(const RkabGeom& geo, RkabArgs& a, hipStream_t s)
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)geo.lds);
     if (e != hipSuccess) return e;
   }
-  return hipLaunchCooperativeKernel(fn, dim3(geo.G), dim3(geo.nt), args, (unsigned)geo.lds, s);
+  return launch_persistent(fn, dim3(geo.G), dim3(geo.nt), args, (unsigned)geo.lds, s);
 }
 
 hipError_t launch_rkab_chunk(const SolveShape& sh, const RkabGeom& geo, const RowRec* rec,

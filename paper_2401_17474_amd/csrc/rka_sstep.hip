@@ -851,7 +851,7 @@ static hipError_t launch_sstep_t(const RkaSstepGeom& geo, SstepArgs& a, hipStrea
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  return hipLaunchCooperativeKernel(fn, dim3(geo.G), dim3(geo.nt), args, (unsigned)lds, s);
+  return launch_persistent(fn, dim3(geo.G), dim3(geo.nt), args, (unsigned)lds, s);
 }
 
 hipError_t launch_sstep_chunk(const SolveShape& sh, const RkaSstepGeom& geo, const RowRec* rec,

@@ -1,0 +1,173 @@
+"""GPU parity of RKA in blocks of p iterations with coefficients from a
+streaming pass (kernel 4, rka_block = 2): per block the scales are s = M c
+with M = (I + N)^-1 formed ahead of the iterations from the inner products of
+the block's rows (Eq. (7) unrolled over the block), and only the p q dot
+products with x^(k) cross the chip.  The same iteration in exact arithmetic:
+FP64 x within 1e-12 of the oracle on the same row stream, over block lengths,
+ragged block and chunk ends, stopping tests, resumed streams, storage types,
+row orders and weights, and launch geometries."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import assert_x_close, host, say, to_dev, vec
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+rka = pytest.importorskip("paper_2401_17474_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rka.lib()
+
+
+def _system(m, n, dtype="f64", seed=1, noise=0.01):
+    A, xs, b = workloads.gaussian_system(m, n, seed=seed, noise_var=noise, dtype=dtype)
+    return np.array(A), xs, b
+
+
+def _odt(dtype):
+    return "bf16" if dtype == "bf16" else None
+
+
+CASES = [
+    # m, n, dtype, q, p (0: the library's), K, grid
+    (3000, 2000, "f64", 16, 0, 40, 0),      # 4 iterations per block, default grid
+    (3000, 2000, "f64", 16, 8, 41, 0),      # 128 rows per block, ragged last block
+    (3000, 2000, "f64", 8, 0, 37, 0),
+    (3000, 2000, "f64", 4, 16, 50, 0),
+    (3000, 2000, "f64", 32, 0, 20, 0),
+    (3000, 2000, "f64", 64, 0, 15, 0),      # 2 iterations of 64 rows
+    (3000, 2000, "f64", 5, 12, 33, 0),      # odd q, 60 rows
+    (2500, 999, "f64", 16, 4, 30, 0),       # scalar path, ragged slice
+    (2000, 1000, "f64", 16, 4, 30, 8),      # few workgroups, 64-lane row groups
+    (2000, 1000, "f64", 16, 4, 30, 100),    # more workgroups than exchange values
+    (1500, 4096, "f32", 16, 4, 30, 0),      # narrow storage, FP64 arithmetic
+    (1500, 4096, "bf16", 12, 5, 30, 0),
+    (700, 48, "f64", 8, 4, 25, 2),
+    (3000, 2000, "f64", 256, 1, 6, 0),     # one iteration per block: no coefficients
+    (3000, 2000, "f64", 128, 1, 8, 0),
+    (5000, 10000, "f64", 16, 4, 24, 0),     # long rows
+]
+
+
+@pytest.mark.parametrize("m,n,dtype,q,p,K,grid", CASES)
+def test_blk_vs_oracle(m, n, dtype, q, p, K, grid):
+    say(f"blk {dtype} {m}x{n} q={q} p={p} K={K} grid={grid}")
+    A, _, b = _system(m, n, dtype, seed=m + n + q)
+    x, info, st = rka.solve_ex(to_dev(A, dtype), vec(b), method=0, q=q, alpha=1.1, max_iter=K,
+                               seed=13, steps_per_exchange=p, rka_block=2, grid=grid)
+    assert info.status == rka.OK and info.iterations == K
+    assert st["kernel"] == 4, st
+    if p:
+        assert st["variant"] == p
+    if grid:
+        assert st["grid"] <= grid
+    xo, _ = oracle.rka(A, b, q=q, alpha=1.1, max_iter=K, seed=13, dtype=_odt(dtype))
+    assert_x_close(host(x), xo, what=f"blk q={q} p={st['variant']} G={st['grid']}")
+
+
+def test_blk_resume_offsets_and_chunks():
+    """iter_offset continues the stream; a solve split at a block boundary
+    equals the whole bitwise, and any split is within 1e-12 of the oracle."""
+    say("blk resume")
+    A, _, b = _system(3000, 1024, seed=4)
+    Ad, bd = to_dev(A), vec(b)
+    kw = dict(method=0, q=16, max_iter=0, seed=21, steps_per_exchange=4, rka_block=2)
+
+    def run(K, x0=None, off=0):
+        kw.update(max_iter=K)
+        return rka.solve_ex(Ad, bd, x0=x0, iter_offset=off, **kw)[0]
+
+    full = run(40)
+    assert torch.equal(full, run(40))
+    half = run(12)
+    assert torch.equal(full, run(28, x0=half, off=12))
+    part = run(13)
+    rest = run(27, x0=part, off=13)
+    xo, _ = oracle.rka(A, b, q=16, max_iter=40, seed=21)
+    assert_x_close(host(rest), xo, what="blk resumed off a block boundary")
+
+
+@pytest.mark.parametrize("ce", [1, 5, 7, 16])
+def test_blk_stops_where_the_one_iteration_kernel_stops(ce):
+    """Blocks end at stopping tests: the test at iteration k sees x^(k), so the
+    stopping count equals the column kernel's, and x matches the oracle's
+    after that count."""
+    say(f"blk stop check_every={ce}")
+    A, xs, _ = _system(4000, 200, seed=5, noise=0.0)
+    b = A @ xs
+    Ad, bd, xd = to_dev(A), vec(b), vec(xs)
+    common = dict(method=0, q=8, alpha=1.0, max_iter=200000, tol=1e-8, x_ref=xd, seed=3,
+                  check_every=ce)
+    x1, i1, s1 = rka.solve_ex(Ad, bd, steps_per_exchange=1, **common)
+    x4, i4, s4 = rka.solve_ex(Ad, bd, steps_per_exchange=8, rka_block=2, **common)
+    assert s1["kernel"] == 1 and s4["kernel"] == 4
+    assert i4.status == i1.status == rka.OK and i4.iterations == i1.iterations
+    assert i4.iterations % ce == 0
+    xo, _ = oracle.rka(A, b, q=8, alpha=1.0, max_iter=i4.iterations, seed=3)
+    assert_x_close(host(x4), xo, what="blk stopped iterate")
+
+
+@pytest.mark.parametrize("variant", ["cyclic", "blocks", "worker_alpha", "row_weight"])
+def test_blk_row_orders_and_weights(variant):
+    say(f"blk {variant}")
+    m, n, q, K = 2400, 1000, 8, 30
+    A, _, b = _system(m, n, seed=31)
+    Ad, bd = to_dev(A), vec(b)
+    w = oracle.row_norms(A)
+    kw = dict(method=0, q=q, max_iter=K, seed=17, steps_per_exchange=4, rka_block=2)
+    z = np.zeros(n)
+    if variant == "cyclic":
+        x, info, st = rka.solve_ex(Ad, bd, sampling=2, **kw)
+        xo = oracle.rka_given(A, b, z, oracle.indices_cyclic(m, 0, K, q), q=q)
+    elif variant == "blocks":
+        x, info, st = rka.solve_ex(Ad, bd, sampling=1, **kw)
+        xo = oracle.rka_given(A, b, z, oracle.indices_blocks(w, 17, 0, K, q), q=q)
+    elif variant == "worker_alpha":
+        wa = np.linspace(0.6, 1.4, q)
+        x, info, st = rka.solve_ex(Ad, bd, worker_alpha=vec(wa), **kw)
+        xo = oracle.rka_walpha_given(A, b, z, oracle.indices(w, 17, 0, K, q), wa, q=q)
+    else:
+        wr = 0.5 + np.random.default_rng(3).random(m)
+        x, info, st = rka.solve_ex(Ad, bd, row_weight=vec(wr), **kw)
+        xo = oracle.rka_wrow_given(A, b, z, oracle.indices(w, 17, 0, K, q), wr, q=q)
+    assert info.status == rka.OK and st["kernel"] == 4
+    assert_x_close(host(x), xo, what=f"blk {variant}")
+
+
+def test_blk_falls_back_when_blocks_do_not_fit():
+    """More than 256 rows per iteration: the library runs another kernel (the
+    same iteration)."""
+    A, _, b = _system(3000, 1000, seed=2)
+    x, info, st = rka.solve_ex(to_dev(A), vec(b), method=0, q=300, max_iter=5, seed=3,
+                               rka_block=2)
+    assert info.status == rka.OK and st["kernel"] in (1, 2)
+    xo, _ = oracle.rka(A, b, q=300, max_iter=5, seed=3)
+    assert_x_close(host(x), xo, what="fallback")
+    with pytest.raises(rka.RKAError):
+        rka.solve_ex(to_dev(A), vec(b), method=0, q=4, max_iter=5, rka_block=3)
+
+
+def test_library_chooses_blocks_with_precomputed_coefficients():
+    """Left to the library (steps_per_exchange = 0, rka_block = 0), RKA up to
+    q = 64 on a shape with several workgroups runs kernel 4; a stopping test
+    every iteration, or q above 64, runs the one-iteration kernel."""
+    say("blk auto selection")
+    A, xs, b = _system(3000, 2000, seed=9)
+    Ad, bd = to_dev(A), vec(b)
+    for q in (8, 16, 64):
+        x, info, st = rka.solve_ex(Ad, bd, method=0, q=q, max_iter=24, seed=4)
+        assert info.status == rka.OK and st["kernel"] == 4 and st["variant"] >= 2, (q, st)
+        xo, _ = oracle.rka(A, b, q=q, max_iter=24, seed=4)
+        assert_x_close(host(x), xo, what=f"auto q={q}")
+    _, _, st = rka.solve_ex(Ad, bd, method=0, q=16, max_iter=24, seed=4, tol=1e-30,
+                            x_ref=vec(xs), check_every=1)
+    assert st["kernel"] == 1
+    _, _, st = rka.solve_ex(Ad, bd, method=0, q=128, max_iter=8, seed=4)
+    assert st["kernel"] == 1

@@ -60,7 +60,7 @@ def test_kernels_asked_for_on_shapes_they_cannot_take():
     # three columns: the block kernel on three one-column workgroups
     A = np.random.default_rng(42).standard_normal((50, 3))
     x, info, st = rka.solve_ex(to_dev(A), vec(b), method=0, q=4, max_iter=12, seed=2,
-                               steps_per_exchange=4)
+                               steps_per_exchange=4, rka_block=1)
     assert st["kernel"] == 3 and st["grid"] == 3
     xo, _ = oracle.rka(A, b, q=4, max_iter=12, seed=2)
     assert_x_close(host(x), xo, 1e-12, "block kernel, one column per workgroup")

@@ -193,6 +193,19 @@ def test_rka_allreduce_modes_and_grids(q, grid, allreduce):
     assert_x_close(host(x), xo, what=f"rka q={q} grid={grid} mode={allreduce}")
 
 
+def test_rka_two_phase_exchange_with_more_workgroups_than_threads():
+    """2000 FP64 columns at q = 17: more workgroups than threads per workgroup,
+    so a reducer polls some slots in a second round (under the bounded wait)."""
+    say("rka G > NT")
+    A, _, b = _system(3000, 2000, seed=17)
+    x, info, st = rka.solve_ex(to_dev(A), vec(b), method=0, q=17, max_iter=30, seed=9,
+                               steps_per_exchange=1)
+    assert info.status == rka.OK and st["kernel"] == 1 and st["variant"] == 0
+    assert st["grid"] > st["threads"], st
+    xo, _ = oracle.rka(A, b, q=17, max_iter=30, seed=9)
+    assert_x_close(host(x), xo, what="rka G > NT")
+
+
 def test_rka_wide_q_falls_back_to_worker_kernel():
     # q rows per slice beyond the column kernel's tile: same iteration, other kernel
     say("rka q=2000")

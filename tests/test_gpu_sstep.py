@@ -1,5 +1,6 @@
-"""GPU parity of RKA with several iterations per exchange (the block form of
-Eq. (7) whose later dot products come from the first through the row inner
+"""GPU parity of RKA with several iterations per exchange, with the row inner
+products formed inside the exchange (kernel 3, rka_block = 1; the block form
+of Eq. (7) whose later dot products come from the first through the row inner
 products): FP64 x within 1e-12 of the oracle on the same row stream for
 block lengths 2..8, ragged q, ragged chunks and offsets, the scalar and
 vector paths and narrow storage; the stopping test at the same iteration as
@@ -45,7 +46,8 @@ def test_sstep_vs_oracle(m, n, q, p, K, off, dtype):
     A, _, b = workloads.gaussian_system(m, n, seed=31, noise_var=1e-2, dtype=dtype)
     A = np.array(A)
     x, info, st = rka.solve_ex(to_dev(A, dtype), vec(b), method=0, q=q, alpha=1.1, max_iter=K,
-                               seed=6, iter_offset=off, steps_per_exchange=p)
+                               seed=6, iter_offset=off, steps_per_exchange=p,
+                               rka_block=1)
     assert info.status == rka.OK and info.iterations == K
     assert st["kernel"] == 3 and st["variant"] == p
     odt = "bf16" if dtype == "bf16" else None
@@ -61,7 +63,7 @@ def test_sstep_stops_where_the_one_iteration_kernel_stops(check_every, p):
     kw = dict(method=0, q=16, alpha=8.0, max_iter=20000, tol=1e-8, x_ref=vec(xs),
               check_every=check_every, seed=2)
     x1, i1, s1 = rka.solve_ex(to_dev(A), vec(b), steps_per_exchange=1, **kw)
-    xp, ip, sp = rka.solve_ex(to_dev(A), vec(b), steps_per_exchange=p, **kw)
+    xp, ip, sp = rka.solve_ex(to_dev(A), vec(b), steps_per_exchange=p, rka_block=1, **kw)
     assert s1["kernel"] == 1 and sp["kernel"] == 3
     assert i1.status == rka.OK and ip.status == rka.OK
     assert ip.iterations == i1.iterations and ip.iterations % check_every == 0
@@ -73,7 +75,7 @@ def test_sstep_cyclic_order_and_row_weights():
     wrow = np.random.default_rng(33).uniform(0.5, 1.5, size=1800)
     K = 30
     x, info, st = rka.solve_ex(to_dev(A), vec(b), method=0, q=16, max_iter=K, sampling=2,
-                               row_weight=vec(wrow), steps_per_exchange=4)
+                               row_weight=vec(wrow), steps_per_exchange=4, rka_block=1)
     assert st["kernel"] == 3
     xo = oracle.rka_wrow_given(A, b, np.zeros(1200), oracle.indices_cyclic(1800, 0, K, 16, 1),
                                wrow, q=16)
@@ -83,8 +85,10 @@ def test_sstep_cyclic_order_and_row_weights():
 def test_sstep_is_deterministic():
     A, _, b = workloads.gaussian_system(3000, 2500, seed=34, noise_var=1e-2)
     Ad, bd = to_dev(np.array(A)), vec(b)
-    xa, _, _ = rka.solve_ex(Ad, bd, method=0, q=16, max_iter=50, seed=3, steps_per_exchange=4)
-    xb, _, _ = rka.solve_ex(Ad, bd, method=0, q=16, max_iter=50, seed=3, steps_per_exchange=4)
+    xa, _, _ = rka.solve_ex(Ad, bd, method=0, q=16, max_iter=50, seed=3, steps_per_exchange=4,
+                            rka_block=1)
+    xb, _, _ = rka.solve_ex(Ad, bd, method=0, q=16, max_iter=50, seed=3, steps_per_exchange=4,
+                            rka_block=1)
     assert np.array_equal(host(xa), host(xb))
 
 
@@ -93,7 +97,7 @@ def test_sstep_falls_back_when_the_block_does_not_fit():
     A = np.array(A)
     # q p = 128 rows exceed the block tile: the one-iteration kernel runs
     x, info, st = rka.solve_ex(to_dev(A), vec(b), method=0, q=32, max_iter=10,
-                               steps_per_exchange=4)
+                               steps_per_exchange=4, rka_block=1)
     assert st["kernel"] == 1
     idx = oracle.indices(oracle.row_norms(A), 1, 0, 10, 32)
     assert_x_close(host(x), oracle.rka_given(A, b, np.zeros(1000), idx, q=32), 1e-12, "fallback")
