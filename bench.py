@@ -37,7 +37,7 @@ METRIC = "row projections/s + HBM GB/s; time to 1e-6 rel. error, plain FP64 vs c
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--m", type=int, default=80000)
     ap.add_argument("--n", type=int, default=10000)
@@ -45,11 +45,13 @@ def parse():
     ap.add_argument("--cells", default="all", help="all | rka | rkab | comma list like rkab:256:10")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plateau", action="store_true",
+                    help="skip the time-to-plateau passes of the cells")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the precision / batching / differentiation measurements")
-    ap.add_argument("--forms", default="precision,batching,differentiation,distributed_approach,"
-                    "coherent_rows,paper_table2")
+    ap.add_argument("--forms", default="precision,precision_200000x20000,batching,"
+                    "differentiation,distributed_approach,coherent_rows")
     ap.add_argument("--batch-systems", type=int, default=512)
     ap.add_argument("--batch-sample", type=int, default=16,
                     help="systems solved one by one in plain FP64 for the batching comparison")
@@ -87,13 +89,15 @@ def make_cells(spec, astar):
 def kernel_name(stats, storage="double", vec=2, rkab=False):
     """Template instance as named in the library: <storage, accumulation,
     elements per 16-byte vec, register bucket, all-gather / iterate in LDS>
-    (the block kernel: <storage, elements per vec, rows per thread, RKAB>)."""
+    (the block kernels: <storage, elements per vec, rows per thread[, RKAB]>)."""
     acc = "float" if stats.get("accumulate") == 1 else "double"
     flag = "true" if stats.get("variant") == 1 else "false"
     if stats["kernel"] == 1:
         return f"rka_col_kernel<{storage}, {acc}, {vec}, {stats['bucket']}, {flag}>"
     if stats["kernel"] == 3:
         return f"rka_sstep_kernel<{storage}, {vec}, {stats['bucket']}, {'true' if rkab else 'false'}>"
+    if stats["kernel"] == 4:
+        return f"rka_blk_kernel<{storage}, {vec}, {stats['bucket']}>"
     return f"rkab_kernel<{storage}, {acc}, {vec}, {stats['bucket']}, {flag}>"
 
 
@@ -119,6 +123,125 @@ def cpu_baseline(A, b, seconds):
                        f"({info['projections']} projections) including its row norms and "
                        f"running sum, {dt:.1f} s wall"),
             "host_cpu": _cpu_model(), "host_threads": os.cpu_count()}
+
+
+def copy_ceiling(gib=4, reps=7):
+    """STREAM-copy ceiling of this GPU in the same run: a device-to-device copy
+    of `gib` GiB (torch), read + write bytes over its HIP-event time, median
+    of `reps`."""
+    import torch
+    n = (gib << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    times.sort()
+    ms = times[len(times) // 2]
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"gbps": 2 * n * 8 / (ms / 1e3) / 1e9, "bytes_moved": 2 * n * 8, "median_ms": ms,
+            "reps": reps, "how": f"torch device-to-device copy of {gib} GiB, HIP events"}
+
+
+def time_to_plateau(P, b, x_ls, cell, rate, seed, max_segments=400):
+    """Time to the error plateau of one cell, with the paper's two passes
+    (Sec. 3.1): pass 1 runs the cell in segments that resume the same row
+    stream and measures ||x - x_LS|| / ||x_LS|| after each, until the error has
+    not fallen by 1 % over the last 10 segments (a stationary error: RKA and
+    RKAB stall at a horizon above x_LS on an inconsistent system, Sec. 2.3.1);
+    the plateau error is the median of the last 10, and K_p the first
+    iteration count whose error is within 10 % of it.  Pass 2 times a fresh
+    solve of exactly K_p iterations without stopping tests (HIP events on the
+    solve's stream, and wall time)."""
+    import torch
+    meth, q, bs, alpha, _ = cell
+    method = 0 if meth == "rka" else 1
+    # segment length: about 1/20 of the e-folds to a 1e-4 error reduction
+    k_est = 9.2 / max(rate * (bs if method == 1 else 1), 1e-12)
+    seg = max(1, int(k_est / 20))
+    x = torch.zeros_like(x_ls)
+    nls = float(x_ls.norm())
+    errs, ks, k = [], [], 0
+    for _ in range(max_segments):
+        x, info, _ = P.solve(b, method=method, q=q, block_size=bs, alpha=alpha, max_iter=seg,
+                             seed=seed, x0=x, iter_offset=k, raise_on_error=False)
+        k += seg
+        e = float((x - x_ls).norm()) / nls
+        errs.append(e)
+        ks.append(k)
+        if info.status < 0 or not math.isfinite(e):
+            return {"status": info.status, "iterations": k, "rel_err": e, "diverged": True}
+        if len(errs) > 10 and errs[-1] > 0.99 * errs[-11]:
+            break
+    tail = sorted(errs[-10:])
+    plateau = tail[len(tail) // 2]
+    kp = next(kk for kk, e in zip(ks, errs) if e <= 1.1 * plateau)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, info, st = P.solve(b, method=method, q=q, block_size=bs, alpha=alpha, max_iter=kp,
+                          seed=seed, timing=True)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    return {"plateau_rel_err": plateau, "iterations_to_plateau": kp, "segment": seg,
+            "segments": len(errs), "rel_err_at_kp": float((x - x_ls).norm()) / nls,
+            "ms_to_plateau": wall, "kernel_ms_to_plateau": st["iterate_ms"] + st["coef_ms"],
+            "projections_to_plateau": info.projections}
+
+
+def cpu_baseline_cells(workloads):
+    """The oracle on the smaller configurations, whole: the 4000 x 200 FP64
+    consistent solve to 1e-8 (q = 8, alpha = 1 and alpha*), and the forward +
+    backward of the differentiable least-squares solve at 20000 x 1000 FP32
+    (the GPU path's steps, each by the oracle: refined forward with the range
+    projection, the minimum-norm column solve, the row solve for lambda, the
+    rank-2 gradient)."""
+    import numpy as np
+    import oracle
+    import paper_2401_17474_amd as rka  # Eq. (6) only (a host function)
+    out = {}
+    A, xs, _ = workloads.gaussian_system(4000, 200, seed=workloads.DATA_SEED + 1)
+    b = A @ xs
+    sv = np.linalg.svd(A, compute_uv=False)
+    F = float(np.sum(sv ** 2))
+    for name, alpha in (("alpha_1", 1.0), ("alpha_star", None)):
+        a = alpha if alpha is not None else rka.alpha_star(sv[-1] ** 2 / F, sv[0] ** 2 / F, 8)
+        t0 = time.perf_counter()
+        x, info = oracle.rka(A, b, q=8, alpha=a, max_iter=200000, tol=1e-8, x_ref=xs, seed=3)
+        dt = time.perf_counter() - t0
+        out[f"4000x200_rka_q8_{name}"] = {"seconds": dt, "iterations": info["iterations"],
+                                          "projections_per_s": info["projections"] / dt,
+                                          "alpha": a, "status": info["status"]}
+    # differentiation form, 20000 x 1000 FP32 storage
+    m, n, q = 20000, 1000, 64
+    A, xs, b = workloads.gaussian_system(m, n, seed=workloads.DATA_SEED + 6, noise_var=1e-2,
+                                         dtype="f32")
+    A = np.array(A)
+    t = np.random.default_rng(workloads.DATA_SEED + 6).standard_normal(n)
+    s_ext = _mp_extremes(m, n)
+    al = rka.alpha_star(*s_ext, q)
+    k = int(math.ceil(1.1 * 9.2 / _rate(s_ext, al, q)))
+    t0 = time.perf_counter()
+    x, _ = oracle.refine(A, b, q=q, acc32=1, alpha=al, inner_iters=k, range_iters=k, range_q=q,
+                         range_alpha=al, sweeps=3, seed=3)
+    t_fwd = time.perf_counter() - t0
+    At = oracle.transpose(A)
+    g = 2 * (x - t)
+    z, _ = oracle.refine(At, g, q=q, acc32=0, alpha=al, inner_iters=k, sweeps=3, seed=4)
+    lam, _ = oracle.refine(A, z, q=q, acc32=1, alpha=al, inner_iters=k, sweeps=3, seed=5)
+    r = b - A.astype(np.float64) @ x
+    dA = np.outer(r, lam) - np.outer(z, x)
+    t_all = time.perf_counter() - t0
+    out["20000x1000_f32_forward_backward"] = {
+        "seconds": t_all, "forward_seconds": t_fwd, "q": q, "alpha": al, "inner_iters": k,
+        "sweeps": 3, "dA_norm": float(np.linalg.norm(dA))}
+    return out
 
 
 # -- the three forms -------------------------------------------------------------
@@ -226,12 +349,12 @@ def bench_precision(rka, A, xs, b, x_ls, s_ext):
         As = A64 if dt == torch.float64 else A64.to(dt)
         x, info, st = rka.solve_ex(As, b3, method=0, q=q3, alpha=a3, max_iter=K3, seed=2,
                                    accumulate=acc, timing=True)
-        it_s = st["iterate_ms"] / 1e3
+        it_s = (st["iterate_ms"] + st["coef_ms"]) / 1e3
         bpp = N * esz + 20
         y, gms = _timed(lambda: rka.gemv(As, x3, c=b3, gamma=-1.0))
         thr[name] = {"projections_per_s": info.projections / it_s,
                      "hbm_gbps": info.projections * bpp / it_s / 1e9,
-                     "us_per_iteration": st["iterate_ms"] * 1e3 / K3,
+                     "us_per_iteration": (st["iterate_ms"] + st["coef_ms"]) * 1e3 / K3,
                      "kernel": kernel_name(st, {"fp64": "double", "fp32": "float",
                                                 "bf16": "rka::bf16_t"}[name],
                                            16 // esz),
@@ -241,6 +364,99 @@ def bench_precision(rka, A, xs, b, x_ls, s_ext):
         torch.cuda.empty_cache()
     out["inner_throughput_200000x20000_rka_q64"] = thr
     del A64, b3, x3
+    torch.cuda.empty_cache()
+    return out
+
+
+def _lsq_normal_equations(Aw_rows, b, n, chunk=20000):
+    """x_LS of min ||A x - b|| in FP64 from the normal equations, G = A^T A
+    summed over row chunks (A widened to FP64 chunk by chunk), Cholesky, and
+    one refinement step with the FP64 residual (cond(A) < 2 for these iid
+    Gaussian shapes, so G is well conditioned).  A measurement aid."""
+    import torch
+    m = b.shape[0]
+    G = torch.zeros((n, n), dtype=torch.float64, device=b.device)
+    Atb = torch.zeros(n, dtype=torch.float64, device=b.device)
+    for r0 in range(0, m, chunk):
+        Ac = Aw_rows(r0, min(m, r0 + chunk))
+        G += Ac.T @ Ac
+        Atb += Ac.T @ b[r0:r0 + Ac.shape[0]]
+        del Ac
+    L = torch.linalg.cholesky(G)
+    x = torch.cholesky_solve(Atb[:, None], L)[:, 0]
+    Atr = torch.zeros(n, dtype=torch.float64, device=b.device)
+    for r0 in range(0, m, chunk):
+        Ac = Aw_rows(r0, min(m, r0 + chunk))
+        Atr += Ac.T @ (b[r0:r0 + Ac.shape[0]] - Ac @ x)
+        del Ac
+    x = x + torch.cholesky_solve(Atr[:, None], L)[:, 0]
+    del G, L
+    return x
+
+
+def bench_precision_large(rka):
+    """The precision form at 200000 x 20000 (b = A x* + N(0, 1e-4)): A stored
+    as BF16 (8 GB) and as FP32 (16 GB) -- each rounded matrix is the problem
+    matrix -- solved to 1e-10 relative error against that matrix's FP64
+    least-squares solution by horizon-free FP64 refinement around binary32
+    inner solves, error reported per sweep; and the time to 1e-6 of BF16 /
+    FP32 against the same refinement in plain FP64 (FP64 storage and
+    arithmetic) on the FP64 matrix.  Inner solves: RKA with q = 64 and
+    alpha* (Eq. (6)) from the Marchenko-Pastur edges; the range projection
+    on the transposed copy with q = 8."""
+    import torch
+    dev = torch.device("cuda:0")
+    M, N = 200000, 20000
+    # q = 64 on A; q = 8 on the 200000-column transpose, whose slices leave
+    # the one-iteration kernel room for 8 rows per workgroup in FP64
+    q, qc = 64, 8
+    s_ext = _mp_extremes(M, N)
+    al, alc = rka.alpha_star(*s_ext, q), rka.alpha_star(*s_ext, qc)
+    k_in = int(math.ceil(1.1 * 9.2 / _rate(s_ext, al, q)))      # ~1e-4 per inner solve
+    k_col = int(math.ceil(1.1 * 9.2 / _rate(s_ext, alc, qc)))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(240117474 + 3)
+    A64 = torch.randn((M, N), generator=gen, device=dev, dtype=torch.float64)
+    xs = torch.randn(N, generator=gen, device=dev, dtype=torch.float64)
+    e = 1e-2 * torch.randn(M, generator=gen, device=dev, dtype=torch.float64)
+    out = {"shape": f"{M}x{N}", "noise": "N(0, 1e-4)", "q": q, "alpha": al, "range_q": qc,
+           "range_alpha": alc, "inner_iters": k_in, "range_iters": k_col}
+    runs = {}
+    for name, dt in (("bf16", torch.bfloat16), ("fp32", torch.float32), ("fp64", torch.float64)):
+        As = A64 if dt == torch.float64 else A64.to(dt)
+        b = (A64 @ xs if dt == torch.float64 else
+             torch.cat([As[r0:r0 + 20000].to(torch.float64) @ xs for r0 in range(0, M, 20000)]))
+        b = b + e
+        log(f"[bench] 200000x20000 {name}: least-squares reference")
+        x_ls = _lsq_normal_equations(lambda r0, r1: As[r0:r1].to(torch.float64), b, N)
+        At = rka.transpose(As)
+        PA, PT = rka.Plan(As), rka.Plan(At)
+        acc = 0 if dt == torch.float64 else 1
+        entry = {}
+        targets = (1e-6,) if dt == torch.float64 else (1e-6, 1e-10)
+        for tol in targets:
+            (x, ri), ms = _timed(lambda: rka.refine_solve(
+                None, b, plan=PA, plan_t=PT, q=q, alpha=al, accumulate=acc, inner_iters=k_in,
+                range_iters=k_col, range_q=qc, range_alpha=alc, max_sweeps=8, tol=tol,
+                x_ref=x_ls, raise_on_error=False))
+            entry[f"to_{tol:g}"] = {"ms": ms, "sweeps": ri.sweeps, "status": ri.status,
+                                    "per_sweep_rel_err": ri.measures,
+                                    "final_rel_err": float((x - x_ls).norm() / x_ls.norm()),
+                                    "projections": ri.projections}
+            if ri.status < 0 and ri.status != rka.NOT_CONVERGED:
+                entry[f"to_{tol:g}"]["error"] = rka.lib().rka_last_error().decode()
+        runs[name] = entry
+        PA.close()
+        PT.close()
+        del At, b, x_ls
+        if As is not A64:
+            del As
+        torch.cuda.empty_cache()
+    for name in ("bf16", "fp32"):
+        runs[name]["speedup_vs_fp64_to_1e-06"] = (runs["fp64"]["to_1e-06"]["ms"] /
+                                                 runs[name]["to_1e-06"]["ms"])
+    out["runs"] = runs
+    del A64, xs, e
     torch.cuda.empty_cache()
     return out
 
@@ -328,9 +544,15 @@ def bench_batching(rka, workloads, count, n_sample, seed):
               (rng.choice(rest, size=k_rest, replace=False), len(rest))]
     t_plain = 0.0
     extrap = 0.0
+    extrap_tuned = 0.0
     plain = []
+
+    def tuned_alpha(A64, qq):
+        lo, hi, F = rka.spectral_bounds(A64, steps=min(120, min(A64.shape)), seed=5)
+        return rka.alpha_star(lo / F, hi / F, qq)
+
     for members, size in strata:
-        t_stratum = 0.0
+        t_stratum = t_tuned = 0.0
         for i in sorted(int(v) for v in members):
             S = systems[i]
             A64 = S.A.to(torch.float64)
@@ -338,23 +560,52 @@ def bench_batching(rka, workloads, count, n_sample, seed):
                                                           max_iter=2000000, tol=1e-6,
                                                           x_ref=planted[i], check_every=10,
                                                           raise_on_error=False))
+            # tuned plain FP64: q = 64 (at most m / 4) with alpha* of Eq. (6)
+            qt = max(1, min(64, S.A.shape[0] // 4))
+            at, t_alpha = _timed(lambda: tuned_alpha(A64, qt))
+            (x, info_t, _), tt = _timed(lambda: rka.solve_ex(A64, S.B, method=0, q=qt, alpha=at,
+                                                             max_iter=2000000, tol=1e-6,
+                                                             x_ref=planted[i], check_every=10,
+                                                             raise_on_error=False))
             t_stratum += t
+            t_tuned += tt
             plain.append({"m": S.A.shape[0], "n": S.A.shape[1], "ms": t,
                           "iterations": info.iterations, "status": info.status,
+                          "tuned_q": qt, "tuned_alpha": at, "tuned_ms": tt,
+                          "tuned_alpha_ms": t_alpha, "tuned_iterations": info_t.iterations,
+                          "tuned_status": info_t.status,
                           "stratum": "hardest 5%" if size == len(hard) else "rest"})
             del A64
         t_plain += t_stratum
         extrap += t_stratum / len(members) * size
+        extrap_tuned += t_tuned / len(members) * size
     A64 = Ash.to(torch.float64)
-    t_sh = 0.0
+    t_sh = t_sh_tuned = 0.0
+    a_sh = tuned_alpha(A64, 64)
     for r in range(4):
         (x, info, _), t = _timed(lambda: rka.solve_ex(A64, Bsh[r].contiguous(), method=0, q=16,
                                                       alpha=1.0, max_iter=2000000, tol=1e-6,
                                                       x_ref=Xs[r].contiguous(), check_every=10,
                                                       raise_on_error=False))
+        (x, info, _), tt = _timed(lambda: rka.solve_ex(A64, Bsh[r].contiguous(), method=0, q=64,
+                                                       alpha=a_sh, max_iter=2000000, tol=1e-6,
+                                                       x_ref=Xs[r].contiguous(), check_every=10,
+                                                       raise_on_error=False))
         t_sh += t
+        t_sh_tuned += tt
     del A64
     extrap += t_sh / 4 * R
+    extrap_tuned += t_sh_tuned / 4 * R
+    # HBM bytes of the batch: the rows each task read (once per iteration,
+    # worker and projection, shared by the task's right-hand sides) plus one
+    # FP64-residual pass over every matrix per refinement sweep
+    row_bytes = 0
+    for r, S in zip(res, systems):
+        n_ = S.A.shape[1]
+        nrhs = S.B.shape[0] if S.B.dim() > 1 else 1
+        tasks = -(-nrhs // max(1, r["rhs_per_task"]))
+        row_bytes += r["iterations"] * r["q"] * r["block_size"] * (4 * n_ + 20) * tasks
+    resid_bytes = 3 * total_bytes
     return {
         "systems": count, "shared_matrix": f"{Msh}x{Nsh} with {R} right-hand sides",
         "matrix_bytes": total_bytes, "tune_ms": tune_ms, "tune_trials": trials,
@@ -364,7 +615,18 @@ def bench_batching(rka, workloads, count, n_sample, seed):
         "plain_fp64_rka_sample": plain, "plain_fp64_shared_ms_per_rhs": t_sh / 4,
         "plain_fp64_extrapolated_ms": extrap,
         "speedup_vs_plain_fp64": extrap / ms,
-        "note": ("plain FP64 RKA (q=16, alpha=1) measured one solve at a time on a sample "
+        "plain_fp64_tuned_extrapolated_ms": extrap_tuned,
+        "speedup_vs_tuned_plain_fp64": extrap_tuned / ms,
+        "hbm_bytes_upper_bound": row_bytes + resid_bytes,
+        "hbm_gbps": (row_bytes + resid_bytes) / (ms / 1e3) / 1e9,
+        "hbm_frac_of_peak": (row_bytes + resid_bytes) / (ms / 1e3) / 1e9 / PEAK_HBM_GBPS,
+        "hbm_note": ("rows read per task iteration (iterations summed over the refinement "
+                     "sweeps; an upper bound, since stopped tasks read no rows) plus one FP32 "
+                     "pass per matrix per sweep for the FP64 residual, over the graph time "
+                     "including set-up"),
+        "note": ("plain FP64 RKA measured one solve at a time -- q=16, alpha=1, and tuned: "
+                 "q=64 (at most m/4) with alpha* from the device Lanczos (its time excluded) -- "
+                 "on a sample "
                  f"stratified by the batch's work to convergence ({k_hard} of the hardest "
                  f"{len(hard)} systems, {k_rest} of the other {len(rest)}) and on 4 of the "
                  "shared right-hand sides; each stratum's mean scaled by its size"),
@@ -522,53 +784,6 @@ def bench_coherent(rka, workloads):
     return out
 
 
-# The paper's Table 2 (80000 x 10000 consistent set, ||x - x*||^2 < 1e-8; EPYC 9554P, seconds):
-# context for the form below, not a target (other hardware, other draws of the data).
-PAPER_TABLE2_S = {"q": [2, 4, 8, 16, 64],
-                  "rkab_alpha1_bs_n": [47, 46, 46, 47, 81],
-                  "rka_alpha1": [157, 235, 322, 389, 883],
-                  "rka_alpha_star": [89, 66, 46, 31, 45],
-                  "computing_alpha_star": [2500, 2514, 2513, 2506, 2503],
-                  "rk_sequential": 50}
-
-
-def bench_paper_table2(rka, workloads):
-    """The runs of the paper's Table 2 on one MI355X: 80000 x 10000 from the
-    Sec. 3.1 recipe (each row its own mean and spread), stop at
-    ||x - x*||^2 < 1e-8 (Sec. 3.1), RK, RKAB with alpha = 1 and block size n,
-    RKA with alpha = 1 and alpha* of Eq. (6) for q in {2, 4, 8, 16, 64}, and
-    the time to compute alpha* (device Lanczos)."""
-    import torch
-    dev = torch.device("cuda:0")
-    m, n = 80000, 10000
-    A, xs, b = workloads.paper_rows_system(m, n, seed=workloads.DATA_SEED + 13, rng="torch",
-                                           device=dev)
-    tol = 1e-4 / float(torch.linalg.norm(xs))  # ||x - x*|| < 1e-4 as a relative error
-    (lo, hi, F), astar_ms = _timed(lambda: rka.spectral_bounds(A, steps=160, seed=7))
-    out = {"shape": f"{m}x{n}", "stop": "||x - x*||^2 < 1e-8", "alpha_star_ms": astar_ms,
-           "s_min": lo / F, "s_max": hi / F, "paper_cpu_seconds": PAPER_TABLE2_S, "rows": []}
-
-    def run(**kw):
-        (x, info, st), ms = _timed(lambda: rka.solve_ex(A, b, tol=tol, x_ref=xs, seed=3,
-                                                        raise_on_error=False, **kw))
-        return {"ms": ms, "iterations": info.iterations, "projections": info.projections,
-                "status": info.status, "kernel": st["kernel"]}
-
-    out["rk"] = run(method=0, q=1, max_iter=3000000, check_every=50)
-    for q in PAPER_TABLE2_S["q"]:
-        a = rka.alpha_star(lo / F, hi / F, q)
-        row = {"q": q, "alpha_star": a,
-               "rkab_alpha1_bs_n": run(method=1, q=q, block_size=n, alpha=1.0, max_iter=400,
-                                       check_every=1),
-               "rka_alpha1": run(method=0, q=q, alpha=1.0, max_iter=3000000, check_every=50),
-               "rka_alpha_star": run(method=0, q=q, alpha=a, max_iter=3000000, check_every=10)}
-        out["rows"].append(row)
-        log(f"[bench] table 2 q={q} done")
-    del A, b, xs
-    torch.cuda.empty_cache()
-    return out
-
-
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -631,16 +846,21 @@ def main():
     del G, L, r
     torch.cuda.empty_cache()
 
+    log("[bench] copy ceiling")
+    ceiling = copy_ceiling()
     cells = make_cells(args.cells, astar)
     esz = 8
     bytes_per_proj = n * esz + 8 + 8 + 4  # row + b_i + ||a_i||^2 + index
     out = torch.empty(n, dtype=torch.float64, device=dev)
+    # the sampling distribution of Eq. (4), once per matrix: every cell's
+    # solve reuses its row norms and running sum
+    plan, plan_ms = _timed(lambda: rka.Plan(A))
 
     def run_cell(c, seed):
         meth, q, bs, alpha, _ = c
         K = max(1, args.rows_per_cell // (q * bs))
-        x, info, st = rka.solve_ex(A, b, method=0 if meth == "rka" else 1, q=q, block_size=bs,
-                                   alpha=alpha, max_iter=K, seed=seed, timing=True, out=out)
+        x, info, st = plan.solve(b, method=0 if meth == "rka" else 1, q=q, block_size=bs,
+                                 alpha=alpha, max_iter=K, seed=seed, timing=True, out=out)
         return x, info, st
 
     log(f"[bench] warmup {args.warmup} step(s) of {len(cells)} cells")
@@ -650,14 +870,16 @@ def main():
     torch.cuda.synchronize()
 
     log(f"[bench] timing {args.steps} step(s)")
-    per_cell = {i: {"proj": 0, "wall": 0.0, "iter_ms": 0.0, "launches": 0, "setup_ms": 0.0,
-                    "sample_ms": 0.0} for i in range(len(cells))}
+    per_cell = {i: {"proj": 0, "wall": 0.0, "iter_ms": 0.0, "coef_ms": 0.0, "launches": 0,
+                    "setup_ms": 0.0, "sample_ms": 0.0} for i in range(len(cells))}
     kern = {}
     errs = {}
     total_proj = 0
+    step_s = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for s in range(args.steps):
+        t_step = time.perf_counter()
         for i, c in enumerate(cells):
             t0 = time.perf_counter()
             x, info, st = run_cell(c, args.seed + s)
@@ -666,6 +888,7 @@ def main():
             pc["proj"] += info.projections
             pc["wall"] += dt
             pc["iter_ms"] += st["iterate_ms"]
+            pc["coef_ms"] += st["coef_ms"]
             pc["launches"] += st["iterate_launches"]
             pc["setup_ms"] += st["norms_ms"] + st["prefix_ms"]
             pc["sample_ms"] += st["sample_ms"]
@@ -676,24 +899,37 @@ def main():
             kk["ms"] += st["iterate_ms"]
             kk["launches"] += st["iterate_launches"]
             kk["bytes"] += info.projections * bytes_per_proj
+            if st["kernel"] == 4 and st["coef_ms"] > 0:
+                # the coefficient pass streams every row of the chunk once
+                kc = kern.setdefault("blk_coef_kernel<double>", {"ms": 0.0, "launches": 0,
+                                                                 "bytes": 0.0})
+                kc["ms"] += st["coef_ms"]
+                kc["launches"] += st["iterate_launches"]
+                kc["bytes"] += info.projections * n * esz
             if s == args.steps - 1:
                 errs[i] = float((x - x_ls).norm() / x_ls.norm())
+        torch.cuda.synchronize()
+        step_s.append(time.perf_counter() - t_step)
         log(f"[bench] step {s + 1}/{args.steps} done")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
 
-    value = total_proj / wall
+    # every step moves the same projections: the headline is the median step
+    proj_per_step = total_proj / args.steps
+    med_step = sorted(step_s)[len(step_s) // 2]
+    value = proj_per_step / med_step
     cells_out = []
     for i, c in enumerate(cells):
         pc = per_cell[i]
         meth, q, bs, alpha, alab = c
-        it_s = pc["iter_ms"] / 1e3
+        it_s = (pc["iter_ms"] + pc["coef_ms"]) / 1e3
         cells_out.append({
             "method": meth, "q": q, "block_size": bs, "alpha": round(alpha, 4), "alpha_kind": alab,
             "projections_per_s": pc["proj"] / pc["wall"],
             "kernel_projections_per_s": pc["proj"] / it_s if it_s > 0 else None,
             "kernel_hbm_gbps": pc["proj"] * bytes_per_proj / it_s / 1e9 if it_s > 0 else None,
             "iterate_ms_per_solve": pc["iter_ms"] / args.steps,
+            "coef_ms_per_solve": pc["coef_ms"] / args.steps,
             "setup_ms_per_solve": pc["setup_ms"] / args.steps,
             "sample_ms_per_solve": pc["sample_ms"] / args.steps,
             "kernel": kernel_name(pc["stats"], rkab=meth == "rkab"), "grid": pc["stats"]["grid"],
@@ -707,19 +943,33 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": pmc_traffic(dom_name),
             "kernel": dom_name, "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch":
-            bytes_per_launch, "bytes_per_projection": bytes_per_proj}
+            bytes_per_launch, "bytes_per_projection": bytes_per_proj,
+            "copy_ceiling_gbps": round(ceiling["gbps"], 1),
+            "frac_of_copy_ceiling": round(achieved / ceiling["gbps"], 4)}
+
+    # time to the error plateau of every cell (two passes, Sec. 3.1)
+    plateau = []
+    if not args.no_plateau:
+        s_ext = (s_min, s_max)
+        for c in cells:
+            meth, q, bs, alpha, alab = c
+            log(f"[bench] time to plateau {meth} q={q} bs={bs} alpha={alab}")
+            rate = _rate(s_ext, alpha if meth == "rka" else 1.0, q)
+            r = time_to_plateau(plan, b, x_ls, c, rate, seed=args.seed + 77)
+            r.update({"method": meth, "q": q, "block_size": bs, "alpha_kind": alab})
+            plateau.append(r)
 
     forms = {}
     if not args.no_forms:
         wanted = set(args.forms.split(","))
         for name, fn in (("precision", lambda: bench_precision(rka, A, xs, b, x_ls,
                                                                 (s_min, s_max))),
+                         ("precision_200000x20000", lambda: bench_precision_large(rka)),
                          ("batching", lambda: bench_batching(rka, workloads, args.batch_systems,
                                                              args.batch_sample, args.seed)),
                          ("differentiation", lambda: bench_differentiation(rka)),
                          ("distributed_approach", lambda: bench_distributed(rka, workloads)),
-                         ("coherent_rows", lambda: bench_coherent(rka, workloads)),
-                         ("paper_table2", lambda: bench_paper_table2(rka, workloads))):
+                         ("coherent_rows", lambda: bench_coherent(rka, workloads))):
             if name not in wanted:
                 continue
             log(f"[bench] form: {name}")
@@ -737,10 +987,14 @@ def main():
         bh = b.cpu().numpy()
         cpu = cpu_baseline(Ah, bh, args.cpu_seconds)
         del Ah
+        log("[bench] CPU oracle on the smaller configurations")
+        cpu["other_configurations"] = cpu_baseline_cells(workloads)
 
     line = {
         "metric": METRIC, "value": value, "unit": "row projections/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": med_step * 1e3,
+        "mean_ms_per_step": wall / args.steps * 1e3, "value_mean": total_proj / wall,
+        "step_ms": [round(t * 1e3, 2) for t in step_s],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"RKA/RKAB grid on a {m}x{n} FP64 N(0,1) system, "
@@ -749,6 +1003,9 @@ def main():
                    "cells": len(cells), "parallelism": "single GPU"},
         "hbm_gbps": value * bytes_per_proj / 1e9,
         "roofline": roof,
+        "copy_ceiling": ceiling,
+        "plan_setup_ms": plan_ms,
+        "time_to_plateau": plateau,
         "cpu_baseline": cpu,
         "alpha_star": {str(q): astar[q] for q in astar}, "s_min": s_min, "s_max": s_max,
         "alpha_star_device_ms": astar_ms,

@@ -33,7 +33,8 @@
  *     unit of the device, or the grid option) fixes the order in which
  *     partial sums meet, and the kernels that run several RKA iterations per
  *     exchange end a block wherever a stopping test falls (every
- *     check_every iterations), so check_every moves block ends.  Results of
+ *     check_every iterations) or a chunk of iterations ends, so check_every
+ *     and the block length move block ends.  Results of
  *     different launches agree to rounding (for FP64 arithmetic within
  *     1e-12 relative of the plain iteration in every case tested).
  *   - Return value: an rka_status.  Arguments are validated before any

@@ -185,6 +185,8 @@ int validate(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const 
 
 // Row records per chunk: at most 4 Mi entries (128 MiB).
 constexpr int64_t kRecBudget = 4ll << 20;
+// Kernel 4's coefficients per chunk: at most 512 MiB.
+constexpr int64_t kCoefBudget = 512ll << 20;
 // Largest q for which the library runs several RKA iterations per exchange
 // by itself (steps_per_exchange = 0): measured at 80000 x 10000 FP64, blocks
 // of 64 / q iterations take 4.5 us per iteration at q = 16 (one-iteration
@@ -295,7 +297,10 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
     }
     if (multi) {
       if (want_blk) use_blk = rka::rka_blk_plan(sh, sstep >= 1 ? sstep : 0, &kgeo);
-      if (!use_blk && rblk != 2) use_sstep = rka::rka_sstep_plan(sh, sstep >= 2 ? sstep : 0, &sgeo);
+      // kernel 3 where kernel 4 does not fit (left to the library: only
+      // where kernel 3 beats the column kernel, q <= kAutoSstepMaxQ)
+      if (!use_blk && rblk != 2 && (sstep >= 2 || q <= kAutoSstepMaxQ))
+        use_sstep = rka::rka_sstep_plan(sh, sstep >= 2 ? sstep : 0, &sgeo);
     }
   }
   bool use_col = !block && !use_sstep && !use_blk && rka::rka_col_plan(sh, &cgeo);
@@ -341,6 +346,18 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   if (use_blk) {
     nslots = (size_t)kgeo.G * kgeo.nv;
     nsslots = (size_t)kgeo.nv;
+    // chunks short enough that their coefficients take at most kCoefBudget
+    // bytes (a chunk boundary costs two launches; a block's M is up to 57 KB)
+    // (coef_blocks(kc) <= kCoefBudget / per_blk; p = 1 has no coefficients)
+    if (kgeo.cstride > 0) {
+      const int64_t per_blk = (int64_t)kgeo.cstride * 8;
+      const double room = (double)(kCoefBudget / per_blk - 3);
+      const double per_it =
+          1.0 / kgeo.p + (in_kernel_check > 0 ? 1.0 / (double)in_kernel_check : 0.0);
+      int64_t kcap = (int64_t)(room / per_it);
+      if (kcap < kgeo.p) kcap = kgeo.p;
+      if (kc_max > kcap) kc_max = kcap;
+    }
   } else if (use_sstep) {
     nslots = (size_t)sgeo.G * sgeo.nv;
     nsslots = (size_t)sgeo.nv;

@@ -568,6 +568,29 @@ __global__ __launch_bounds__(kBThreads) void rka_blk_kernel(BlkArgs p) {
       if (ok && u == 0 && team < cnt) red.put16(v0 + team, sum, tag);
     }
     BPROF(2);
+    // The next block's rows and records, issued while the other workgroups'
+    // phase-1 sums arrive: the issue stalls on the CU's outstanding-load
+    // limit wherever it sits, and here the stall overlaps a wait (measured
+    // 2.08 against 2.15 us per iteration at q = 16 with the issue after the
+    // exchange).  Their addresses use the row indices loaded one block
+    // earlier.
+    int kn = kl, Ln = L;
+    bool checkn = false;
+    if (b + 1 < nblk) p.lay.locate(b + 1, &kn, &Ln, &checkn);
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) an[i] = load_raw<T, V>(A + (int64_t)rows_n[i] * p.lda + cvl * V);
+    if (b + 1 < nblk && t < Ln * q) {
+      const RowRec r = p.rec[(int64_t)kn * q + t];
+      mb = r.b;
+      mw = r.wn;
+      ma = r.alpha;
+    }
+    if (b + 2 < nblk) {
+      int kn2, Ln2;
+      bool t2;
+      p.lay.locate(b + 2, &kn2, &Ln2, &t2);
+      load_rows(kn2, Ln2, rows_n);
+    }
     // phase 2: every workgroup reads all nv sums
     if (__syncthreads_and(ok))
       ok = blk_gather(red, p.nv_max, nv, tag, [&](int Lx) { return Lx; }, HV, t, NT);
@@ -592,28 +615,9 @@ __global__ __launch_bounds__(kBThreads) void rka_blk_kernel(BlkArgs p) {
         break;
       }
     }
-    // This wave's loads of M have landed in LDS (nothing else of its memory
-    // traffic is outstanding after the polls, so the wait is free).  Then the
-    // next block's rows and records, in flight across the rest of this block:
-    // their addresses use the row indices loaded one block earlier.
+    // This wave's loads of M landed before its phase-1 poll loads returned
+    // (loads return in order); the wait makes that explicit at no cost.
     __builtin_amdgcn_s_waitcnt(0);
-    int kn = kl, Ln = L;
-    bool checkn = false;
-    if (b + 1 < nblk) p.lay.locate(b + 1, &kn, &Ln, &checkn);
-#pragma unroll
-    for (int i = 0; i < RPT; ++i) an[i] = load_raw<T, V>(A + (int64_t)rows_n[i] * p.lda + cvl * V);
-    if (b + 1 < nblk && t < Ln * q) {
-      const RowRec r = p.rec[(int64_t)kn * q + t];
-      mb = r.b;
-      mw = r.wn;
-      ma = r.alpha;
-    }
-    if (b + 2 < nblk) {
-      int kn2, Ln2;
-      bool t2;
-      p.lay.locate(b + 2, &kn2, &Ln2, &t2);
-      load_rows(kn2, Ln2, rows_n);
-    }
     // (4) c_r = alpha_r (b_r - <a_r, x^(k)>) / w_r, then s = M c: row r of
     // iteration jr adds M_{r,c} c_c over the jr q rows c of earlier
     // iterations (contiguous in M's row packing); a team of trm lanes per
@@ -626,16 +630,21 @@ __global__ __launch_bounds__(kBThreads) void rka_blk_kernel(BlkArgs p) {
       const int jr = r < R ? r / q : 0, rho = r - jr * q;
       const double* mr = MC + blk_rowoff(q, jr, rho);
       const int nterm = jr * q;
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      double a4[4] = {0.0, 0.0, 0.0, 0.0};
       int c = u;
-      for (; c + 3 * TR < nterm; c += 4 * TR) {
-        a0 = fma(mr[c], CC[c], a0);
-        a1 = fma(mr[c + TR], CC[c + TR], a1);
-        a2 = fma(mr[c + 2 * TR], CC[c + 2 * TR], a2);
-        a3 = fma(mr[c + 3 * TR], CC[c + 3 * TR], a3);
+      // eight terms' loads in flight before the first multiply-add
+      for (; c + 7 * TR < nterm; c += 8 * TR) {
+        double mv[8], cv[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          mv[i] = mr[c + i * TR];
+          cv[i] = CC[c + i * TR];
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) a4[i & 3] = fma(mv[i], cv[i], a4[i & 3]);
       }
-      for (; c < nterm; c += TR) a0 = fma(mr[c], CC[c], a0);
-      double acc = (a0 + a1) + (a2 + a3);
+      for (; c < nterm; c += TR) a4[0] = fma(mr[c], CC[c], a4[0]);
+      double acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
       acc = team_sum(acc, TR);
       if (r < R) sr = CC[r] + acc;
     }
@@ -717,7 +726,7 @@ static size_t blk_lds_bytes(int q, int p, int nsvp, int V, int NT, int G) {
 }
 
 constexpr size_t kBMaxLds = 150 * 1024;
-constexpr int kBMaxRPT = 16;
+constexpr int kBMaxRPT = 11;  // 16 rows per thread (two register tiles of them) spill
 
 bool rka_blk_plan(const SolveShape& sh, int p_req, RkaBlkGeom* geo) {
   const int esz = sh.dtype == 0 ? 8 : (sh.dtype == 1 ? 4 : 2);
@@ -726,9 +735,10 @@ bool rka_blk_plan(const SolveShape& sh, int p_req, RkaBlkGeom* geo) {
   const int64_t nvec = sh.vec_ok ? sh.n / V : sh.n;
   const int q = sh.q;
   // rows per block: at most 128 (256 with one iteration per block, which
-  // needs no coefficients); default blocks of 64 rows (128 for q > 32)
+  // needs no coefficients); by default as many as fit (at 80000 x 10000
+  // FP64, q = 16: 2.1 us per iteration with 128 rows, 3.3 us with 64)
   const int rmax = kBMaxRows;
-  int p = p_req > 0 ? p_req : std::max(1, (q <= 32 ? 64 : rmax) / q);
+  int p = p_req > 0 ? p_req : std::max(1, rmax / q);
   if (p > 1 && p > rmax / q) p = rmax / q;
   if (p < 1 || (p == 1 && q > 2 * rmax)) return false;
   const int target = sh.grid > 0 ? sh.grid : sh.num_cu;
@@ -751,9 +761,11 @@ bool rka_blk_plan(const SolveShape& sh, int p_req, RkaBlkGeom* geo) {
     break;
   }
   if (p < 1) return false;
+  // left to the library, one iteration per block is the column kernel's job
+  if (p_req == 0 && p == 1) return false;
   const int R = q * p;
   int rpt = (R + rg - 1) / rg;
-  const int buckets[] = {1, 2, 3, 4, 6, 8, 11, 16};
+  const int buckets[] = {1, 2, 3, 4, 6, 8, 11};
   for (int bk : buckets)
     if (rpt <= bk) {
       rpt = bk;
@@ -852,8 +864,7 @@ static hipError_t launch_blk_rpt(const RkaBlkGeom& geo, BlkArgs& a, hipStream_t 
     case 4: return launch_blk_t<T, V, 4>(geo, a, s);
     case 6: return launch_blk_t<T, V, 6>(geo, a, s);
     case 8: return launch_blk_t<T, V, 8>(geo, a, s);
-    case 11: return launch_blk_t<T, V, 11>(geo, a, s);
-    default: return launch_blk_t<T, V, 16>(geo, a, s);
+    default: return launch_blk_t<T, V, 11>(geo, a, s);
   }
 }
 

@@ -428,7 +428,9 @@ bool rka_col_plan(const SolveShape& sh, RkaColGeom* geo) {
   const int64_t bytes_per_iter = (int64_t)sh.q * sh.n * esz;
   if (sh.grid > 0) return col_plan_at(sh, sh.grid, geo);
   if (bytes_per_iter <= kOneGroupBytes) return col_plan_at(sh, 1, geo);
-  if (sh.q <= kSmallQ) return col_plan_at(sh, std::min(sh.num_cu, kSmallQGrid), geo);
+  // small q: a few dozen workgroups, unless slices that wide do not fit a
+  // workgroup (very long rows), then the wider grids below
+  if (sh.q <= kSmallQ && col_plan_at(sh, std::min(sh.num_cu, kSmallQGrid), geo)) return true;
   if (sh.dtype == 0 && col_plan_at(sh, sh.num_cu * kWideGridNum / kWideGridDen, geo)) return true;
   return col_plan_at(sh, sh.num_cu, geo);
 }

@@ -37,7 +37,7 @@ def _odt(dtype):
 
 CASES = [
     # m, n, dtype, q, p (0: the library's), K, grid
-    (3000, 2000, "f64", 16, 0, 40, 0),      # 4 iterations per block, default grid
+    (3000, 2000, "f64", 16, 0, 40, 0),      # 8 iterations per block (the default), default grid
     (3000, 2000, "f64", 16, 8, 41, 0),      # 128 rows per block, ragged last block
     (3000, 2000, "f64", 8, 0, 37, 0),
     (3000, 2000, "f64", 4, 16, 50, 0),
@@ -171,3 +171,17 @@ def test_library_chooses_blocks_with_precomputed_coefficients():
     assert st["kernel"] == 1
     _, _, st = rka.solve_ex(Ad, bd, method=0, q=128, max_iter=8, seed=4)
     assert st["kernel"] == 1
+
+
+def test_blk_across_chunks():
+    """45000 iterations at q = 32 (p = 4): more than one chunk's coefficients
+    (the library bounds them to 512 MiB, 43676 iterations here), so the solve
+    launches the coefficient pass and the iterations twice; x within 1e-12
+    of the oracle."""
+    say("blk two chunks")
+    A, _, b = _system(3000, 1024, seed=12)
+    x, info, st = rka.solve_ex(to_dev(A), vec(b), method=0, q=32, alpha=1.0, max_iter=45000,
+                               seed=8, rka_block=2)
+    assert info.status == rka.OK and st["kernel"] == 4 and st["iterate_launches"] == 2, st
+    xo, _ = oracle.rka(A, b, q=32, alpha=1.0, max_iter=45000, seed=8)
+    assert_x_close(host(x), xo, what="blk two chunks")

@@ -206,6 +206,19 @@ def test_rka_two_phase_exchange_with_more_workgroups_than_threads():
     assert_x_close(host(x), xo, what="rka G > NT")
 
 
+def test_rka_small_q_on_rows_too_long_for_the_small_grid():
+    """120000 FP64 columns at q = 8: slices of 120000 / 48 columns do not fit a
+    workgroup, so the one-iteration kernel takes a wider grid (no fallback to
+    the worker kernel, whose iterate would not fit)."""
+    say("rka long rows q=8")
+    A, _, b = _system(600, 120000, seed=19)
+    x, info, st = rka.solve_ex(to_dev(A), vec(b), method=0, q=8, max_iter=6, seed=5,
+                               steps_per_exchange=1)
+    assert info.status == rka.OK and st["kernel"] == 1 and st["grid"] > 48, st
+    xo, _ = oracle.rka(A, b, q=8, max_iter=6, seed=5)
+    assert_x_close(host(x), xo, what="rka long rows")
+
+
 def test_rka_wide_q_falls_back_to_worker_kernel():
     # q rows per slice beyond the column kernel's tile: same iteration, other kernel
     say("rka q=2000")
@@ -300,10 +313,12 @@ def test_deterministic_and_resumable(block):
         return host(rka.rkab_solve(Ad, bd, q=16, block_size=block, max_iter=K, seed=4, x0=x0,
                                    iter_offset=off)[0])
 
-    full = run(30)
-    assert np.array_equal(full, run(30))
-    half = run(12)
-    rest = run(18, x0=vec(half), off=12)
+    # bitwise across a split that falls on a block boundary (RKA at q = 16
+    # runs blocks of 8 iterations per exchange by default)
+    full = run(32)
+    assert np.array_equal(full, run(32))
+    half = run(16)
+    rest = run(16, x0=vec(half), off=16)
     assert np.array_equal(full, rest)
 
 
