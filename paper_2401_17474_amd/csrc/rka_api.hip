@@ -372,7 +372,8 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
     // the fixed buffers first, then as many iterations of row records per
     // chunk as the rest holds (at most the stream-ordered path's chunk)
     auto R = [](size_t b) { return Scratch::round(b > 0 ? b : 16); };
-    size_t fixed = R(sizeof(rka::DevStatus)) + R(part_len * 8) + R(8);
+    size_t fixed = R(sizeof(rka::DevStatus)) + R(part_len * 8) +
+                   R(rka::kGridBarCounters * sizeof(unsigned));
     if (own_norms) fixed += R((size_t)m * 8);
     if (own_prefix) fixed += R((size_t)m * 8) + R(n_last * 8);
     if (nslots) fixed += R(32 * nslots) + R(32 * nsslots);
@@ -408,7 +409,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   }
   HIP_TRY(sc.get(&rec, (size_t)(kc_max * per_iter)));
   HIP_TRY(sc.get(&part, part_len));
-  HIP_TRY(sc.get(&bar, 2));
+  HIP_TRY(sc.get(&bar, rka::kGridBarCounters));
   if (nslots) {
     HIP_TRY(sc.get(&slots, 2 * nslots));
     HIP_TRY(sc.get(&sslots, 2 * nsslots));

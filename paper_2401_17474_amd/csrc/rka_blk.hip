@@ -122,10 +122,13 @@ constexpr int kBMaxRows = 128;   // q p
 constexpr int kBThreads = 512;   // iteration kernel
 constexpr int kBPoll = 2;        // slots one lane polls in either phase
 constexpr int kBBatch = 4;       // poll loads in flight per lane
-constexpr int kCThreads = 256;   // coefficient kernel (4 waves)
+constexpr int kCThreads = 512;   // coefficient kernel: 8 waves, two per SIMD (an FP64 MFMA
+                                 // issues every ~60 ns from one wave per SIMD; two waves
+                                 // per SIMD reach the unit's ~48 TF/s)
+constexpr int kCWaves = kCThreads / 64;
 constexpr int kCElems = 4096;    // elements of a staged chunk (rows x columns)
 constexpr int kCPre = kCElems / kCThreads;  // staged elements per lane
-constexpr int kCMaxSlots = 9;    // 16 x 16 Gram tiles per wave (36 = 8 * 9 / 2 over 4 waves)
+constexpr int kCMaxSlots = 5;    // 16 x 16 Gram tiles per wave (36 = 8 * 9 / 2 over 8 waves)
 
 // ===========================================================================
 // The coefficient pass: M of every block of a chunk.
@@ -142,6 +145,7 @@ struct CoefArgs {
   double* coef;       // nblk x cstride
   int32_t ncoef;      // coefficients of a full block
   int32_t cstride;    // doubles between blocks in coef (a multiple of 128)
+  int32_t cbuf;       // LDS-direct staging: bytes per chunk buffer
 };
 
 template <typename T>
@@ -164,7 +168,7 @@ __host__ __device__ __forceinline__ int blk_rowoff(int q, int jr, int rho) {
 //
 // Tiles: the lower 16 x 16 tiles (I, J), J <= I, that hold a pair of rows
 // from different iterations, in the order I = 0, 1, ...; J = 0 .. I; wave W
-// takes every fourth from the W-th into its NS slots (slots past its share
+// takes every eighth from the W-th into its NS slots (slots past its share
 // repeat tile (0, 0); their sums are never used).  Per 4 columns a lane loads
 // both fragments of every slot (lane l: column c + l / 16, row 16 I + l % 16),
 // the next 4 columns' while the current ones feed v_mfma_f64_16x16x4f64.
@@ -174,6 +178,56 @@ __host__ __device__ __forceinline__ int blk_rowoff(int q, int jr, int rho) {
 // Element e: row e >> lcw, column e & (CW - 1) -- consecutive lanes read
 // consecutive columns of a row.  Loads are unconditional (clamped rows and
 // columns); elements past the block's rows or past n are zero.
+// This wave's tiles (see above): slot u holds tile (tI[u], tJ[u]); returns
+// the number of slots used.
+template <int NS>
+__device__ __forceinline__ int coef_tiles(int R, int RG, int q, int wv, int (&tI)[NS],
+                                          int (&tJ)[NS]) {
+  int nt = 0;
+#pragma unroll
+  for (int u = 0; u < NS; ++u) tI[u] = tJ[u] = 0;
+  int idx = 0;
+  for (int I = 0; I < RG; ++I)
+    for (int J = 0; J <= I; ++J) {
+      const int rlast = (16 * I + 15 < R ? 16 * I + 15 : R - 1);
+      if (rlast / q > (16 * J) / q) {  // some row of I is of a later iteration
+        if (idx % kCWaves == wv && nt < NS) {
+#pragma unroll
+          for (int u = 0; u < NS; ++u)
+            if (u == nt) {
+              tI[u] = I;
+              tJ[u] = J;
+            }
+          ++nt;
+        }
+        ++idx;
+      }
+    }
+  return nt;
+}
+
+// N = alpha_r / (q w_r) <a_r, a_c> for rows r, c of iterations j > l, from
+// this wave's tiles, into NB (q x q blocks by pair).
+template <int NS>
+__device__ __forceinline__ void coef_store_n(const f64x4 (&acc)[NS], const int (&tI)[NS],
+                                             const int (&tJ)[NS], int nt, int lane, int R, int q,
+                                             const double* FAC, double* NB) {
+#pragma unroll
+  for (int u = 0; u < NS; ++u) {
+    if (u < nt) {
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int r = 16 * tI[u] + lane / 16 + 4 * rr, c = 16 * tJ[u] + (lane & 15);
+        if (r < R && c < R) {
+          const int jr = r / q, lc = c / q;
+          if (jr > lc)
+            NB[blk_pair(jr, lc) * q * q + (r - jr * q) * q + (c - lc * q)] = FAC[r] * acc[u][rr];
+        }
+      }
+    }
+  }
+}
+
 template <typename T, int NS>
 __device__ __forceinline__ void coef_gram(const CoefArgs& p, const T* __restrict__ A, double* S,
                                           double* NB, const double* FAC, const int64_t* ROW, int R,
@@ -181,28 +235,7 @@ __device__ __forceinline__ void coef_gram(const CoefArgs& p, const T* __restrict
   const int t = threadIdx.x, q = p.q, lane = t & (kWave - 1), wv = t / kWave;
   const int CW = 1 << p.lcw, RP = 16 * RG;
   int tI[NS], tJ[NS];
-  int nt = 0;
-#pragma unroll
-  for (int u = 0; u < NS; ++u) tI[u] = tJ[u] = 0;
-  {
-    int idx = 0;
-    for (int I = 0; I < RG; ++I)
-      for (int J = 0; J <= I; ++J) {
-        const int rlast = (16 * I + 15 < R ? 16 * I + 15 : R - 1);
-        if (rlast / q > (16 * J) / q) {  // some row of I is of a later iteration
-          if (idx % 4 == wv && nt < NS) {
-#pragma unroll
-            for (int u = 0; u < NS; ++u)
-              if (u == nt) {
-                tI[u] = I;
-                tJ[u] = J;
-              }
-            ++nt;
-          }
-          ++idx;
-        }
-      }
-  }
+  const int nt = coef_tiles<NS>(R, RG, q, wv, tI, tJ);
   f64x4 acc[NS];
 #pragma unroll
   for (int u = 0; u < NS; ++u) acc[u] = (f64x4){0.0, 0.0, 0.0, 0.0};
@@ -257,21 +290,121 @@ __device__ __forceinline__ void coef_gram(const CoefArgs& p, const T* __restrict
     }
   }
   __syncthreads();  // every wave is done with S: NB takes its place
-  // N = alpha_r / (q w_r) <a_r, a_c> for rows r, c of iterations j > l
+  coef_store_n<NS>(acc, tI, tJ, nt, lane, R, q, FAC, NB);
+}
+
+// The same on the 16-byte vector path, staged by LDS-direct loads
+// (global_load_lds: lane l of a wave writes its 16 bytes at the
+// instruction's LDS base + 16 l): one instruction carries rows 2k (lanes
+// 0..31) and 2k + 1 (lanes 32..63) of a 512-byte column segment, CW = 512 /
+// sizeof(T) columns; a row pair takes kCPairBytes of LDS (32 bytes of
+// padding, so that the 16 rows of a fragment read fall on 8 bank pairs).
+// Two buffers of cbuf bytes: the next chunk's 64 KB are in flight during the
+// current chunk's MFMAs, with no registers spent on them.  Rows past the
+// block load a clamped row (they only reach products that are never
+// stored); columns past n are zeroed in LDS after the last chunk lands.
+constexpr int kCPairBytes = 1024 + 32;
+template <typename T, int NS>
+__device__ __forceinline__ void coef_gram_dma(const CoefArgs& p, const T* __restrict__ A,
+                                              char* SB, double* NB, const double* FAC,
+                                              const int64_t* ROW, int R, int RG) {
+  constexpr int EPL = 16 / (int)sizeof(T);  // elements per lane per load
+  constexpr int CW = 32 * EPL;              // columns per chunk
+  const int t = threadIdx.x, q = p.q, lane = t & (kWave - 1), wv = t / kWave;
+  const int npairs = 8 * RG;                // row pairs staged (16 RG rows)
+  int tI[NS], tJ[NS];
+  const int nt = coef_tiles<NS>(R, RG, q, wv, tI, tJ);
+  f64x4 acc[NS];
+#pragma unroll
+  for (int u = 0; u < NS; ++u) acc[u] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  // this lane's rows: pair wv + 4 i, row 2 (wv + 4 i) + lane / 32
+  constexpr int kMaxPI = kBMaxRows / 2 / kCWaves;  // row pairs per wave
+  const T* rowp[kMaxPI];
+#pragma unroll
+  for (int i = 0; i < kMaxPI; ++i) {
+    const int r = 2 * (wv + kCWaves * i) + (lane >> 5);
+    rowp[i] = A + ROW[r < R ? r : R - 1] * p.lda + (lane & 31) * EPL;
+  }
+  const int nch = (int)((p.n + CW - 1) / CW);
+  auto issue = [&](int c, int buf) {
+    const int64_t c0 = (int64_t)c * CW;
+    // the last chunk's lanes past n read the row's last 16 bytes instead
+    const int64_t shift = c0 + (lane & 31) * EPL + EPL > p.n ? p.n - EPL - (c0 + (lane & 31) * EPL) : 0;
+    char* base = SB + (size_t)buf * p.cbuf;
+#pragma unroll
+    for (int i = 0; i < kMaxPI; ++i) {
+      const int k = wv + kCWaves * i;
+      if (k < npairs)
+        __builtin_amdgcn_global_load_lds((const void*)(rowp[i] + c0 + shift),
+                                         (__attribute__((address_space(3))) void*)(base + k * kCPairBytes),
+                                         16, 0, 0);
+    }
+  };
+  // fragment byte offsets of each slot's two rows within a buffer
+  int offI[NS], offJ[NS];
 #pragma unroll
   for (int u = 0; u < NS; ++u) {
-    if (u < nt) {
+    const int ri = 16 * tI[u] + (lane & 15), rj = 16 * tJ[u] + (lane & 15);
+    offI[u] = (ri >> 1) * kCPairBytes + (ri & 1) * 512 + 2 * (lane >> 4) * (int)sizeof(T);
+    offJ[u] = (rj >> 1) * kCPairBytes + (rj & 1) * 512 + 2 * (lane >> 4) * (int)sizeof(T);
+  }
+  // Two MFMA steps per fragment read: over 8 columns 8P .. 8P + 7, lane l
+  // reads columns 8P + 2 (l / 16) and 8P + 2 (l / 16) + 1 of each of its
+  // slots' rows with one LDS read (two elements), the first feeding step
+  // 2P and the second step 2P + 1 (each step still sums 4 distinct columns;
+  // together the 8).  Half the LDS reads, and few enough in flight for the
+  // wait counter to track them one step ahead.
+  struct Pair2 {
+    T v[2];
+  };
+  double fa[4 * NS], fb[4 * NS];
+  auto load = [&](double(&f)[4 * NS], const char* base, int c) {
+    const char* bc = base + c * (int)sizeof(T);
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr) {
-        const int r = 16 * tI[u] + lane / 16 + 4 * rr, c = 16 * tJ[u] + (lane & 15);
-        if (r < R && c < R) {
-          const int jr = r / q, lc = c / q;
-          if (jr > lc)
-            NB[blk_pair(jr, lc) * q * q + (r - jr * q) * q + (c - lc * q)] = FAC[r] * acc[u][rr];
-        }
+    for (int u = 0; u < NS; ++u) {
+      const Pair2 a = *(const Pair2*)(bc + offI[u]);
+      const Pair2 bb = *(const Pair2*)(bc + offJ[u]);
+      f[4 * u] = widen(a.v[0]);
+      f[4 * u + 1] = widen(bb.v[0]);
+      f[4 * u + 2] = widen(a.v[1]);
+      f[4 * u + 3] = widen(bb.v[1]);
+    }
+  };
+  auto step2 = [&](const double(&f)[4 * NS]) {
+#pragma unroll
+    for (int u = 0; u < NS; ++u)
+      acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[4 * u], f[4 * u + 1], acc[u], 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < NS; ++u)
+      acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[4 * u + 2], f[4 * u + 3], acc[u], 0, 0, 0);
+  };
+  issue(0, 0);
+  for (int c = 0; c < nch; ++c) {
+    // this wave's loads of chunk c have landed; after the barrier every
+    // wave's have, and every wave is done with chunk c - 1's buffer
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    const char* base = SB + (size_t)(c & 1) * p.cbuf;
+    const int64_t c0 = (int64_t)c * CW;
+    if (c0 + CW > p.n) {  // the last chunk: zero the columns past n
+      const int valid = (int)(p.n - c0);
+      for (int e = t; e < 2 * npairs * (CW - valid); e += kCThreads) {
+        const int r = e / (CW - valid), col = valid + e - r * (CW - valid);
+        *(T*)((char*)base + (r >> 1) * kCPairBytes + (r & 1) * 512 + col * (int)sizeof(T)) = T{};
       }
+      __syncthreads();
+    }
+    if (c + 1 < nch) issue(c + 1, (c + 1) & 1);
+    load(fa, base, 0);
+    for (int k = 0; k < CW; k += 16) {  // CW is a multiple of 16
+      load(fb, base, k + 8);
+      step2(fa);
+      if (k + 16 < CW) load(fa, base, k + 16);
+      step2(fb);
     }
   }
+  __syncthreads();  // every wave is done with both buffers: NB takes their place
+  coef_store_n<NS>(acc, tI, tJ, nt, lane, R, q, FAC, NB);
 }
 
 // The inner products of a block's rows are the needed lower 16 x 16 tiles of
@@ -281,17 +414,19 @@ __device__ __forceinline__ void coef_gram(const CoefArgs& p, const T* __restrict
 // register r (D[i][j] = the inner product of rows 16 I + i and 16 J + j).
 // The staged chunk and N (then M) share LDS: N is written once the last
 // chunk has been used.
-template <typename T, int NS>
+template <typename T, int NS, bool DMA>
 __global__ __launch_bounds__(kCThreads) void blk_coef_kernel(CoefArgs p) {
   const T* __restrict__ A = (const T*)p.A;
   const int t = threadIdx.x, q = p.q;
   extern __shared__ double lds[];
-  // S: the staged chunk, column-major S[c RS + r]; NB: N (then M) in q x q
-  // blocks by pair, over S once the Gram tiles are complete
+  // S: the staged chunk (column-major S[c RS + r], or the two LDS-direct
+  // buffers); NB: N (then M) in q x q blocks by pair, over S once the Gram
+  // tiles are complete
   const int CW = 1 << p.lcw;
-  double* S = lds;                                                      // CW * RS
+  double* S = lds;
   double* NB = lds;                                                     // ncoef
-  const int nS = CW * p.RS > p.ncoef ? CW * p.RS : p.ncoef;
+  const int nSt = DMA ? p.cbuf / 4 : CW * p.RS;                         // doubles
+  const int nS = nSt > p.ncoef ? nSt : p.ncoef;
   double* FAC = lds + nS;                        // kBMaxRows  alpha_r / (q w_r)
   int64_t* ROW = (int64_t*)(FAC + kBMaxRows);    // kBMaxRows
   for (int b = blockIdx.x; b < p.lay.nblk; b += gridDim.x) {
@@ -306,7 +441,10 @@ __global__ __launch_bounds__(kCThreads) void blk_coef_kernel(CoefArgs p) {
       FAC[r] = rc.alpha * p.inv_q / rc.wn;
     }
     __syncthreads();  // ROW and FAC are complete
-    coef_gram<T, NS>(p, A, S, NB, FAC, ROW, R, RG);  // the Gram tiles, then N into NB
+    if constexpr (DMA)  // the Gram tiles, then N into NB
+      coef_gram_dma<T, NS>(p, A, (char*)S, NB, FAC, ROW, R, RG);
+    else
+      coef_gram<T, NS>(p, A, S, NB, FAC, ROW, R, RG);
     __syncthreads();
     // block forward substitution, in place (N_{j,l} becomes M_{j,l}):
     //   M_{j,l} = -N_{j,l} - sum_{t=l+1}^{j-1} N_{j,t} M_{t,l}
@@ -802,19 +940,24 @@ bool rka_blk_plan(const SolveShape& sh, int p_req, RkaBlkGeom* geo) {
     geo->clcw = l;
   }
   // Gram tiles of a full block (those of a shorter block are among them),
-  // spread over the 4 waves
+  // spread over the waves
   {
     int nt = 0;
     for (int I = 0; I < RP / 16; ++I)
       for (int J = 0; J <= I; ++J)
         if (std::min(16 * I + 15, R - 1) / q > (16 * J) / q) ++nt;
-    const int per = (nt + 3) / 4;
-    geo->cslots = per <= 2 ? 2 : per <= 4 ? 4 : per <= 6 ? 6 : per <= 7 ? 7 : kCMaxSlots;
+    const int per = (nt + kCWaves - 1) / kCWaves;
+    geo->cslots = per <= 2 ? 2 : per <= 3 ? 3 : per <= 4 ? 4 : kCMaxSlots;
   }
   // the staged chunk and N share LDS
   geo->clds = (std::max((size_t)(1 << geo->clcw) * geo->crs, (size_t)blk_ncoef(q, p)) + kBMaxRows) *
                   sizeof(double) + kBMaxRows * sizeof(int64_t);
   if (geo->clds > kBMaxLds) return false;
+  // LDS-direct staging: two buffers of (rows rounded to 16) / 2 row pairs
+  geo->cbuf = (RP / 2) * kCPairBytes;
+  geo->clds_dma = (std::max((size_t)2 * geo->cbuf, (size_t)blk_ncoef(q, p) * sizeof(double)) +
+                   kBMaxRows * sizeof(double)) + kBMaxRows * sizeof(int64_t);
+  if (geo->clds_dma > kBMaxLds) geo->clds_dma = 0;  // register staging only
   return true;
 }
 
@@ -822,26 +965,35 @@ int64_t rka_blk_nblk(const RkaBlkGeom& geo, int64_t k0, int64_t K, int64_t check
   return BlkLayout::make(k0, K, check_every, geo.p).nblk;
 }
 
-template <typename T, int NS>
+template <typename T, int NS, bool DMA>
 static hipError_t launch_coef_ns(const RkaBlkGeom& geo, CoefArgs& a, int grid, hipStream_t s) {
-  const void* fn = (const void*)blk_coef_kernel<T, NS>;
-  if (geo.clds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)geo.clds);
+  const void* fn = (const void*)blk_coef_kernel<T, NS, DMA>;
+  const size_t lds = DMA ? geo.clds_dma : geo.clds;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((blk_coef_kernel<T, NS>), dim3(grid), dim3(kCThreads), geo.clds, s, a);
+  hipLaunchKernelGGL((blk_coef_kernel<T, NS, DMA>), dim3(grid), dim3(kCThreads), lds, s, a);
   return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t launch_coef_t(const RkaBlkGeom& geo, CoefArgs& a, int grid, hipStream_t s) {
+template <typename T, bool DMA>
+static hipError_t launch_coef_d(const RkaBlkGeom& geo, CoefArgs& a, int grid, hipStream_t s) {
   switch (geo.cslots) {
-    case 2: return launch_coef_ns<T, 2>(geo, a, grid, s);
-    case 4: return launch_coef_ns<T, 4>(geo, a, grid, s);
-    case 6: return launch_coef_ns<T, 6>(geo, a, grid, s);
-    case 7: return launch_coef_ns<T, 7>(geo, a, grid, s);
-    default: return launch_coef_ns<T, kCMaxSlots>(geo, a, grid, s);
+    case 2: return launch_coef_ns<T, 2, DMA>(geo, a, grid, s);
+    case 3: return launch_coef_ns<T, 3, DMA>(geo, a, grid, s);
+    case 4: return launch_coef_ns<T, 4, DMA>(geo, a, grid, s);
+    default: return launch_coef_ns<T, kCMaxSlots, DMA>(geo, a, grid, s);
   }
+}
+
+// LDS-direct staging on the 16-byte vector path (rows 16-byte aligned, n a
+// multiple of the vector), register staging otherwise
+template <typename T>
+static hipError_t launch_coef_t(const RkaBlkGeom& geo, CoefArgs& a, int grid, bool vec,
+                                hipStream_t s) {
+  return vec && geo.clds_dma > 0 ? launch_coef_d<T, true>(geo, a, grid, s)
+                                 : launch_coef_d<T, false>(geo, a, grid, s);
 }
 
 template <typename T, int V, int RPT>
@@ -887,11 +1039,12 @@ hipError_t launch_blk_coef(const SolveShape& sh, const RkaBlkGeom& geo, const Ro
   c.inv_q = 1.0 / (double)sh.q;
   c.coef = coef;
   c.ncoef = geo.ncoef;
+  c.cbuf = geo.cbuf;
   const int grid = (int)std::min<int64_t>(nblk, (int64_t)sh.num_cu * 4);
   switch (sh.dtype) {
-    case 0: return launch_coef_t<double>(geo, c, grid, s);
-    case 1: return launch_coef_t<float>(geo, c, grid, s);
-    default: return launch_coef_t<bf16_t>(geo, c, grid, s);
+    case 0: return launch_coef_t<double>(geo, c, grid, sh.vec_ok, s);
+    case 1: return launch_coef_t<float>(geo, c, grid, sh.vec_ok, s);
+    default: return launch_coef_t<bf16_t>(geo, c, grid, sh.vec_ok, s);
   }
 }
 

@@ -368,16 +368,26 @@ __device__ __forceinline__ void wait_memory() {
 // wait_memory() before arriving; readers use load_agent().  Agent-coherent
 // accesses go to the coherence point shared by all XCDs, so no L2
 // write-back or invalidate is needed (those cost ~40 us per barrier at 256
-// workgroups on MI355X; this barrier costs ~4 us).  `ctr` is zeroed before
-// the launch; `target` advances identically in every workgroup.
-// Returns false (in every thread of the workgroup) if the wait gave up.
-__device__ __forceinline__ bool grid_arrive_wait(unsigned* ctr, unsigned& target,
-                                                 unsigned nblocks) {
-  __shared__ int timed_out;
-  target += nblocks;
+// workgroups on MI355X; this barrier costs ~4 us).  `ctr` (kGridBarCounters
+// words, one used) is zeroed before the launch; `epoch` (barriers passed)
+// advances identically in every workgroup.  (A two-level counter -- groups
+// of 16 workgroups, the last arrival of a group counting on a top counter --
+// measured slower: the wait is the spread of the arrivals, not the atomics.)
+constexpr int kGridBarCounters = 2;
+// The barrier in two halves, so that a workgroup can issue work between its
+// arrival and its wait: grid_arrive (every thread calls it, after its
+// wait_memory) and grid_wait (every thread; false in every thread if the wait
+// gave up).
+__device__ __forceinline__ void grid_arrive(unsigned* ctr, unsigned& epoch, unsigned nblocks) {
+  (void)nblocks;
+  ++epoch;
   __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool grid_wait(unsigned* ctr, unsigned epoch, unsigned nblocks) {
+  __shared__ int timed_out;
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned target = epoch * nblocks;
     unsigned spins = 0;
     while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target &&
            ++spins < kSpinLimit)
@@ -387,12 +397,17 @@ __device__ __forceinline__ bool grid_arrive_wait(unsigned* ctr, unsigned& target
   __syncthreads();
   return !timed_out;
 }
+__device__ __forceinline__ bool grid_arrive_wait(unsigned* ctr, unsigned& epoch,
+                                                 unsigned nblocks) {
+  grid_arrive(ctr, epoch, nblocks);
+  return grid_wait(ctr, epoch, nblocks);
+}
 
 // All workgroups of the grid (one workgroup: a block barrier), for callers
 // that have nothing to overlap with the wait.
-__device__ __forceinline__ bool sync_grid(unsigned* ctr, unsigned& target, unsigned nblocks) {
+__device__ __forceinline__ bool sync_grid(unsigned* ctr, unsigned& epoch, unsigned nblocks) {
   wait_memory();
-  if (nblocks > 1) return grid_arrive_wait(ctr, target, nblocks);
+  if (nblocks > 1) return grid_arrive_wait(ctr, epoch, nblocks);
   __syncthreads();
   return true;
 }

@@ -126,6 +126,8 @@ struct RkaBlkGeom {
   int crs;               // coefficient pass: column stride of its staged chunk
   int clcw;              // log2 of its staged chunk's columns
   int cslots;            // its Gram tiles per wave
+  int cbuf;              // its LDS-direct staging: bytes per chunk buffer
+  size_t clds_dma;       // LDS bytes with LDS-direct staging (0: not possible)
   size_t clds;
 };
 // p_req = 0: the largest p that fits (q p <= 128).  FP64 arithmetic, RKA only.

@@ -17,6 +17,25 @@
 
 namespace rka {
 
+// Phase timing of workgroups 0 and G/2 (printed at the end of a launch), for
+// builds with RKA_RKAB_PROF defined only.
+#ifdef RKA_RKAB_PROF
+#define RPROF_DECL                             \
+  uint64_t rp_t[8] = {0, 0, 0, 0, 0, 0, 0, 0}; \
+  uint64_t rp_last = __builtin_readcyclecounter();
+#define RPROF(i)                                          \
+  do {                                                    \
+    const uint64_t rp_now = __builtin_readcyclecounter(); \
+    rp_t[i] += rp_now - rp_last;                          \
+    rp_last = rp_now;                                     \
+  } while (0)
+#else
+#define RPROF_DECL
+#define RPROF(i) \
+  do {           \
+  } while (0)
+#endif
+
 // ===========================================================================
 // RKAB, worker-split persistent kernel.
 // ===========================================================================
@@ -126,7 +145,7 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
   };
 
   const CoherentBuf xb(p.x, n);
-  unsigned target = 0;
+  unsigned epoch = 0;  // grid barriers passed
   bool stopped = false;
   int64_t kl = 0;
   const int bs = p.bs;
@@ -146,6 +165,7 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
   };
   stage_first(0, g);
   issue_first();
+  RPROF_DECL
   for (; kl < p.K; ++kl) {
     const int64_t k = p.k0 + kl;
     for (int w = g; w < p.q; w += p.G) {
@@ -156,6 +176,7 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
 #pragma unroll
         for (int e = 0; e < V; ++e) vat(i, e) = (C)xb.load(c * V + e);
       }
+      RPROF(0);
       int next_blk = 2;
       // block b goes into the slot of block b-2 once rows of block b-1 are
       // being projected; the ring looks at most four rows ahead
@@ -185,6 +206,7 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
       if (jj + 1 < bs) project(B1, jj + 1);
       if (jj + 2 < bs) project(B2, jj + 2);
       if (jj + 3 < bs) project(B0, jj + 3);
+      RPROF(1);
       const bool same_iter = w + p.G < p.q;
       __syncthreads();  // every thread is done with the staged records
       if (same_iter)
@@ -199,16 +221,23 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
         for (int e = 0; e < V; ++e) vw.store(c * V + e, vat(i, e));
       }
       if (same_iter) issue_first();
+      RPROF(2);
     }
-    // grid barrier: v's published; then the next iteration's first rows are
-    // requested, to stream in during the barrier and the average
+    // grid barrier: v's published.  The workgroup arrives, then requests the
+    // next iteration's first rows (to stream in during the wait and the
+    // average), then waits: issuing two rows stalls on the CU's
+    // outstanding-load limit, and before the arrival that stall delayed
+    // every workgroup's arrival.
     wait_memory();
+    RPROF(3);
+    if (p.G > 1) grid_arrive(p.bar, epoch, (unsigned)p.G);
     if (kl + 1 < p.K) issue_first();
     bool ok = true;
     if (p.G > 1)
-      ok = grid_arrive_wait(p.bar, target, (unsigned)p.G);
+      ok = grid_wait(p.bar, epoch, (unsigned)p.G);
     else
       __syncthreads();
+    RPROF(4);
     if (!ok) {
       if (t == 0) note_timeout(p.st);
       stopped = true;
@@ -248,7 +277,12 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
         }
       }
     } else {
-      const int le = t / tpe, sub = t % tpe;
+      // thread (le, sub) sums element le over the workers sub, sub + tpe,
+      // ...; consecutive threads take consecutive elements of the same
+      // workers, so a wave's loads read contiguous slices of two workers'
+      // iterates instead of 64 workers' single elements
+      const bool act = t < E * tpe;
+      const int le = act ? t % E : E, sub = act ? t / E : 0;
       const int64_t ci = e0 + (le < E ? le : 0);
       C acc = 0;
       if (le < E) {
@@ -264,7 +298,7 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
           for (int u = 0; u < 8; ++u) acc += vv[u];
         }
       }
-      AV[t] = acc;
+      if (act) AV[le * tpe + sub] = acc;
       __syncthreads();
       if (t < E) {
         C sum = 0;
@@ -281,7 +315,10 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
       const double s = block_sum(err, RED);
       if (t == 0) store_agent(&p.part[g], s);
     }
-    if (!sync_grid(p.bar, target, (unsigned)p.G)) {
+    RPROF(5);
+    const bool synced = sync_grid(p.bar, epoch, (unsigned)p.G);
+    RPROF(6);
+    if (!synced) {
       if (t == 0) note_timeout(p.st);
       stopped = true;
       break;
@@ -303,6 +340,14 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
       }
     }
   }
+#ifdef RKA_RKAB_PROF
+  if (t == 0 && (g == 0 || g == p.G / 2))
+    printf("rkab-prof g=%d iters=%lld x_load=%llu projections=%llu publish=%llu drain=%llu "
+           "barrier1=%llu average=%llu barrier2=%llu\n",
+           g, (long long)kl, (unsigned long long)rp_t[0], (unsigned long long)rp_t[1],
+           (unsigned long long)rp_t[2], (unsigned long long)rp_t[3], (unsigned long long)rp_t[4],
+           (unsigned long long)rp_t[5], (unsigned long long)rp_t[6]);
+#endif
   if (!stopped && g == 0 && t == 0) p.st->iterations = p.k0 + p.K;
 }
 
@@ -406,7 +451,7 @@ hipError_t launch_rkab_chunk(const SolveShape& sh, const RkabGeom& geo, const Ro
   a.bar = bar;
   a.st = st;
   if (geo.G > 1) {
-    hipError_t e = launch_zero(bar, 8, s);  // bar has room for two counters
+    hipError_t e = launch_zero(bar, kGridBarCounters * sizeof(unsigned), s);
     if (e != hipSuccess) return e;
   }
   if (sh.acc == 1) {
