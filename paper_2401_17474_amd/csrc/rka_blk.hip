@@ -671,8 +671,9 @@ __global__ __launch_bounds__(kBThreads) void rka_blk_kernel(BlkArgs p) {
     }
     BPROF(0);
     __syncthreads();
-    // (2) the nv partials leave in one coalesced pass
-    for (int v = t; v < nv; v += NT) part.put16((int64_t)g * p.nv_max + v, HV[v], tag);
+    // (2) the nv partials leave, value-major (slot v G + g), so that a
+    // reducer's G slots of one value are contiguous
+    for (int v = t; v < nv; v += NT) part.put16((int64_t)v * G + g, HV[v], tag);
     // (3) the block's coefficients M (L2-resident) straight into LDS, 16 bytes
     // a lane and 1 KB a wave per load, in flight across the exchange (issued
     // after the barrier above, which would otherwise wait for them)
@@ -692,16 +693,14 @@ __global__ __launch_bounds__(kBThreads) void rka_blk_kernel(BlkArgs p) {
       const int C = (nv + G - 1) / G;
       const int v0 = g * C;
       const int cnt = nv - v0 < C ? (nv - v0 > 0 ? nv - v0 : 0) : C;
+      // consecutive lanes poll consecutive slots: L = c G + gg is slot
+      // (v0 + c) G + gg
       ok = blk_gather(part, G * p.nv_max, G * cnt, tag,
-                      [&](int Lx) {
-                        const int gg = Lx / cnt, c = Lx - gg * cnt;
-                        return gg * p.nv_max + v0 + c;
-                      },
-                      PG, t, NT);
+                      [&](int Lx) { return v0 * G + Lx; }, PG, t, NT);
       const int TR = p.trp, team = t / TR, u = t & (TR - 1);
       double sum = 0.0;
       if (team < cnt)
-        for (int gg = u; gg < G; gg += TR) sum += PG[gg * cnt + team];
+        for (int gg = u; gg < G; gg += TR) sum += PG[team * G + gg];
       sum = team_sum(sum, TR);
       if (ok && u == 0 && team < cnt) red.put16(v0 + team, sum, tag);
     }

@@ -49,6 +49,7 @@ struct RkabArgs {
   int32_t q, bs, G, ns;
   int64_t k0, K, check_every;
   void* vbuf;    // q x (nvec * V): the workers' iterates (accumulation type)
+  int32_t avg_one_rsrc;  // the average's offsets fit 31 bits (one buffer resource)
   double* part;  // G
   unsigned* bar;
   DevStatus* st;
@@ -56,6 +57,33 @@ struct RkabArgs {
 
 constexpr int kRkabThreads = 512;
 constexpr int kStage = 256;  // row records staged in LDS per window slot
+
+// W consecutive elements of C at byte offset `off` of a device-coherent
+// buffer: one 16-byte access when W sizeof(C) = 16, else one element.  An
+// offset at or past the buffer's end reads 0 and touches no memory (the
+// range check applies to the lane's offset, so it is passed whole there).
+template <typename C, int W>
+__device__ __forceinline__ void load_units(__amdgpu_buffer_rsrc_t r, int off, C (&v)[W]) {
+  if constexpr (W * sizeof(C) == 16) {
+    const u32x4_t w = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, kCoherentSC1);
+    if constexpr (sizeof(C) == 8) {
+      v[0] = __builtin_bit_cast(double, ((uint64_t)w[1] << 32) | w[0]);
+      v[1] = __builtin_bit_cast(double, ((uint64_t)w[3] << 32) | w[2]);
+    } else {
+      // each element through a scalar: this compiler's bit cast of a vector
+      // element expression reads element 0 whatever the index
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t e = w[k];
+        v[k] = __builtin_bit_cast(float, e);
+      }
+    }
+  } else if constexpr (sizeof(C) == 8) {
+    v[0] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kCoherentSC1));
+  } else {
+    v[0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kCoherentSC1));
+  }
+}
 
 // VLDS = false: the worker's iterate v lives in registers (short rows);
 // VLDS = true: v lives in LDS (VPT * NT * V doubles of dynamic shared memory),
@@ -82,7 +110,8 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
   __shared__ C REDC[NT / kWave];
   __shared__ double Lb[2 * kStage], Lw[2 * kStage], La[2 * kStage];
   __shared__ int32_t Lr[2 * kStage];
-  __shared__ C AV[NT];  // partial sums of the average
+  constexpr int kAW = 16 / (int)sizeof(C);  // elements of C in 16 bytes
+  __shared__ C AV[kAW * NT];                 // partial sums of the average
   extern __shared__ double vlds_raw[];
   C* vlds = (C*)vlds_raw;
   C* vbuf = (C*)p.vbuf;
@@ -244,20 +273,21 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
       break;
     }
     // x^(k+1) = (1/q) sum_w v_w over this workgroup's column slice.  Each
-    // element's sum over the workers is split over tpe threads (strided
-    // worker subsets, each in increasing order) and the tpe partial sums are
+    // element's sum over the workers is split over tpu threads (strided
+    // worker subsets, each in increasing order) and the tpu partial sums are
     // then added in order: a fixed order for a given launch geometry.
     const bool check = p.check_every > 0 && ((k + 1) % p.check_every) == 0;
     const int64_t e0 = (int64_t)g * p.ns * V;
     const int64_t e1 = ((int64_t)(g + 1) * p.ns * V < n) ? (int64_t)(g + 1) * p.ns * V : n;
     const int E = e1 > e0 ? (int)(e1 - e0) : 0;
-    int tpe = 1;
-    if (E > 0 && E < NT) {
-      tpe = NT / E;
-      if (tpe > p.q) tpe = p.q;
-    }
+    constexpr int W = (V % kAW == 0) ? kAW : 1;  // elements per load of the split average
+    // loads of a thread in flight (fewer for narrow storage, whose row
+    // buffers leave fewer registers free)
+    constexpr int kAvgDepth = V <= 2 ? 8 : 4;
+    const int U = E / W;
     double err = 0.0;
-    if (tpe == 1) {
+    if (!p.avg_one_rsrc || U == 0 || U > NT) {
+      // a thread per element, the workers in order
       for (int64_t ci = e0 + t; ci < e1; ci += NT) {
         C acc = 0;
         int w = 0;
@@ -277,36 +307,54 @@ __global__ __launch_bounds__(kRkabThreads) void rkab_kernel(RkabArgs p) {
         }
       }
     } else {
-      // thread (le, sub) sums element le over the workers sub, sub + tpe,
-      // ...; consecutive threads take consecutive elements of the same
-      // workers, so a wave's loads read contiguous slices of two workers'
-      // iterates instead of 64 workers' single elements
-      const bool act = t < E * tpe;
-      const int le = act ? t % E : E, sub = act ? t / E : 0;
-      const int64_t ci = e0 + (le < E ? le : 0);
-      C acc = 0;
-      if (le < E) {
-        for (int w0 = sub; w0 < p.q; w0 += 8 * tpe) {
-          C vv[8];
+      // thread (lu, sub) sums unit lu of the slice (W consecutive elements,
+      // one 16-byte access on the vector path) over the workers sub,
+      // sub + tpu, ...; consecutive threads take consecutive units of the
+      // same workers.  Every load goes through one buffer resource based at
+      // the slice, uniform over the workgroup (a resource per worker would
+      // differ between the lanes of a wave, and the compiler would then
+      // serialise each load over the lanes' resources); offsets past the
+      // last worker read 0 without touching memory.  kAvgDepth loads are in
+      // flight before the first addition.
+      int tpu = NT / U;
+      if (tpu > p.q) tpu = p.q;
+      const bool act = t < U * tpu;
+      const int lu = act ? t % U : 0, sub = act ? t / U : 0;
+      const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+          vbuf + e0, (short)0, (int)(((int64_t)p.q * n - e0) * (int64_t)sizeof(C)),
+          kRawBufferWord3);
+      // worker w's unit lu is at byte (w n + lu W) sizeof(C); a batch's loads
+      // are tpu n sizeof(C) bytes apart, and those of workers past the last
+      // fall beyond the resource
+      const int wstride = (int)((int64_t)tpu * n * (int64_t)sizeof(C));
+      C acc[W];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int w = w0 + u * tpe;
-            const C val = CoherentOf<C>(vbuf + (size_t)(w < p.q ? w : p.q - 1) * n, n).load(ci);
-            vv[u] = w < p.q ? val : (C)0;
+      for (int e = 0; e < W; ++e) acc[e] = 0;
+      if (act) {
+        for (int w0 = sub; w0 < p.q; w0 += kAvgDepth * tpu) {
+          const int voff = (int)(((int64_t)w0 * n + lu * W) * (int64_t)sizeof(C));
+          C vv[kAvgDepth][W];
+#pragma unroll
+          for (int u = 0; u < kAvgDepth; ++u) load_units<C, W>(r, voff + u * wstride, vv[u]);
+          // a worker past the last adds +0, which leaves a sum started at +0
+          // unchanged
+#pragma unroll
+          for (int u = 0; u < kAvgDepth; ++u) {
+#pragma unroll
+            for (int e = 0; e < W; ++e) acc[e] += vv[u][e];
           }
-#pragma unroll
-          for (int u = 0; u < 8; ++u) acc += vv[u];
         }
+#pragma unroll
+        for (int e = 0; e < W; ++e) AV[(lu * W + e) * tpu + sub] = acc[e];
       }
-      if (act) AV[le * tpe + sub] = acc;
       __syncthreads();
-      if (t < E) {
+      for (int le = t; le < E; le += NT) {
         C sum = 0;
-        for (int u = 0; u < tpe; ++u) sum += AV[t * tpe + u];
+        for (int u = 0; u < tpu; ++u) sum += AV[le * tpu + u];
         const C xn = sum / (C)p.q;
-        xb.store(e0 + t, (double)xn);
+        xb.store(e0 + le, (double)xn);
         if (check) {
-          const double dd = (double)xn - p.x_ref[e0 + t];
+          const double dd = (double)xn - p.x_ref[e0 + le];
           err = fma(dd, dd, err);
         }
       }
@@ -372,7 +420,7 @@ static int vpt_limit_lds(int dtype, int V, int acc) {
   if (acc == 1) return dtype == 2 ? 4 : 8;
   return dtype == 0 ? 10 : (dtype == 1 ? 6 : 3);
 }
-constexpr size_t kMaxLds = 140 * 1024;  // 160 KiB minus the static LDS above
+constexpr size_t kMaxLds = 136 * 1024;  // 160 KiB minus the static LDS above (~23 KiB)
 
 bool rkab_plan(const SolveShape& sh, RkabGeom* geo) {
   const int esz = sh.dtype == 0 ? 8 : (sh.dtype == 1 ? 4 : 2);
@@ -447,6 +495,12 @@ hipError_t launch_rkab_chunk(const SolveShape& sh, const RkabGeom& geo, const Ro
   a.K = K;
   a.check_every = check_every;
   a.vbuf = vbuf;
+  {
+    const int64_t csz = sh.acc == 1 ? (int64_t)sizeof(float) : (int64_t)sizeof(double);
+    // every offset of the average (workers below q + 8 tpu, tpu <= q) within
+    // 31 bits
+    a.avg_one_rsrc = (int64_t)9 * sh.q * a.nvec * V * csz < (1ll << 31) ? 1 : 0;
+  }
   a.part = part;
   a.bar = bar;
   a.st = st;
