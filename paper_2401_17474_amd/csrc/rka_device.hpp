@@ -368,30 +368,41 @@ __device__ __forceinline__ void wait_memory() {
 // wait_memory() before arriving; readers use load_agent().  Agent-coherent
 // accesses go to the coherence point shared by all XCDs, so no L2
 // write-back or invalidate is needed (those cost ~40 us per barrier at 256
-// workgroups on MI355X; this barrier costs ~4 us).  `ctr` (kGridBarCounters
-// words, one used) is zeroed before the launch; `epoch` (barriers passed)
-// advances identically in every workgroup.  (A two-level counter -- groups
-// of 16 workgroups, the last arrival of a group counting on a top counter --
-// measured slower: the wait is the spread of the arrivals, not the atomics.)
-constexpr int kGridBarCounters = 2;
+// workgroups on MI355X).  `ctr` (kGridBarCounters words) is zeroed before the
+// launch; `epoch` (barriers passed) advances identically in every workgroup.
+//
+// Word 0 counts arrivals.  The workgroup whose arrival completes the count
+// writes the epoch into kBarGroups release flags, each on a 128-byte line of
+// its own (word 32 (1 + k)), and workgroup g polls flag g % kBarGroups (with
+// workgroups dealt round-robin over the XCDs, the workgroups of one XCD).
+// When every workgroup polled the counter itself, the polls and the
+// arrivals' atomics met on one line: at 256 workgroups the last workgroup to
+// arrive saw the release ~8 us after its own arrival (2-3 us at 64).
+constexpr int kBarGroups = 8;
+constexpr int kGridBarCounters = 32 * (1 + kBarGroups);
 // The barrier in two halves, so that a workgroup can issue work between its
 // arrival and its wait: grid_arrive (every thread calls it, after its
 // wait_memory) and grid_wait (every thread; false in every thread if the wait
 // gave up).
 __device__ __forceinline__ void grid_arrive(unsigned* ctr, unsigned& epoch, unsigned nblocks) {
-  (void)nblocks;
   ++epoch;
   __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) {
+    const unsigned before =
+        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (before == epoch * nblocks - 1) {  // the last arrival: every data write is complete
+#pragma unroll
+      for (int k = 0; k < kBarGroups; ++k) store_agent(ctr + 32 * (1 + k), epoch);
+    }
+  }
 }
 __device__ __forceinline__ bool grid_wait(unsigned* ctr, unsigned epoch, unsigned nblocks) {
+  (void)nblocks;
   __shared__ int timed_out;
   if (threadIdx.x == 0) {
-    const unsigned target = epoch * nblocks;
+    const unsigned* flag = ctr + 32 * (1 + blockIdx.x % kBarGroups);
     unsigned spins = 0;
-    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target &&
-           ++spins < kSpinLimit)
-      __builtin_amdgcn_s_sleep(1);
+    while (load_agent(flag) < epoch && ++spins < kSpinLimit) __builtin_amdgcn_s_sleep(1);
     timed_out = spins >= kSpinLimit;
   }
   __syncthreads();
