@@ -345,7 +345,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   };
   if (use_blk) {
     nslots = (size_t)kgeo.G * kgeo.nv;
-    nsslots = (size_t)kgeo.nv;
+    nsslots = (size_t)kgeo.nv * rka::kBlkRedCopies;
     // chunks short enough that their coefficients take at most kCoefBudget
     // bytes (a chunk boundary costs two launches; a block's M is up to 57 KB)
     // (coef_blocks(kc) <= kCoefBudget / per_blk; p = 1 has no coefficients)

@@ -503,7 +503,7 @@ struct BlkArgs {
   int32_t trp;        // lanes per value in the reduce-scatter
   int32_t trm;        // lanes per row of s = M c
   uint64_t* part;     // G x nv_max tagged slots
-  uint64_t* red;      // nv_max tagged slots
+  uint64_t* red;      // kBlkRedCopies x nv_max tagged slots
   DevStatus* st;
 };
 
@@ -588,7 +588,7 @@ __global__ __launch_bounds__(kBThreads) void rka_blk_kernel(BlkArgs p) {
   }
 
   const TagSlots part(p.part, (int64_t)G * p.nv_max);
-  const TagSlots red(p.red, p.nv_max);
+  const TagSlots red(p.red, (int64_t)kBlkRedCopies * p.nv_max);
 
   auto load_rows = [&](int kl2, int L2, int* rows) {
     const int R2 = L2 * q;
@@ -701,8 +701,9 @@ __global__ __launch_bounds__(kBThreads) void rka_blk_kernel(BlkArgs p) {
       double sum = 0.0;
       if (team < cnt)
         for (int gg = u; gg < G; gg += TR) sum += PG[team * G + gg];
-      sum = team_sum(sum, TR);
-      if (ok && u == 0 && team < cnt) red.put16(v0 + team, sum, tag);
+      sum = team_sum(sum, TR);  // in every lane of the team
+      if (ok && team < cnt)
+        for (int c = u; c < kBlkRedCopies; c += TR) red.put16(c * p.nv_max + v0 + team, sum, tag);
     }
     BPROF(2);
     // The next block's rows and records, issued while the other workgroups'
@@ -728,9 +729,12 @@ __global__ __launch_bounds__(kBThreads) void rka_blk_kernel(BlkArgs p) {
       p.lay.locate(b + 2, &kn2, &Ln2, &t2);
       load_rows(kn2, Ln2, rows_n);
     }
-    // phase 2: every workgroup reads all nv sums
-    if (__syncthreads_and(ok))
-      ok = blk_gather(red, p.nv_max, nv, tag, [&](int Lx) { return Lx; }, HV, t, NT);
+    // phase 2: every workgroup reads all nv sums (from its copy)
+    if (__syncthreads_and(ok)) {
+      const int cp = (g % kBlkRedCopies) * p.nv_max;
+      ok = blk_gather(red, kBlkRedCopies * p.nv_max, nv, tag, [&](int Lx) { return cp + Lx; }, HV,
+                      t, NT);
+    }
     BPROF(3);
     if (!__syncthreads_and(ok)) {
       if (t == 0) note_timeout(p.st);
