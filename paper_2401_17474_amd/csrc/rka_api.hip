@@ -364,7 +364,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   } else if (use_col) {
     // 16-byte slots: 2 words each
     nslots = (size_t)(cgeo.gather ? 2 : 1) * G * (q + 1);
-    nsslots = (size_t)q + 1;
+    nsslots = ((size_t)q + 1) * rka::kColScalCopies;
   } else {
     vb = (size_t)q * (size_t)n * (acc == 1 ? sizeof(float) : sizeof(double));
   }

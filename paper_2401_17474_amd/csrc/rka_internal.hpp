@@ -118,6 +118,8 @@ hipError_t launch_sstep_chunk(const SolveShape& sh, const RkaSstepGeom& geo, con
 // g % kBlkRedCopies, so that each copy's lines are polled by a fraction of
 // the workgroups while the reducers write them.
 constexpr int kBlkRedCopies = 8;
+// The same for the column kernel's two-phase exchange (its q + 1 scales).
+constexpr int kColScalCopies = 8;
 struct RkaBlkGeom {
   int G, nsv, rg, nt, rpt;
   int nsvp;              // lanes per row group (nsv rounded up to a power of two)

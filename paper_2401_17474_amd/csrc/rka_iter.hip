@@ -43,7 +43,7 @@ struct RkaColArgs {
   int32_t tr_g;       // lanes that sum one row's G gathered partials (all-gather only)
   int64_t k0, K, check_every;
   uint64_t* part;  // tagged slots: gather 2 x G x (q+1) (by iteration parity); else G x (q+1)
-  uint64_t* scal;  // tagged slots: q+1 scales (two-phase exchange)
+  uint64_t* scal;  // tagged slots: kColScalCopies x (q+1) scales (two-phase exchange)
   DevStatus* st;
 };
 
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
         d = team_sum(d, TR);
         if (u == 0 && r < q) {
           if (G > 1)
-            part.put((int64_t)g * (q + 1) + r, (double)d, tag);
+            part.put((int64_t)r * G + g, (double)d, tag);
           else
             SC[r] = (r0 == 0) ? scale_of(mine_a, mine_b, mine_w, (double)d)
                               : scale_of(p.rec[kl * q + r].alpha, p.rec[kl * q + r].b,
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
       s = wave_sum(s);
       if (t == 0) {
         if (G > 1)
-          part.put((int64_t)g * (q + 1) + q, s, tag);
+          part.put((int64_t)q * G + g, s, tag);
         else
           SC[q] = s;
       }
@@ -196,7 +196,8 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
     if (G > 1) {
       if constexpr (GATHER) {
         // every workgroup polls every row's partials and sums them in the
-        // same fixed order (slot L = gg * nr + r of this thread's share)
+        // same fixed order (slot L = r G + gg of this thread's share: the
+        // slots are value-major, row r's G partials contiguous)
         const int total = G * nr;
         bool have[kPollMax];
 #pragma unroll
@@ -206,7 +207,7 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
 #pragma unroll
           for (int u = 0; u < kPollMax; ++u) {
             const int L = t + NT * u < total ? t + NT * u : total - 1;
-            part.fetch((int64_t)(L / nr) * (q + 1) + L % nr, lo[u], hi[u]);
+            part.fetch(L, lo[u], hi[u]);
           }
           bool all = true;
 #pragma unroll
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
             double v;
             if (!have[u] && TagSlots::decode(lo[u], hi[u], tag, v)) {
               const int L = t + NT * u;
-              PG[(L / nr) * (q + 1) + L % nr] = v;
+              PG[(L % G) * (q + 1) + L / G] = v;
               have[u] = true;
             }
             all = all && have[u];
@@ -250,7 +251,9 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
         }
       } else if constexpr (!GATHER) {
         // phase 1: workgroup g sums the partials of rows g, g + G, ...
-        const TagSlots scal(p.scal, q + 1);
+        // the q + 1 sums go to kColScalCopies copies; workgroup g polls
+        // copy g % kColScalCopies
+        const TagSlots scal(p.scal, (int64_t)kColScalCopies * (q + 1));
         for (int r = g; r < nr; r += G) {
           RowRec rr;
           if (t == 0 && r < q) rr = p.rec[kl * q + r];  // in flight with the polls
@@ -258,7 +261,7 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
           bool have = t >= G;
           for (unsigned spins = 0;; ++spins) {
             uint64_t lo, hi;
-            part.fetch((int64_t)(t < G ? t : G - 1) * (q + 1) + r, lo, hi);
+            part.fetch((int64_t)r * G + (t < G ? t : G - 1), lo, hi);
             double pv;
             if (!have && TagSlots::decode(lo, hi, tag, pv)) {
               v = pv;
@@ -280,7 +283,7 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
             double pv = 0.0;
             bool got = false;
             for (unsigned spins = 0; spins < kSpinLimit; ++spins) {
-              part.fetch((int64_t)gg * (q + 1) + r, lo, hi);
+              part.fetch((int64_t)r * G + gg, lo, hi);
               if (TagSlots::decode(lo, hi, tag, pv)) {
                 got = true;
                 break;
@@ -292,7 +295,10 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
           }
           if (!__syncthreads_and(got_all)) ok = false;
           const double D = block_sum(v, RED);
-          if (t == 0) scal.put(r, r < q ? scale_of(rr.alpha, rr.b, rr.wn, D) : D, tag);
+          if (t == 0) {
+            const double sv = r < q ? scale_of(rr.alpha, rr.b, rr.wn, D) : D;
+            for (int c = 0; c < kColScalCopies; ++c) scal.put(c * (q + 1) + r, sv, tag);
+          }
         }
         // phase 2: every workgroup polls the q scales (one slot per thread
         // per round; one round unless q + 1 exceeds the thread count)
@@ -301,7 +307,7 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
           bool have = L >= nr;
           for (unsigned spins = 0;; ++spins) {
             uint64_t lo, hi;
-            scal.fetch(L < nr ? L : nr - 1, lo, hi);
+            scal.fetch((g % kColScalCopies) * (q + 1) + (L < nr ? L : nr - 1), lo, hi);
             double v;
             if (!have && TagSlots::decode(lo, hi, tag, v)) {
               SC[L] = v;
