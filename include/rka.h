@@ -183,8 +183,10 @@ typedef struct rka_opts {
                                iteration in exact arithmetic, kernel 3).  2 needs FP64
                                arithmetic and q <= 256, else kernel 2 runs.          */
     int32_t rka_block;      /* RKA only, with several iterations per exchange: 0 = chosen
-                               by the library (kernel 4 when it fits and q <= 64,
-                               else kernel 3); 1 = the inner products between the
+                               by the library (kernel 4 when it fits: blocks of
+                               several iterations for q <= 64, of one iteration for
+                               64 < q <= 256; else kernel 3 for q <= 16, else the
+                               column-split kernel); 1 = the inner products between the
                                block's rows travel in the exchange (kernel 3); 2 = a
                                streaming pass over the chunk's rows forms, per block,
                                M = (I + N)^-1 with N_{r,c} = alpha_r <a_r, a_c> /

@@ -202,13 +202,16 @@ constexpr int kAutoSstepMaxQ = 16;
 // q = 64, bs = 2: 29 -> 15; q = 4, bs = 32: 94 -> 35.
 constexpr int kAutoSubBlockMaxQ = 16;
 // RKA blocks with coefficients from a streaming pass (kernel 4) are the
-// library's choice for several iterations per exchange up to q = 64.
-// Measured at 80000 x 10000 FP64, us per iteration with the coefficient
-// pass included, kernel 4 against the best other kernel: q = 8: 1.17 (2.56,
-// kernel 3); q = 16: 2.13 (5.0, kernel 3); q = 32: 4.1 (8.0, one-iteration
-// kernel); q = 64: 7.6 (8.7, one-iteration kernel).
+// library's choice up to q = 256 wherever they fit: several iterations per
+// block up to q = 64, one above.  Measured at 80000 x 10000 FP64, us per
+// iteration with the coefficient pass included, kernel 4 against the best
+// other kernel: q = 8: 1.07 (2.54, kernel 3); q = 16: 1.92 (4.4, kernel 3);
+// q = 32: 3.45 (7.1, one-iteration kernel); q = 64: 6.1 (7.8); q = 96: 8.1
+// (9.2); q = 128: 9.1 (10.0); q = 160: 10.7 (12.5).  With one iteration per
+// block at 20000 x 1000 and 40000 x 5000, q = 96 to 256: 2% to 46% faster
+// than the one-iteration kernel.
 constexpr bool kAutoBlk = true;
-constexpr int kAutoBlkMaxQ = 64;
+constexpr int kAutoBlkMaxQ = 256;
 
 int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
                const double* b, const double* x0, double* x, int32_t q, int32_t bs, double alpha,
@@ -345,7 +348,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   };
   if (use_blk) {
     nslots = (size_t)kgeo.G * kgeo.nv;
-    nsslots = (size_t)kgeo.nv * rka::kBlkRedCopies;
+    nsslots = (size_t)kgeo.nv * rka::kSumCopies;
     // chunks short enough that their coefficients take at most kCoefBudget
     // bytes (a chunk boundary costs two launches; a block's M is up to 57 KB)
     // (coef_blocks(kc) <= kCoefBudget / per_blk; p = 1 has no coefficients)
@@ -360,11 +363,11 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
     }
   } else if (use_sstep) {
     nslots = (size_t)sgeo.G * sgeo.nv;
-    nsslots = (size_t)sgeo.nv;
+    nsslots = (size_t)sgeo.nv * rka::kSumCopies;
   } else if (use_col) {
     // 16-byte slots: 2 words each
     nslots = (size_t)(cgeo.gather ? 2 : 1) * G * (q + 1);
-    nsslots = ((size_t)q + 1) * rka::kColScalCopies;
+    nsslots = ((size_t)q + 1) * rka::kSumCopies;
   } else {
     vb = (size_t)q * (size_t)n * (acc == 1 ? sizeof(float) : sizeof(double));
   }

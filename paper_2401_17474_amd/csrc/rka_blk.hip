@@ -502,8 +502,8 @@ struct BlkArgs {
   int32_t tr;         // lanes per row for the slice sums of the dot products
   int32_t trp;        // lanes per value in the reduce-scatter
   int32_t trm;        // lanes per row of s = M c
-  uint64_t* part;     // G x nv_max tagged slots
-  uint64_t* red;      // kBlkRedCopies x nv_max tagged slots
+  uint64_t* part;     // nv_max x G tagged slots, value-major
+  uint64_t* red;      // kSumCopies x nv_max tagged slots
   DevStatus* st;
 };
 
@@ -588,7 +588,7 @@ __global__ __launch_bounds__(kBThreads) void rka_blk_kernel(BlkArgs p) {
   }
 
   const TagSlots part(p.part, (int64_t)G * p.nv_max);
-  const TagSlots red(p.red, (int64_t)kBlkRedCopies * p.nv_max);
+  const TagSlots red(p.red, (int64_t)kSumCopies * p.nv_max);
 
   auto load_rows = [&](int kl2, int L2, int* rows) {
     const int R2 = L2 * q;
@@ -703,7 +703,7 @@ __global__ __launch_bounds__(kBThreads) void rka_blk_kernel(BlkArgs p) {
         for (int gg = u; gg < G; gg += TR) sum += PG[team * G + gg];
       sum = team_sum(sum, TR);  // in every lane of the team
       if (ok && team < cnt)
-        for (int c = u; c < kBlkRedCopies; c += TR) red.put16(c * p.nv_max + v0 + team, sum, tag);
+        for (int c = u; c < kSumCopies; c += TR) red.put16(c * p.nv_max + v0 + team, sum, tag);
     }
     BPROF(2);
     // The next block's rows and records, issued while the other workgroups'
@@ -731,8 +731,8 @@ __global__ __launch_bounds__(kBThreads) void rka_blk_kernel(BlkArgs p) {
     }
     // phase 2: every workgroup reads all nv sums (from its copy)
     if (__syncthreads_and(ok)) {
-      const int cp = (g % kBlkRedCopies) * p.nv_max;
-      ok = blk_gather(red, kBlkRedCopies * p.nv_max, nv, tag, [&](int Lx) { return cp + Lx; }, HV,
+      const int cp = (g % kSumCopies) * p.nv_max;
+      ok = blk_gather(red, kSumCopies * p.nv_max, nv, tag, [&](int Lx) { return cp + Lx; }, HV,
                       t, NT);
     }
     BPROF(3);
@@ -902,8 +902,10 @@ bool rka_blk_plan(const SolveShape& sh, int p_req, RkaBlkGeom* geo) {
     break;
   }
   if (p < 1) return false;
-  // left to the library, one iteration per block is the column kernel's job
-  if (p_req == 0 && p == 1) return false;
+  // left to the library, one iteration per block only where q itself fills
+  // a block (q > 64); below, a block cut to one iteration by the register
+  // tile is the column kernel's job
+  if (p_req == 0 && p == 1 && q <= kBMaxRows / 2) return false;
   const int R = q * p;
   int rpt = (R + rg - 1) / rg;
   const int buckets[] = {1, 2, 3, 4, 6, 8, 11};

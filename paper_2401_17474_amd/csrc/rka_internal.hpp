@@ -114,12 +114,11 @@ hipError_t launch_sstep_chunk(const SolveShape& sh, const RkaSstepGeom& geo, con
 // Geometry of RKA in blocks of p iterations with precomputed coefficients
 // (rka_blk.hip): column slices as in the column-split kernel; the
 // coefficient pass runs 8 x 8 inner-product tiles of f lanes each.
-// Copies of kernel 4's summed exchange values: workgroup g reads copy
-// g % kBlkRedCopies, so that each copy's lines are polled by a fraction of
-// the workgroups while the reducers write them.
-constexpr int kBlkRedCopies = 8;
-// The same for the column kernel's two-phase exchange (its q + 1 scales).
-constexpr int kColScalCopies = 8;
+// Copies of the summed values of a two-phase exchange (column kernel,
+// kernels 3 and 4): the reducers write every copy and workgroup g reads copy
+// g % kSumCopies, so that each copy's lines are polled by a fraction of the
+// workgroups while they are written.
+constexpr int kSumCopies = 8;
 struct RkaBlkGeom {
   int G, nsv, rg, nt, rpt;
   int nsvp;              // lanes per row group (nsv rounded up to a power of two)

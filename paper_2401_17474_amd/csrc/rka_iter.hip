@@ -43,7 +43,7 @@ struct RkaColArgs {
   int32_t tr_g;       // lanes that sum one row's G gathered partials (all-gather only)
   int64_t k0, K, check_every;
   uint64_t* part;  // tagged slots: gather 2 x G x (q+1) (by iteration parity); else G x (q+1)
-  uint64_t* scal;  // tagged slots: kColScalCopies x (q+1) scales (two-phase exchange)
+  uint64_t* scal;  // tagged slots: kSumCopies x (q+1) scales (two-phase exchange)
   DevStatus* st;
 };
 
@@ -251,9 +251,9 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
         }
       } else if constexpr (!GATHER) {
         // phase 1: workgroup g sums the partials of rows g, g + G, ...
-        // the q + 1 sums go to kColScalCopies copies; workgroup g polls
-        // copy g % kColScalCopies
-        const TagSlots scal(p.scal, (int64_t)kColScalCopies * (q + 1));
+        // the q + 1 sums go to kSumCopies copies; workgroup g polls
+        // copy g % kSumCopies
+        const TagSlots scal(p.scal, (int64_t)kSumCopies * (q + 1));
         for (int r = g; r < nr; r += G) {
           RowRec rr;
           if (t == 0 && r < q) rr = p.rec[kl * q + r];  // in flight with the polls
@@ -297,7 +297,7 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
           const double D = block_sum(v, RED);
           if (t == 0) {
             const double sv = r < q ? scale_of(rr.alpha, rr.b, rr.wn, D) : D;
-            for (int c = 0; c < kColScalCopies; ++c) scal.put(c * (q + 1) + r, sv, tag);
+            for (int c = 0; c < kSumCopies; ++c) scal.put(c * (q + 1) + r, sv, tag);
           }
         }
         // phase 2: every workgroup polls the q scales (one slot per thread
@@ -307,7 +307,7 @@ __global__ __launch_bounds__(kMaxColThreads) void rka_col_kernel(RkaColArgs p) {
           bool have = L >= nr;
           for (unsigned spins = 0;; ++spins) {
             uint64_t lo, hi;
-            scal.fetch((g % kColScalCopies) * (q + 1) + (L < nr ? L : nr - 1), lo, hi);
+            scal.fetch((g % kSumCopies) * (q + 1) + (L < nr ? L : nr - 1), lo, hi);
             double v;
             if (!have && TagSlots::decode(lo, hi, tag, v)) {
               SC[L] = v;

@@ -75,7 +75,7 @@ struct SstepArgs {
                       // keeps its reads off the vector memory counter)
   int64_t k0, K, check_every;
   uint64_t* part;     // G x nv_max tagged slots: per-workgroup partial sums
-  uint64_t* red;      // nv_max tagged slots: the summed values
+  uint64_t* red;      // kSumCopies x nv_max tagged slots: the summed values
   DevStatus* st;
 };
 
@@ -316,7 +316,7 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
     // one tag per exchange of the solve: iteration, then sub-block
     const uint32_t tag = (uint32_t)(k * nsub + sb + 1);
     const TagSlots part(p.part, (int64_t)G * p.nv_max);
-    const TagSlots red(p.red, p.nv_max);
+    const TagSlots red(p.red, (int64_t)kSumCopies * p.nv_max);
 
     if (t < R) {
       RB[t] = mb;
@@ -521,7 +521,11 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
     }
 
     // the workgroup's nv partial sums leave in one coalesced pass (a fixed
-    // number of stores per lane: an index past the slots drops the store)
+    // number of stores per lane: an index past the slots drops the store).
+    // Value-major slots (a value's G partials contiguous, as in kernel 4)
+    // measured slower here: the scattered stores cost more than the polls
+    // save (80000 x 10000 FP64, RKAB q = 16, bs = 10: 22.3 against 20.5 us
+    // per outer iteration).
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < kSPoll; ++s) {
@@ -549,13 +553,16 @@ __global__ __launch_bounds__(kSThreads) void rka_sstep_kernel(SstepArgs p) {
       double sum = 0.0;
       if (team < cnt)
         for (int gg = u; gg < G; gg += TR) sum += PG[gg * cnt + team];
-      sum = team_sum(sum, TR);
-      if (ok && u == 0 && team < cnt) red.put16(v0 + team, sum, tag);
+      sum = team_sum(sum, TR);  // in every lane of the team
+      if (ok && team < cnt)
+        for (int c = u; c < kSumCopies; c += TR) red.put16(c * p.nv_max + v0 + team, sum, tag);
     }
     SPROF(3);
-    // phase 2: every workgroup reads all nv sums
-    if (__syncthreads_and(ok))
-      ok = gather(red, p.nv_max, nv, tag, [&](int Lx) { return Lx; }, HV);
+    // phase 2: every workgroup reads all nv sums (from its copy)
+    if (__syncthreads_and(ok)) {
+      const int cpo = (g % kSumCopies) * p.nv_max;
+      ok = gather(red, kSumCopies * p.nv_max, nv, tag, [&](int Lx) { return cpo + Lx; }, HV);
+    }
     if (!__syncthreads_and(ok)) {
       if (t == 0) note_timeout(p.st);
       stopped = true;

@@ -155,21 +155,23 @@ def test_blk_falls_back_when_blocks_do_not_fit():
 
 
 def test_library_chooses_blocks_with_precomputed_coefficients():
-    """Left to the library (steps_per_exchange = 0, rka_block = 0), RKA up to
-    q = 64 on a shape with several workgroups runs kernel 4; a stopping test
-    every iteration, or q above 64, runs the one-iteration kernel."""
+    """Left to the library (steps_per_exchange = 0, rka_block = 0), RKA on a
+    shape with several workgroups runs kernel 4: several iterations per block
+    up to q = 64, one iteration per block up to q = 256.  A stopping test
+    every iteration, or q above 256, runs the one-iteration kernel."""
     say("blk auto selection")
     A, xs, b = _system(3000, 2000, seed=9)
     Ad, bd = to_dev(A), vec(b)
-    for q in (8, 16, 64):
-        x, info, st = rka.solve_ex(Ad, bd, method=0, q=q, max_iter=24, seed=4)
-        assert info.status == rka.OK and st["kernel"] == 4 and st["variant"] >= 2, (q, st)
-        xo, _ = oracle.rka(A, b, q=q, max_iter=24, seed=4)
+    for q, K in ((8, 24), (16, 24), (64, 24), (100, 9), (256, 5)):
+        x, info, st = rka.solve_ex(Ad, bd, method=0, q=q, max_iter=K, seed=4)
+        want_p = (lambda p: p >= 2) if q <= 64 else (lambda p: p == 1)
+        assert info.status == rka.OK and st["kernel"] == 4 and want_p(st["variant"]), (q, st)
+        xo, _ = oracle.rka(A, b, q=q, max_iter=K, seed=4)
         assert_x_close(host(x), xo, what=f"auto q={q}")
     _, _, st = rka.solve_ex(Ad, bd, method=0, q=16, max_iter=24, seed=4, tol=1e-30,
                             x_ref=vec(xs), check_every=1)
     assert st["kernel"] == 1
-    _, _, st = rka.solve_ex(Ad, bd, method=0, q=128, max_iter=8, seed=4)
+    _, _, st = rka.solve_ex(Ad, bd, method=0, q=300, max_iter=4, seed=4)
     assert st["kernel"] == 1
 
 
