@@ -708,10 +708,12 @@ __global__ __launch_bounds__(kBThreads) void rka_blk_kernel(BlkArgs p) {
     BPROF(2);
     // The next block's rows and records, issued while the other workgroups'
     // phase-1 sums arrive: the issue stalls on the CU's outstanding-load
-    // limit wherever it sits, and here the stall overlaps a wait (measured
-    // 2.08 against 2.15 us per iteration at q = 16 with the issue after the
-    // exchange).  Their addresses use the row indices loaded one block
-    // earlier.
+    // limit wherever it sits, and here the stall overlaps a wait.  Measured
+    // at q = 16, p = 8, us per iteration: 1.92 here; 2.02 with the issue at
+    // the start of the block (phase 2 no longer waits for the rows, but the
+    // stalled issue delays the dot products and partial sums by ~5k
+    // cycles); 2.15 with the issue after the exchange.  Their addresses use
+    // the row indices loaded one block earlier.
     int kn = kl, Ln = L;
     bool checkn = false;
     if (b + 1 < nblk) p.lay.locate(b + 1, &kn, &Ln, &checkn);
@@ -892,11 +894,14 @@ bool rka_blk_plan(const SolveShape& sh, int p_req, RkaBlkGeom* geo) {
   int nsvp = 1;
   while (nsvp < nsv) nsvp *= 2;
   const int rg = NT / nsvp;
-  // the largest p whose rows fit the register tile and LDS
+  // the largest p whose rows fit the register tile and LDS (narrow storage
+  // on the vector path: fewer rows per thread, the widened rows taking more
+  // registers; the larger tiles spill on gfx950)
+  const int rpt_cap = V == 1 ? kBMaxRPT : (sh.dtype == 0 ? kBMaxRPT : (sh.dtype == 1 ? 6 : 4));
   for (; p >= 1; --p) {
     const int R = q * p;
     const int rpt = (R + rg - 1) / rg;
-    if (rpt > kBMaxRPT) continue;
+    if (rpt > rpt_cap) continue;
     if (blk_lds_bytes(q, p, nsvp, V, NT, G) > kBMaxLds) continue;
     if (R + 1 > kBPoll * NT || (int64_t)G * ((R + 1 + G - 1) / G) > (int64_t)kBPoll * NT) continue;
     break;
