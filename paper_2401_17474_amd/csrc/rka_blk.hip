@@ -712,8 +712,9 @@ __global__ __launch_bounds__(kBThreads) void rka_blk_kernel(BlkArgs p) {
     // at q = 16, p = 8, us per iteration: 1.92 here; 2.02 with the issue at
     // the start of the block (phase 2 no longer waits for the rows, but the
     // stalled issue delays the dot products and partial sums by ~5k
-    // cycles); 2.15 with the issue after the exchange.  Their addresses use
-    // the row indices loaded one block earlier.
+    // cycles); 1.96 with half the rows issued before the partial sums and
+    // half here; 2.15 with the issue after the exchange.  Their addresses
+    // use the row indices loaded one block earlier.
     int kn = kl, Ln = L;
     bool checkn = false;
     if (b + 1 < nblk) p.lay.locate(b + 1, &kn, &Ln, &checkn);
