@@ -187,6 +187,9 @@ int validate(const void* A, int dtype, int64_t m, int64_t n, int64_t lda, const 
 constexpr int64_t kRecBudget = 4ll << 20;
 // Kernel 4's coefficients per chunk: at most 512 MiB.
 constexpr int64_t kCoefBudget = 512ll << 20;
+// Kernel 4's first chunk where a stopping test may end the solve (iterations;
+// the chunks after it double).
+constexpr int64_t kFirstBlkChunk = 1024;
 // Largest q for which the library runs several RKA iterations per exchange
 // by itself (steps_per_exchange = 0): measured at 80000 x 10000 FP64, blocks
 // of 64 / q iterations take 4.5 us per iteration at q = 16 (one-iteration
@@ -455,8 +458,18 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
     tm.end();
   }
   int64_t launches = 0;
+  // Kernel 4 forms a chunk's coefficients before its iterations, so where a
+  // stopping test may end the solve early its chunks start short and double
+  // (at most one chunk's coefficient pass beyond the stop, twice the work
+  // up to it); the passes of the chunks after a stop return at once.
+  int64_t kc_grow = kc_max;
+  if (use_blk && tol > 0.0) {
+    kc_grow = std::max<int64_t>(kFirstBlkChunk, 4 * check_every);
+    if (kc_grow > kc_max) kc_grow = kc_max;
+  }
   for (int64_t k = 0; k < max_iter;) {
-    int64_t kc = max_iter - k < kc_max ? max_iter - k : kc_max;
+    int64_t kc = max_iter - k < kc_grow ? max_iter - k : kc_grow;
+    if (kc_grow < kc_max) kc_grow = std::min<int64_t>(2 * kc_grow, kc_max);
     if (resid_mode) {
       const int64_t to_check = check_every - (k % check_every);
       if (to_check < kc) kc = to_check;
@@ -467,7 +480,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
     tm.end();
     if (use_blk) {
       tm.begin(kCoef);
-      HIP_TRY(rka::launch_blk_coef(sh, kgeo, rec, k, kc, in_kernel_check, coef, s));
+      HIP_TRY(rka::launch_blk_coef(sh, kgeo, rec, k, kc, in_kernel_check, coef, st, s));
       tm.end();
     }
     tm.begin(kIterate);

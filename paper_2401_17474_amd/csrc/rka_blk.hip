@@ -146,6 +146,7 @@ struct CoefArgs {
   int32_t ncoef;      // coefficients of a full block
   int32_t cstride;    // doubles between blocks in coef (a multiple of 128)
   int32_t cbuf;       // LDS-direct staging: bytes per chunk buffer
+  const DevStatus* st;  // a solve that has stopped needs no more coefficients
 };
 
 template <typename T>
@@ -416,6 +417,7 @@ __device__ __forceinline__ void coef_gram_dma(const CoefArgs& p, const T* __rest
 // chunk has been used.
 template <typename T, int NS, bool DMA>
 __global__ __launch_bounds__(kCThreads) void blk_coef_kernel(CoefArgs p) {
+  if (p.st->done) return;
   const T* __restrict__ A = (const T*)p.A;
   const int t = threadIdx.x, q = p.q;
   extern __shared__ double lds[];
@@ -1033,7 +1035,7 @@ static hipError_t launch_blk_rpt(const RkaBlkGeom& geo, BlkArgs& a, hipStream_t 
 
 hipError_t launch_blk_coef(const SolveShape& sh, const RkaBlkGeom& geo, const RowRec* rec,
                            int64_t k0, int64_t K, int64_t check_every, double* coef,
-                           hipStream_t s) {
+                           const DevStatus* st, hipStream_t s) {
   if (geo.p <= 1) return hipSuccess;  // one iteration per block: no coefficients
   const BlkLayout lay = BlkLayout::make(k0, K, check_every, geo.p);
   const int64_t nblk = lay.nblk;
@@ -1051,6 +1053,7 @@ hipError_t launch_blk_coef(const SolveShape& sh, const RkaBlkGeom& geo, const Ro
   c.coef = coef;
   c.ncoef = geo.ncoef;
   c.cbuf = geo.cbuf;
+  c.st = st;
   const int grid = (int)std::min<int64_t>(nblk, (int64_t)sh.num_cu * 4);
   switch (sh.dtype) {
     case 0: return launch_coef_t<double>(geo, c, grid, sh.vec_ok, s);

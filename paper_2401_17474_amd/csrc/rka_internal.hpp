@@ -143,7 +143,7 @@ int64_t rka_blk_nblk(const RkaBlkGeom& geo, int64_t k0, int64_t K, int64_t check
 // rka_blk_nblk(...) x cstride doubles.
 hipError_t launch_blk_coef(const SolveShape& sh, const RkaBlkGeom& geo, const RowRec* rec,
                            int64_t k0, int64_t K, int64_t check_every, double* coef,
-                           hipStream_t s);
+                           const DevStatus* st, hipStream_t s);
 // The chunk's iterations from those coefficients; part: G x nv, red: nv
 // tagged slots (zeroed once per solve).
 hipError_t launch_blk_iter(const SolveShape& sh, const RkaBlkGeom& geo, const RowRec* rec,
