@@ -34,11 +34,16 @@
  *     partial sums meet, and the kernels that run several RKA iterations per
  *     exchange end a block wherever a stopping test falls (every
  *     check_every iterations) or a chunk of iterations ends, so check_every
- *     and the block length move block ends.  Results of
+ *     and the block length move block ends (with tol > 0 the chunks of the
+ *     kernel with precomputed coefficients start at max(1024, 4 check_every)
+ *     iterations and double).  Results of
  *     different launches agree to rounding (for FP64 arithmetic within
  *     1e-12 relative of the plain iteration in every case tested).
  *   - Return value: an rka_status.  Arguments are validated before any
  *     work is enqueued; a violation returns RKA_EINVAL and touches nothing.
+ *     So is a shape that no kernel's register and LDS tiles hold: RKA with
+ *     long rows and many workers (FP64, n of about 16000 or more with
+ *     q > 88) returns RKA_EINVAL with a message naming n.
  *     No entry point throws, aborts or exits.  rka_status_string() names a
  *     status; rka_last_error() gives a thread-local message for the last
  *     failing call.
