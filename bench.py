@@ -901,8 +901,8 @@ def main():
             kk["bytes"] += info.projections * bytes_per_proj
             if st["kernel"] == 4 and st["coef_ms"] > 0:
                 # the coefficient pass streams every row of the chunk once
-                kc = kern.setdefault("blk_coef_kernel<double>", {"ms": 0.0, "launches": 0,
-                                                                 "bytes": 0.0})
+                cname = "blk_coef_rkab_kernel<double>" if c[0] == "rkab" else "blk_coef_kernel<double>"
+                kc = kern.setdefault(cname, {"ms": 0.0, "launches": 0, "bytes": 0.0})
                 kc["ms"] += st["coef_ms"]
                 kc["launches"] += st["iterate_launches"]
                 kc["bytes"] += info.projections * n * esz

@@ -187,11 +187,16 @@ typedef struct rka_opts {
                                forms each worker's projections in order: the same
                                iteration in exact arithmetic, kernel 3).  2 needs FP64
                                arithmetic and q <= 256, else kernel 2 runs.          */
-    int32_t rka_block;      /* RKA only, with several iterations per exchange: 0 = chosen
-                               by the library (kernel 4 when it fits: blocks of
-                               several iterations for q <= 64, of one iteration for
-                               64 < q <= 256; else kernel 3 for q <= 16, else the
-                               column-split kernel); 1 = the inner products between the
+    int32_t rka_block;      /* RKA with several iterations per exchange, and
+                               column-split RKAB: 0 = chosen by the library (kernel 4
+                               when it fits: for RKA blocks of several iterations
+                               for q <= 64, of one iteration for 64 < q <= 256, else
+                               kernel 3 for q <= 16, else the column-split kernel;
+                               for column-split RKAB one outer iteration per block
+                               when q bs <= 256 and bs <= 12 fit, with M_w = (I +
+                               N_w)^-1 per worker from its own rows, N_w[j][l] =
+                               alpha_j <a_j, a_l> / ||a_j||^2 for l < j, else kernel
+                               3); 1 = the inner products between the
                                block's rows travel in the exchange (kernel 3); 2 = a
                                streaming pass over the chunk's rows forms, per block,
                                M = (I + N)^-1 with N_{r,c} = alpha_r <a_r, a_c> /

@@ -284,9 +284,14 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   if (block && acc == 0 && split != 1 && (split == 2 || q * 4 <= ncu)) {
     // RKAB with every workgroup holding a slice of every worker's rows: asked
     // for, or chosen when the workers alone would leave most CUs idle and
-    // the outer iteration fits one exchange or q is small
+    // the outer iteration fits one exchange or q is small.  Where one outer
+    // iteration's q bs rows fit a block of kernel 4 (and rka_block is not 1),
+    // the workers' inner products come from its streaming pass and the
+    // exchange carries only the q bs dot products with x^(k); else kernel 3
+    // carries the inner products in the exchange.
+    if (rblk != 1) use_blk = rka::rka_blk_plan_rkab(sh, &kgeo);
     rka::RkaSstepGeom cand{};
-    if (rka::rka_sstep_plan(sh, 1, &cand) &&
+    if (!use_blk && rblk != 2 && rka::rka_sstep_plan(sh, 1, &cand) &&
         (split == 2 || cand.c == bs || q <= kAutoSubBlockMaxQ)) {
       sgeo = cand;
       use_sstep = true;

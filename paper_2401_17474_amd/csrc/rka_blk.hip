@@ -486,6 +486,106 @@ __global__ __launch_bounds__(kCThreads) void blk_coef_kernel(CoefArgs p) {
 }
 
 // ===========================================================================
+// Column-split RKAB, one block per outer iteration (Sec. 3.4.1).  Worker w
+// projects its bs rows in order starting from x^(k), so its scales satisfy
+// (I + N_w) s_w = c_w with c_j = alpha_j (b_j - <a_j, x^(k)>) / ||a_j||^2 and
+// N_w[j][l] = alpha_j <a_j, a_l> / ||a_j||^2 for l < j (the worker's own
+// earlier rows, weight 1), and x^(k+1) = x^(k) + (1/q) sum_w sum_j s_{w,j}
+// a_{w,j} is the average of the workers' iterates.  This pass forms
+// M_w = (I + N_w)^-1 for every (block, worker) task: one workgroup per task,
+// lanes over the columns with the bs (bs - 1) / 2 inner products in
+// registers, the workgroup's sums in wave order, then the forward
+// substitution on one lane.  Output per block: worker w's strictly lower
+// part at w bs (bs - 1) / 2, row j's j coefficients contiguous.
+// ===========================================================================
+constexpr int kRThreads = 256;
+
+struct CoefRkabArgs {
+  const void* A;
+  int64_t lda, nvec;
+  const RowRec* rec;  // K x q x bs records of the chunk
+  BlkLayout lay;
+  int32_t q;          // workers
+  int32_t cstride;    // doubles between blocks in coef
+  double* coef;
+  const DevStatus* st;  // a solve that has stopped needs no more coefficients
+};
+
+template <typename T, int V, int BS>
+__global__ __launch_bounds__(kRThreads) void blk_coef_rkab_kernel(CoefRkabArgs p) {
+  using raw_t = typename Vec<T, V>::raw_t;
+  constexpr int NP = BS * (BS - 1) / 2;
+  if (p.st->done) return;
+  const T* __restrict__ A = (const T*)p.A;
+  const int t = threadIdx.x, lane = t & (kWave - 1), wv = t / kWave;
+  __shared__ double RED[kRThreads / kWave][NP];
+  __shared__ double GR[NP];
+  __shared__ double FAC[BS];
+  __shared__ int64_t ROW[BS];
+  const int64_t ntask = (int64_t)p.lay.nblk * p.q;
+  for (int64_t task = blockIdx.x; task < ntask; task += gridDim.x) {
+    const int b = (int)(task / p.q), w = (int)(task - (int64_t)b * p.q);
+    int kl, L;
+    bool test;
+    p.lay.locate(b, &kl, &L, &test);
+    __syncthreads();  // the previous task's LDS reads are done
+    if (t < BS) {
+      const RowRec rc = p.rec[((int64_t)kl * p.q + w) * BS + t];
+      ROW[t] = rc.row;
+      FAC[t] = rc.alpha / rc.wn;
+    }
+    __syncthreads();
+    double acc[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) acc[i] = 0.0;
+    for (int64_t c = t; c < p.nvec; c += kRThreads) {
+      raw_t a[BS];
+#pragma unroll
+      for (int j = 0; j < BS; ++j) a[j] = load_raw<T, V>(A + ROW[j] * p.lda + c * V);
+#pragma unroll
+      for (int j = 1; j < BS; ++j) {
+#pragma unroll
+        for (int l = 0; l < j; ++l) {
+#pragma unroll
+          for (int e = 0; e < V; ++e)
+            acc[j * (j - 1) / 2 + l] =
+                fma(raw_elem<T, V>(a[j], e), raw_elem<T, V>(a[l], e), acc[j * (j - 1) / 2 + l]);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      const double v = wave_sum(acc[i]);
+      if (lane == 0) RED[wv][i] = v;
+    }
+    __syncthreads();
+    if (t < NP) {
+      double sum = 0.0;
+      for (int u = 0; u < kRThreads / kWave; ++u) sum += RED[u][t];
+      GR[t] = sum;
+    }
+    __syncthreads();
+    if (t == 0) {
+      // M[j][l] = -N[j][l] - sum_{tt = l+1}^{j-1} N[j][tt] M[tt][l], j ascending
+      double M[NP];
+      double* out = p.coef + (size_t)b * p.cstride + (size_t)w * NP;
+#pragma unroll
+      for (int j = 1; j < BS; ++j) {
+#pragma unroll
+        for (int l = 0; l < j; ++l) {
+          double sacc = FAC[j] * GR[j * (j - 1) / 2 + l];
+#pragma unroll
+          for (int tt = l + 1; tt < j; ++tt)
+            sacc = fma(FAC[j] * GR[j * (j - 1) / 2 + tt], M[tt * (tt - 1) / 2 + l], sacc);
+          M[j * (j - 1) / 2 + l] = -sacc;
+          out[j * (j - 1) / 2 + l] = -sacc;
+        }
+      }
+    }
+  }
+}
+
+// ===========================================================================
 // The iteration kernel.
 // ===========================================================================
 struct BlkArgs {
@@ -504,6 +604,8 @@ struct BlkArgs {
   int32_t tr;         // lanes per row for the slice sums of the dot products
   int32_t trp;        // lanes per value in the reduce-scatter
   int32_t trm;        // lanes per row of s = M c
+  int32_t rkab_bs;    // column-split RKAB: projections per worker (0: RKA)
+  int32_t ncoef_rkab; // column-split RKAB: coefficients per block, workers x bs (bs - 1) / 2
   uint64_t* part;     // nv_max x G tagged slots, value-major
   uint64_t* red;      // kSumCopies x nv_max tagged slots
   DevStatus* st;
@@ -681,7 +783,8 @@ __global__ __launch_bounds__(kBThreads) void rka_blk_kernel(BlkArgs p) {
     // after the barrier above, which would otherwise wait for them)
     {
       const double* Mg = p.coef + (size_t)b * p.cstride;
-      const int npieces = (q * q * (L * (L - 1) / 2) + 127) / 128;  // within cstride
+      const int ncur = p.rkab_bs ? p.ncoef_rkab : q * q * (L * (L - 1) / 2);
+      const int npieces = (ncur + 127) / 128;  // within cstride
       const int wv = t / kWave, lane = t & (kWave - 1);
       for (int i = wv; i < npieces; i += NT / kWave)
         __builtin_amdgcn_global_load_lds((const void*)(Mg + 128 * i + 2 * lane),
@@ -773,9 +876,23 @@ __global__ __launch_bounds__(kBThreads) void rka_blk_kernel(BlkArgs p) {
     double sr = 0.0;
     {
       const int TR = p.trm, r = t / TR, u = t & (TR - 1);
-      const int jr = r < R ? r / q : 0, rho = r - jr * q;
-      const double* mr = MC + blk_rowoff(q, jr, rho);
-      const int nterm = jr * q;
+      // row r's coefficients (contiguous in M) and the rows they multiply:
+      // RKA, row r = jr q + rho: the jr q rows of earlier iterations; RKAB,
+      // row r = w bs + j of worker w: the worker's j earlier rows
+      int rowoff, nterm, cbase;
+      if (p.rkab_bs) {
+        const int bs = p.rkab_bs, w = r < R ? r / bs : 0, j = r < R ? r - w * bs : 0;
+        rowoff = w * (bs * (bs - 1) / 2) + j * (j - 1) / 2;
+        nterm = j;
+        cbase = w * bs;
+      } else {
+        const int jr = r < R ? r / q : 0, rho = r - jr * q;
+        rowoff = blk_rowoff(q, jr, rho);
+        nterm = jr * q;
+        cbase = 0;
+      }
+      const double* mr = MC + rowoff;
+      const double* cc = CC + cbase;
       double a4[4] = {0.0, 0.0, 0.0, 0.0};
       int c = u;
       // eight terms' loads in flight before the first multiply-add
@@ -784,12 +901,12 @@ __global__ __launch_bounds__(kBThreads) void rka_blk_kernel(BlkArgs p) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
           mv[i] = mr[c + i * TR];
-          cv[i] = CC[c + i * TR];
+          cv[i] = cc[c + i * TR];
         }
 #pragma unroll
         for (int i = 0; i < 8; ++i) a4[i & 3] = fma(mv[i], cv[i], a4[i & 3]);
       }
-      for (; c < nterm; c += TR) a4[0] = fma(mr[c], CC[c], a4[0]);
+      for (; c < nterm; c += TR) a4[0] = fma(mr[c], cc[c], a4[0]);
       double acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
       acc = team_sum(acc, TR);
       if (r < R) sr = CC[r] + acc;
@@ -863,12 +980,14 @@ static int pow2_at_most(int v) {
   return r;
 }
 
-static size_t blk_lds_bytes(int q, int p, int nsvp, int V, int NT, int G) {
-  const int Rmax = q * p, nv = Rmax + 1;
-  const int cstride = (blk_ncoef(q, p) + 127) & ~127;
+static size_t blk_lds_bytes_c(int cstride, int Rmax, int nsvp, int V, int NT, int G) {
+  const int nv = Rmax + 1;
   size_t d = (size_t)cstride + nv + 4 * Rmax + (size_t)(NT / kWave) * nsvp * V + (size_t)nsvp * V +
              (size_t)G * ((nv + G - 1) / G);
   return d * sizeof(double);
+}
+static size_t blk_lds_bytes(int q, int p, int nsvp, int V, int NT, int G) {
+  return blk_lds_bytes_c((blk_ncoef(q, p) + 127) & ~127, q * p, nsvp, V, NT, G);
 }
 
 constexpr size_t kBMaxLds = 150 * 1024;
@@ -974,6 +1093,24 @@ bool rka_blk_plan(const SolveShape& sh, int p_req, RkaBlkGeom* geo) {
   return true;
 }
 
+bool rka_blk_plan_rkab(const SolveShape& sh, RkaBlkGeom* geo) {
+  const int q = sh.q, bs = sh.bs;
+  if (sh.acc != 0 || bs < 2 || bs > kRkabBlkMaxBs) return false;
+  // the block kernel with one outer iteration's q bs rows per block
+  SolveShape s1 = sh;
+  s1.q = q * bs;
+  s1.bs = 1;
+  if ((int64_t)q * bs > 2 * kBMaxRows || !rka_blk_plan(s1, 1, geo) || geo->p != 1) return false;
+  const int esz = sh.dtype == 0 ? 8 : (sh.dtype == 1 ? 4 : 2);
+  const int V = sh.vec_ok ? 16 / esz : 1;
+  geo->rkab_bs = bs;
+  geo->rkab_q = q;
+  geo->ncoef = q * (bs * (bs - 1) / 2);
+  geo->cstride = (geo->ncoef + 127) & ~127;
+  geo->lds = blk_lds_bytes_c(geo->cstride, q * bs, geo->nsvp, V, geo->nt, geo->G);
+  return geo->lds <= kBMaxLds;
+}
+
 int64_t rka_blk_nblk(const RkaBlkGeom& geo, int64_t k0, int64_t K, int64_t check_every) {
   return BlkLayout::make(k0, K, check_every, geo.p).nblk;
 }
@@ -1033,9 +1170,67 @@ static hipError_t launch_blk_rpt(const RkaBlkGeom& geo, BlkArgs& a, hipStream_t 
   }
 }
 
+template <typename T, int V, int BS>
+static hipError_t launch_coef_rkab_bs(CoefRkabArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((blk_coef_rkab_kernel<T, V, BS>), dim3(grid), dim3(kRThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T, int V>
+static hipError_t launch_coef_rkab_t(CoefRkabArgs& a, int bs, int grid, hipStream_t s) {
+  switch (bs) {
+    case 2: return launch_coef_rkab_bs<T, V, 2>(a, grid, s);
+    case 3: return launch_coef_rkab_bs<T, V, 3>(a, grid, s);
+    case 4: return launch_coef_rkab_bs<T, V, 4>(a, grid, s);
+    case 5: return launch_coef_rkab_bs<T, V, 5>(a, grid, s);
+    case 6: return launch_coef_rkab_bs<T, V, 6>(a, grid, s);
+    case 7: return launch_coef_rkab_bs<T, V, 7>(a, grid, s);
+    case 8: return launch_coef_rkab_bs<T, V, 8>(a, grid, s);
+    case 9: return launch_coef_rkab_bs<T, V, 9>(a, grid, s);
+    case 10: return launch_coef_rkab_bs<T, V, 10>(a, grid, s);
+    case 11: return launch_coef_rkab_bs<T, V, 11>(a, grid, s);
+    default: return launch_coef_rkab_bs<T, V, kRkabBlkMaxBs>(a, grid, s);
+  }
+}
+
+static hipError_t launch_blk_coef_rkab(const SolveShape& sh, const RkaBlkGeom& geo,
+                                       const RowRec* rec, int64_t k0, int64_t K,
+                                       int64_t check_every, double* coef, const DevStatus* st,
+                                       hipStream_t s) {
+  const BlkLayout lay = BlkLayout::make(k0, K, check_every, 1);
+  const int esz = sh.dtype == 0 ? 8 : (sh.dtype == 1 ? 4 : 2);
+  CoefRkabArgs a{};
+  a.A = sh.A;
+  a.lda = sh.lda;
+  a.nvec = sh.vec_ok ? sh.n / (16 / esz) : sh.n;
+  a.rec = rec;
+  a.lay = lay;
+  a.q = geo.rkab_q;
+  a.cstride = geo.cstride;
+  a.coef = coef;
+  a.st = st;
+  const int64_t ntask = lay.nblk * (int64_t)geo.rkab_q;
+  const int grid = (int)std::min<int64_t>(ntask, (int64_t)sh.num_cu * 8);
+  if (grid < 1) return hipSuccess;
+  const int bs = geo.rkab_bs;
+  switch (sh.dtype) {
+    case 0:
+      return sh.vec_ok ? launch_coef_rkab_t<double, 2>(a, bs, grid, s)
+                       : launch_coef_rkab_t<double, 1>(a, bs, grid, s);
+    case 1:
+      return sh.vec_ok ? launch_coef_rkab_t<float, 4>(a, bs, grid, s)
+                       : launch_coef_rkab_t<float, 1>(a, bs, grid, s);
+    default:
+      return sh.vec_ok ? launch_coef_rkab_t<bf16_t, 8>(a, bs, grid, s)
+                       : launch_coef_rkab_t<bf16_t, 1>(a, bs, grid, s);
+  }
+}
+
 hipError_t launch_blk_coef(const SolveShape& sh, const RkaBlkGeom& geo, const RowRec* rec,
                            int64_t k0, int64_t K, int64_t check_every, double* coef,
                            const DevStatus* st, hipStream_t s) {
+  if (geo.rkab_bs > 0)
+    return launch_blk_coef_rkab(sh, geo, rec, k0, K, check_every, coef, st, s);
   if (geo.p <= 1) return hipSuccess;  // one iteration per block: no coefficients
   const BlkLayout lay = BlkLayout::make(k0, K, check_every, geo.p);
   const int64_t nblk = lay.nblk;
@@ -1075,9 +1270,13 @@ hipError_t launch_blk_iter(const SolveShape& sh, const RkaBlkGeom& geo, const Ro
   a.coef = coef;
   a.x = sh.x;
   a.x_ref = sh.x_ref;
-  a.inv_q = 1.0 / (double)sh.q;
+  // column-split RKAB: a block is one outer iteration of q bs rows, and the
+  // update averages over the q workers
+  a.inv_q = 1.0 / (double)(geo.rkab_bs ? geo.rkab_q : sh.q);
   a.lay = lay;
-  a.q = sh.q;
+  a.q = geo.rkab_bs ? geo.rkab_q * geo.rkab_bs : sh.q;
+  a.rkab_bs = geo.rkab_bs;
+  a.ncoef_rkab = geo.rkab_bs ? geo.ncoef : 0;
   a.nsv = geo.nsv;
   a.nsvp = geo.nsvp;
   a.rg = geo.rg;

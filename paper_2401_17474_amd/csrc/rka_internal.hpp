@@ -134,9 +134,15 @@ struct RkaBlkGeom {
   int cbuf;              // its LDS-direct staging: bytes per chunk buffer
   size_t clds_dma;       // LDS bytes with LDS-direct staging (0: not possible)
   size_t clds;
+  int rkab_bs;           // column-split RKAB: projections per worker (0: RKA)
+  int rkab_q;            // column-split RKAB: workers
 };
 // p_req = 0: the largest p that fits (q p <= 128).  FP64 arithmetic, RKA only.
 bool rka_blk_plan(const SolveShape& sh, int p_req, RkaBlkGeom* geo);
+// Column-split RKAB in the same kernel, one outer iteration per block (q bs
+// rows, at most 256, and 2 <= bs <= kRkabBlkMaxBs); FP64 arithmetic.
+constexpr int kRkabBlkMaxBs = 12;
+bool rka_blk_plan_rkab(const SolveShape& sh, RkaBlkGeom* geo);
 // blocks of a chunk [k0, k0 + K) with stopping tests every check_every (0: none)
 int64_t rka_blk_nblk(const RkaBlkGeom& geo, int64_t k0, int64_t K, int64_t check_every);
 // The coefficient pass of a chunk (nothing for p = 1) into coef:

@@ -187,3 +187,94 @@ def test_blk_across_chunks():
     assert info.status == rka.OK and st["kernel"] == 4 and st["iterate_launches"] == 2, st
     xo, _ = oracle.rka(A, b, q=32, alpha=1.0, max_iter=45000, seed=8)
     assert_x_close(host(x), xo, what="blk two chunks")
+
+
+RKAB_CASES = [
+    # m, n, dtype, q, bs, K, grid
+    (2000, 1000, "f64", 16, 10, 8, 0),      # 160 rows per outer iteration
+    (3000, 2000, "f64", 8, 12, 6, 0),       # the longest worker block
+    (1500, 777, "f64", 6, 4, 10, 0),        # scalar path, ragged slice
+    (2500, 1024, "f64", 32, 2, 9, 0),
+    (1500, 4096, "f32", 16, 5, 6, 0),       # narrow storage, FP64 arithmetic
+    (1500, 640, "bf16", 16, 5, 6, 0),
+    (700, 48, "f64", 8, 4, 12, 2),          # two workgroups
+    (2000, 1000, "f64", 16, 3, 7, 100),     # more workgroups than exchange values
+]
+
+
+@pytest.mark.parametrize("m,n,dtype,q,bs,K,grid", RKAB_CASES)
+def test_blk_rkab_vs_oracle(m, n, dtype, q, bs, K, grid):
+    """Column-split RKAB in kernel 4: one outer iteration's q bs rows per block,
+    each worker's scales from M_w = (I + N_w)^-1 of its own rows (streaming
+    pass), x^(k+1) the average of the workers' iterates (Sec. 3.4.1): within
+    1e-12 of the oracle on the same row stream."""
+    say(f"blk rkab {dtype} {m}x{n} q={q} bs={bs} K={K} grid={grid}")
+    A, _, b = _system(m, n, dtype, seed=m + n + q + bs)
+    x, info, st = rka.solve_ex(to_dev(A, dtype), vec(b), method=1, q=q, block_size=bs,
+                               alpha=0.9, max_iter=K, seed=11, rkab_split=2, rka_block=2,
+                               grid=grid)
+    assert info.status == rka.OK and info.iterations == K and info.projections == K * q * bs
+    assert st["kernel"] == 4 and st["variant"] == 1, st
+    if grid:
+        assert st["grid"] <= grid
+    odt = _odt(dtype)
+    idx = oracle.indices(oracle.row_norms(A, dtype=odt), 11, 0, K, q, bs)
+    xo = oracle.rkab_given(A, b, np.zeros(n), idx, q=q, block_size=bs, alpha=0.9, dtype=odt)
+    assert_x_close(host(x), xo, what=f"blk rkab q={q} bs={bs}")
+
+
+def test_blk_rkab_stops_where_the_worker_kernel_stops():
+    say("blk rkab stop")
+    A, xs, _ = _system(4000, 300, seed=37, noise=0.0)
+    b = A @ xs
+    kw = dict(method=1, q=8, block_size=6, max_iter=20000, tol=1e-8, x_ref=vec(xs),
+              check_every=5, seed=3)
+    x1, i1, s1 = rka.solve_ex(to_dev(A), vec(b), rkab_split=1, **kw)
+    x4, i4, s4 = rka.solve_ex(to_dev(A), vec(b), rkab_split=2, rka_block=2, **kw)
+    assert s1["kernel"] == 2 and s4["kernel"] == 4
+    assert i1.status == i4.status == rka.OK
+    assert i4.iterations == i1.iterations and i4.iterations % 5 == 0
+    xo, _ = oracle.rkab(A, b, q=8, block_size=6, max_iter=i4.iterations, seed=3)
+    assert_x_close(host(x4), xo, what="blk rkab stopped iterate")
+
+
+@pytest.mark.parametrize("variant", ["cyclic", "worker_alpha", "row_weight"])
+def test_blk_rkab_row_orders_and_weights(variant):
+    say(f"blk rkab {variant}")
+    m, n, q, bs, K = 2400, 1000, 8, 5, 9
+    A, _, b = _system(m, n, seed=41)
+    Ad, bd = to_dev(A), vec(b)
+    w = oracle.row_norms(A)
+    kw = dict(method=1, q=q, block_size=bs, max_iter=K, seed=17, rkab_split=2, rka_block=2)
+    z = np.zeros(n)
+    if variant == "cyclic":
+        x, info, st = rka.solve_ex(Ad, bd, sampling=2, **kw)
+        xo = oracle.rkab_given(A, b, z, oracle.indices_cyclic(m, 0, K, q, bs), q=q, block_size=bs)
+    elif variant == "worker_alpha":
+        wa = np.linspace(0.6, 1.4, q)
+        x, info, st = rka.solve_ex(Ad, bd, worker_alpha=vec(wa), **kw)
+        xo = oracle.rkab_walpha_given(A, b, z, oracle.indices(w, 17, 0, K, q, bs), wa, q=q,
+                                      block_size=bs)
+    else:
+        wr = 0.5 + np.random.default_rng(5).random(m)
+        x, info, st = rka.solve_ex(Ad, bd, row_weight=vec(wr), **kw)
+        xo = oracle.rkab_wrow_given(A, b, z, oracle.indices(w, 17, 0, K, q, bs), wr, q=q,
+                                    block_size=bs)
+    assert info.status == rka.OK and st["kernel"] == 4
+    assert_x_close(host(x), xo, what=f"blk rkab {variant}")
+
+
+def test_library_chooses_blocks_for_column_split_rkab():
+    """Left to the library, RKAB with few workers whose outer iteration fits a
+    block (q bs <= 256, bs <= 12) runs kernel 4; longer worker blocks run
+    kernel 3; rka_block = 1 asks for kernel 3."""
+    say("blk rkab auto selection")
+    A, _, b = _system(2000, 1000, seed=43)
+    Ad, bd = to_dev(A), vec(b)
+    _, _, st = rka.solve_ex(Ad, bd, method=1, q=16, block_size=10, max_iter=4, seed=2)
+    assert st["kernel"] == 4, st
+    _, _, st = rka.solve_ex(Ad, bd, method=1, q=16, block_size=30, max_iter=2, seed=2)
+    assert st["kernel"] == 3, st
+    _, _, st = rka.solve_ex(Ad, bd, method=1, q=16, block_size=10, max_iter=4, seed=2,
+                            rka_block=1)
+    assert st["kernel"] == 3, st

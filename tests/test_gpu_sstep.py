@@ -127,7 +127,7 @@ def test_rkab_column_split_vs_oracle(m, n, q, bs, K, dtype, c):
     A, _, b = workloads.gaussian_system(m, n, seed=36, noise_var=1e-2, dtype=dtype)
     A = np.array(A)
     x, info, st = rka.solve_ex(to_dev(A, dtype), vec(b), method=1, q=q, block_size=bs,
-                               alpha=0.9, max_iter=K, seed=7, rkab_split=2)
+                               alpha=0.9, max_iter=K, seed=7, rkab_split=2, rka_block=1)
     assert info.status == rka.OK and info.iterations == K and info.projections == K * q * bs
     assert st["kernel"] == 3 and 1 <= st["variant"] <= bs
     if c is not None:
@@ -146,7 +146,7 @@ def test_rkab_column_split_stops_where_the_worker_kernel_stops():
     kw = dict(method=1, q=8, block_size=6, max_iter=20000, tol=1e-8, x_ref=vec(xs),
               check_every=5, seed=3)
     x1, i1, s1 = rka.solve_ex(to_dev(A), vec(b), rkab_split=1, **kw)
-    x2, i2, s2 = rka.solve_ex(to_dev(A), vec(b), rkab_split=2, **kw)
+    x2, i2, s2 = rka.solve_ex(to_dev(A), vec(b), rkab_split=2, rka_block=1, **kw)
     assert s1["kernel"] == 2 and s2["kernel"] == 3
     assert i1.status == rka.OK and i2.status == rka.OK
     assert i2.iterations == i1.iterations and i2.iterations % 5 == 0
