@@ -226,8 +226,9 @@ typedef struct rka_stats {
                                  thread (kernel 1) or 16-byte vecs per thread (kernel 2) */
     int32_t variant;          /* kernel 1: 1 = one-barrier all-gather of the partials;
                                  kernel 2: 1 = worker iterate kept in LDS;
-                                 kernel 3: RKA iterations per exchange (p), or RKAB
-                                 projections per worker per exchange (c)          */
+                                 kernels 3 and 4: RKA iterations per exchange (p), or
+                                 RKAB projections per worker per exchange (c; c < bs:
+                                 sub-blocks)                                      */
     int32_t accumulate;       /* accumulation type used: 0 = FP64, 1 = FP32             */
     double coef_ms;           /* kernel 4: the coefficient passes, summed over chunks
                                  (not in iterate_ms); 0 for the other kernels           */

@@ -352,7 +352,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
   auto coef_blocks = [&](int64_t kc) -> int64_t {
     int64_t nb = kc / kgeo.p + 2;
     if (in_kernel_check > 0) nb += kc / in_kernel_check + 1;
-    return nb;
+    return nb * (kgeo.rkab_bs ? kgeo.rkab_nsub : 1);  // RKAB: sub-blocks per outer iteration
   };
   if (use_blk) {
     nslots = (size_t)kgeo.G * kgeo.nv;
@@ -362,7 +362,8 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
     // (coef_blocks(kc) <= kCoefBudget / per_blk; p = 1 has no coefficients)
     if (kgeo.cstride > 0) {
       const int64_t per_blk = (int64_t)kgeo.cstride * 8;
-      const double room = (double)(kCoefBudget / per_blk - 3);
+      const double room =
+          (double)(kCoefBudget / per_blk / (kgeo.rkab_bs ? kgeo.rkab_nsub : 1) - 3);
       const double per_it =
           1.0 / kgeo.p + (in_kernel_check > 0 ? 1.0 / (double)in_kernel_check : 0.0);
       int64_t kcap = (int64_t)(room / per_it);
@@ -533,7 +534,7 @@ int solve_impl(bool block, const void* A, int dtype, int64_t m, int64_t n, int64
       stats->grid = kgeo.G;
       stats->threads = kgeo.nt;
       stats->bucket = kgeo.rpt;
-      stats->variant = kgeo.p;
+      stats->variant = kgeo.rkab_bs ? kgeo.rkab_c : kgeo.p;
     } else if (use_sstep) {
       stats->kernel = 3;
       stats->grid = sgeo.G;

@@ -504,8 +504,10 @@ struct CoefRkabArgs {
   const void* A;
   int64_t lda, nvec;
   const RowRec* rec;  // K x q x bs records of the chunk
-  BlkLayout lay;
+  BlkLayout lay;      // per outer iteration
   int32_t q;          // workers
+  int32_t bs;         // projections per worker per outer iteration
+  int32_t nsub;       // blocks per outer iteration (sub-blocks of BS projections, the last shorter)
   int32_t cstride;    // doubles between blocks in coef
   double* coef;
   const DevStatus* st;  // a solve that has stopped needs no more coefficients
@@ -522,15 +524,20 @@ __global__ __launch_bounds__(kRThreads) void blk_coef_rkab_kernel(CoefRkabArgs p
   __shared__ double GR[NP];
   __shared__ double FAC[BS];
   __shared__ int64_t ROW[BS];
-  const int64_t ntask = (int64_t)p.lay.nblk * p.q;
+  const int64_t ntask = (int64_t)p.lay.nblk * p.nsub * p.q;
   for (int64_t task = blockIdx.x; task < ntask; task += gridDim.x) {
     const int b = (int)(task / p.q), w = (int)(task - (int64_t)b * p.q);
+    const int bo = b / p.nsub, sb = b - bo * p.nsub;
+    const int cs = BS < p.bs - sb * BS ? BS : p.bs - sb * BS;  // this sub-block's steps
     int kl, L;
     bool test;
-    p.lay.locate(b, &kl, &L, &test);
+    p.lay.locate(bo, &kl, &L, &test);
     __syncthreads();  // the previous task's LDS reads are done
     if (t < BS) {
-      const RowRec rc = p.rec[((int64_t)kl * p.q + w) * BS + t];
+      // steps past a short last sub-block repeat its last row: their
+      // products are formed but their coefficients never read
+      const RowRec rc =
+          p.rec[((int64_t)kl * p.q + w) * p.bs + sb * BS + (t < cs ? t : cs - 1)];
       ROW[t] = rc.row;
       FAC[t] = rc.alpha / rc.wn;
     }
@@ -605,7 +612,9 @@ struct BlkArgs {
   int32_t trp;        // lanes per value in the reduce-scatter
   int32_t trm;        // lanes per row of s = M c
   int32_t rkab_bs;    // column-split RKAB: projections per worker (0: RKA)
-  int32_t ncoef_rkab; // column-split RKAB: coefficients per block, workers x bs (bs - 1) / 2
+  int32_t rkab_c;     // column-split RKAB: projections per worker per block (c <= bs)
+  int32_t nsub;       // column-split RKAB: blocks per outer iteration (1: RKA)
+  int32_t ncoef_rkab; // column-split RKAB: coefficients per block, workers x c (c - 1) / 2
   uint64_t* part;     // nv_max x G tagged slots, value-major
   uint64_t* red;      // kSumCopies x nv_max tagged slots
   DevStatus* st;
@@ -654,7 +663,11 @@ __device__ __forceinline__ bool blk_gather(const TagSlots& sl, int oob, int tota
   }
 }
 
-template <typename T, int V, int RPT>
+// MODE 0: RKA; 1: column-split RKAB, one block per outer iteration; 2:
+// column-split RKAB in sub-blocks (every worker's iterate kept for the slice).
+// Compile-time, so that each instance carries only its own paths (the RKA
+// instances measured 2-4 % slower with the RKAB branches taken at run time).
+template <typename T, int V, int RPT, int MODE>
 __global__ __launch_bounds__(kBThreads) void rka_blk_kernel(BlkArgs p) {
   using raw_t = typename Vec<T, V>::raw_t;
   if (p.st->done) return;
@@ -681,7 +694,12 @@ __global__ __launch_bounds__(kBThreads) void rka_blk_kernel(BlkArgs p) {
   double* U = RA + Rmax;                  // (NT / 64) * NSVP * V  update sums per wave
   double* XS = U + (size_t)(NT / kWave) * NSVP * V;  // NSVP * V  new slice of x
   double* PG = XS + (size_t)NSVP * V;     // G * ceil(nv_max / G)  gathered partials
+  // column-split RKAB in several blocks per outer iteration: every worker's
+  // iterate for the slice, and the row groups' update sums
+  double* VW = PG + (size_t)G * ((p.nv_max + G - 1) / G);  // q * NSVP * V
+  double* UW = VW + (size_t)q * NSVP * V;                   // NT * V
   const int nwaves = NT / kWave;
+  const int nsub = MODE == 2 ? p.nsub : 1;
 
   double xv[V];
 #pragma unroll
@@ -690,32 +708,70 @@ __global__ __launch_bounds__(kBThreads) void rka_blk_kernel(BlkArgs p) {
 #pragma unroll
     for (int e = 0; e < V; ++e) XS[t * V + e] = xv[e];
   }
+  if constexpr (MODE == 2) {  // every worker starts the outer iteration from x
+    __syncthreads();
+    for (int i = t; i < q * NSVP * V; i += NT) VW[i] = XS[i % (NSVP * V)];
+  }
+
+  // Block b of the chunk: its first chunk-local iteration kl, its length L
+  // (iterations; for RKAB the steps of each worker), a test at its start,
+  // and its sub-block sb.  RKAB: blocks are the nsub sub-blocks of each
+  // outer iteration.  With one block per outer iteration its rows are
+  // worker-major (row r = w L + jj), as the records lie; with sub-blocks
+  // step-major (row r = jj q + w: worker w's step sb c + jj), so that with
+  // q dividing the row groups every row a thread holds belongs to worker
+  // rgi mod q (the records then lie bs apart: step-major cost 1.5 us per
+  // outer iteration at q = 16, bs = 10, where no sub-blocks need it).
+  auto locate = [&](int bb, int* kl_, int* L_, bool* test_, int* sb_) {
+    if constexpr (MODE != 0) {
+      const int bo = bb / nsub, sb2 = bb - bo * nsub;
+      int L1;
+      p.lay.locate(bo, kl_, &L1, test_);
+      *test_ = *test_ && sb2 == 0;
+      *sb_ = sb2;
+      *L_ = p.rkab_c < p.rkab_bs - sb2 * p.rkab_c ? p.rkab_c : p.rkab_bs - sb2 * p.rkab_c;
+    } else {
+      p.lay.locate(bb, kl_, L_, test_);
+      *sb_ = 0;
+    }
+  };
+  // the record of row r of a block
+  auto recidx = [&](int kl_, int sb_, int r) -> int64_t {
+    if constexpr (MODE == 2) {
+      const int jj = r / q, w = r - jj * q;
+      return ((int64_t)kl_ * q + w) * p.rkab_bs + sb_ * p.rkab_c + jj;
+    } else if constexpr (MODE == 1) {
+      return (int64_t)kl_ * q * p.rkab_bs + r;
+    } else {
+      return (int64_t)kl_ * q + r;
+    }
+  };
 
   const TagSlots part(p.part, (int64_t)G * p.nv_max);
   const TagSlots red(p.red, (int64_t)kSumCopies * p.nv_max);
 
-  auto load_rows = [&](int kl2, int L2, int* rows) {
+  auto load_rows = [&](int kl2, int L2, int sb2, int* rows) {
     const int R2 = L2 * q;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int br = rgi + rg * i;
-      rows[i] = (int)p.rec[(int64_t)kl2 * q + (br < R2 ? br : R2 - 1)].row;
+      rows[i] = (int)p.rec[recidx(kl2, sb2, br < R2 ? br : R2 - 1)].row;
     }
   };
   raw_t a[RPT], an[RPT];
   int rows_n[RPT];
   double mb = 0.0, mw = 1.0, ma = 0.0;  // record of block row t
-  int b = 0, kl = 0, L = 1;
+  int b = 0, kl = 0, L = 1, sb = 0;
   bool check = false;
-  p.lay.locate(0, &kl, &L, &check);
-  const int nblk = p.lay.nblk;
+  locate(0, &kl, &L, &check, &sb);
+  const int nblk = p.lay.nblk * nsub;
   {
     int rows0[RPT];
-    load_rows(kl, L, rows0);
+    load_rows(kl, L, sb, rows0);
 #pragma unroll
     for (int i = 0; i < RPT; ++i) a[i] = load_raw<T, V>(A + (int64_t)rows0[i] * p.lda + cvl * V);
     if (t < L * q) {
-      const RowRec r = p.rec[(int64_t)kl * q + t];
+      const RowRec r = p.rec[recidx(kl, sb, t)];
       mb = r.b;
       mw = r.wn;
       ma = r.alpha;
@@ -723,10 +779,10 @@ __global__ __launch_bounds__(kBThreads) void rka_blk_kernel(BlkArgs p) {
 #pragma unroll
     for (int i = 0; i < RPT; ++i) rows_n[i] = rows0[i];
     if (nblk > 1) {
-      int kl1, L1;
+      int kl1, L1, sb1;
       bool t1;
-      p.lay.locate(1, &kl1, &L1, &t1);
-      load_rows(kl1, L1, rows_n);
+      locate(1, &kl1, &L1, &t1, &sb1);
+      load_rows(kl1, L1, sb1, rows_n);
     }
   }
 
@@ -735,7 +791,7 @@ __global__ __launch_bounds__(kBThreads) void rka_blk_kernel(BlkArgs p) {
   while (b < nblk) {
     const int64_t k = p.lay.k0 + kl;
     const int R = L * q, nv = R + 1;
-    const uint32_t tag = (uint32_t)(k + 1);
+    const uint32_t tag = (uint32_t)(k * nsub + sb + 1);  // one per exchange
     if (t < R) {
       RB[t] = mb;
       RW[t] = mw;
@@ -783,7 +839,7 @@ __global__ __launch_bounds__(kBThreads) void rka_blk_kernel(BlkArgs p) {
     // after the barrier above, which would otherwise wait for them)
     {
       const double* Mg = p.coef + (size_t)b * p.cstride;
-      const int ncur = p.rkab_bs ? p.ncoef_rkab : q * q * (L * (L - 1) / 2);
+      const int ncur = MODE != 0 ? p.ncoef_rkab : q * q * (L * (L - 1) / 2);
       const int npieces = (ncur + 127) / 128;  // within cstride
       const int wv = t / kWave, lane = t & (kWave - 1);
       for (int i = wv; i < npieces; i += NT / kWave)
@@ -820,22 +876,23 @@ __global__ __launch_bounds__(kBThreads) void rka_blk_kernel(BlkArgs p) {
     // cycles); 1.96 with half the rows issued before the partial sums and
     // half here; 2.15 with the issue after the exchange.  Their addresses
     // use the row indices loaded one block earlier.
-    int kn = kl, Ln = L;
+    int kn = kl, Ln = L, sbn = sb;
     bool checkn = false;
-    if (b + 1 < nblk) p.lay.locate(b + 1, &kn, &Ln, &checkn);
+    if (b + 1 < nblk) locate(b + 1, &kn, &Ln, &checkn, &sbn);
 #pragma unroll
     for (int i = 0; i < RPT; ++i) an[i] = load_raw<T, V>(A + (int64_t)rows_n[i] * p.lda + cvl * V);
     if (b + 1 < nblk && t < Ln * q) {
-      const RowRec r = p.rec[(int64_t)kn * q + t];
+      const RowRec r = p.rec[recidx(kn, sbn, t)];
       mb = r.b;
       mw = r.wn;
       ma = r.alpha;
     }
     if (b + 2 < nblk) {
       int kn2, Ln2;
+      int sb2;
       bool t2;
-      p.lay.locate(b + 2, &kn2, &Ln2, &t2);
-      load_rows(kn2, Ln2, rows_n);
+      locate(b + 2, &kn2, &Ln2, &t2, &sb2);
+      load_rows(kn2, Ln2, sb2, rows_n);
     }
     // phase 2: every workgroup reads all nv sums (from its copy)
     if (__syncthreads_and(ok)) {
@@ -876,19 +933,29 @@ __global__ __launch_bounds__(kBThreads) void rka_blk_kernel(BlkArgs p) {
     double sr = 0.0;
     {
       const int TR = p.trm, r = t / TR, u = t & (TR - 1);
-      // row r's coefficients (contiguous in M) and the rows they multiply:
-      // RKA, row r = jr q + rho: the jr q rows of earlier iterations; RKAB,
-      // row r = w bs + j of worker w: the worker's j earlier rows
-      int rowoff, nterm, cbase;
-      if (p.rkab_bs) {
-        const int bs = p.rkab_bs, w = r < R ? r / bs : 0, j = r < R ? r - w * bs : 0;
-        rowoff = w * (bs * (bs - 1) / 2) + j * (j - 1) / 2;
-        nterm = j;
-        cbase = w * bs;
+      // row r = jr q + rho's coefficients (contiguous in M) and the rows they
+      // multiply: RKA, the jr q rows of earlier iterations; RKAB, worker
+      // rho's jr earlier steps of the block, rows l q + rho (M_rho packed at
+      // rho c (c - 1) / 2)
+      // (one RKAB block per outer iteration: row r = w L + jj, the worker's
+      // earlier steps contiguous)
+      const int jr = r < R ? r / q : 0, rho = r - jr * q;
+      int rowoff, nterm, cstep, cbase;
+      if constexpr (MODE == 2) {
+        rowoff = rho * (p.rkab_c * (p.rkab_c - 1) / 2) + jr * (jr - 1) / 2;
+        nterm = jr;
+        cstep = q;
+        cbase = rho;
+      } else if constexpr (MODE == 1) {
+        const int w = r < R ? r / L : 0, jj = r < R ? r - w * L : 0;
+        rowoff = w * (p.rkab_c * (p.rkab_c - 1) / 2) + jj * (jj - 1) / 2;
+        nterm = jj;
+        cstep = 1;
+        cbase = w * L;
       } else {
-        const int jr = r < R ? r / q : 0, rho = r - jr * q;
         rowoff = blk_rowoff(q, jr, rho);
         nterm = jr * q;
+        cstep = 1;
         cbase = 0;
       }
       const double* mr = MC + rowoff;
@@ -901,12 +968,12 @@ __global__ __launch_bounds__(kBThreads) void rka_blk_kernel(BlkArgs p) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
           mv[i] = mr[c + i * TR];
-          cv[i] = cc[c + i * TR];
+          cv[i] = cc[(c + i * TR) * cstep];
         }
 #pragma unroll
         for (int i = 0; i < 8; ++i) a4[i & 3] = fma(mv[i], cv[i], a4[i & 3]);
       }
-      for (; c < nterm; c += TR) a4[0] = fma(mr[c], cc[c], a4[0]);
+      for (; c < nterm; c += TR) a4[0] = fma(mr[c], cc[c * cstep], a4[0]);
       double acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
       acc = team_sum(acc, TR);
       if (r < R) sr = CC[r] + acc;
@@ -928,31 +995,64 @@ __global__ __launch_bounds__(kBThreads) void rka_blk_kernel(BlkArgs p) {
 #pragma unroll
       for (int e = 0; e < V; ++e) uu[e] = fma(s, raw_elem<T, V>(a[i], e), uu[e]);
     }
-    for (int off = NSVP; off < kWave; off *= 2) {
+    if constexpr (MODE == 2) {
+      // RKAB in sub-blocks: every row of this thread is worker rgi mod q's,
+      // whose iterate takes the sum with weight 1; the row groups of a
+      // worker add in order, and the last sub-block of an outer iteration
+      // forms x^(k+1) = (1/q) sum_w v_w, from which every worker restarts
+      const int SW = NSVP * V;
 #pragma unroll
-      for (int e = 0; e < V; ++e) uu[e] += __shfl_xor(uu[e], off, kWave);
-    }
-    if ((t & (kWave - 1)) < NSVP) {
+      for (int e = 0; e < V; ++e) UW[rgi * SW + j * V + e] = uu[e];
+      __syncthreads();
+      for (int i = t; i < q * SW; i += NT) {
+        const int w = i / SW, rest = i - w * SW;
+        double acc = 0.0;
+        for (int gi = w; gi < rg; gi += q) acc += UW[gi * SW + rest];
+        VW[i] += acc;
+      }
+      __syncthreads();
+      if (sb == nsub - 1) {
+        if (t < SW) {
+          double acc = 0.0;
+          for (int w = 0; w < q; ++w) acc += VW[w * SW + t];
+          XS[t] = acc * p.inv_q;
+        }
+        __syncthreads();
+        for (int i = t; i < q * SW; i += NT) VW[i] = XS[i % SW];
+        __syncthreads();
+      }
+      if (colv) {
 #pragma unroll
-      for (int e = 0; e < V; ++e) U[((t / kWave) * NSVP + j) * V + e] = uu[e];
-    }
-    __syncthreads();
-    if (t < NSVP * V) {
-      const int jj = t / V, e = t - jj * V;
-      double acc = 0.0;
-      for (int w = 0; w < nwaves; ++w) acc += U[(w * NSVP + jj) * V + e];
-      XS[t] = fma(acc, p.inv_q, XS[t]);
-    }
-    __syncthreads();
-    if (colv) {
+        for (int e = 0; e < V; ++e) xv[e] = VW[(rgi % q) * SW + j * V + e];
+      }
+    } else {
+      for (int off = NSVP; off < kWave; off *= 2) {
 #pragma unroll
-      for (int e = 0; e < V; ++e) xv[e] = XS[j * V + e];
+        for (int e = 0; e < V; ++e) uu[e] += __shfl_xor(uu[e], off, kWave);
+      }
+      if ((t & (kWave - 1)) < NSVP) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) U[((t / kWave) * NSVP + j) * V + e] = uu[e];
+      }
+      __syncthreads();
+      if (t < NSVP * V) {
+        const int jj = t / V, e = t - jj * V;
+        double acc = 0.0;
+        for (int w = 0; w < nwaves; ++w) acc += U[(w * NSVP + jj) * V + e];
+        XS[t] = fma(acc, p.inv_q, XS[t]);
+      }
+      __syncthreads();
+      if (colv) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) xv[e] = XS[j * V + e];
+      }
     }
 #pragma unroll
     for (int i = 0; i < RPT; ++i) a[i] = an[i];
     ++b;
     kl = kn;
     L = Ln;
+    sb = sbn;
     check = checkn;
     BPROF(5);
   }
@@ -1094,21 +1194,74 @@ bool rka_blk_plan(const SolveShape& sh, int p_req, RkaBlkGeom* geo) {
 }
 
 bool rka_blk_plan_rkab(const SolveShape& sh, RkaBlkGeom* geo) {
-  const int q = sh.q, bs = sh.bs;
-  if (sh.acc != 0 || bs < 2 || bs > kRkabBlkMaxBs) return false;
-  // the block kernel with one outer iteration's q bs rows per block
-  SolveShape s1 = sh;
-  s1.q = q * bs;
-  s1.bs = 1;
-  if ((int64_t)q * bs > 2 * kBMaxRows || !rka_blk_plan(s1, 1, geo) || geo->p != 1) return false;
+  const int qw = sh.q, bs = sh.bs;
+  if (sh.acc != 0 || bs < 2) return false;
   const int esz = sh.dtype == 0 ? 8 : (sh.dtype == 1 ? 4 : 2);
   const int V = sh.vec_ok ? 16 / esz : 1;
+  const int64_t nvec = sh.vec_ok ? sh.n / V : sh.n;
+  const int target = sh.grid > 0 ? sh.grid : sh.num_cu;
+  int64_t nsv = (nvec + target - 1) / target;
+  if (nsv < 1) nsv = 1;
+  if (nsv > kWave) return false;
+  const int G = (int)((nvec + nsv - 1) / nsv);
+  if (G < 2) return false;
+  const int NT = kBThreads;
+  int nsvp = 1;
+  while (nsvp < nsv) nsvp *= 2;
+  const int rg = NT / nsvp;
+  const int rpt_cap = V == 1 ? kBMaxRPT : (sh.dtype == 0 ? kBMaxRPT : (sh.dtype == 1 ? 6 : 4));
+  // c steps per worker per block: the whole outer iteration if its q bs rows
+  // fit, else nsub sub-blocks of at most c (then every row group must serve
+  // one worker: q divides the row groups)
+  auto lds_of = [&](int c, int nsub) {
+    const int cstride = ((qw * (c * (c - 1) / 2)) + 127) & ~127;
+    size_t l = blk_lds_bytes_c(cstride, qw * c, nsvp, V, NT, G);
+    if (nsub > 1) l += ((size_t)qw * nsvp * V + (size_t)NT * V) * sizeof(double);
+    return l;
+  };
+  auto fits = [&](int c, int nsub) {
+    const int R = qw * c;
+    if (R > 2 * kBMaxRows || (R + rg - 1) / rg > rpt_cap) return false;
+    if (R + 1 > kBPoll * NT || (int64_t)G * ((R + 1 + G - 1) / G) > (int64_t)kBPoll * NT) return false;
+    if (nsub > 1 && rg % qw != 0) return false;
+    return lds_of(c, nsub) <= kBMaxLds;
+  };
+  int c = std::min(bs, kRkabBlkMaxBs);
+  for (; c >= 2; --c)
+    if (fits(c, (bs + c - 1) / c)) break;
+  if (c < 2) return false;
+  const int nsub = (bs + c - 1) / c;
+  c = (bs + nsub - 1) / nsub;  // balanced sub-blocks (no longer than before: still fits)
+  const int R = qw * c;
+  int rpt = (R + rg - 1) / rg;
+  const int buckets[] = {1, 2, 3, 4, 6, 8, 11};
+  for (int bk : buckets)
+    if (rpt <= bk) {
+      rpt = bk;
+      break;
+    }
+  geo->G = G;
+  geo->nsv = (int)nsv;
+  geo->nsvp = nsvp;
+  geo->rg = rg;
+  geo->nt = NT;
+  geo->rpt = rpt;
+  geo->p = 1;  // blocks are laid out per outer iteration, nsub of them each
+  geo->nv = R + 1;
+  geo->tr = 1;
+  {
+    const int C = (R + 1 + G - 1) / G;
+    geo->trp = pow2_at_most(std::max(1, std::min(64, NT / C)));
+  }
+  geo->trm = pow2_at_most(std::max(1, std::min(64, NT / R)));
   geo->rkab_bs = bs;
-  geo->rkab_q = q;
-  geo->ncoef = q * (bs * (bs - 1) / 2);
+  geo->rkab_q = qw;
+  geo->rkab_c = c;
+  geo->rkab_nsub = nsub;
+  geo->ncoef = qw * (c * (c - 1) / 2);
   geo->cstride = (geo->ncoef + 127) & ~127;
-  geo->lds = blk_lds_bytes_c(geo->cstride, q * bs, geo->nsvp, V, geo->nt, geo->G);
-  return geo->lds <= kBMaxLds;
+  geo->lds = lds_of(c, nsub);
+  return true;
 }
 
 int64_t rka_blk_nblk(const RkaBlkGeom& geo, int64_t k0, int64_t K, int64_t check_every) {
@@ -1146,9 +1299,9 @@ static hipError_t launch_coef_t(const RkaBlkGeom& geo, CoefArgs& a, int grid, bo
                                  : launch_coef_d<T, false>(geo, a, grid, s);
 }
 
-template <typename T, int V, int RPT>
+template <typename T, int V, int RPT, int MODE>
 static hipError_t launch_blk_t(const RkaBlkGeom& geo, BlkArgs& a, hipStream_t s) {
-  const void* fn = (const void*)rka_blk_kernel<T, V, RPT>;
+  const void* fn = (const void*)rka_blk_kernel<T, V, RPT, MODE>;
   if (geo.lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)geo.lds);
     if (e != hipSuccess) return e;
@@ -1157,17 +1310,24 @@ static hipError_t launch_blk_t(const RkaBlkGeom& geo, BlkArgs& a, hipStream_t s)
   return launch_persistent(fn, dim3(geo.G), dim3(geo.nt), args, (unsigned)geo.lds, s);
 }
 
+template <typename T, int V, int MODE>
+static hipError_t launch_blk_rpt_s(const RkaBlkGeom& geo, BlkArgs& a, hipStream_t s) {
+  switch (geo.rpt) {
+    case 1: return launch_blk_t<T, V, 1, MODE>(geo, a, s);
+    case 2: return launch_blk_t<T, V, 2, MODE>(geo, a, s);
+    case 3: return launch_blk_t<T, V, 3, MODE>(geo, a, s);
+    case 4: return launch_blk_t<T, V, 4, MODE>(geo, a, s);
+    case 6: return launch_blk_t<T, V, 6, MODE>(geo, a, s);
+    case 8: return launch_blk_t<T, V, 8, MODE>(geo, a, s);
+    default: return launch_blk_t<T, V, 11, MODE>(geo, a, s);
+  }
+}
+
 template <typename T, int V>
 static hipError_t launch_blk_rpt(const RkaBlkGeom& geo, BlkArgs& a, hipStream_t s) {
-  switch (geo.rpt) {
-    case 1: return launch_blk_t<T, V, 1>(geo, a, s);
-    case 2: return launch_blk_t<T, V, 2>(geo, a, s);
-    case 3: return launch_blk_t<T, V, 3>(geo, a, s);
-    case 4: return launch_blk_t<T, V, 4>(geo, a, s);
-    case 6: return launch_blk_t<T, V, 6>(geo, a, s);
-    case 8: return launch_blk_t<T, V, 8>(geo, a, s);
-    default: return launch_blk_t<T, V, 11>(geo, a, s);
-  }
+  if (!geo.rkab_bs) return launch_blk_rpt_s<T, V, 0>(geo, a, s);
+  return geo.rkab_nsub > 1 ? launch_blk_rpt_s<T, V, 2>(geo, a, s)
+                           : launch_blk_rpt_s<T, V, 1>(geo, a, s);
 }
 
 template <typename T, int V, int BS>
@@ -1206,13 +1366,15 @@ static hipError_t launch_blk_coef_rkab(const SolveShape& sh, const RkaBlkGeom& g
   a.rec = rec;
   a.lay = lay;
   a.q = geo.rkab_q;
+  a.bs = geo.rkab_bs;
+  a.nsub = geo.rkab_nsub;
   a.cstride = geo.cstride;
   a.coef = coef;
   a.st = st;
-  const int64_t ntask = lay.nblk * (int64_t)geo.rkab_q;
+  const int64_t ntask = lay.nblk * (int64_t)geo.rkab_nsub * geo.rkab_q;
   const int grid = (int)std::min<int64_t>(ntask, (int64_t)sh.num_cu * 8);
   if (grid < 1) return hipSuccess;
-  const int bs = geo.rkab_bs;
+  const int bs = geo.rkab_c;
   switch (sh.dtype) {
     case 0:
       return sh.vec_ok ? launch_coef_rkab_t<double, 2>(a, bs, grid, s)
@@ -1274,8 +1436,10 @@ hipError_t launch_blk_iter(const SolveShape& sh, const RkaBlkGeom& geo, const Ro
   // update averages over the q workers
   a.inv_q = 1.0 / (double)(geo.rkab_bs ? geo.rkab_q : sh.q);
   a.lay = lay;
-  a.q = geo.rkab_bs ? geo.rkab_q * geo.rkab_bs : sh.q;
+  a.q = geo.rkab_bs ? geo.rkab_q : sh.q;  // RKAB: rows step-major, q workers per step
   a.rkab_bs = geo.rkab_bs;
+  a.rkab_c = geo.rkab_c;
+  a.nsub = geo.rkab_bs ? geo.rkab_nsub : 1;
   a.ncoef_rkab = geo.rkab_bs ? geo.ncoef : 0;
   a.nsv = geo.nsv;
   a.nsvp = geo.nsvp;

@@ -136,11 +136,15 @@ struct RkaBlkGeom {
   size_t clds;
   int rkab_bs;           // column-split RKAB: projections per worker (0: RKA)
   int rkab_q;            // column-split RKAB: workers
+  int rkab_c;            // column-split RKAB: projections per worker per block
+  int rkab_nsub;         // column-split RKAB: blocks per outer iteration
 };
 // p_req = 0: the largest p that fits (q p <= 128).  FP64 arithmetic, RKA only.
 bool rka_blk_plan(const SolveShape& sh, int p_req, RkaBlkGeom* geo);
-// Column-split RKAB in the same kernel, one outer iteration per block (q bs
-// rows, at most 256, and 2 <= bs <= kRkabBlkMaxBs); FP64 arithmetic.
+// Column-split RKAB in the same kernel: one outer iteration per block where
+// its q bs rows fit (at most 256, bs <= kRkabBlkMaxBs), else sub-blocks of
+// c <= kRkabBlkMaxBs steps per worker (q dividing the row groups); FP64
+// arithmetic.
 constexpr int kRkabBlkMaxBs = 12;
 bool rka_blk_plan_rkab(const SolveShape& sh, RkaBlkGeom* geo);
 // blocks of a chunk [k0, k0 + K) with stopping tests every check_every (0: none)

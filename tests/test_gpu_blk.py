@@ -199,22 +199,31 @@ RKAB_CASES = [
     (1500, 640, "bf16", 16, 5, 6, 0),
     (700, 48, "f64", 8, 4, 12, 2),          # two workgroups
     (2000, 1000, "f64", 16, 3, 7, 100),     # more workgroups than exchange values
+    # sub-blocks of c steps per worker, every worker's iterate kept per slice
+    (3000, 2000, "f64", 16, 40, 3, 0),      # 4 sub-blocks of 10
+    (2000, 1200, "f64", 4, 150, 2, 0),      # 13 sub-blocks, the last shorter
+    (1500, 777, "f64", 8, 30, 4, 0),        # scalar path
+    (1500, 640, "bf16", 8, 25, 3, 0),
+    (1500, 4096, "f32", 16, 13, 3, 0),      # two sub-blocks, 7 and 6
 ]
 
 
 @pytest.mark.parametrize("m,n,dtype,q,bs,K,grid", RKAB_CASES)
 def test_blk_rkab_vs_oracle(m, n, dtype, q, bs, K, grid):
-    """Column-split RKAB in kernel 4: one outer iteration's q bs rows per block,
-    each worker's scales from M_w = (I + N_w)^-1 of its own rows (streaming
-    pass), x^(k+1) the average of the workers' iterates (Sec. 3.4.1): within
-    1e-12 of the oracle on the same row stream."""
+    """Column-split RKAB in kernel 4: one outer iteration's q bs rows per block
+    (or sub-blocks of c steps per worker, each worker's iterate kept for the
+    slice), each worker's scales from M_w = (I + N_w)^-1 of its own rows
+    (streaming pass), x^(k+1) the average of the workers' iterates (Sec.
+    3.4.1): within 1e-12 of the oracle on the same row stream."""
     say(f"blk rkab {dtype} {m}x{n} q={q} bs={bs} K={K} grid={grid}")
     A, _, b = _system(m, n, dtype, seed=m + n + q + bs)
     x, info, st = rka.solve_ex(to_dev(A, dtype), vec(b), method=1, q=q, block_size=bs,
                                alpha=0.9, max_iter=K, seed=11, rkab_split=2, rka_block=2,
                                grid=grid)
     assert info.status == rka.OK and info.iterations == K and info.projections == K * q * bs
-    assert st["kernel"] == 4 and st["variant"] == 1, st
+    assert st["kernel"] == 4 and 2 <= st["variant"] <= min(bs, 12), st
+    if q * bs <= 256 and bs <= 12:  # one block per outer iteration where it fits
+        assert st["variant"] == bs, st
     if grid:
         assert st["grid"] <= grid
     odt = _odt(dtype)
@@ -236,6 +245,17 @@ def test_blk_rkab_stops_where_the_worker_kernel_stops():
     assert i4.iterations == i1.iterations and i4.iterations % 5 == 0
     xo, _ = oracle.rkab(A, b, q=8, block_size=6, max_iter=i4.iterations, seed=3)
     assert_x_close(host(x4), xo, what="blk rkab stopped iterate")
+    # sub-blocks: tests fall at outer iterations only
+    A, xs, _ = _system(3000, 400, seed=40, noise=0.0)
+    b = A @ xs
+    kw = dict(method=1, q=4, block_size=90, max_iter=5000, tol=1e-9, x_ref=vec(xs),
+              check_every=2, seed=5)
+    x1, i1, s1 = rka.solve_ex(to_dev(A), vec(b), rkab_split=1, **kw)
+    x4, i4, s4 = rka.solve_ex(to_dev(A), vec(b), rkab_split=2, rka_block=2, **kw)
+    assert s1["kernel"] == 2 and s4["kernel"] == 4
+    assert i1.status == i4.status == rka.OK and i4.iterations == i1.iterations
+    xo, _ = oracle.rkab(A, b, q=4, block_size=90, max_iter=i4.iterations, seed=5)
+    assert_x_close(host(x4), xo, what="blk rkab sub-blocks stopped iterate")
 
 
 @pytest.mark.parametrize("variant", ["cyclic", "worker_alpha", "row_weight"])
@@ -265,15 +285,18 @@ def test_blk_rkab_row_orders_and_weights(variant):
 
 
 def test_library_chooses_blocks_for_column_split_rkab():
-    """Left to the library, RKAB with few workers whose outer iteration fits a
-    block (q bs <= 256, bs <= 12) runs kernel 4; longer worker blocks run
-    kernel 3; rka_block = 1 asks for kernel 3."""
+    """Left to the library, column-split RKAB runs kernel 4: one block per
+    outer iteration where q bs <= 256 and bs <= 12 fit, else sub-blocks where
+    q divides the row groups; otherwise kernel 3 (q = 12 here); rka_block = 1
+    asks for kernel 3."""
     say("blk rkab auto selection")
     A, _, b = _system(2000, 1000, seed=43)
     Ad, bd = to_dev(A), vec(b)
     _, _, st = rka.solve_ex(Ad, bd, method=1, q=16, block_size=10, max_iter=4, seed=2)
     assert st["kernel"] == 4, st
     _, _, st = rka.solve_ex(Ad, bd, method=1, q=16, block_size=30, max_iter=2, seed=2)
+    assert st["kernel"] == 4, st
+    _, _, st = rka.solve_ex(Ad, bd, method=1, q=12, block_size=30, max_iter=2, seed=2)
     assert st["kernel"] == 3, st
     _, _, st = rka.solve_ex(Ad, bd, method=1, q=16, block_size=10, max_iter=4, seed=2,
                             rka_block=1)

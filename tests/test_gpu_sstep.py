@@ -159,7 +159,7 @@ def test_rkab_sub_blocks_stop_where_the_worker_kernel_stops():
     kw = dict(method=1, q=4, block_size=90, max_iter=5000, tol=1e-9, x_ref=vec(xs),
               check_every=2, seed=5)
     x1, i1, s1 = rka.solve_ex(to_dev(A), vec(b), rkab_split=1, **kw)
-    x2, i2, s2 = rka.solve_ex(to_dev(A), vec(b), rkab_split=2, **kw)
+    x2, i2, s2 = rka.solve_ex(to_dev(A), vec(b), rkab_split=2, rka_block=1, **kw)
     assert s1["kernel"] == 2 and s2["kernel"] == 3 and s2["variant"] < 90
     assert i1.status == rka.OK and i2.status == rka.OK
     assert i2.iterations == i1.iterations
@@ -171,7 +171,7 @@ def test_rkab_column_split_cyclic_and_row_weights():
     wrow = np.random.default_rng(38).uniform(0.5, 1.5, size=1500)
     K, q, bs = 12, 10, 30  # sub-blocks of 25 and 5
     x, info, st = rka.solve_ex(to_dev(A), vec(b), method=1, q=q, block_size=bs, max_iter=K,
-                               sampling=2, row_weight=vec(wrow), rkab_split=2)
+                               sampling=2, row_weight=vec(wrow), rkab_split=2, rka_block=1)
     assert st["kernel"] == 3
     xo = oracle.rkab_wrow_given(A, b, np.zeros(900), oracle.indices_cyclic(1500, 0, K, q, bs),
                                 wrow, q=q, block_size=bs)
