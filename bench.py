@@ -86,7 +86,7 @@ def make_cells(spec, astar):
     return out
 
 
-def kernel_name(stats, storage="double", vec=2, rkab=False):
+def kernel_name(stats, storage="double", vec=2, rkab=False, bs=1):
     """Template instance as named in the library: <storage, accumulation,
     elements per 16-byte vec, register bucket, all-gather / iterate in LDS>
     (the block kernels: <storage, elements per vec, rows per thread[, RKAB]>)."""
@@ -97,7 +97,9 @@ def kernel_name(stats, storage="double", vec=2, rkab=False):
     if stats["kernel"] == 3:
         return f"rka_sstep_kernel<{storage}, {vec}, {stats['bucket']}, {'true' if rkab else 'false'}>"
     if stats["kernel"] == 4:
-        return f"rka_blk_kernel<{storage}, {vec}, {stats['bucket']}>"
+        # mode 0: RKA; RKAB: 1 with one block per outer iteration, 2 in sub-blocks
+        mode = 0 if not rkab else (2 if stats["variant"] < bs else 1)
+        return f"rka_blk_kernel<{storage}, {vec}, {stats['bucket']}, {mode}>"
     return f"rkab_kernel<{storage}, {acc}, {vec}, {stats['bucket']}, {flag}>"
 
 
@@ -111,11 +113,20 @@ def cpu_baseline(A, b, seconds):
         _, info = oracle.rka(A, b, q=q, alpha=1.0, max_iter=K, seed=3)
         return time.perf_counter() - t0, info
 
+    timed(0)                       # pages A in before anything is timed
     t_setup, _ = timed(0)          # row norms + running sum over all of A
-    t_probe, _ = timed(40)
-    per_iter = max((t_probe - t_setup) / 40, 1e-6)
-    K = max(40, int((seconds - t_setup) / per_iter))
-    dt, info = timed(K)
+    # The sample grows until one run fills the budget, each next length from
+    # the rate just measured but at most 8x longer: a setup time that varies
+    # between calls cannot make the estimate run away (a difference of two
+    # timings did once, giving a sample of millions of iterations)
+    K = 64
+    while True:
+        dt, info = timed(K)
+        log(f"[bench] CPU oracle baseline: {K} iterations in {dt:.1f} s")
+        if dt >= 0.8 * seconds or K >= (1 << 22):
+            break
+        per_iter = max((dt - t_setup) / K, dt / K / 4, 1e-7)
+        K = int(min(8 * K, max(2 * K, (seconds - t_setup) / per_iter)))
     return {"value": info["projections"] / dt, "unit": "row projections/s", "cores": 1,
             "kind": "oracle",
             "sample": (f"oracle RKA (plain C, FP64, single thread) on the same {A.shape[0]}x"
@@ -894,7 +905,7 @@ def main():
             pc["sample_ms"] += st["sample_ms"]
             pc["stats"] = st
             total_proj += info.projections
-            name = kernel_name(st, rkab=c[0] == "rkab")
+            name = kernel_name(st, rkab=c[0] == "rkab", bs=c[2])
             kk = kern.setdefault(name, {"ms": 0.0, "launches": 0, "bytes": 0.0})
             kk["ms"] += st["iterate_ms"]
             kk["launches"] += st["iterate_launches"]
@@ -932,7 +943,7 @@ def main():
             "coef_ms_per_solve": pc["coef_ms"] / args.steps,
             "setup_ms_per_solve": pc["setup_ms"] / args.steps,
             "sample_ms_per_solve": pc["sample_ms"] / args.steps,
-            "kernel": kernel_name(pc["stats"], rkab=meth == "rkab"), "grid": pc["stats"]["grid"],
+            "kernel": kernel_name(pc["stats"], rkab=meth == "rkab", bs=bs), "grid": pc["stats"]["grid"],
             "threads": pc["stats"]["threads"],
             "rel_err_vs_x_ls": errs.get(i),
         })
