@@ -193,10 +193,13 @@ typedef struct rka_opts {
                                for q <= 64, of one iteration for 64 < q <= 256, else
                                kernel 3 for q <= 16, else the column-split kernel;
                                for column-split RKAB one outer iteration per block
-                               when q bs <= 256 and bs <= 12 fit, with M_w = (I +
-                               N_w)^-1 per worker from its own rows, N_w[j][l] =
-                               alpha_j <a_j, a_l> / ||a_j||^2 for l < j, else kernel
-                               3); 1 = the inner products between the
+                               when q bs <= 256 and bs <= 12 fit, else sub-blocks of
+                               c <= 12 projections per worker (q dividing the
+                               workgroup's row groups; every worker's iterate kept
+                               for the slice), with M_w = (I + N_w)^-1 per worker
+                               from its own rows, N_w[j][l] = alpha_j <a_j, a_l> /
+                               ||a_j||^2 for l < j, else kernel 3); 1 = the inner
+                               products between the
                                block's rows travel in the exchange (kernel 3); 2 = a
                                streaming pass over the chunk's rows forms, per block,
                                M = (I + N)^-1 with N_{r,c} = alpha_r <a_r, a_c> /
