@@ -205,6 +205,9 @@ RKAB_CASES = [
     (1500, 777, "f64", 8, 30, 4, 0),        # scalar path
     (1500, 640, "bf16", 8, 25, 3, 0),
     (1500, 4096, "f32", 16, 13, 3, 0),      # two sub-blocks, 7 and 6
+    (700, 48, "f64", 8, 20, 5, 2),          # sub-blocks on two workgroups
+    (1500, 300, "f64", 1, 40, 4, 0),        # one worker: RK over the stream, in sub-blocks
+    (1500, 300, "f64", 2, 25, 4, 0),
 ]
 
 
