@@ -29,8 +29,9 @@
  *     (the rows drawn, the projections, the average) depends only on the
  *     inputs and the method parameters (q, block_size, alpha, seed,
  *     iter_offset, max_iter, tol).  Its floating-point rounding also depends
- *     on the launch: the number of workgroups (by default one per compute
- *     unit of the device, or the grid option) fixes the order in which
+ *     on the launch: the number of workgroups (by default chosen from the
+ *     device's compute units and the row length, or the grid option) fixes
+ *     the order in which
  *     partial sums meet, and the kernels that run several RKA iterations per
  *     exchange end a block wherever a stopping test falls (every
  *     check_every iterations) or a chunk of iterations ends, so check_every
