@@ -52,7 +52,9 @@ CASES = [
     (700, 48, "f64", 8, 4, 25, 2),
     (3000, 2000, "f64", 256, 1, 6, 0),     # one iteration per block: no coefficients
     (3000, 2000, "f64", 128, 1, 8, 0),
-    (5000, 10000, "f64", 16, 4, 24, 0),     # long rows
+    (5000, 10000, "f64", 16, 4, 24, 0),     # long rows: 24-vec (384-byte) slices, the last 8
+    (3000, 7000, "f64", 16, 0, 40, 0),      # 16-vec slices (14 rounded up to a line), the last 12
+    (1500, 20000, "f32", 16, 4, 24, 0),     # narrow storage, 24-vec slices
 ]
 
 
@@ -208,6 +210,9 @@ RKAB_CASES = [
     (700, 48, "f64", 8, 20, 5, 2),          # sub-blocks on two workgroups
     (1500, 300, "f64", 1, 40, 4, 0),        # one worker: RK over the stream, in sub-blocks
     (1500, 300, "f64", 2, 25, 4, 0),
+    # slices rounded up to a whole team of lanes, the last one ragged
+    (3000, 5000, "f64", 16, 10, 6, 0),      # 16-vec slices (10 rounded up), the last 4
+    (2000, 7000, "f64", 8, 30, 3, 0),       # sub-blocks on 16-vec slices, the last 12
 ]
 
 
