@@ -210,7 +210,9 @@ typedef struct rka_opts {
                                alpha_r (b_r - <a_r, x^(k)>) / ||a_r||^2 (the same
                                iteration in exact arithmetic, kernel 4; q p <= 128,
                                or p = 1 and q <= 256, else the column-split kernel
-                               runs).                                                 */
+                               runs; column-split RKAB that kernel 4 does not hold
+                               runs on the worker-split kernel 2, which
+                               rka_stats.kernel reports).                             */
 } rka_opts;
 
 /* Launch facts and phase times of one rka_solve_ex call. */

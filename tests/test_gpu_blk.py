@@ -240,6 +240,23 @@ def test_blk_rkab_vs_oracle(m, n, dtype, q, bs, K, grid):
     assert_x_close(host(x), xo, what=f"blk rkab q={q} bs={bs}")
 
 
+def test_blk_rkab_falls_back_to_the_worker_kernel():
+    """Column-split RKAB asked of kernel 4 (rka_block 2) where its row groups
+    cannot each serve whole workers (q = 64 on 32-lane teams at n = 10000) runs
+    on the worker-split kernel, says so in the stats, and is still RKAB (Sec.
+    3.4.1): within 1e-12 of the oracle on the same row stream."""
+    m, n, q, bs, K = 1500, 10000, 64, 10, 3
+    say(f"blk rkab fallback {m}x{n} q={q} bs={bs} K={K}")
+    A, _, b = _system(m, n, "f64", seed=m + n + q + bs)
+    x, info, st = rka.solve_ex(to_dev(A), vec(b), method=1, q=q, block_size=bs, alpha=0.9,
+                               max_iter=K, seed=11, rkab_split=2, rka_block=2)
+    assert info.status == rka.OK and info.iterations == K, info
+    assert st["kernel"] == 2, st
+    idx = oracle.indices(oracle.row_norms(A), 11, 0, K, q, bs)
+    xo = oracle.rkab_given(A, b, np.zeros(n), idx, q=q, block_size=bs, alpha=0.9)
+    assert_x_close(host(x), xo, what="blk rkab fallback")
+
+
 def test_blk_rkab_stops_where_the_worker_kernel_stops():
     say("blk rkab stop")
     A, xs, _ = _system(4000, 300, seed=37, noise=0.0)
