@@ -55,6 +55,7 @@ CASES = [
     (5000, 10000, "f64", 16, 4, 24, 0),     # long rows: 24-vec (384-byte) slices, the last 8
     (3000, 7000, "f64", 16, 0, 40, 0),      # 16-vec slices (14 rounded up to a line), the last 12
     (1500, 20000, "f32", 16, 4, 24, 0),     # narrow storage, 24-vec slices
+    (1000, 40000, "bf16", 16, 4, 16, 0),
 ]
 
 
@@ -213,6 +214,7 @@ RKAB_CASES = [
     # slices rounded up to a whole team of lanes, the last one ragged
     (3000, 5000, "f64", 16, 10, 6, 0),      # 16-vec slices (10 rounded up), the last 4
     (2000, 7000, "f64", 8, 30, 3, 0),       # sub-blocks on 16-vec slices, the last 12
+    (1500, 20000, "f32", 16, 5, 4, 0),      # narrow storage, 32-vec slices (20 rounded up)
 ]
 
 
