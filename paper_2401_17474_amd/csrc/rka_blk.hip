@@ -207,9 +207,15 @@ __device__ __forceinline__ int coef_tiles(int R, int RG, int q, int wv, int (&tI
   return nt;
 }
 
+// Row of a 16-row tile that fragment lane i (0..15) supplies on the
+// LDS-direct path: the 8 lanes of a fragment read served together take
+// rows of 8 different pairs (see kCPairBytes).
+__device__ __forceinline__ int frag_row(int i) { return 2 * (i & 7) + (i >> 3); }
+
 // N = alpha_r / (q w_r) <a_r, a_c> for rows r, c of iterations j > l, from
-// this wave's tiles, into NB (q x q blocks by pair).
-template <int NS>
+// this wave's tiles, into NB (q x q blocks by pair).  FR: the tiles' rows
+// were supplied in frag_row order.
+template <int NS, bool FR = false>
 __device__ __forceinline__ void coef_store_n(const f64x4 (&acc)[NS], const int (&tI)[NS],
                                              const int (&tJ)[NS], int nt, int lane, int R, int q,
                                              const double* FAC, double* NB) {
@@ -218,7 +224,8 @@ __device__ __forceinline__ void coef_store_n(const f64x4 (&acc)[NS], const int (
     if (u < nt) {
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) {
-        const int r = 16 * tI[u] + lane / 16 + 4 * rr, c = 16 * tJ[u] + (lane & 15);
+        const int ri = lane / 16 + 4 * rr, ci = lane & 15;
+        const int r = 16 * tI[u] + (FR ? frag_row(ri) : ri), c = 16 * tJ[u] + (FR ? frag_row(ci) : ci);
         if (r < R && c < R) {
           const int jr = r / q, lc = c / q;
           if (jr > lc)
@@ -298,13 +305,17 @@ __device__ __forceinline__ void coef_gram(const CoefArgs& p, const T* __restrict
 // (global_load_lds: lane l of a wave writes its 16 bytes at the
 // instruction's LDS base + 16 l): one instruction carries rows 2k (lanes
 // 0..31) and 2k + 1 (lanes 32..63) of a 512-byte column segment, CW = 512 /
-// sizeof(T) columns; a row pair takes kCPairBytes of LDS (32 bytes of
-// padding, so that the 16 rows of a fragment read fall on 8 bank pairs).
+// sizeof(T) columns; a row pair takes kCPairBytes of LDS (16 bytes of
+// padding: pairs lie 16 bytes apart modulo 128, so the 8 lanes a 16-byte
+// fragment read serves together, taking rows of 8 different pairs in
+// frag_row order, fall on 8 different 16-byte bank groups; with the rows in
+// order, rows 2k and 2k + 1 of a pair lie 512 bytes apart, on the same
+// banks).
 // Two buffers of cbuf bytes: the next chunk's 64 KB are in flight during the
 // current chunk's MFMAs, with no registers spent on them.  Rows past the
 // block load a clamped row (they only reach products that are never
 // stored); columns past n are zeroed in LDS after the last chunk lands.
-constexpr int kCPairBytes = 1024 + 32;
+constexpr int kCPairBytes = 1024 + 16;
 template <typename T, int NS>
 __device__ __forceinline__ void coef_gram_dma(const CoefArgs& p, const T* __restrict__ A,
                                               char* SB, double* NB, const double* FAC,
@@ -345,7 +356,7 @@ __device__ __forceinline__ void coef_gram_dma(const CoefArgs& p, const T* __rest
   int offI[NS], offJ[NS];
 #pragma unroll
   for (int u = 0; u < NS; ++u) {
-    const int ri = 16 * tI[u] + (lane & 15), rj = 16 * tJ[u] + (lane & 15);
+    const int ri = 16 * tI[u] + frag_row(lane & 15), rj = 16 * tJ[u] + frag_row(lane & 15);
     offI[u] = (ri >> 1) * kCPairBytes + (ri & 1) * 512 + 2 * (lane >> 4) * (int)sizeof(T);
     offJ[u] = (rj >> 1) * kCPairBytes + (rj & 1) * 512 + 2 * (lane >> 4) * (int)sizeof(T);
   }
@@ -405,7 +416,7 @@ __device__ __forceinline__ void coef_gram_dma(const CoefArgs& p, const T* __rest
     }
   }
   __syncthreads();  // every wave is done with both buffers: NB takes their place
-  coef_store_n<NS>(acc, tI, tJ, nt, lane, R, q, FAC, NB);
+  coef_store_n<NS, true>(acc, tI, tJ, nt, lane, R, q, FAC, NB);
 }
 
 // The inner products of a block's rows are the needed lower 16 x 16 tiles of
