@@ -370,10 +370,14 @@ __device__ __forceinline__ void coef_gram_dma(const CoefArgs& p, const T* __rest
     T v[2];
   };
   double fa[4 * NS], fb[4 * NS];
-  auto load = [&](double(&f)[4 * NS], const char* base, int c) {
+  // NA: the slots a wave runs; a wave holding fewer tiles than slots skips
+  // its last (dummy) slot's reads and MFMAs (at q = 16, 28 tiles over 8
+  // waves of 4 slots: 1/8 of the MFMA time of the SIMDs that carry them)
+  auto load = [&](auto na, double(&f)[4 * NS], const char* base, int c) {
+    constexpr int NA = decltype(na)::value;
     const char* bc = base + c * (int)sizeof(T);
 #pragma unroll
-    for (int u = 0; u < NS; ++u) {
+    for (int u = 0; u < NA; ++u) {
       const Pair2 a = *(const Pair2*)(bc + offI[u]);
       const Pair2 bb = *(const Pair2*)(bc + offJ[u]);
       f[4 * u] = widen(a.v[0]);
@@ -382,39 +386,47 @@ __device__ __forceinline__ void coef_gram_dma(const CoefArgs& p, const T* __rest
       f[4 * u + 3] = widen(bb.v[1]);
     }
   };
-  auto step2 = [&](const double(&f)[4 * NS]) {
+  auto step2 = [&](auto na, const double(&f)[4 * NS]) {
+    constexpr int NA = decltype(na)::value;
 #pragma unroll
-    for (int u = 0; u < NS; ++u)
+    for (int u = 0; u < NA; ++u)
       acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[4 * u], f[4 * u + 1], acc[u], 0, 0, 0);
 #pragma unroll
-    for (int u = 0; u < NS; ++u)
+    for (int u = 0; u < NA; ++u)
       acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[4 * u + 2], f[4 * u + 3], acc[u], 0, 0, 0);
   };
-  issue(0, 0);
-  for (int c = 0; c < nch; ++c) {
-    // this wave's loads of chunk c have landed; after the barrier every
-    // wave's have, and every wave is done with chunk c - 1's buffer
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    const char* base = SB + (size_t)(c & 1) * p.cbuf;
-    const int64_t c0 = (int64_t)c * CW;
-    if (c0 + CW > p.n) {  // the last chunk: zero the columns past n
-      const int valid = (int)(p.n - c0);
-      for (int e = t; e < 2 * npairs * (CW - valid); e += kCThreads) {
-        const int r = e / (CW - valid), col = valid + e - r * (CW - valid);
-        *(T*)((char*)base + (r >> 1) * kCPairBytes + (r & 1) * 512 + col * (int)sizeof(T)) = T{};
-      }
+  // every wave meets the same barriers in either instance
+  auto run = [&](auto na) {
+    issue(0, 0);
+    for (int c = 0; c < nch; ++c) {
+      // this wave's loads of chunk c have landed; after the barrier every
+      // wave's have, and every wave is done with chunk c - 1's buffer
+      __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
+      const char* base = SB + (size_t)(c & 1) * p.cbuf;
+      const int64_t c0 = (int64_t)c * CW;
+      if (c0 + CW > p.n) {  // the last chunk: zero the columns past n
+        const int valid = (int)(p.n - c0);
+        for (int e = t; e < 2 * npairs * (CW - valid); e += kCThreads) {
+          const int r = e / (CW - valid), col = valid + e - r * (CW - valid);
+          *(T*)((char*)base + (r >> 1) * kCPairBytes + (r & 1) * 512 + col * (int)sizeof(T)) = T{};
+        }
+        __syncthreads();
+      }
+      if (c + 1 < nch) issue(c + 1, (c + 1) & 1);
+      load(na, fa, base, 0);
+      for (int k = 0; k < CW; k += 16) {  // CW is a multiple of 16
+        load(na, fb, base, k + 8);
+        step2(na, fa);
+        if (k + 16 < CW) load(na, fa, base, k + 16);
+        step2(na, fb);
+      }
     }
-    if (c + 1 < nch) issue(c + 1, (c + 1) & 1);
-    load(fa, base, 0);
-    for (int k = 0; k < CW; k += 16) {  // CW is a multiple of 16
-      load(fb, base, k + 8);
-      step2(fa);
-      if (k + 16 < CW) load(fa, base, k + 16);
-      step2(fb);
-    }
-  }
+  };
+  if (__builtin_amdgcn_readfirstlane(nt) >= NS)
+    run(std::integral_constant<int, NS>{});
+  else
+    run(std::integral_constant<int, NS - 1>{});
   __syncthreads();  // every wave is done with both buffers: NB takes their place
   coef_store_n<NS, true>(acc, tI, tJ, nt, lane, R, q, FAC, NB);
 }
